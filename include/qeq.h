@@ -1,0 +1,146 @@
+/*
+ * qeq.h -- C ABI of the MI355X particle-mesh charge-equilibration library.
+ *
+ * Problem (RuNNer 2.0 paper, "Electrostatics and Charge Equilibration":
+ * eq. elec_energy, eq. qeq_energy, eq. 4G_qeq_prime; SI "Fourth-Generation
+ * HDNNPs and Charge Equilibration", eq. qeq).  Given positions r_i in a
+ * periodic cell, Gaussian widths sigma_i, hardnesses J_i > 0,
+ * electronegativities chi_i and a total charge Q_tot, find the charges q that
+ * minimise
+ *
+ *     E_QEq(q) = E_elec(q) + sum_i (chi_i q_i + J_i q_i^2 / 2)   s.t.  sum_i q_i = Q_tot,
+ *
+ * where E_elec = q^T E q / 2 is the Coulomb energy of normalised Gaussian
+ * charges (non-periodic kernel E_ii = 1/(sigma_i sqrt(pi)),
+ * E_ij = erf(r_ij / (sqrt2 gamma_ij)) / r_ij, gamma_ij^2 = sigma_i^2 + sigma_j^2),
+ * made periodic with a neutralising background and tin-foil boundary.
+ * Stationarity gives (E + diag J) q = -chi + mu 1 (the SI's form; mu = -lambda
+ * of the main text's bordered system).
+ *
+ * Method (paper, "Electrostatics Solvers", eq. matvec; SI "Particle--Particle--
+ * Particle--Mesh Method"): conjugate gradients on the constraint plane, whose
+ * matrix-vector product (E v)_i = dE_elec/dq_i is evaluated without forming E:
+ * smooth particle-mesh Ewald with order-p cardinal B-splines, a 3-D FFT,
+ * multiplication by the Gaussian-screened reciprocal kernel
+ * 4 pi exp(-eta^2 k^2 / 2) / (V k^2), back-interpolation, plus a real-space
+ * pair term [erf(r/(sqrt2 gamma)) - erf(r/(sqrt2 eta))]/r inside r_cut, the
+ * Gaussian self term and the background term.
+ *
+ * Conventions for every call:
+ *   - Atomic units (bohr, Hartree, e).
+ *   - A cell is 9 doubles, row-major, ROWS = lattice vectors; it is a HOST
+ *     pointer.  Every per-atom array is a DEVICE pointer on the plan's device,
+ *     contiguous, owned by the caller.  pos is n x 3 row-major.
+ *   - All device work is enqueued on the stream given to qeq_plan_create; the
+ *     calls return after the stream has drained (they read back a status).
+ *   - Return value: 0 on success; QEQ_NOT_CONVERGED (+1) when max_iter was
+ *     reached (outputs hold the last iterate, stats are valid); a negative
+ *     code on error (outputs untouched or partially written; no exception
+ *     crosses the ABI).  qeq_strerror() names every code.
+ *   - A plan is not thread-safe: one host thread at a time, and calls on one
+ *     plan must not overlap.
+ */
+#ifndef QEQ_H
+#define QEQ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QEQ_OK             0
+#define QEQ_NOT_CONVERGED  1
+#define QEQ_EINVAL        -1  /* n < 1, J_i <= 0, sigma_i <= 0, non-finite input, singular cell */
+#define QEQ_ECELL         -2  /* cell too skewed / grid too small for the spline order */
+#define QEQ_ENOMEM        -3  /* device allocation failed */
+#define QEQ_EHIP          -4  /* a HIP runtime call failed */
+#define QEQ_EPLAN         -5  /* unsupported grid size or spline order, n > n_atoms_max */
+
+typedef struct qeq_plan qeq_plan;   /* opaque; owns device workspace and the saved tape */
+
+typedef struct qeq_params {
+    double  eta;             /* std. dev. of the Ewald screening Gaussian (bohr); reciprocal
+                                kernel exp(-eta^2 k^2 / 2), real-space erf(r/(sqrt2 eta))/r */
+    double  r_cut;           /* real-space cutoff (bohr); all periodic images are included */
+    double  max_spacing;     /* grid spacing bound (bohr), used when grid[0] == 0 */
+    int32_t grid[3];         /* FFT grid K1,K2,K3: multiples of 4 with prime factors in
+                                {2,3,5}, 12 <= K <= 512; grid[0] == 0 derives it per cell */
+    int32_t spline_order;    /* p: even, 4 <= p <= 8 (cardinal B-spline M_p) */
+    double  tol;             /* stop when ||P(A q + chi_eff)|| <= tol ||P chi_eff||, P = I - 11^T/N */
+    int32_t max_iter;        /* CG iteration cap */
+    int32_t self_correction; /* 1: replace each atom's mesh self-interaction by the exact
+                                reciprocal self term (energy and force), 0: plain SPME */
+} qeq_params;
+
+typedef struct qeq_stats {   /* host memory */
+    int32_t status;          /* same code the call returned */
+    int32_t iters;           /* CG iterations taken */
+    double  rel_resid;       /* recursive projected residual at exit (relative) */
+    double  true_rel_resid;  /* projected residual of A q + chi recomputed at exit (relative) */
+    double  mu;              /* Lagrange multiplier: (E + diag J) q + chi = mu 1 */
+    double  e_qeq;           /* E_QEq at q */
+    double  e_elec;          /* E_elec at q */
+} qeq_stats;
+
+/* Default parameters: eta 2.0, r_cut 11.0, max_spacing 0.8, grid derived,
+   p = 6, tol 1e-6, max_iter 1000, self_correction 1. */
+void qeq_params_default(qeq_params* p);
+
+/* Create a plan for up to n_atoms_max atoms on the current HIP device.
+   hip_stream: a hipStream_t (NULL = the default stream).  Returns QEQ_EPLAN
+   for an unsupported grid or spline order, QEQ_EINVAL for bad parameters. */
+int qeq_plan_create(qeq_plan** out, const qeq_params* params, int32_t n_atoms_max,
+                    void* hip_stream);
+int qeq_plan_destroy(qeq_plan* plan);
+
+/* Solve the QEq problem (eq. 4G_qeq_prime) for one periodic structure.
+   pos (n*3), sigma, J, chi (n each): device, read-only.
+   q0 (n, device) or NULL: initial guess, projected onto sum = q_tot; NULL
+   starts from q_tot/n.
+   q (n, device, out): charges.
+   energies (2, device, out) or NULL: [E_QEq, E_elec].
+   forces (n*3, device, out) or NULL: -dE_QEq/dr at the solution.  At the
+   stationary point this equals -dE_elec/dr at fixed q, so no extra solve is
+   needed (SI eq. 4g_force_trick with a constant chi and J).
+   stats (host, out) or NULL.
+   The call saves a tape (sorted geometry, pair list, q, potential) that
+   qeq_backward uses; the next solve on the plan replaces it. */
+int qeq_solve(qeq_plan* plan, int32_t n, const double* pos, const double* cell,
+              const double* sigma, const double* J, const double* chi, double q_tot,
+              const double* q0, double* q, double* energies, double* forces,
+              qeq_stats* stats);
+
+/* y = E v with the plan's particle-mesh operator (no J), for checking the
+   matrix-vector product of eq. matvec on its own.  parts is a bit mask:
+   1 reciprocal (mesh) part, 2 real-space pair part, 4 self terms (Gaussian
+   self energy and mesh self-correction), 8 background term; 15 = all of E.
+   v, y: n doubles on the device. */
+int qeq_matvec(qeq_plan* plan, int32_t n, const double* pos, const double* cell,
+               const double* sigma, const double* v, double* y, int32_t parts);
+
+/* Per-stage timers (the paper's per-stage timing of a step, here with HIP
+   events on the plan's stream).  kind_mask selects which launch kinds are
+   bracketed with events during later calls; 0 switches timing off.  Kinds:
+     0 spread + axis-3 R2C FFT      1 axis-2 forward FFT
+     2 axis-1 FFT + Green + inverse 3 axis-2 inverse FFT
+     4 axis-3 C2R FFT               5 interpolation + pair product (CG)
+     6 CG update                    7 CG direction
+     8 final energies / forces
+   CG-loop launches that found the solve already converged are not counted. */
+int qeq_profile(qeq_plan* plan, uint32_t kind_mask);
+
+/* Copies accumulated milliseconds and launch counts for the first n_kinds
+   kinds into total_ms / launches (host arrays, may be NULL), optionally
+   resets them, and returns the number of kinds the library knows (9).
+   Synchronises the plan's stream. */
+int qeq_profile_read(qeq_plan* plan, double* total_ms, int64_t* launches, int32_t n_kinds,
+                     int32_t reset);
+
+const char* qeq_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QEQ_H */

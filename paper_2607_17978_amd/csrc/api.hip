@@ -1,0 +1,643 @@
+// Host side of the library: plans (device workspace, FFT tables, cell cache),
+// the solve / matvec orchestration on the plan's stream, and the C ABI.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "internal.h"
+
+int qeq_check(hipError_t e) {
+    if (e == hipSuccess) return QEQ_OK;
+    if (e == hipErrorOutOfMemory) return QEQ_ENOMEM;
+    return QEQ_EHIP;
+}
+
+// ---------------------------------------------------------------- stage timers
+static hipEvent_t prof_event(qeq_plan* pl) {
+    if (!pl->prof_pool.empty()) {
+        hipEvent_t e = pl->prof_pool.back();
+        pl->prof_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+ProfScope::ProfScope(qeq_plan* p, int kind) : pl(p) {
+    on = kind >= 0 && kind < PK_COUNT && (p->prof_mask >> kind) & 1u;
+    rec.kind = kind;
+    rec.it = p->cur_it;
+    rec.a = rec.b = nullptr;
+    if (!on) return;
+    rec.a = prof_event(p);
+    rec.b = prof_event(p);
+    if (!rec.a || !rec.b || hipEventRecord(rec.a, p->stream) != hipSuccess) on = false;
+}
+
+ProfScope::~ProfScope() {
+    if (!on) {
+        if (rec.a) pl->prof_pool.push_back(rec.a);
+        if (rec.b) pl->prof_pool.push_back(rec.b);
+        return;
+    }
+    if (hipEventRecord(rec.b, pl->stream) == hipSuccess) pl->prof_pending.push_back(rec);
+}
+
+// Accumulate the recorded durations (stream already synchronised).  Launches
+// of CG iterations at or beyond the number of live iterations found the done
+// flag set and returned at once; they are dropped.
+void prof_flush(qeq_plan* pl, int live_iters) {
+    for (ProfRec& r : pl->prof_pending) {
+        float ms = 0.f;
+        bool live = r.it < 0 || r.it < live_iters;
+        if (live && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            pl->prof_ms[r.kind] += ms;
+            pl->prof_n[r.kind] += 1;
+        }
+        pl->prof_pool.push_back(r.a);
+        pl->prof_pool.push_back(r.b);
+    }
+    pl->prof_pending.clear();
+}
+
+namespace {
+
+const double PI = 3.14159265358979323846;
+
+template <typename T>
+int dalloc(T** p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+    return e == hipSuccess ? QEQ_OK : QEQ_ENOMEM;
+}
+
+template <typename T>
+void dfree(T*& p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+bool smooth_235(int n) {
+    for (int f : {2, 3, 5})
+        while (n % f == 0) n /= f;
+    return n == 1;
+}
+
+// Radix plan: all factors 5 and 3 first, then the power of two as 8s with a
+// final 4 or 2.
+bool radix_plan(int K, FftAxis* ax) {
+    int n = K, ns = 0;
+    while (n % 5 == 0) { ax->radix[ns++] = 5; n /= 5; }
+    while (n % 3 == 0) { ax->radix[ns++] = 3; n /= 3; }
+    while (n % 8 == 0) { ax->radix[ns++] = 8; n /= 8; }
+    if (n == 4) { ax->radix[ns++] = 4; n = 1; }
+    if (n == 2) { ax->radix[ns++] = 2; n = 1; }
+    if (n != 1 || ns > QEQ_FFT_MAXST) return false;
+    ax->nst = ns;
+    ax->K = K;
+    return true;
+}
+
+// Cardinal B-spline M_p at the integers 0..p (host, FP64).
+void bspline_integer_values(int p, double* out) {
+    double c[QEQ_MAXP + 1] = {0}, dc[QEQ_MAXP + 1] = {0};
+    // weights at w = 0: c[k] = M_p(k)
+    c[0] = 0.0;
+    c[1] = 1.0;
+    for (int k = 2; k <= QEQ_MAXP; ++k) c[k] = 0.0;
+    for (int n = 3; n <= p; ++n) {
+        double inv = 1.0 / (n - 1);
+        for (int k = n - 1; k >= 1; --k) c[k] = (k * c[k] + (n - k) * c[k - 1]) * inv;
+        c[0] = 0.0;
+    }
+    (void)dc;
+    for (int k = 0; k <= p; ++k) out[k] = k < QEQ_MAXP + 1 ? c[k] : 0.0;
+}
+
+// |b(m)|^2 = 1 / |sum_{k=0}^{p-2} M_p(k+1) exp(2 pi i m k / K)|^2  (Essmann et al.)
+void bspline_moduli(int K, int p, std::vector<float>& out) {
+    double M[QEQ_MAXP + 1];
+    bspline_integer_values(p, M);
+    out.resize(K);
+    for (int m = 0; m < K; ++m) {
+        double re = 0.0, im = 0.0;
+        for (int k = 0; k <= p - 2; ++k) {
+            double a = 2.0 * PI * (double)m * k / K;
+            re += M[k + 1] * cos(a);
+            im += M[k + 1] * sin(a);
+        }
+        double d = re * re + im * im;
+        out[m] = d > 1e-30 ? (float)(1.0 / d) : 0.f;
+    }
+}
+
+void inv3(const double* H, double* Hi, double* det) {
+    double a = H[0], b = H[1], c = H[2], d = H[3], e = H[4], f = H[5], g = H[6], h = H[7], i = H[8];
+    double A = e * i - f * h, B = -(d * i - f * g), C = d * h - e * g;
+    double D = -(b * i - c * h), E = a * i - c * g, F = -(a * h - b * g);
+    double G = b * f - c * e, Hh = -(a * f - c * d), I = a * e - b * d;
+    *det = a * A + b * B + c * C;
+    double r = 1.0 / *det;
+    Hi[0] = A * r; Hi[1] = D * r; Hi[2] = G * r;
+    Hi[3] = B * r; Hi[4] = E * r; Hi[5] = Hh * r;
+    Hi[6] = C * r; Hi[7] = F * r; Hi[8] = I * r;
+}
+
+double pair_f(double r, double eta, double zeta) {
+    const double s2 = 0.70710678118654752440;
+    if (r < 1e-12) return sqrt(2.0 / PI) * (1.0 / eta - 1.0 / zeta);
+    return (erf(r * s2 / eta) - erf(r * s2 / zeta)) / r;
+}
+
+// C_eta = (4 pi / V) sum_{k != 0} exp(-eta^2 k^2 / 2) / k^2 evaluated with a
+// second, wider split zeta: C_eta = C_zeta + sum_n f(|n H|) - 2 pi (zeta^2 - eta^2) / V,
+// f(r) = [erf(r/(sqrt2 eta)) - erf(r/(sqrt2 zeta))] / r (Poisson summation of
+// the difference kernel), which needs few k vectors and few lattice vectors.
+double reciprocal_self_constant(const double* H, const double* Hinv, double vol, double eta) {
+    double widths[3], lengths[3];
+    for (int a = 0; a < 3; ++a) {
+        double n2 = 0.0, l2 = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            n2 += Hinv[c * 3 + a] * Hinv[c * 3 + a];
+            l2 += H[a * 3 + c] * H[a * 3 + c];
+        }
+        widths[a] = 1.0 / sqrt(n2);
+        lengths[a] = sqrt(l2);
+    }
+    double zeta = std::max(eta, 0.3 * cbrt(vol));
+    const double X = 6.5 * sqrt(2.0);
+    // k-space with zeta
+    double kmax = X / zeta;
+    int mm[3];
+    for (int a = 0; a < 3; ++a) mm[a] = (int)ceil(kmax * lengths[a] / (2 * PI)) + 1;
+    double ks = 0.0;
+    for (int m1 = -mm[0]; m1 <= mm[0]; ++m1)
+        for (int m2 = -mm[1]; m2 <= mm[1]; ++m2)
+            for (int m3 = -mm[2]; m3 <= mm[2]; ++m3) {
+                if (!m1 && !m2 && !m3) continue;
+                double k[3];
+                for (int c = 0; c < 3; ++c)
+                    k[c] = 2 * PI * (Hinv[c * 3 + 0] * m1 + Hinv[c * 3 + 1] * m2 + Hinv[c * 3 + 2] * m3);
+                double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+                if (k2 > kmax * kmax) continue;
+                ks += exp(-0.5 * zeta * zeta * k2) / k2;
+            }
+    ks *= 4 * PI / vol;
+    // real-space lattice sum of the difference kernel
+    double rmax = X * zeta;
+    int nn[3];
+    for (int a = 0; a < 3; ++a) nn[a] = (int)ceil(rmax / widths[a]) + 1;
+    double rs = 0.0;
+    for (int n1 = -nn[0]; n1 <= nn[0]; ++n1)
+        for (int n2 = -nn[1]; n2 <= nn[1]; ++n2)
+            for (int n3 = -nn[2]; n3 <= nn[2]; ++n3) {
+                double x[3];
+                for (int c = 0; c < 3; ++c) x[c] = n1 * H[0 * 3 + c] + n2 * H[1 * 3 + c] + n3 * H[2 * 3 + c];
+                double r = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+                if (r > rmax) continue;
+                rs += pair_f(r, eta, zeta);
+            }
+    return ks + rs - 2 * PI * (zeta * zeta - eta * eta) / vol;
+}
+
+void free_grid(qeq_plan* pl) {
+    for (int a = 0; a < 3; ++a) {
+        dfree(pl->tw[a]);
+        dfree(pl->bmod[a]);
+    }
+    dfree(pl->grid_r);
+    dfree(pl->grid_c);
+    dfree(pl->bin_count);
+    dfree(pl->bin_start);
+    dfree(pl->bin_fill);
+    pl->K[0] = pl->K[1] = pl->K[2] = 0;
+    pl->theta_valid = false;
+}
+
+int ensure_grid(qeq_plan* pl, const int K[3]) {
+    if (pl->K[0] == K[0] && pl->K[1] == K[1] && pl->K[2] == K[2]) return QEQ_OK;
+    free_grid(pl);
+    int p = pl->prm.spline_order;
+    for (int a = 0; a < 3; ++a) {
+        if (K[a] < 12 || K[a] > 512 || K[a] % 4 != 0 || !smooth_235(K[a]) || K[a] < 2 * p)
+            return QEQ_EPLAN;
+    }
+    for (int a = 0; a < 3; ++a) {
+        FftAxis ax;
+        if (!radix_plan(K[a], &ax)) return QEQ_EPLAN;
+        std::vector<float2> tw(K[a]);
+        for (int j = 0; j < K[a]; ++j) {
+            double ang = -2.0 * PI * (double)j / (double)K[a];
+            tw[j] = make_float2((float)cos(ang), (float)sin(ang));
+        }
+        QEQ_TRY(dalloc(&pl->tw[a], K[a]));
+        QEQ_HIP(hipMemcpy(pl->tw[a], tw.data(), sizeof(float2) * K[a], hipMemcpyHostToDevice));
+        ax.tw = pl->tw[a];
+        pl->axes.ax[a] = ax;
+        std::vector<float> bm;
+        bspline_moduli(K[a], p, bm);
+        QEQ_TRY(dalloc(&pl->bmod[a], K[a]));
+        QEQ_HIP(hipMemcpy(pl->bmod[a], bm.data(), sizeof(float) * K[a], hipMemcpyHostToDevice));
+    }
+    size_t nreal = (size_t)K[0] * K[1] * K[2];
+    size_t ncplx = (size_t)(K[2] / 2 + 1) * K[0] * K[1];
+    QEQ_TRY(dalloc(&pl->grid_r, nreal));
+    QEQ_TRY(dalloc(&pl->grid_c, ncplx));
+    int nb = K[0] * K[1] + 1;
+    QEQ_TRY(dalloc(&pl->bin_count, nb));
+    QEQ_TRY(dalloc(&pl->bin_start, nb + 1));
+    QEQ_TRY(dalloc(&pl->bin_fill, nb));
+    pl->grid_bytes = nreal * 4 + ncplx * 8;
+    pl->K[0] = K[0];
+    pl->K[1] = K[1];
+    pl->K[2] = K[2];
+    pl->theta_valid = false;
+    return QEQ_OK;
+}
+
+int ilog2(int x) {
+    int l = 0;
+    while ((1 << l) < x) ++l;
+    return l;
+}
+
+// Geometry, grid and kernel parameters for one call.
+int prepare(qeq_plan* pl, int n, const double* cell, double q_tot) {
+    if (n < 1 || !cell) return QEQ_EINVAL;
+    if (n > pl->n_max) return QEQ_EPLAN;
+    for (int t = 0; t < 9; ++t)
+        if (!isfinite(cell[t])) return QEQ_EINVAL;
+    if (!isfinite(q_tot)) return QEQ_EINVAL;
+    KParams& k = pl->kp;
+    memset(&k, 0, sizeof(k));
+    double det;
+    double Hi[9];
+    inv3(cell, Hi, &det);
+    if (!(det > 0.0) || !isfinite(det)) return QEQ_EINVAL;
+    for (int t = 0; t < 9; ++t) {
+        k.H[t] = cell[t];
+        k.Hinv[t] = Hi[t];
+    }
+    k.vol = det;
+    // metric (H H^T)^-1 = Hinv^T Hinv
+    double Mm[9];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double s = 0.0;
+            for (int c = 0; c < 3; ++c) s += Hi[c * 3 + a] * Hi[c * 3 + b];
+            Mm[a * 3 + b] = s;
+        }
+    k.M[0] = Mm[0];
+    k.M[1] = Mm[4];
+    k.M[2] = Mm[8];
+    k.M[3] = Mm[1];
+    k.M[4] = Mm[2];
+    k.M[5] = Mm[5];
+    double widths[3], lengths[3];
+    for (int a = 0; a < 3; ++a) {
+        widths[a] = 1.0 / sqrt(Mm[a * 3 + a]);
+        lengths[a] = sqrt(cell[a * 3] * cell[a * 3] + cell[a * 3 + 1] * cell[a * 3 + 1] +
+                          cell[a * 3 + 2] * cell[a * 3 + 2]);
+    }
+    int K[3];
+    for (int a = 0; a < 3; ++a) {
+        if (pl->prm.grid[0] > 0) {
+            K[a] = pl->prm.grid[a];
+        } else {
+            int m = (int)ceil(lengths[a] / pl->prm.max_spacing - 1e-12);
+            m = std::max(m, 12);
+            m = (m + 3) / 4 * 4;
+            while (!smooth_235(m)) m += 4;
+            K[a] = m;
+        }
+    }
+    QEQ_TRY(ensure_grid(pl, K));
+    const int p = pl->prm.spline_order;
+    k.n = n;
+    k.p = p;
+    k.K1 = K[0];
+    k.K2 = K[1];
+    k.K3 = K[2];
+    k.K3h = K[2] / 2 + 1;
+    // axis-2 tile: 16, 8 or 4 rows, with LDS per block within 48 KB
+    int tw = 16;
+    while (tw > 4 && (K[1] % tw != 0 || (size_t)K[0] * tw * 8 > 49152 ||
+                      (size_t)K[2] * (tw / 2) * 8 + (size_t)(K[2] / 2 + 1) * tw * 8 > 49152))
+        tw >>= 1;
+    if (K[1] % tw != 0 || K[1] < tw + p - 1) return QEQ_EPLAN;
+    k.TW = tw;
+    k.TWlog2 = ilog2(tw);
+    k.ntile = K[1] / tw;
+    int nr = 16;
+    while (nr > 1 && (size_t)K[1] * nr * 8 > 49152) nr >>= 1;
+    k.NR = nr;
+    k.NRlog2 = ilog2(nr);
+    // every FFT stage must fit the per-thread register budget
+    if ((size_t)K[0] * tw > (size_t)QEQ_FFT_EMAX * QEQ_FFT_THREADS ||
+        (size_t)K[1] * nr > (size_t)QEQ_FFT_EMAX * QEQ_FFT_THREADS ||
+        (size_t)K[2] * (tw / 2) > (size_t)QEQ_FFT_EMAX * QEQ_FFT_THREADS)
+        return QEQ_EPLAN;
+    // real-space cells: at least half a cutoff wide
+    double rc = pl->prm.r_cut;
+    int ncell = 1;
+    for (int a = 0; a < 3; ++a) {
+        int nc = (int)floor(2.0 * widths[a] / rc);
+        nc = std::max(1, std::min(nc, 256));
+        k.nc[a] = nc;
+        k.ns[a] = (int)ceil(rc * nc / widths[a] - 1e-12);
+        if (k.ns[a] > 64) return QEQ_ECELL;
+        ncell *= nc;
+    }
+    if (ncell + 1 > pl->ncell_alloc) {
+        dfree(pl->cell_count);
+        dfree(pl->cell_start);
+        dfree(pl->cell_fill);
+        QEQ_TRY(dalloc(&pl->cell_count, ncell + 1));
+        QEQ_TRY(dalloc(&pl->cell_start, ncell + 2));
+        QEQ_TRY(dalloc(&pl->cell_fill, ncell + 1));
+        pl->ncell_alloc = ncell + 1;
+    }
+    k.parts = QEQ_PART_RECIP | QEQ_PART_REAL | QEQ_PART_SELF | QEQ_PART_BG;
+    k.self_corr = pl->prm.self_correction;
+    k.eta = pl->prm.eta;
+    k.rc = rc;
+    k.rc2 = rc * rc;
+    k.green_pref = 4.0 * PI / det;
+    k.bg_pref = 2.0 * PI / det;
+    k.q_tot = q_tot;
+    k.tol = pl->prm.tol;
+    bool same_cell = true;
+    for (int t = 0; t < 9; ++t) same_cell = same_cell && (pl->cell_cached[t] == cell[t]);
+    if (!same_cell || !pl->theta_valid) {
+        pl->c_eta = reciprocal_self_constant(k.H, k.Hinv, det, k.eta);
+        pl->theta_valid = false;
+    }
+    k.c_eta = pl->c_eta;
+    if (k.self_corr && !pl->theta_valid) {
+        QEQ_TRY(launch_theta(pl));
+        pl->theta_valid = true;
+    }
+    for (int t = 0; t < 9; ++t) pl->cell_cached[t] = cell[t];
+    return QEQ_OK;
+}
+
+// Geometry-dependent setup on the device; one host sync (pair count, input flag).
+int setup_geometry(qeq_plan* pl, const double* pos, const double* sigma, const double* J,
+                   const double* chi) {
+    QEQ_HIP(hipMemsetAsync(pl->sc, 0, sizeof(CgScalars), pl->stream));
+    QEQ_TRY(launch_stage(pl, pos, sigma, J, chi));
+    QEQ_TRY(launch_sort_bins(pl));
+    QEQ_TRY(launch_gather(pl, pos, sigma, J, chi));
+    QEQ_TRY(launch_cells_and_pairs(pl));   // synchronises for the pair count
+    QEQ_HIP(hipMemcpyAsync(pl->sc_host, pl->sc, sizeof(CgScalars), hipMemcpyDeviceToHost, pl->stream));
+    QEQ_HIP(hipStreamSynchronize(pl->stream));
+    if (pl->sc_host->err & QEQ_ERRBIT_INPUT) return QEQ_EINVAL;
+    if (pl->kp.self_corr) QEQ_TRY(launch_selfcorr(pl));
+    return QEQ_OK;
+}
+
+int solve_impl(qeq_plan* pl, int n, const double* pos, const double* cell, const double* sigma,
+               const double* J, const double* chi, double q_tot, const double* q0, double* q,
+               double* energies, double* forces, qeq_stats* stats) {
+    if (!pos || !sigma || !J || !chi || !q) return QEQ_EINVAL;
+    pl->tape_valid = false;
+    QEQ_TRY(prepare(pl, n, cell, q_tot));
+    QEQ_TRY(setup_geometry(pl, pos, sigma, J, chi));
+    const int* done = &pl->sc->done;
+    // initial guess (projected onto the constraint plane)
+    QEQ_TRY(launch_cg_init_q(pl, q0));
+    const int chunk = 8;
+    int it = 0;
+    bool conv = false;
+    // The recursive residual of CG drifts from the true one by the FP32 error
+    // of the matvecs, which scales with |q| along the way.  After convergence
+    // the final matvec (which also yields energies and forces) measures the
+    // true residual; if it exceeds the tolerance by more than the FP32 floor,
+    // CG restarts from the current charges.
+    const double restart_thr = 2.0 * std::max(pl->prm.tol, 1e-7);
+    for (int restart = 0;; ++restart) {
+        // residual of the current q and the first direction
+        QEQ_TRY(launch_mesh_potential(pl, pl->q, done));
+        QEQ_TRY(launch_interp(pl, pl->q, pl->y, QEQ_MODE_CG, 0));
+        QEQ_TRY(launch_cg_init_r(pl));
+        QEQ_TRY(launch_cg_dir(pl, 1, 1));
+        conv = false;
+        int local = 0;
+        while (it < pl->prm.max_iter) {
+            int m = std::min(chunk, pl->prm.max_iter - it);
+            for (int t = 0; t < m; ++t, ++it, ++local) {
+                int parity = local & 1;
+                pl->cur_it = it;
+                QEQ_TRY(launch_mesh_potential(pl, pl->pvec, done));
+                QEQ_TRY(launch_interp(pl, pl->pvec, pl->y, QEQ_MODE_CG, parity));
+                QEQ_TRY(launch_cg_update(pl, parity));
+                QEQ_TRY(launch_cg_dir(pl, parity, 0));
+            }
+            pl->cur_it = -1;
+            QEQ_HIP(hipMemcpyAsync(pl->sc_host, pl->sc, sizeof(CgScalars), hipMemcpyDeviceToHost,
+                                   pl->stream));
+            QEQ_HIP(hipStreamSynchronize(pl->stream));
+            if (pl->sc_host->done) break;
+        }
+        QEQ_HIP(hipMemcpyAsync(pl->sc_host, pl->sc, sizeof(CgScalars), hipMemcpyDeviceToHost, pl->stream));
+        QEQ_HIP(hipStreamSynchronize(pl->stream));
+        conv = pl->sc_host->done != 0;
+        // final matvec on q: energies, mu, true residual, forces; scatter to caller order
+        QEQ_TRY(launch_mesh_potential(pl, pl->q, nullptr));
+        QEQ_TRY(launch_final(pl, q, energies, forces));
+        QEQ_HIP(hipMemcpyAsync(pl->out_host, pl->final_dev, 4 * sizeof(double), hipMemcpyDeviceToHost,
+                               pl->stream));
+        QEQ_HIP(hipMemcpyAsync(pl->sc_host, pl->sc, sizeof(CgScalars), hipMemcpyDeviceToHost, pl->stream));
+        QEQ_HIP(hipStreamSynchronize(pl->stream));
+        bool gap = !(pl->out_host[3] <= restart_thr);
+        if (!conv || !gap || restart >= 4 || it >= pl->prm.max_iter) {
+            if (conv && gap) conv = false;
+            break;
+        }
+        QEQ_HIP(hipMemsetAsync(&pl->sc->done, 0, sizeof(int), pl->stream));
+    }
+    prof_flush(pl, pl->sc_host->iters);
+    int status = conv ? QEQ_OK : QEQ_NOT_CONVERGED;
+    if (pl->sc_host->err & QEQ_ERRBIT_INPUT) status = QEQ_EINVAL;
+    if (!isfinite(pl->out_host[0])) status = status == QEQ_OK ? QEQ_NOT_CONVERGED : status;
+    if (stats) {
+        stats->status = status;
+        stats->iters = pl->sc_host->iters;
+        stats->rel_resid = pl->sc_host->res;
+        stats->true_rel_resid = pl->out_host[3];
+        stats->mu = pl->out_host[2];
+        stats->e_qeq = pl->out_host[0];
+        stats->e_elec = pl->out_host[1];
+    }
+    pl->tape_valid = status >= 0;
+    return status;
+}
+
+}  // namespace
+
+extern "C" {
+
+void qeq_params_default(qeq_params* p) {
+    if (!p) return;
+    p->eta = 2.0;
+    p->r_cut = 11.0;
+    p->max_spacing = 0.8;
+    p->grid[0] = p->grid[1] = p->grid[2] = 0;
+    p->spline_order = 6;
+    p->tol = 1e-6;
+    p->max_iter = 1000;
+    p->self_correction = 1;
+}
+
+int qeq_plan_create(qeq_plan** out, const qeq_params* params, int32_t n_atoms_max, void* hip_stream) {
+    if (!out || !params || n_atoms_max < 1) return QEQ_EINVAL;
+    *out = nullptr;
+    const qeq_params& p = *params;
+    if (!(p.eta > 0.0) || !(p.r_cut > 0.0) || !(p.tol > 0.0) || p.max_iter < 0) return QEQ_EINVAL;
+    if (p.grid[0] <= 0 && !(p.max_spacing > 0.0)) return QEQ_EINVAL;
+    if (p.spline_order < 4 || p.spline_order > QEQ_MAXP || (p.spline_order & 1)) return QEQ_EPLAN;
+    qeq_plan* pl = new (std::nothrow) qeq_plan();
+    if (!pl) return QEQ_ENOMEM;
+    pl->prm = p;
+    pl->n_max = n_atoms_max;
+    pl->stream = (hipStream_t)hip_stream;
+    (void)hipGetDevice(&pl->dev);
+    size_t n = (size_t)n_atoms_max;
+    int rc = QEQ_OK;
+    auto A = [&](int r) {
+        if (rc == QEQ_OK) rc = r;
+    };
+    A(dalloc(&pl->perm, n));
+    A(dalloc(&pl->key, n));
+    A(dalloc(&pl->frac, 3 * n));
+    A(dalloc(&pl->home, 4 * n));
+    A(dalloc(&pl->wts, 3 * QEQ_MAXP * n));
+    A(dalloc(&pl->dwts, 3 * QEQ_MAXP * n));
+    A(dalloc(&pl->sig, n));
+    A(dalloc(&pl->Jv, n));
+    A(dalloc(&pl->chi, n));
+    A(dalloc(&pl->chi_raw, n));
+    A(dalloc(&pl->dself, n));
+    A(dalloc(&pl->dinv, n));
+    A(dalloc(&pl->selfgrad, 3 * n));
+    A(dalloc(&pl->q, n));
+    A(dalloc(&pl->r, n));
+    A(dalloc(&pl->pvec, n));
+    A(dalloc(&pl->y, n));
+    A(dalloc(&pl->forces_s, 3 * n));
+    A(dalloc(&pl->gtmp, n));
+    A(dalloc(&pl->rowptr, n + 1));
+    A(dalloc(&pl->cell_atoms, n));
+    A(dalloc(&pl->rowcnt, n + 1));
+    int np = 2 * QEQ_MAXP - 1;
+    A(dalloc(&pl->theta_tab, (size_t)np * np * np));
+    pl->nblk_max = nblocks(n_atoms_max) + 1;
+    A(dalloc(&pl->part, (size_t)2 * pl->nblk_max * QEQ_NPART));
+    A(dalloc(&pl->sc, 1));
+    A(dalloc(&pl->final_dev, 16));
+    if (rc == QEQ_OK && hipHostMalloc((void**)&pl->sc_host, sizeof(CgScalars)) != hipSuccess) rc = QEQ_ENOMEM;
+    if (rc == QEQ_OK && hipHostMalloc((void**)&pl->out_host, 16 * sizeof(double)) != hipSuccess)
+        rc = QEQ_ENOMEM;
+    if (rc == QEQ_OK && p.grid[0] > 0) rc = ensure_grid(pl, p.grid);
+    if (rc != QEQ_OK) {
+        qeq_plan_destroy(pl);
+        return rc;
+    }
+    *out = pl;
+    return QEQ_OK;
+}
+
+int qeq_plan_destroy(qeq_plan* pl) {
+    if (!pl) return QEQ_OK;
+    if (pl->stream) (void)hipStreamSynchronize(pl->stream);
+    prof_flush(pl, 0);
+    for (hipEvent_t e : pl->prof_pool) (void)hipEventDestroy(e);
+    pl->prof_pool.clear();
+    free_grid(pl);
+    dfree(pl->perm); dfree(pl->key); dfree(pl->frac); dfree(pl->home); dfree(pl->wts); dfree(pl->dwts);
+    dfree(pl->sig); dfree(pl->Jv); dfree(pl->chi); dfree(pl->chi_raw); dfree(pl->dself); dfree(pl->dinv);
+    dfree(pl->selfgrad); dfree(pl->q); dfree(pl->r); dfree(pl->pvec); dfree(pl->y); dfree(pl->forces_s);
+    dfree(pl->gtmp); dfree(pl->rowptr); dfree(pl->rowcnt); dfree(pl->theta_tab); dfree(pl->part);
+    dfree(pl->sc); dfree(pl->final_dev);
+    dfree(pl->cell_count); dfree(pl->cell_start); dfree(pl->cell_fill); dfree(pl->cell_atoms);
+    dfree(pl->col); dfree(pl->kval); dfree(pl->pdr);
+    if (pl->sc_host) (void)hipHostFree(pl->sc_host);
+    if (pl->out_host) (void)hipHostFree(pl->out_host);
+    delete pl;
+    return QEQ_OK;
+}
+
+int qeq_solve(qeq_plan* plan, int32_t n, const double* pos, const double* cell, const double* sigma,
+              const double* J, const double* chi, double q_tot, const double* q0, double* q,
+              double* energies, double* forces, qeq_stats* stats) {
+    if (!plan) return QEQ_EINVAL;
+    int rc = solve_impl(plan, n, pos, cell, sigma, J, chi, q_tot, q0, q, energies, forces, stats);
+    if (rc < 0 && stats) {
+        memset(stats, 0, sizeof(*stats));
+        stats->status = rc;
+    }
+    return rc;
+}
+
+int qeq_matvec(qeq_plan* plan, int32_t n, const double* pos, const double* cell, const double* sigma,
+               const double* v, double* y, int32_t parts) {
+    if (!plan || !pos || !sigma || !v || !y) return QEQ_EINVAL;
+    if (parts < 0 || parts > 15) return QEQ_EINVAL;
+    qeq_plan* pl = plan;
+    pl->tape_valid = false;
+    QEQ_TRY(prepare(pl, n, cell, 0.0));
+    QEQ_TRY(setup_geometry(pl, pos, sigma, nullptr, nullptr));
+    pl->kp.parts = parts;
+    QEQ_TRY(launch_matvec_io(pl, v, nullptr, 0));
+    if (parts & QEQ_PART_RECIP) QEQ_TRY(launch_mesh_potential(pl, pl->pvec, nullptr));
+    QEQ_TRY(launch_interp(pl, pl->pvec, pl->y, QEQ_MODE_MATVEC, 0));
+    QEQ_TRY(launch_matvec_io(pl, nullptr, y, 1));
+    QEQ_HIP(hipStreamSynchronize(pl->stream));
+    pl->kp.parts = 15;
+    return QEQ_OK;
+}
+
+int qeq_profile(qeq_plan* plan, uint32_t kind_mask) {
+    if (!plan) return QEQ_EINVAL;
+    plan->prof_mask = kind_mask & ((1u << PK_COUNT) - 1u);
+    return QEQ_OK;
+}
+
+int qeq_profile_read(qeq_plan* plan, double* total_ms, int64_t* launches, int32_t n_kinds,
+                     int32_t reset) {
+    if (!plan || n_kinds < 0) return QEQ_EINVAL;
+    if (plan->stream) QEQ_HIP(hipStreamSynchronize(plan->stream));
+    prof_flush(plan, 1 << 30);
+    for (int k = 0; k < n_kinds && k < PK_COUNT; ++k) {
+        if (total_ms) total_ms[k] = plan->prof_ms[k];
+        if (launches) launches[k] = plan->prof_n[k];
+    }
+    if (reset) {
+        for (int k = 0; k < PK_COUNT; ++k) {
+            plan->prof_ms[k] = 0.0;
+            plan->prof_n[k] = 0;
+        }
+    }
+    return PK_COUNT;
+}
+
+const char* qeq_strerror(int code) {
+    switch (code) {
+        case QEQ_OK: return "success";
+        case QEQ_NOT_CONVERGED: return "CG reached max_iter before the residual tolerance";
+        case QEQ_EINVAL: return "invalid argument (n, J <= 0, sigma <= 0, non-finite input or singular cell)";
+        case QEQ_ECELL: return "cell too skewed for the real-space cell list";
+        case QEQ_ENOMEM: return "device allocation failed";
+        case QEQ_EHIP: return "HIP runtime error";
+        case QEQ_EPLAN: return "unsupported grid or spline order, or n larger than the plan";
+        default: return "unknown status code";
+    }
+}
+
+}  // extern "C"

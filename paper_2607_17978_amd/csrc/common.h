@@ -1,0 +1,259 @@
+// Device-side building blocks shared by the kernels of the particle-mesh QEq
+// library: complex arithmetic, cardinal B-splines, the LDS-resident mixed-radix
+// Stockham FFT and block reductions in FP64.  gfx950 only (64-wide waves).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define QEQ_MAXP 8          // largest supported spline order
+#define QEQ_FFT_MAXST 10    // largest number of radix stages
+#define QEQ_FFT_EMAX 40     // complex elements one thread holds during a stage
+
+// ---------------------------------------------------------------------------
+// complex helpers (float2 = re, im)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+// multiply by -i (forward) or +i (inverse)
+__device__ __forceinline__ float2 cmul_mi(float2 a, bool inv) {
+    return inv ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+
+// ---------------------------------------------------------------------------
+// Cardinal B-splines (Essmann et al. smooth PME; the paper's PPPM solver).
+// For an atom at grid coordinate u with base h = floor(u), w = u - h, grid
+// point h - k (k = 0..p-1) gets weight M_p(w + k).  The recursion
+//   M_n(x) = [x M_{n-1}(x) + (n - x) M_{n-1}(x - 1)] / (n - 1),  M_2(x) = 1 - |x - 1|
+// is evaluated on the p shifted arguments at once; the derivative is
+//   M_n'(x) = M_{n-1}(x) - M_{n-1}(x - 1).
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void bspline_weights(T w, int p, T* c, T* dc) {
+    T prev[QEQ_MAXP];
+    c[0] = w;
+    c[1] = T(1) - w;
+#pragma unroll
+    for (int k = 2; k < QEQ_MAXP; ++k) c[k] = T(0);
+    for (int n = 3; n <= p; ++n) {
+        if (n == p) {
+            for (int k = 0; k < QEQ_MAXP; ++k) prev[k] = c[k];
+        }
+        T inv = T(1) / T(n - 1);
+        // c_n[k] = ((w+k) c[k] + (n - w - k) c[k-1]) / (n-1), descending k
+        for (int k = n - 1; k >= 1; --k)
+            c[k] = ((w + T(k)) * c[k] + (T(n) - w - T(k)) * c[k - 1]) * inv;
+        c[0] = w * c[0] * inv;
+    }
+    if (p == 2) {
+        prev[0] = T(1);
+        for (int k = 1; k < QEQ_MAXP; ++k) prev[k] = T(0);
+    }
+    dc[0] = prev[0];
+    for (int k = 1; k < p; ++k) dc[k] = prev[k] - prev[k - 1];
+}
+
+// ---------------------------------------------------------------------------
+// FFT plan for one axis length K = 2^a 3^b 5^c: radix list and twiddles
+// W_K^j = exp(-2 pi i j / K) (computed in FP64 on the host, stored FP32).
+// ---------------------------------------------------------------------------
+struct FftAxis {
+    int K;
+    int nst;
+    int radix[QEQ_FFT_MAXST];
+    const float2* tw;   // device table, K entries
+};
+
+// Small DFTs: X[k] = sum_n x[n] W^{nk}, W = exp(-+ 2 pi i / R) (forward / inverse).
+template <int R> __device__ __forceinline__ void dft(float2* v, bool inv);
+
+template <> __device__ __forceinline__ void dft<2>(float2* v, bool) {
+    float2 a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+}
+
+template <> __device__ __forceinline__ void dft<3>(float2* v, bool inv) {
+    const float c1 = -0.5f, s1 = 0.86602540378443864676f;
+    float2 a = v[0], b = v[1], c = v[2];
+    float2 sbc = cadd(b, c), dbc = csub(b, c);
+    float2 t = make_float2(a.x + c1 * sbc.x, a.y + c1 * sbc.y);
+    float2 u = cmul_mi(cscale(dbc, s1), inv);   // -i s1 (b - c) forward
+    v[0] = cadd(a, sbc);
+    v[1] = cadd(t, u);
+    v[2] = csub(t, u);
+}
+
+template <> __device__ __forceinline__ void dft<4>(float2* v, bool inv) {
+    float2 a = v[0], b = v[1], c = v[2], d = v[3];
+    float2 s0 = cadd(a, c), d0 = csub(a, c);
+    float2 s1 = cadd(b, d), d1 = cmul_mi(csub(b, d), inv);
+    v[0] = cadd(s0, s1);
+    v[2] = csub(s0, s1);
+    v[1] = cadd(d0, d1);
+    v[3] = csub(d0, d1);
+}
+
+template <> __device__ __forceinline__ void dft<5>(float2* v, bool inv) {
+    // cos / sin of 2 pi / 5 and 4 pi / 5
+    const float c1 = 0.30901699437494742410f, c2 = -0.80901699437494742410f;
+    const float s1 = 0.95105651629515357212f, s2 = 0.58778525229247312917f;
+    float2 a = v[0];
+    float2 p1 = cadd(v[1], v[4]), m1 = csub(v[1], v[4]);
+    float2 p2 = cadd(v[2], v[3]), m2 = csub(v[2], v[3]);
+    float2 t1 = make_float2(a.x + c1 * p1.x + c2 * p2.x, a.y + c1 * p1.y + c2 * p2.y);
+    float2 t2 = make_float2(a.x + c2 * p1.x + c1 * p2.x, a.y + c2 * p1.y + c1 * p2.y);
+    // forward: X1 = t1 - i (s1 m1 + s2 m2), X2 = t2 - i (s2 m1 - s1 m2)
+    float2 u1 = cmul_mi(make_float2(s1 * m1.x + s2 * m2.x, s1 * m1.y + s2 * m2.y), inv);
+    float2 u2 = cmul_mi(make_float2(s2 * m1.x - s1 * m2.x, s2 * m1.y - s1 * m2.y), inv);
+    v[0] = make_float2(a.x + p1.x + p2.x, a.y + p1.y + p2.y);
+    v[1] = cadd(t1, u1);
+    v[4] = csub(t1, u1);
+    v[2] = cadd(t2, u2);
+    v[3] = csub(t2, u2);
+}
+
+template <> __device__ __forceinline__ void dft<8>(float2* v, bool inv) {
+    const float h = 0.70710678118654752440f;
+    float2 e[4] = {v[0], v[2], v[4], v[6]};
+    float2 o[4] = {v[1], v[3], v[5], v[7]};
+    dft<4>(e, inv);
+    dft<4>(o, inv);
+    // W8^k o[k], W8 = exp(-+ i pi / 4)
+    float2 w1 = inv ? make_float2(h, h) : make_float2(h, -h);
+    float2 w3 = inv ? make_float2(-h, h) : make_float2(-h, -h);
+    o[1] = cmul(o[1], w1);
+    o[2] = cmul_mi(o[2], inv);
+    o[3] = cmul(o[3], w3);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        v[k] = cadd(e[k], o[k]);
+        v[k + 4] = csub(e[k], o[k]);
+    }
+}
+
+// One Stockham (decimation-in-time, self-sorting) stage of radix R on ncol
+// interleaved columns held in LDS: element (index k, column c) lives at
+// buf[k * ncol + c].  Each butterfly j of a column reads x[j + r K/R],
+// applies the twiddles W_{Ns R}^{(j mod Ns) r}, does a length-R DFT and writes
+// y[(j / Ns) Ns R + (j mod Ns) + r Ns].  The stage is done in place: all reads
+// go to registers before a barrier, then all writes.
+template <int R>
+__device__ __forceinline__ void fft_stage(float2* buf, int K, int Ns, int ncol_log2,
+                                          const float2* tw, bool inv, int tid, int nthr) {
+    constexpr int MAXIT = (QEQ_FFT_EMAX + R - 1) / R;
+    const int per = K / R;
+    const int ncol = 1 << ncol_log2;
+    const int nitems = per * ncol;
+    const int step = K / (Ns * R);
+    float2 v[MAXIT][R];
+#pragma unroll
+    for (int it = 0; it < MAXIT; ++it) {
+        int item = tid + it * nthr;
+        if (item < nitems) {
+            int c = item & (ncol - 1), j = item >> ncol_log2;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[it][r] = buf[(j + r * per) * ncol + c];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < MAXIT; ++it) {
+        int item = tid + it * nthr;
+        if (item < nitems) {
+            int c = item & (ncol - 1), j = item >> ncol_log2;
+            int k = j % Ns;
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                float2 w = tw[k * r * step];
+                if (inv) w.y = -w.y;
+                v[it][r] = cmul(v[it][r], w);
+            }
+            dft<R>(v[it], inv);
+            int base = (j - k) * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[(base + r * Ns) * ncol + c] = v[it][r];
+        }
+    }
+    __syncthreads();
+}
+
+// Full length-K transform of ncol columns in LDS (unnormalised both ways).
+__device__ __forceinline__ void fft_lds(float2* buf, const FftAxis& ax, int ncol_log2,
+                                        const float2* tw_lds, bool inv, int tid, int nthr) {
+    int Ns = 1;
+    for (int s = 0; s < ax.nst; ++s) {
+        int R = ax.radix[s];
+        switch (R) {
+            case 2: fft_stage<2>(buf, ax.K, Ns, ncol_log2, tw_lds, inv, tid, nthr); break;
+            case 3: fft_stage<3>(buf, ax.K, Ns, ncol_log2, tw_lds, inv, tid, nthr); break;
+            case 4: fft_stage<4>(buf, ax.K, Ns, ncol_log2, tw_lds, inv, tid, nthr); break;
+            case 5: fft_stage<5>(buf, ax.K, Ns, ncol_log2, tw_lds, inv, tid, nthr); break;
+            default: fft_stage<8>(buf, ax.K, Ns, ncol_log2, tw_lds, inv, tid, nthr); break;
+        }
+        Ns *= R;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 block reductions (wave64 shuffles, then LDS across waves)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sum NV values over the block; result valid in thread 0.  blockDim <= 1024.
+template <int NV>
+__device__ __forceinline__ void block_sum(double* v) {
+    __shared__ double red[16][NV];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) red[wid][k] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < nw; ++w) {
+#pragma unroll
+            for (int k = 0; k < NV; ++k) v[k] += red[w][k];
+        }
+    }
+    __syncthreads();
+}
+
+// Every thread of the block obtains the totals of NV per-block partial sums
+// laid out as part[b * NV + k], b < nparts.
+template <int NV>
+__device__ __forceinline__ void reduce_partials(const double* part, int nparts, double* out) {
+    __shared__ double tot[NV];
+    double v[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = 0.0;
+    for (int b = threadIdx.x; b < nparts; b += blockDim.x) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) v[k] += part[b * NV + k];
+    }
+    block_sum<NV>(v);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) tot[k] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) out[k] = tot[k];
+    __syncthreads();
+}
+
+__device__ __forceinline__ int wrap_idx(int i, int K) {
+    i %= K;
+    return i < 0 ? i + K : i;
+}

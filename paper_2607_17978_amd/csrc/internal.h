@@ -1,0 +1,218 @@
+// Internal interfaces of the particle-mesh QEq library: the kernel-argument
+// bundle, the plan (device workspace) and the host launchers of every kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "common.h"
+#include "../../include/qeq.h"
+
+#define QEQ_BLOCK 256         // threads per block for per-atom kernels
+#define QEQ_FFT_THREADS 256   // threads per block for FFT passes
+#define QEQ_NPART 8           // doubles per block in partial-sum buffers
+
+// Bits of the device error word.
+#define QEQ_ERRBIT_INPUT 1
+
+// Interp / final-kernel modes
+#define QEQ_MODE_CG 0         // y = (E + diag J) p over the selected parts
+#define QEQ_MODE_MATVEC 1     // y = E v over the selected parts (no J)
+#define QEQ_MODE_FINAL 2      // y = E q, forces, energy partials
+
+#define QEQ_PART_RECIP 1
+#define QEQ_PART_REAL 2
+#define QEQ_PART_SELF 4
+#define QEQ_PART_BG 8
+
+// Everything a kernel needs to know about the problem, passed by value.
+struct KParams {
+    int n;
+    int p;                    // spline order
+    int K1, K2, K3, K3h;      // grid; K3h = K3 / 2 + 1 (half spectrum along axis 3)
+    int TW, TWlog2, ntile;    // axis-2 row tile of the axis-3 and axis-1 passes
+    int NR, NRlog2;           // rows per block of the axis-2 pass
+    int nc[3];                // real-space cell-list dims
+    int ns[3];                // stencil half-widths in cells
+    int parts;                // operator parts (QEQ_PART_*)
+    int self_corr;
+    double H[9];              // rows = lattice vectors
+    double Hinv[9];
+    double M[6];              // (H H^T)^-1: 11 22 33 12 13 23
+    double vol;
+    double eta;
+    double rc, rc2;
+    double green_pref;        // 4 pi / V
+    double bg_pref;           // 2 pi / V
+    double q_tot;
+    double c_eta;             // (4 pi / V) sum_{k != 0} exp(-eta^2 k^2 / 2) / k^2
+    double tol;
+};
+
+// Scalars that live on the device between CG kernels.
+struct CgScalars {
+    double rz[2];             // r.z of the current direction, double-buffered by parity
+    double chi_norm;          // ||P chi_eff||
+    double chi_sum;           // sum chi_eff
+    double dinv_sum;          // sum 1 / D
+    double res;               // relative residual after the last update
+    double alpha;
+    int iters;
+    int done;
+    int err;                  // QEQ_ERRBIT_*
+    int pad;
+};
+
+// Kinds of kernel launches that the per-stage timers can bracket with events.
+enum ProfKind {
+    PK_SPREAD_R2C = 0,   // spread + axis-3 real-to-complex FFT
+    PK_ROWS_FWD,         // axis-2 forward FFT
+    PK_COLS_GREEN,       // axis-1 forward FFT, Green's function, axis-1 inverse FFT
+    PK_ROWS_INV,         // axis-2 inverse FFT
+    PK_C2R,              // axis-3 complex-to-real FFT
+    PK_INTERP,           // back-interpolation + real-space product (CG matvec)
+    PK_CG_UPDATE,
+    PK_CG_DIR,
+    PK_FINAL,            // final matvec epilogue: energies and forces
+    PK_COUNT
+};
+
+struct ProfRec {
+    int kind;
+    int it;              // CG iteration of the launch, -1 outside the loop
+    hipEvent_t a, b;
+};
+
+struct DeviceAxes {
+    FftAxis ax[3];
+};
+
+struct qeq_plan {
+    qeq_params prm;
+    int n_max = 0;
+    int dev = 0;
+    hipStream_t stream = nullptr;
+
+    // grid-dependent state
+    int K[3] = {0, 0, 0};
+    DeviceAxes axes;
+    float2* tw[3] = {nullptr, nullptr, nullptr};
+    float* bmod[3] = {nullptr, nullptr, nullptr};   // |b_a(m)|^2 per axis
+    float* grid_r = nullptr;                        // real grid K1 K2 K3
+    float2* grid_c = nullptr;                       // half spectrum [m3][m1][m2]
+    int* bin_count = nullptr;                       // K1 K2 + 1
+    int* bin_start = nullptr;
+    int* bin_fill = nullptr;
+    size_t grid_bytes = 0;
+
+    // cell-dependent cache
+    double cell_cached[9] = {0};
+    bool theta_valid = false;
+    double c_eta = 0.0;
+    double* theta_tab = nullptr;                    // (2p-1)^3 mesh kernel values
+
+    // per-atom (sorted order unless noted)
+    int* perm = nullptr;
+    int* key = nullptr;           // original order: grid bin key
+    double* frac = nullptr;       // n x 3
+    int* home = nullptr;          // n x 4 (h1, h2, h3, cell)
+    float* wts = nullptr;         // n x 3 x MAXP
+    float* dwts = nullptr;        // n x 3 x MAXP
+    double* sig = nullptr;
+    double* Jv = nullptr;
+    double* chi = nullptr;        // chi_eff (sorted)
+    double* chi_raw = nullptr;    // chi (sorted)
+    double* dself = nullptr;      // Gaussian self term + mesh self-correction
+    double* dinv = nullptr;       // Jacobi preconditioner 1 / D
+    double* selfgrad = nullptr;   // n x 3: d(theta^T Theta theta)/du
+    double* q = nullptr;
+    double* r = nullptr;
+    double* pvec = nullptr;
+    double* y = nullptr;
+    double* forces_s = nullptr;   // n x 3 (sorted)
+    double* gtmp = nullptr;       // n: final gradient vector
+
+    // real-space cell list and pair list
+    int ncell_alloc = 0;
+    int* cell_count = nullptr;
+    int* cell_start = nullptr;
+    int* cell_fill = nullptr;
+    int* cell_atoms = nullptr;
+    int* rowptr = nullptr;        // n + 1
+    int* rowcnt = nullptr;
+    size_t nnz_cap = 0;
+    int* col = nullptr;
+    float* kval = nullptr;
+    float4* pdr = nullptr;        // (dx, dy, dz, K'(r)/r)
+    long long nnz = 0;
+
+    // reductions
+    double* part = nullptr;       // [2][nblk_max][QEQ_NPART]
+    int nblk_max = 0;
+    CgScalars* sc = nullptr;
+    CgScalars* sc_host = nullptr; // pinned
+    double* out_host = nullptr;   // pinned, 16 doubles
+    double* final_dev = nullptr;  // 16 doubles on device
+
+    KParams kp;
+    bool tape_valid = false;
+
+    // per-stage timers
+    unsigned prof_mask = 0;
+    int cur_it = -1;
+    std::vector<ProfRec> prof_pending;
+    std::vector<hipEvent_t> prof_pool;
+    double prof_ms[PK_COUNT] = {0};
+    long long prof_n[PK_COUNT] = {0};
+};
+
+// Brackets one launch with events when its kind is enabled.
+struct ProfScope {
+    qeq_plan* pl;
+    ProfRec rec;
+    bool on;
+    ProfScope(qeq_plan* p, int kind);
+    ~ProfScope();
+};
+void prof_flush(qeq_plan* pl, int live_iters);
+
+// ------------------------------------------------------------------ helpers
+int qeq_check(hipError_t e);
+#define QEQ_TRY(x)                                   \
+    do {                                             \
+        int _rc = (x);                               \
+        if (_rc != QEQ_OK) return _rc;               \
+    } while (0)
+#define QEQ_HIP(x) QEQ_TRY(qeq_check(x))
+
+inline int nblocks(int n, int b = QEQ_BLOCK) { return (n + b - 1) / b; }
+
+// ------------------------------------------------------------------ setup kernels (setup.hip)
+int launch_stage(qeq_plan* pl, const double* pos, const double* sigma, const double* J,
+                 const double* chi);
+int launch_sort_bins(qeq_plan* pl);
+int launch_gather(qeq_plan* pl, const double* pos, const double* sigma, const double* J,
+                  const double* chi);
+int launch_cells_and_pairs(qeq_plan* pl);
+int launch_theta(qeq_plan* pl);          // mesh kernel table for the self-correction
+int launch_selfcorr(qeq_plan* pl);
+int launch_scan(qeq_plan* pl, const int* in, int* out, int m);
+
+// ------------------------------------------------------------------ mesh kernels (mesh.hip)
+// Reciprocal potential of the charges src (sorted, FP64): real grid phi in grid_r.
+int launch_mesh_potential(qeq_plan* pl, const double* src, const int* done);
+size_t qeq_mesh_max_smem(const KParams& k);
+// Inverse transforms only (grid_c already holds a spectrum) -> grid_r.
+int launch_mesh_inverse(qeq_plan* pl);
+int launch_write_green(qeq_plan* pl);
+
+// ------------------------------------------------------------------ solver kernels (solve.hip)
+int launch_interp(qeq_plan* pl, const double* src, double* dst, int mode, int parity);
+int launch_cg_init_q(qeq_plan* pl, const double* q0);
+int launch_cg_init_r(qeq_plan* pl);
+int launch_cg_update(qeq_plan* pl, int parity);
+int launch_cg_dir(qeq_plan* pl, int parity, int init);
+int launch_final(qeq_plan* pl, double* q_out, double* energies, double* forces_out);
+int launch_matvec_io(qeq_plan* pl, const double* v_orig, double* y_orig, int stage);

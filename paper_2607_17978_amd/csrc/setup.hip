@@ -1,0 +1,457 @@
+// Per-geometry setup: input staging and validation, spatial sort of atoms by
+// grid column, B-spline weights, the real-space cell list and pair list, and
+// the per-atom mesh self-interaction correction.
+#include <math.h>
+
+#include "internal.h"
+
+namespace {
+
+__device__ __forceinline__ bool finite_d(double x) { return isfinite(x); }
+
+__device__ __forceinline__ void frac_coords(const KParams& k, const double* x, double* s) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double v = x[0] * k.Hinv[0 * 3 + a] + x[1] * k.Hinv[1 * 3 + a] + x[2] * k.Hinv[2 * 3 + a];
+        v -= floor(v);
+        if (!(v >= 0.0 && v < 1.0)) v = 0.0;   // v == 1 after rounding, or non-finite input
+        s[a] = v;
+    }
+}
+
+__device__ __forceinline__ int grid_home(double s, int K) {
+    int h = (int)floor(s * (double)K);
+    return h < 0 ? 0 : (h >= K ? K - 1 : h);
+}
+
+// ---------------------------------------------------------------------------
+// Stage (original order): validate, fractional coordinates, grid-column key.
+// ---------------------------------------------------------------------------
+__global__ void k_stage(KParams k, const double* __restrict__ pos, const double* __restrict__ sigma,
+                        const double* __restrict__ J, const double* __restrict__ chi,
+                        int* __restrict__ key, int* __restrict__ bin_count, CgScalars* sc) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= k.n) return;
+    double x[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
+    double jj = J ? J[i] : 1.0, ch = chi ? chi[i] : 0.0;
+    bool ok = finite_d(x[0]) && finite_d(x[1]) && finite_d(x[2]) && finite_d(ch) &&
+              sigma[i] > 0.0 && jj > 0.0 && finite_d(sigma[i]) && finite_d(jj);
+    if (!ok) atomicOr(&sc->err, QEQ_ERRBIT_INPUT);
+    double s[3];
+    frac_coords(k, x, s);
+    int h1 = grid_home(s[0], k.K1), h2 = grid_home(s[1], k.K2);
+    int kk = h1 * k.K2 + h2;
+    key[i] = kk;
+    atomicAdd(&bin_count[kk], 1);
+}
+
+__global__ void k_scatter(int n, const int* __restrict__ key, const int* __restrict__ start,
+                          int* __restrict__ fill, int* __restrict__ perm) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int kk = key[i];
+    int slot = start[kk] + atomicAdd(&fill[kk], 1);
+    perm[slot] = i;
+}
+
+// Deterministic order inside each bucket: ascending index.
+__global__ void k_bucket_sort(int nb, const int* __restrict__ start, int* __restrict__ v) {
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    int lo = start[b], hi = start[b + 1];
+    for (int a = lo + 1; a < hi; ++a) {
+        int x = v[a];
+        int c = a - 1;
+        while (c >= lo && v[c] > x) {
+            v[c + 1] = v[c];
+            --c;
+        }
+        v[c + 1] = x;
+    }
+}
+
+// Exclusive scan of m ints into out[0..m], out[m] = total; one block.
+__global__ void k_scan(const int* __restrict__ in, int* __restrict__ out, int m) {
+    __shared__ int part[1024];
+    const int t = threadIdx.x, nt = blockDim.x;
+    int chunk = (m + nt - 1) / nt;
+    int lo = t * chunk, hi = min(m, lo + chunk);
+    int s = 0;
+    for (int a = lo; a < hi; ++a) s += in[a];
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < nt; off <<= 1) {
+        int v = (t >= off) ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int run = part[t] - s;
+    for (int a = lo; a < hi; ++a) {
+        out[a] = run;
+        run += in[a];
+    }
+    if (t == nt - 1) out[m] = part[t];
+}
+
+// ---------------------------------------------------------------------------
+// Gather (sorted order): copy per-atom data, B-spline weights, cell key.
+// ---------------------------------------------------------------------------
+__global__ void k_gather(KParams k, const double* __restrict__ pos, const double* __restrict__ sigma,
+                         const double* __restrict__ J, const double* __restrict__ chi,
+                         const int* __restrict__ perm, double* __restrict__ frac, int* __restrict__ home,
+                         float* __restrict__ wts, float* __restrict__ dwts, double* __restrict__ sig_s,
+                         double* __restrict__ J_s, double* __restrict__ chi_s,
+                         double* __restrict__ chi_raw_s, double* __restrict__ dself,
+                         double* __restrict__ dinv, int* __restrict__ cell_count,
+                         double* __restrict__ part) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    double acc[3] = {0.0, 0.0, 0.0};
+    if (s < k.n) {
+        int i = perm[s];
+        double x[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
+        double f[3];
+        frac_coords(k, x, f);
+        int Kd[3] = {k.K1, k.K2, k.K3};
+        int h[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            frac[3 * s + a] = f[a];
+            double u = f[a] * (double)Kd[a];
+            h[a] = grid_home(f[a], Kd[a]);
+            double w = u - (double)h[a];
+            double c[QEQ_MAXP], dc[QEQ_MAXP];
+            bspline_weights<double>(w, k.p, c, dc);
+            for (int kk = 0; kk < QEQ_MAXP; ++kk) {
+                wts[(s * 3 + a) * QEQ_MAXP + kk] = kk < k.p ? (float)c[kk] : 0.f;
+                dwts[(s * 3 + a) * QEQ_MAXP + kk] = kk < k.p ? (float)dc[kk] : 0.f;
+            }
+        }
+        int c[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            c[a] = (int)(f[a] * (double)k.nc[a]);
+            if (c[a] >= k.nc[a]) c[a] = k.nc[a] - 1;
+        }
+        int ck = (c[0] * k.nc[1] + c[1]) * k.nc[2] + c[2];
+        home[4 * s + 0] = h[0];
+        home[4 * s + 1] = h[1];
+        home[4 * s + 2] = h[2];
+        home[4 * s + 3] = ck;
+        atomicAdd(&cell_count[ck], 1);
+        double sg = sigma[i], jj = J ? J[i] : 1.0, c0 = chi ? chi[i] : 0.0;
+        double ce = c0 + k.bg_pref * k.q_tot * sg * sg;
+        sig_s[s] = sg;
+        J_s[s] = jj;
+        chi_s[s] = ce;
+        chi_raw_s[s] = c0;
+        const double rsqpi = 0.56418958354775628695;   // 1/sqrt(pi)
+        dself[s] = rsqpi / sg - 0.79788456080286535588 / k.eta;   // - sqrt(2/pi)/eta
+        dinv[s] = 1.0 / (jj + rsqpi / sg);
+        acc[0] = ce;
+        acc[1] = dinv[s];
+    }
+    block_sum<3>(acc);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x * QEQ_NPART + 0] = acc[0];
+        part[blockIdx.x * QEQ_NPART + 1] = acc[1];
+    }
+}
+
+// ||P chi_eff|| needs the mean first: two passes over chi_eff.
+__global__ void k_chi_norm(int n, const double* __restrict__ chi_s, double* __restrict__ part,
+                           int nparts, double* __restrict__ part_out) {
+    double tot[2];
+    // reduce first-pass partials (layout stride QEQ_NPART)
+    __shared__ double sh_mean;
+    {
+        double v[1] = {0.0};
+        for (int b = threadIdx.x; b < nparts; b += blockDim.x) v[0] += part[b * QEQ_NPART];
+        block_sum<1>(v);
+        if (threadIdx.x == 0) sh_mean = v[0] / (double)n;
+        __syncthreads();
+    }
+    double mean = sh_mean;
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    tot[0] = 0.0;
+    tot[1] = 0.0;
+    if (s < n) {
+        double d = chi_s[s] - mean;
+        tot[0] = d * d;
+    }
+    block_sum<2>(tot);
+    if (threadIdx.x == 0) {
+        part_out[blockIdx.x * QEQ_NPART + 0] = tot[0];
+        part_out[blockIdx.x * QEQ_NPART + 1] = mean;
+    }
+}
+
+__global__ void k_chi_finish(int n, const double* __restrict__ part1, const double* __restrict__ part2,
+                             int nparts, CgScalars* sc) {
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nparts; b += blockDim.x) {
+        v[0] += part1[b * QEQ_NPART];
+        v[1] += part2[b * QEQ_NPART];
+        v[2] += part1[b * QEQ_NPART + 1];
+    }
+    block_sum<3>(v);
+    if (threadIdx.x == 0) {
+        sc->chi_sum = v[0];
+        sc->chi_norm = sqrt(v[1]);
+        sc->dinv_sum = v[2];
+    }
+}
+
+__global__ void k_cell_scatter(int n, const int* __restrict__ home, const int* __restrict__ start,
+                               int* __restrict__ fill, int* __restrict__ atoms) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    int ck = home[4 * s + 3];
+    atoms[start[ck] + atomicAdd(&fill[ck], 1)] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Real-space pair kernel K(r) = [erf(r/(sqrt2 gamma)) - erf(r/(sqrt2 eta))]/r
+// over every periodic image within r_cut (the erfc-difference of the Ewald
+// split for Gaussian charges, SI "Ewald Summation").
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void pair_kernel(double r, double gam, double eta, double* K, double* dKr) {
+    const double two_sqrtpi = 1.12837916709551257390;
+    double a = 0.70710678118654752440 / gam, b = 0.70710678118654752440 / eta;
+    if (r < 1e-4) {
+        *K = two_sqrtpi * ((a - b) - (a * a * a - b * b * b) * r * r / 3.0);
+        *dKr = -two_sqrtpi * 2.0 * (a * a * a - b * b * b) / 3.0;
+        return;
+    }
+    double e = erf(a * r) - erf(b * r);
+    double kv = e / r;
+    double d = (two_sqrtpi * (a * exp(-a * a * r * r) - b * exp(-b * b * r * r)) - kv) / r;
+    *K = kv;
+    *dKr = d / r;
+}
+
+template <bool FILL>
+__global__ void k_pairs(KParams k, const double* __restrict__ frac, const int* __restrict__ home,
+                        const double* __restrict__ sig, const int* __restrict__ cell_start,
+                        const int* __restrict__ cell_atoms, int* __restrict__ rowcnt,
+                        const int* __restrict__ rowptr, int* __restrict__ col, float* __restrict__ kval,
+                        float4* __restrict__ pdr) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= k.n) return;
+    double si[3] = {frac[3 * i], frac[3 * i + 1], frac[3 * i + 2]};
+    int ck = home[4 * i + 3];
+    int c3 = ck % k.nc[2];
+    int c2 = (ck / k.nc[2]) % k.nc[1];
+    int c1 = ck / (k.nc[2] * k.nc[1]);
+    double sgi = sig[i];
+    int cnt = 0;
+    int off = FILL ? rowptr[i] : 0;
+    for (int d1 = -k.ns[0]; d1 <= k.ns[0]; ++d1) {
+        int r1 = c1 + d1;
+        int w1 = wrap_idx(r1, k.nc[0]);
+        int sh1 = (r1 - w1) / k.nc[0];
+        for (int d2 = -k.ns[1]; d2 <= k.ns[1]; ++d2) {
+            int r2 = c2 + d2;
+            int w2 = wrap_idx(r2, k.nc[1]);
+            int sh2 = (r2 - w2) / k.nc[1];
+            for (int d3 = -k.ns[2]; d3 <= k.ns[2]; ++d3) {
+                int r3 = c3 + d3;
+                int w3 = wrap_idx(r3, k.nc[2]);
+                int sh3 = (r3 - w3) / k.nc[2];
+                int cell = (w1 * k.nc[1] + w2) * k.nc[2] + w3;
+                bool home_img = (sh1 == 0 && sh2 == 0 && sh3 == 0);
+                for (int t = cell_start[cell]; t < cell_start[cell + 1]; ++t) {
+                    int j = cell_atoms[t];
+                    if (home_img && j == i) continue;
+                    double ds0 = frac[3 * j] + sh1 - si[0];
+                    double ds1 = frac[3 * j + 1] + sh2 - si[1];
+                    double ds2 = frac[3 * j + 2] + sh3 - si[2];
+                    // d = r_j(image) - r_i, Cartesian (row vector ds times H)
+                    double dx = ds0 * k.H[0] + ds1 * k.H[3] + ds2 * k.H[6];
+                    double dy = ds0 * k.H[1] + ds1 * k.H[4] + ds2 * k.H[7];
+                    double dz = ds0 * k.H[2] + ds1 * k.H[5] + ds2 * k.H[8];
+                    double r2v = dx * dx + dy * dy + dz * dz;
+                    if (r2v >= k.rc2) continue;
+                    if (FILL) {
+                        double sj = sig[j];
+                        double K, dKr;
+                        pair_kernel(sqrt(r2v), sqrt(sgi * sgi + sj * sj), k.eta, &K, &dKr);
+                        col[off] = j;
+                        kval[off] = (float)K;
+                        // store r_i - r_j(image) for the force
+                        pdr[off] = make_float4((float)(-dx), (float)(-dy), (float)(-dz), (float)dKr);
+                        ++off;
+                    }
+                    ++cnt;
+                }
+            }
+        }
+    }
+    if (!FILL) rowcnt[i] = cnt;
+}
+
+// ---------------------------------------------------------------------------
+// Mesh self-interaction correction.  The mesh reproduces the reciprocal self
+// term C_eta of atom i as theta_i^T Theta theta_i, which depends on where the
+// atom sits inside its grid cell; c_i = C_eta - theta_i^T Theta theta_i is
+// added to the diagonal (and its position derivative to the force), so the
+// self term becomes exact.  With separable spline weights W_a,
+//   theta_i^T Theta theta_i = sum_d Theta(d) R_1(d_1) R_2(d_2) R_3(d_3),
+//   R_a(d) = sum_{k' - k = d} W_a[k] W_a[k'],  |d_a| <= p - 1.
+// ---------------------------------------------------------------------------
+__global__ void k_theta_extract(KParams k, const float* __restrict__ grid, double* __restrict__ tab) {
+    int np = 2 * k.p - 1;
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= np * np * np) return;
+    int d3 = t % np - (k.p - 1);
+    int d2 = (t / np) % np - (k.p - 1);
+    int d1 = t / (np * np) - (k.p - 1);
+    int g1 = wrap_idx(d1, k.K1), g2 = wrap_idx(d2, k.K2), g3 = wrap_idx(d3, k.K3);
+    tab[t] = (double)grid[((size_t)g1 * k.K2 + g2) * k.K3 + g3];
+}
+
+__global__ void k_selfcorr(KParams k, const double* __restrict__ frac, const double* __restrict__ tab,
+                           double* __restrict__ dself, double* __restrict__ selfgrad) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= k.n) return;
+    const int p = k.p, np = 2 * p - 1;
+    int Kd[3] = {k.K1, k.K2, k.K3};
+    double R[3][2 * QEQ_MAXP - 1], dR[3][2 * QEQ_MAXP - 1];
+    for (int a = 0; a < 3; ++a) {
+        double u = frac[3 * i + a] * (double)Kd[a];
+        double w = u - floor(u);
+        double c[QEQ_MAXP], dc[QEQ_MAXP];
+        bspline_weights<double>(w, p, c, dc);
+        for (int d = 0; d < np; ++d) {
+            R[a][d] = 0.0;
+            dR[a][d] = 0.0;
+        }
+        for (int k1 = 0; k1 < p; ++k1)
+            for (int k2 = 0; k2 < p; ++k2) {
+                int d = k2 - k1 + (p - 1);
+                R[a][d] += c[k1] * c[k2];
+                dR[a][d] += dc[k1] * c[k2] + c[k1] * dc[k2];
+            }
+    }
+    double s = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0;
+    for (int a = 0; a < np; ++a)
+        for (int b = 0; b < np; ++b) {
+            double t = 0.0, t1 = 0.0;
+            const double* row = tab + (a * np + b) * np;
+            for (int c = 0; c < np; ++c) {
+                t += row[c] * R[2][c];
+                t1 += row[c] * dR[2][c];
+            }
+            s += R[0][a] * R[1][b] * t;
+            g0 += dR[0][a] * R[1][b] * t;
+            g1 += R[0][a] * dR[1][b] * t;
+            g2 += R[0][a] * R[1][b] * t1;
+        }
+    dself[i] += k.c_eta - s;
+    selfgrad[3 * i + 0] = g0;
+    selfgrad[3 * i + 1] = g1;
+    selfgrad[3 * i + 2] = g2;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+int launch_scan(qeq_plan* pl, const int* in, int* out, int m) {
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, pl->stream, in, out, m);
+    return qeq_check(hipGetLastError());
+}
+
+int launch_stage(qeq_plan* pl, const double* pos, const double* sigma, const double* J,
+                 const double* chi) {
+    const KParams& k = pl->kp;
+    int nb = k.K1 * k.K2;
+    QEQ_HIP(hipMemsetAsync(pl->bin_count, 0, sizeof(int) * (nb + 1), pl->stream));
+    QEQ_HIP(hipMemsetAsync(pl->bin_fill, 0, sizeof(int) * (nb + 1), pl->stream));
+    hipLaunchKernelGGL(k_stage, dim3(nblocks(k.n)), dim3(QEQ_BLOCK), 0, pl->stream, k, pos, sigma,
+                       J, chi, pl->key, pl->bin_count, pl->sc);
+    return qeq_check(hipGetLastError());
+}
+
+int launch_sort_bins(qeq_plan* pl) {
+    const KParams& k = pl->kp;
+    int nb = k.K1 * k.K2;
+    QEQ_TRY(launch_scan(pl, pl->bin_count, pl->bin_start, nb));
+    hipLaunchKernelGGL(k_scatter, dim3(nblocks(k.n)), dim3(QEQ_BLOCK), 0, pl->stream, k.n, pl->key,
+                       pl->bin_start, pl->bin_fill, pl->perm);
+    hipLaunchKernelGGL(k_bucket_sort, dim3(nblocks(nb)), dim3(QEQ_BLOCK), 0, pl->stream, nb,
+                       pl->bin_start, pl->perm);
+    return qeq_check(hipGetLastError());
+}
+
+int launch_gather(qeq_plan* pl, const double* pos, const double* sigma, const double* J,
+                  const double* chi) {
+    const KParams& k = pl->kp;
+    int ncell = k.nc[0] * k.nc[1] * k.nc[2];
+    QEQ_HIP(hipMemsetAsync(pl->cell_count, 0, sizeof(int) * (ncell + 1), pl->stream));
+    QEQ_HIP(hipMemsetAsync(pl->cell_fill, 0, sizeof(int) * (ncell + 1), pl->stream));
+    int nb = nblocks(k.n);
+    double* part1 = pl->part;
+    double* part2 = pl->part + (size_t)pl->nblk_max * QEQ_NPART;
+    hipLaunchKernelGGL(k_gather, dim3(nb), dim3(QEQ_BLOCK), 0, pl->stream, k, pos, sigma, J, chi,
+                       pl->perm, pl->frac, pl->home, pl->wts, pl->dwts, pl->sig, pl->Jv, pl->chi,
+                       pl->chi_raw, pl->dself, pl->dinv, pl->cell_count, part1);
+    hipLaunchKernelGGL(k_chi_norm, dim3(nb), dim3(QEQ_BLOCK), 0, pl->stream, k.n, pl->chi, part1, nb,
+                       part2);
+    hipLaunchKernelGGL(k_chi_finish, dim3(1), dim3(QEQ_BLOCK), 0, pl->stream, k.n, part1, part2, nb,
+                       pl->sc);
+    return qeq_check(hipGetLastError());
+}
+
+int launch_cells_and_pairs(qeq_plan* pl) {
+    const KParams& k = pl->kp;
+    int ncell = k.nc[0] * k.nc[1] * k.nc[2];
+    QEQ_TRY(launch_scan(pl, pl->cell_count, pl->cell_start, ncell));
+    hipLaunchKernelGGL(k_cell_scatter, dim3(nblocks(k.n)), dim3(QEQ_BLOCK), 0, pl->stream, k.n,
+                       pl->home, pl->cell_start, pl->cell_fill, pl->cell_atoms);
+    hipLaunchKernelGGL(k_bucket_sort, dim3(nblocks(ncell)), dim3(QEQ_BLOCK), 0, pl->stream, ncell,
+                       pl->cell_start, pl->cell_atoms);
+    hipLaunchKernelGGL(k_pairs<false>, dim3(nblocks(k.n)), dim3(QEQ_BLOCK), 0, pl->stream, k,
+                       pl->frac, pl->home, pl->sig, pl->cell_start, pl->cell_atoms, pl->rowcnt,
+                       pl->rowptr, pl->col, pl->kval, pl->pdr);
+    QEQ_TRY(launch_scan(pl, pl->rowcnt, pl->rowptr, k.n));
+    int nnz = 0;
+    QEQ_HIP(hipMemcpyAsync(&nnz, pl->rowptr + k.n, sizeof(int), hipMemcpyDeviceToHost, pl->stream));
+    QEQ_HIP(hipStreamSynchronize(pl->stream));
+    pl->nnz = nnz;
+    if ((size_t)nnz > pl->nnz_cap) {
+        size_t cap = (size_t)(nnz * 1.25) + 1024;
+        if (pl->col) (void)hipFree(pl->col);
+        if (pl->kval) (void)hipFree(pl->kval);
+        if (pl->pdr) (void)hipFree(pl->pdr);
+        pl->col = nullptr;
+        pl->kval = nullptr;
+        pl->pdr = nullptr;
+        pl->nnz_cap = 0;
+        if (hipMalloc(&pl->col, cap * sizeof(int)) != hipSuccess ||
+            hipMalloc(&pl->kval, cap * sizeof(float)) != hipSuccess ||
+            hipMalloc(&pl->pdr, cap * sizeof(float4)) != hipSuccess)
+            return QEQ_ENOMEM;
+        pl->nnz_cap = cap;
+    }
+    hipLaunchKernelGGL(k_pairs<true>, dim3(nblocks(k.n)), dim3(QEQ_BLOCK), 0, pl->stream, k,
+                       pl->frac, pl->home, pl->sig, pl->cell_start, pl->cell_atoms, pl->rowcnt,
+                       pl->rowptr, pl->col, pl->kval, pl->pdr);
+    return qeq_check(hipGetLastError());
+}
+
+int launch_theta(qeq_plan* pl) {
+    QEQ_TRY(launch_write_green(pl));
+    QEQ_TRY(launch_mesh_inverse(pl));
+    int np = 2 * pl->kp.p - 1;
+    hipLaunchKernelGGL(k_theta_extract, dim3(nblocks(np * np * np)), dim3(QEQ_BLOCK), 0, pl->stream,
+                       pl->kp, pl->grid_r, pl->theta_tab);
+    return qeq_check(hipGetLastError());
+}
+
+int launch_selfcorr(qeq_plan* pl) {
+    hipLaunchKernelGGL(k_selfcorr, dim3(nblocks(pl->kp.n)), dim3(QEQ_BLOCK), 0, pl->stream, pl->kp,
+                       pl->frac, pl->theta_tab, pl->dself, pl->selfgrad);
+    return qeq_check(hipGetLastError());
+}

@@ -1,0 +1,425 @@
+// Back-interpolation, real-space sparse product, projected Jacobi-preconditioned
+// CG (FP64 vectors and reductions) and the final energies / forces.
+//
+// CG works on the constraint plane sum(q) = Q_tot (paper, eq. 4G_qeq_prime):
+// the residual r = -(A q + chi_eff) is kept with zero mean, the preconditioned
+// residual z = D^-1 r - c D^-1 1 with c = sum(D^-1 r) / sum(D^-1) has zero sum,
+// so every search direction stays on the plane.  Per iteration:
+//   mesh (5 passes) -> k_interp (y = A p, partial p.y and sum y)
+//   -> k_cg_update (alpha, q, r, partial sums for z) -> k_cg_dir (beta, p).
+// The background term of charged cells is a rank-two update whose effect on
+// the constrained solution is the shift chi_eff = chi + (2 pi / V) Q sigma^2.
+#include <math.h>
+
+#include "internal.h"
+
+namespace {
+
+// y_i = sum_g theta_i(g) phi(g) + sum_j K_ij v_j + d_i v_i (+ J_i v_i)
+// and, in FINAL mode, the force on atom i.
+template <int MODE>
+__global__ __launch_bounds__(QEQ_BLOCK) void k_interp(
+    KParams k, const double* __restrict__ src, double* __restrict__ dst, const float* __restrict__ grid,
+    const int* __restrict__ home, const float* __restrict__ wts, const float* __restrict__ dwts,
+    const int* __restrict__ rowptr, const int* __restrict__ col, const float* __restrict__ kval,
+    const float4* __restrict__ pdr, const double* __restrict__ dself, const double* __restrict__ Jv,
+    const double* __restrict__ chi_raw, const double* __restrict__ chi_eff, const double* __restrict__ sig,
+    const double* __restrict__ selfgrad, double* __restrict__ forces, double* __restrict__ gvec,
+    double* __restrict__ part, const CgScalars* __restrict__ sc) {
+    if (MODE == QEQ_MODE_CG && sc->done) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double acc[QEQ_NPART];
+#pragma unroll
+    for (int t = 0; t < QEQ_NPART; ++t) acc[t] = 0.0;
+    if (i < k.n) {
+        const double vi = src[i];
+        double y = 0.0;
+        double du[3] = {0.0, 0.0, 0.0};
+        const int p = k.p;
+        if (k.parts & QEQ_PART_RECIP) {
+            const int h1 = home[4 * i], h2 = home[4 * i + 1], h3 = home[4 * i + 2];
+            const float* w = wts + (size_t)i * 3 * QEQ_MAXP;
+            const float* dw = dwts + (size_t)i * 3 * QEQ_MAXP;
+            int g3i[QEQ_MAXP];
+            for (int k3 = 0; k3 < p; ++k3) {
+                int g = h3 - k3;
+                g3i[k3] = g < 0 ? g + k.K3 : g;
+            }
+            for (int k1 = 0; k1 < p; ++k1) {
+                int g1 = h1 - k1;
+                if (g1 < 0) g1 += k.K1;
+                for (int k2 = 0; k2 < p; ++k2) {
+                    int g2 = h2 - k2;
+                    if (g2 < 0) g2 += k.K2;
+                    const float* row = grid + ((size_t)g1 * k.K2 + g2) * k.K3;
+                    float s = 0.f, s3 = 0.f;
+                    for (int k3 = 0; k3 < p; ++k3) {
+                        float v = row[g3i[k3]];
+                        s += w[2 * QEQ_MAXP + k3] * v;
+                        if (MODE == QEQ_MODE_FINAL) s3 += dw[2 * QEQ_MAXP + k3] * v;
+                    }
+                    y += (double)(w[k1] * w[QEQ_MAXP + k2]) * (double)s;
+                    if (MODE == QEQ_MODE_FINAL) {
+                        du[0] += (double)(dw[k1] * w[QEQ_MAXP + k2]) * (double)s;
+                        du[1] += (double)(w[k1] * dw[QEQ_MAXP + k2]) * (double)s;
+                        du[2] += (double)(w[k1] * w[QEQ_MAXP + k2]) * (double)s3;
+                    }
+                }
+            }
+        }
+        double fr[3] = {0.0, 0.0, 0.0};
+        if (k.parts & QEQ_PART_REAL) {
+            const int e1 = rowptr[i + 1];
+            double sr = 0.0;
+            for (int e = rowptr[i]; e < e1; ++e) {
+                double vj = src[col[e]];
+                sr += (double)kval[e] * vj;
+                if (MODE == QEQ_MODE_FINAL) {
+                    float4 d = pdr[e];
+                    double c = (double)d.w * vj;
+                    fr[0] += c * d.x;
+                    fr[1] += c * d.y;
+                    fr[2] += c * d.z;
+                }
+            }
+            y += sr;
+        }
+        if (k.parts & QEQ_PART_SELF) y += dself[i] * vi;
+        if (MODE == QEQ_MODE_CG) {
+            y += Jv[i] * vi;
+            acc[0] = vi * y;
+            acc[1] = y;
+        }
+        dst[i] = y;
+        if (MODE == QEQ_MODE_FINAL) {
+            // forces: -dE/dr_i.  du_a = dE_rec/du_a / q_i, with u_a = K_a s_a.
+            const double Kd[3] = {(double)k.K1, (double)k.K2, (double)k.K3};
+            double sg2 = 0.0;
+            if (k.self_corr && (k.parts & QEQ_PART_SELF)) {
+                // +1/2 q_i^2 d(theta^T Theta theta)/du cancels the mesh self-force
+                for (int a = 0; a < 3; ++a) du[a] -= 0.5 * vi * selfgrad[3 * i + a];
+            }
+            for (int c = 0; c < 3; ++c) {
+                double g = 0.0;
+                for (int a = 0; a < 3; ++a) g += Kd[a] * k.Hinv[c * 3 + a] * du[a];
+                forces[3 * i + c] = -vi * g - vi * fr[c];
+            }
+            (void)sg2;
+            double J = Jv[i];
+            double gi = y + J * vi + chi_eff[i];
+            gvec[i] = gi;
+            acc[0] = vi * y;              // q.E q (no background)
+            acc[1] = chi_raw[i] * vi;     // chi.q
+            acc[2] = J * vi * vi;         // J q^2
+            acc[3] = sig[i] * sig[i] * vi;// sigma^2 q
+            acc[4] = gi;                  // sum of the gradient
+        }
+    }
+    if (MODE != QEQ_MODE_MATVEC) {
+        block_sum<5>(acc);
+        if (threadIdx.x == 0) {
+            for (int t = 0; t < 5; ++t) part[blockIdx.x * QEQ_NPART + t] = acc[t];
+        }
+    }
+}
+
+// q <- q0 (original order, gathered to sorted) or Q/N; partial sum(q).
+__global__ void k_cg_init_q(KParams k, const double* __restrict__ q0, const int* __restrict__ perm,
+                            double* __restrict__ q, double* __restrict__ part, CgScalars* sc) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double v[1] = {0.0};
+    if (i < k.n) {
+        double x = q0 ? q0[perm[i]] : k.q_tot / (double)k.n;
+        if (!isfinite(x)) {
+            x = k.q_tot / (double)k.n;
+            atomicOr(&sc->err, QEQ_ERRBIT_INPUT);
+        }
+        q[i] = x;
+        v[0] = x;
+    }
+    block_sum<1>(v);
+    if (threadIdx.x == 0) part[blockIdx.x * QEQ_NPART] = v[0];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->done = 0;
+        sc->iters = 0;
+    }
+}
+
+__global__ void k_cg_project_q(KParams k, double* __restrict__ q, double* __restrict__ p,
+                               const double* __restrict__ part, int nparts) {
+    __shared__ double shift;
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int b = 0; b < nparts; ++b) s += part[b * QEQ_NPART];
+        shift = (k.q_tot - s) / (double)k.n;
+    }
+    __syncthreads();
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < k.n) {
+        double x = q[i] + shift;
+        q[i] = x;
+        p[i] = x;
+    }
+}
+
+template <int NV>
+__device__ __forceinline__ void reduce_strided(const double* part, int nparts, double* out) {
+    __shared__ double tot[NV];
+    double v[NV];
+#pragma unroll
+    for (int t = 0; t < NV; ++t) v[t] = 0.0;
+    for (int b = threadIdx.x; b < nparts; b += blockDim.x) {
+#pragma unroll
+        for (int t = 0; t < NV; ++t) v[t] += part[b * QEQ_NPART + t];
+    }
+    block_sum<NV>(v);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int t = 0; t < NV; ++t) tot[t] = v[t];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < NV; ++t) out[t] = tot[t];
+    __syncthreads();
+}
+
+// r = -(chi_eff + A q0) projected to zero mean; partial sums for z.
+__global__ void k_cg_init_r(KParams k, const double* __restrict__ y, const double* __restrict__ chi,
+                            const double* __restrict__ dinv, double* __restrict__ r,
+                            const double* __restrict__ part_in, int nparts, double* __restrict__ part_out,
+                            const CgScalars* __restrict__ sc) {
+    double tot[2];
+    reduce_strided<2>(part_in, nparts, tot);
+    const double shift = (sc->chi_sum + tot[1]) / (double)k.n;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double acc[3] = {0.0, 0.0, 0.0};
+    if (i < k.n) {
+        double ri = -chi[i] - y[i] + shift;
+        r[i] = ri;
+        double di = dinv[i];
+        acc[0] = di * ri;
+        acc[1] = di * ri * ri;
+        acc[2] = ri * ri;
+    }
+    block_sum<3>(acc);
+    if (threadIdx.x == 0) {
+        for (int t = 0; t < 3; ++t) part_out[blockIdx.x * QEQ_NPART + t] = acc[t];
+    }
+}
+
+__global__ void k_cg_update(KParams k, const double* __restrict__ p, const double* __restrict__ y,
+                            const double* __restrict__ dinv, double* __restrict__ q, double* __restrict__ r,
+                            const double* __restrict__ part_in, int nparts, double* __restrict__ part_out,
+                            CgScalars* sc, int parity) {
+    if (sc->done) return;
+    double tot[2];
+    reduce_strided<2>(part_in, nparts, tot);
+    const double alpha = sc->rz[parity] / tot[0];
+    const double ymean = tot[1] / (double)k.n;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double acc[3] = {0.0, 0.0, 0.0};
+    if (i < k.n) {
+        q[i] += alpha * p[i];
+        double ri = r[i] - alpha * (y[i] - ymean);
+        r[i] = ri;
+        double di = dinv[i];
+        acc[0] = di * ri;
+        acc[1] = di * ri * ri;
+        acc[2] = ri * ri;
+    }
+    block_sum<3>(acc);
+    if (threadIdx.x == 0) {
+        for (int t = 0; t < 3; ++t) part_out[blockIdx.x * QEQ_NPART + t] = acc[t];
+        if (blockIdx.x == 0) {
+            sc->alpha = alpha;
+            sc->iters += 1;
+        }
+    }
+}
+
+__global__ void k_cg_dir(KParams k, const double* __restrict__ r, const double* __restrict__ dinv,
+                         double* __restrict__ p, const double* __restrict__ part_in, int nparts,
+                         CgScalars* sc, int parity, int init) {
+    if (sc->done) return;
+    double tot[3];
+    reduce_strided<3>(part_in, nparts, tot);
+    const double c = tot[0] / sc->dinv_sum;
+    const double rz = tot[1] - c * tot[0];
+    const double beta = init ? 0.0 : rz / sc->rz[parity];
+    const double res = sc->chi_norm > 0.0 ? sqrt(tot[2]) / sc->chi_norm : sqrt(tot[2]);
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < k.n) p[i] = dinv[i] * (r[i] - c) + beta * p[i];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->rz[parity ^ 1] = rz;
+        sc->res = res;
+        if (res <= k.tol || !(res == res)) sc->done = 1;
+    }
+}
+
+// Final: reduce energy partials, the mean gradient (= mu up to the background
+// constant) and the deviation of the gradient from it; scatter outputs.
+__global__ void k_final2(KParams k, const double* __restrict__ q_s, const double* __restrict__ f_s,
+                         const double* __restrict__ gvec, const int* __restrict__ perm,
+                         double* __restrict__ q_out, double* __restrict__ f_out,
+                         const double* __restrict__ part_in, int nparts, double* __restrict__ part_out) {
+    double tot[5];
+    reduce_strided<5>(part_in, nparts, tot);
+    const double gmean = tot[4] / (double)k.n;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double acc[1] = {0.0};
+    if (i < k.n) {
+        int o = perm[i];
+        if (q_out) q_out[o] = q_s[i];
+        if (f_out) {
+            f_out[3 * o] = f_s[3 * i];
+            f_out[3 * o + 1] = f_s[3 * i + 1];
+            f_out[3 * o + 2] = f_s[3 * i + 2];
+        }
+        double d = gvec[i] - gmean;
+        acc[0] = d * d;
+    }
+    block_sum<1>(acc);
+    if (threadIdx.x == 0) part_out[blockIdx.x * QEQ_NPART] = acc[0];
+}
+
+__global__ void k_final3(KParams k, const double* __restrict__ part5, const double* __restrict__ part1,
+                         int nparts, const CgScalars* __restrict__ sc, double* __restrict__ out,
+                         double* __restrict__ energies) {
+    double tot[5];
+    reduce_strided<5>(part5, nparts, tot);
+    double dev[1];
+    reduce_strided<1>(part1, nparts, dev);
+    if (threadIdx.x == 0) {
+        const double Q = k.q_tot;
+        const double S2 = tot[3];
+        const double e_bg = -0.5 * k.bg_pref * (k.eta * k.eta * Q * Q - 2.0 * Q * S2);
+        const double e_elec = 0.5 * tot[0] + e_bg;
+        const double e_qeq = e_elec + tot[1] + 0.5 * tot[2];
+        const double mu = tot[4] / (double)k.n - k.bg_pref * (k.eta * k.eta * Q - S2);
+        const double tres = sc->chi_norm > 0.0 ? sqrt(dev[0]) / sc->chi_norm : sqrt(dev[0]);
+        out[0] = e_qeq;
+        out[1] = e_elec;
+        out[2] = mu;
+        out[3] = tres;
+        if (energies) {
+            energies[0] = e_qeq;
+            energies[1] = e_elec;
+        }
+    }
+}
+
+// Matrix-vector entry point: permute the input to sorted order, add the
+// background term, permute the output back.
+__global__ void k_perm_in(int n, const double* __restrict__ v, const int* __restrict__ perm,
+                          const double* __restrict__ sig, double* __restrict__ vs, double* __restrict__ part) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double acc[2] = {0.0, 0.0};
+    if (i < n) {
+        double x = v[perm[i]];
+        vs[i] = x;
+        acc[0] = x;
+        acc[1] = sig[i] * sig[i] * x;
+    }
+    block_sum<2>(acc);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x * QEQ_NPART] = acc[0];
+        part[blockIdx.x * QEQ_NPART + 1] = acc[1];
+    }
+}
+
+__global__ void k_perm_out(KParams k, const double* __restrict__ ys, const int* __restrict__ perm,
+                           const double* __restrict__ sig, double* __restrict__ y,
+                           const double* __restrict__ part, int nparts) {
+    double tot[2];
+    reduce_strided<2>(part, nparts, tot);
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= k.n) return;
+    double v = ys[i];
+    if (k.parts & QEQ_PART_BG) {
+        double s2 = sig[i] * sig[i];
+        v -= k.bg_pref * ((k.eta * k.eta - s2) * tot[0] - tot[1]);
+    }
+    y[perm[i]] = v;
+}
+
+}  // namespace
+
+static double* part_buf(qeq_plan* pl, int which) { return pl->part + (size_t)which * pl->nblk_max * QEQ_NPART; }
+
+template <int MODE>
+static void interp_launch(qeq_plan* pl, const double* src, double* dst, double* part) {
+    int nb = nblocks(pl->kp.n);
+    hipLaunchKernelGGL(k_interp<MODE>, dim3(nb), dim3(QEQ_BLOCK), 0, pl->stream, pl->kp, src, dst,
+                       pl->grid_r, pl->home, pl->wts, pl->dwts, pl->rowptr, pl->col, pl->kval, pl->pdr,
+                       pl->dself, pl->Jv, pl->chi_raw, pl->chi, pl->sig, pl->selfgrad, pl->forces_s,
+                       pl->gtmp, part, pl->sc);
+}
+
+int launch_interp(qeq_plan* pl, const double* src, double* dst, int mode, int parity) {
+    (void)parity;
+    double* part = part_buf(pl, 0);
+    ProfScope ps(pl, mode == QEQ_MODE_CG ? PK_INTERP : PK_COUNT);
+    if (mode == QEQ_MODE_CG)
+        interp_launch<QEQ_MODE_CG>(pl, src, dst, part);
+    else if (mode == QEQ_MODE_MATVEC)
+        interp_launch<QEQ_MODE_MATVEC>(pl, src, dst, part);
+    else
+        interp_launch<QEQ_MODE_FINAL>(pl, src, dst, part);
+    return qeq_check(hipGetLastError());
+}
+
+int launch_cg_init_q(qeq_plan* pl, const double* q0) {
+    int nb = nblocks(pl->kp.n);
+    hipLaunchKernelGGL(k_cg_init_q, dim3(nb), dim3(QEQ_BLOCK), 0, pl->stream, pl->kp, q0, pl->perm,
+                       pl->q, part_buf(pl, 1), pl->sc);
+    hipLaunchKernelGGL(k_cg_project_q, dim3(nb), dim3(QEQ_BLOCK), 0, pl->stream, pl->kp, pl->q,
+                       pl->pvec, part_buf(pl, 1), nb);
+    return qeq_check(hipGetLastError());
+}
+
+int launch_cg_init_r(qeq_plan* pl) {
+    int nb = nblocks(pl->kp.n);
+    hipLaunchKernelGGL(k_cg_init_r, dim3(nb), dim3(QEQ_BLOCK), 0, pl->stream, pl->kp, pl->y, pl->chi,
+                       pl->dinv, pl->r, part_buf(pl, 0), nb, part_buf(pl, 1), pl->sc);
+    return qeq_check(hipGetLastError());
+}
+
+int launch_cg_update(qeq_plan* pl, int parity) {
+    int nb = nblocks(pl->kp.n);
+    ProfScope ps(pl, PK_CG_UPDATE);
+    hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(QEQ_BLOCK), 0, pl->stream, pl->kp, pl->pvec, pl->y,
+                       pl->dinv, pl->q, pl->r, part_buf(pl, 0), nb, part_buf(pl, 1), pl->sc, parity);
+    return qeq_check(hipGetLastError());
+}
+
+int launch_cg_dir(qeq_plan* pl, int parity, int init) {
+    int nb = nblocks(pl->kp.n);
+    ProfScope ps(pl, PK_CG_DIR);
+    hipLaunchKernelGGL(k_cg_dir, dim3(nb), dim3(QEQ_BLOCK), 0, pl->stream, pl->kp, pl->r, pl->dinv,
+                       pl->pvec, part_buf(pl, 1), nb, pl->sc, parity, init);
+    return qeq_check(hipGetLastError());
+}
+
+int launch_final(qeq_plan* pl, double* q_out, double* energies, double* forces_out) {
+    int nb = nblocks(pl->kp.n);
+    double* part = part_buf(pl, 0);
+    ProfScope ps(pl, PK_FINAL);
+    interp_launch<QEQ_MODE_FINAL>(pl, pl->q, pl->y, part);
+    hipLaunchKernelGGL(k_final2, dim3(nb), dim3(QEQ_BLOCK), 0, pl->stream, pl->kp, pl->q, pl->forces_s,
+                       pl->gtmp, pl->perm, q_out, forces_out, part, nb, part_buf(pl, 1));
+    hipLaunchKernelGGL(k_final3, dim3(1), dim3(QEQ_BLOCK), 0, pl->stream, pl->kp, part, part_buf(pl, 1),
+                       nb, pl->sc, pl->final_dev, energies);
+    return qeq_check(hipGetLastError());
+}
+
+int launch_matvec_io(qeq_plan* pl, const double* v_orig, double* y_orig, int stage) {
+    int nb = nblocks(pl->kp.n);
+    if (stage == 0) {
+        hipLaunchKernelGGL(k_perm_in, dim3(nb), dim3(QEQ_BLOCK), 0, pl->stream, pl->kp.n, v_orig, pl->perm,
+                           pl->sig, pl->pvec, part_buf(pl, 1));
+    } else {
+        hipLaunchKernelGGL(k_perm_out, dim3(nb), dim3(QEQ_BLOCK), 0, pl->stream, pl->kp, pl->y, pl->perm,
+                           pl->sig, y_orig, part_buf(pl, 1), nb);
+    }
+    return qeq_check(hipGetLastError());
+}

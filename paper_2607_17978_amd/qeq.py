@@ -1,0 +1,223 @@
+"""Thin ctypes binding of the C ABI in include/qeq.h (argument marshalling only).
+
+Every step of the solve runs in the HIP library ``libqeq.so`` that sits next
+to this file; the binding only checks tensor placement / dtype / shape and
+passes raw device pointers.  If the library is missing, importing works but
+every call raises: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqeq.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "qeq.h")
+
+QEQ_OK = 0
+QEQ_NOT_CONVERGED = 1
+QEQ_EINVAL = -1
+QEQ_ECELL = -2
+QEQ_ENOMEM = -3
+QEQ_EHIP = -4
+QEQ_EPLAN = -5
+
+PART_RECIP, PART_REAL, PART_SELF, PART_BG = 1, 2, 4, 8
+PART_ALL = 15
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("eta", ctypes.c_double),
+        ("r_cut", ctypes.c_double),
+        ("max_spacing", ctypes.c_double),
+        ("grid", ctypes.c_int32 * 3),
+        ("spline_order", ctypes.c_int32),
+        ("tol", ctypes.c_double),
+        ("max_iter", ctypes.c_int32),
+        ("self_correction", ctypes.c_int32),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32),
+        ("iters", ctypes.c_int32),
+        ("rel_resid", ctypes.c_double),
+        ("true_rel_resid", ctypes.c_double),
+        ("mu", ctypes.c_double),
+        ("e_qeq", ctypes.c_double),
+        ("e_elec", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class QEqError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"qeq error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library():
+    """Load libqeq.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, dp, i32, f64 = ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    L.qeq_params_default.argtypes = [ctypes.POINTER(Params)]
+    L.qeq_params_default.restype = None
+    L.qeq_plan_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Params), i32, vp]
+    L.qeq_plan_create.restype = ctypes.c_int
+    L.qeq_plan_destroy.argtypes = [vp]
+    L.qeq_plan_destroy.restype = ctypes.c_int
+    L.qeq_solve.argtypes = [vp, i32, dp, ctypes.POINTER(ctypes.c_double), dp, dp, dp, f64, dp, dp, dp,
+                            dp, ctypes.POINTER(Stats)]
+    L.qeq_solve.restype = ctypes.c_int
+    L.qeq_matvec.argtypes = [vp, i32, dp, ctypes.POINTER(ctypes.c_double), dp, dp, dp, i32]
+    L.qeq_matvec.restype = ctypes.c_int
+    L.qeq_profile.argtypes = [vp, ctypes.c_uint32]
+    L.qeq_profile.restype = ctypes.c_int
+    L.qeq_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                                   i32, i32]
+    L.qeq_profile_read.restype = ctypes.c_int
+    L.qeq_strerror.argtypes = [ctypes.c_int]
+    L.qeq_strerror.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def header_functions():
+    """Names of the functions declared in include/qeq.h."""
+    src = open(HEADER_PATH).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(qeq_[a-z_]+|mlp_[a-z_]+)\s*\(", src)))
+
+
+def strerror(code: int) -> str:
+    return load_library().qeq_strerror(code).decode()
+
+
+def default_params() -> Params:
+    p = Params()
+    load_library().qeq_params_default(ctypes.byref(p))
+    return p
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _check_dev(name, t, n, cols=None, device=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    shape = (n,) if cols is None else (n, cols)
+    if tuple(t.shape) != shape:
+        raise ValueError(f"{name} must have shape {shape}, got {tuple(t.shape)}")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, plan is on {device}")
+
+
+def _cell_arg(cell):
+    c = np.ascontiguousarray(np.asarray(cell, dtype=np.float64).reshape(9))
+    return c, c.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class Plan:
+    """A solver plan bound to one device and stream (see qeq_plan_create)."""
+
+    def __init__(self, n_max, eta=2.0, r_cut=11.0, grid=None, max_spacing=0.8, spline_order=6,
+                 tol=1e-6, max_iter=1000, self_correction=True, stream=None):
+        import torch
+        L = load_library()
+        p = default_params()
+        p.eta, p.r_cut, p.max_spacing = eta, r_cut, max_spacing
+        g = grid if grid is not None else (0, 0, 0)
+        for a in range(3):
+            p.grid[a] = int(g[a])
+        p.spline_order, p.tol, p.max_iter = spline_order, tol, max_iter
+        p.self_correction = 1 if self_correction else 0
+        self.params = p
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        rc = L.qeq_plan_create(ctypes.byref(h), ctypes.byref(p), int(n_max),
+                               ctypes.c_void_p(self.stream.cuda_stream))
+        if rc != QEQ_OK:
+            raise QEqError(rc, strerror(rc))
+        self._h = h
+        self.n_max = int(n_max)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().qeq_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, pos, cell, sigma, J, chi, q_tot=0.0, q0=None, forces=True, check=True):
+        """Charges, [E_QEq, E_elec], forces (or None) and the stats dict."""
+        import torch
+        n = int(pos.shape[0])
+        for name, t, c in (("pos", pos, 3), ("sigma", sigma, None), ("J", J, None), ("chi", chi, None)):
+            _check_dev(name, t, n, c, self.device)
+        if q0 is not None:
+            _check_dev("q0", q0, n, None, self.device)
+        q = torch.empty(n, dtype=torch.float64, device=self.device)
+        en = torch.empty(2, dtype=torch.float64, device=self.device)
+        f = torch.empty((n, 3), dtype=torch.float64, device=self.device) if forces else None
+        st = Stats()
+        _, cp = _cell_arg(cell)
+        rc = load_library().qeq_solve(self._h, n, _ptr(pos), cp, _ptr(sigma), _ptr(J), _ptr(chi),
+                                      float(q_tot), _ptr(q0), _ptr(q), _ptr(en), _ptr(f),
+                                      ctypes.byref(st))
+        if check and rc < 0:
+            raise QEqError(rc, strerror(rc))
+        return q, en, f, dict(st.as_dict(), rc=rc)
+
+    PROFILE_KINDS = ("spread_r2c", "fft_rows_fwd", "fft_cols_green", "fft_rows_inv", "c2r",
+                     "interp_pairs", "cg_update", "cg_dir", "final")
+
+    def profile(self, mask):
+        """Bracket the launch kinds in ``mask`` with HIP events (see qeq_profile)."""
+        load_library().qeq_profile(self._h, int(mask))
+
+    def profile_read(self, reset=True):
+        """{kind: (total ms, launches)} accumulated since the last reset."""
+        ms = (ctypes.c_double * 16)()
+        cnt = (ctypes.c_int64 * 16)()
+        nk = load_library().qeq_profile_read(self._h, ms, cnt, 16, 1 if reset else 0)
+        return {self.PROFILE_KINDS[k]: (ms[k], cnt[k]) for k in range(min(nk, len(self.PROFILE_KINDS)))}
+
+    def matvec(self, pos, cell, sigma, v, parts=PART_ALL):
+        """y = E v with the selected operator parts (see qeq_matvec)."""
+        import torch
+        n = int(pos.shape[0])
+        for name, t, c in (("pos", pos, 3), ("sigma", sigma, None), ("v", v, None)):
+            _check_dev(name, t, n, c, self.device)
+        y = torch.empty(n, dtype=torch.float64, device=self.device)
+        _, cp = _cell_arg(cell)
+        rc = load_library().qeq_matvec(self._h, n, _ptr(pos), cp, _ptr(sigma), _ptr(v), _ptr(y),
+                                       int(parts))
+        if rc < 0:
+            raise QEqError(rc, strerror(rc))
+        return y
