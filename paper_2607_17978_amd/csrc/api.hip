@@ -334,6 +334,12 @@ int prepare(qeq_plan* pl, int n, const double* cell, double q_tot) {
     k.TW = tw;
     k.TWlog2 = ilog2(tw);
     k.ntile = K[1] / tw;
+    // the spread pass takes wider tiles when they fit: fewer blocks re-stage
+    // the same atoms (halo p - 1 rows per tile)
+    int tws = tw;
+    (void)tws;   // wider spread tiles (32 rows) measured slower on gfx950; keep the C2R tile
+    k.TWS = tws;
+    k.ntile_s = K[1] / tws;
     int nr = 16;
     while (nr > 1 && (size_t)K[1] * nr * 8 > 49152) nr >>= 1;
     k.NR = nr;
@@ -537,7 +543,7 @@ int qeq_plan_create(qeq_plan** out, const qeq_params* params, int32_t n_atoms_ma
     A(dalloc(&pl->rowcnt, n + 1));
     int np = 2 * QEQ_MAXP - 1;
     A(dalloc(&pl->theta_tab, (size_t)np * np * np));
-    pl->nblk_max = nblocks(n_atoms_max) + 1;
+    pl->nblk_max = std::max(interp_blocks(n_atoms_max), nblocks(n_atoms_max)) + 1;   // most blocks of any reduction
     A(dalloc(&pl->part, (size_t)2 * pl->nblk_max * QEQ_NPART));
     A(dalloc(&pl->sc, 1));
     A(dalloc(&pl->final_dev, 16));

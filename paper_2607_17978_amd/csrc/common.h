@@ -200,6 +200,72 @@ __device__ __forceinline__ void fft_lds(float2* buf, const FftAxis& ax, int ncol
 }
 
 // ---------------------------------------------------------------------------
+// The same Stockham transform with the length, the radix sequence, the column
+// count, the LDS row stride and the thread count fixed at compile time: every
+// index computation folds to shifts and multiplications by constants, only
+// the radices the length needs are instantiated, and register arrays are
+// sized exactly.  Element (k, c) lives at buf[k * KS + c], c < NCOL <= KS.
+// ---------------------------------------------------------------------------
+constexpr int ct_radix_at(int K, int s) {
+    int n = K, idx = 0;
+    while (n % 5 == 0) { if (idx == s) return 5; n /= 5; ++idx; }
+    while (n % 3 == 0) { if (idx == s) return 3; n /= 3; ++idx; }
+    while (n % 8 == 0) { if (idx == s) return 8; n /= 8; ++idx; }
+    if (n == 4) { if (idx == s) return 4; n = 1; ++idx; }
+    if (n == 2) { if (idx == s) return 2; n = 1; ++idx; }
+    return 0;
+}
+
+template <int K, int R, int NS, int NCOL, int KS, int NTHR, bool INV>
+__device__ __forceinline__ void fft_stage_ct(float2* buf, const float2* tw, int tid) {
+    constexpr int PER = K / R;
+    constexpr int NITEMS = PER * NCOL;
+    constexpr int IT = (NITEMS + NTHR - 1) / NTHR;
+    constexpr int STEP = K / (NS * R);
+    float2 v[IT][R];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int item = tid + it * NTHR;
+        if (NITEMS % NTHR == 0 || item < NITEMS) {
+            const int c = item % NCOL, j = item / NCOL;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[it][r] = buf[(j + r * PER) * KS + c];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int item = tid + it * NTHR;
+        if (NITEMS % NTHR == 0 || item < NITEMS) {
+            const int c = item % NCOL, j = item / NCOL;
+            const int kk = j % NS;
+            if (NS > 1) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    float2 w = tw[kk * r * STEP];
+                    if (INV) w.y = -w.y;
+                    v[it][r] = cmul(v[it][r], w);
+                }
+            }
+            dft<R>(v[it], INV);
+            const int base = (j - kk) * R + kk;
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[(base + r * NS) * KS + c] = v[it][r];
+        }
+    }
+    __syncthreads();
+}
+
+template <int K, int NCOL, int KS, int NTHR, bool INV, int S = 0, int NS = 1>
+__device__ __forceinline__ void fft_ct(float2* buf, const float2* tw, int tid) {
+    constexpr int R = ct_radix_at(K, S);
+    if constexpr (R != 0) {
+        fft_stage_ct<K, R, NS, NCOL, KS, NTHR, INV>(buf, tw, tid);
+        fft_ct<K, NCOL, KS, NTHR, INV, S + 1, NS * R>(buf, tw, tid);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // FP64 block reductions (wave64 shuffles, then LDS across waves)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double wave_sum(double v) {

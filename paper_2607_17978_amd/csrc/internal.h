@@ -11,6 +11,7 @@
 #include "../../include/qeq.h"
 
 #define QEQ_BLOCK 256         // threads per block for per-atom kernels
+#define QEQ_VBLOCK 256        // threads per block of the CG vector kernels
 #define QEQ_FFT_THREADS 256   // threads per block for FFT passes
 #define QEQ_NPART 8           // doubles per block in partial-sum buffers
 
@@ -32,7 +33,8 @@ struct KParams {
     int n;
     int p;                    // spline order
     int K1, K2, K3, K3h;      // grid; K3h = K3 / 2 + 1 (half spectrum along axis 3)
-    int TW, TWlog2, ntile;    // axis-2 row tile of the axis-3 and axis-1 passes
+    int TW, TWlog2, ntile;    // axis-2 row tile of the C2R and axis-1 passes
+    int TWS, ntile_s;         // axis-2 row tile of the spread + R2C pass
     int NR, NRlog2;           // rows per block of the axis-2 pass
     int nc[3];                // real-space cell-list dims
     int ns[3];                // stencil half-widths in cells
@@ -58,7 +60,7 @@ struct CgScalars {
     double chi_sum;           // sum chi_eff
     double dinv_sum;          // sum 1 / D
     double res;               // relative residual after the last update
-    double alpha;
+    double alpha;             // step length of the current iteration
     int iters;
     int done;
     int err;                  // QEQ_ERRBIT_*
@@ -188,6 +190,13 @@ int qeq_check(hipError_t e);
 #define QEQ_HIP(x) QEQ_TRY(qeq_check(x))
 
 inline int nblocks(int n, int b = QEQ_BLOCK) { return (n + b - 1) / b; }
+// blocks of the wave-per-atom interpolation kernel: QEQ_BLOCK / 64 atoms per
+// block and round, at most 4096 blocks (waves stride over the atoms), which
+// bounds the partial sums that the next kernel reduces.
+inline int interp_blocks(int n) {
+    int b = (n + QEQ_BLOCK / 64 - 1) / (QEQ_BLOCK / 64);
+    return b < 4096 ? b : 4096;
+}
 
 // ------------------------------------------------------------------ setup kernels (setup.hip)
 int launch_stage(qeq_plan* pl, const double* pos, const double* sigma, const double* J,

@@ -16,8 +16,12 @@
 namespace {
 
 // y_i = sum_g theta_i(g) phi(g) + sum_j K_ij v_j + d_i v_i (+ J_i v_i)
-// and, in FINAL mode, the force on atom i.
-template <int MODE>
+// and, in FINAL mode, the force on atom i.  One wave per atom: lane
+// (k1, k2) < p^2 gathers one row of p consecutive grid values along axis 3,
+// all 64 lanes then stride over the atom's pair-list row; the partial sums
+// are reduced across the wave.  (One thread per atom would leave the chip
+// with a few hundred waves and 216 dependent gathers each.)
+template <int MODE, int PC>
 __global__ __launch_bounds__(QEQ_BLOCK) void k_interp(
     KParams k, const double* __restrict__ src, double* __restrict__ dst, const float* __restrict__ grid,
     const int* __restrict__ home, const float* __restrict__ wts, const float* __restrict__ dwts,
@@ -25,108 +29,118 @@ __global__ __launch_bounds__(QEQ_BLOCK) void k_interp(
     const float4* __restrict__ pdr, const double* __restrict__ dself, const double* __restrict__ Jv,
     const double* __restrict__ chi_raw, const double* __restrict__ chi_eff, const double* __restrict__ sig,
     const double* __restrict__ selfgrad, double* __restrict__ forces, double* __restrict__ gvec,
-    double* __restrict__ part, const CgScalars* __restrict__ sc) {
+    double* __restrict__ part, CgScalars* __restrict__ sc, int parity) {
     if (MODE == QEQ_MODE_CG && sc->done) return;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    constexpr bool FIN = MODE == QEQ_MODE_FINAL;
+    const int lane = threadIdx.x & 63;
+    const int p = PC ? PC : k.p;
+    const int nwaves = gridDim.x * (blockDim.x >> 6);
     double acc[QEQ_NPART];
 #pragma unroll
     for (int t = 0; t < QEQ_NPART; ++t) acc[t] = 0.0;
-    if (i < k.n) {
-        const double vi = src[i];
-        double y = 0.0;
-        double du[3] = {0.0, 0.0, 0.0};
-        const int p = k.p;
-        if (k.parts & QEQ_PART_RECIP) {
+    // waves stride over atoms; the loop trip count is uniform across the block
+    const int rounds = (k.n + nwaves - 1) / nwaves;
+    for (int rnd = 0; rnd < rounds; ++rnd) {
+    const int i = rnd * nwaves + ((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    // per-lane partials: y, du[3] (reciprocal gradient / q), fr[3] (pair gradient / q)
+    double v[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const bool active = i < k.n;
+    if (active) {
+        if ((k.parts & QEQ_PART_RECIP) && lane < p * p) {
+            const int k1 = lane / p, k2 = lane - (lane / p) * p;
             const int h1 = home[4 * i], h2 = home[4 * i + 1], h3 = home[4 * i + 2];
             const float* w = wts + (size_t)i * 3 * QEQ_MAXP;
-            const float* dw = dwts + (size_t)i * 3 * QEQ_MAXP;
-            int g3i[QEQ_MAXP];
-            for (int k3 = 0; k3 < p; ++k3) {
-                int g = h3 - k3;
-                g3i[k3] = g < 0 ? g + k.K3 : g;
+            int g1 = h1 - k1;
+            if (g1 < 0) g1 += k.K1;
+            int g2 = h2 - k2;
+            if (g2 < 0) g2 += k.K2;
+            const float* row = grid + ((size_t)g1 * k.K2 + g2) * k.K3;
+            float s = 0.f, s3 = 0.f;
+#pragma unroll
+            for (int k3 = 0; k3 < (PC ? PC : QEQ_MAXP); ++k3) {
+                if (!PC && k3 >= p) break;
+                int g3 = h3 - k3;
+                if (g3 < 0) g3 += k.K3;
+                const float gv = row[g3];
+                s += w[2 * QEQ_MAXP + k3] * gv;
+                if (FIN) s3 += dwts[(size_t)i * 3 * QEQ_MAXP + 2 * QEQ_MAXP + k3] * gv;
             }
-            for (int k1 = 0; k1 < p; ++k1) {
-                int g1 = h1 - k1;
-                if (g1 < 0) g1 += k.K1;
-                for (int k2 = 0; k2 < p; ++k2) {
-                    int g2 = h2 - k2;
-                    if (g2 < 0) g2 += k.K2;
-                    const float* row = grid + ((size_t)g1 * k.K2 + g2) * k.K3;
-                    float s = 0.f, s3 = 0.f;
-                    for (int k3 = 0; k3 < p; ++k3) {
-                        float v = row[g3i[k3]];
-                        s += w[2 * QEQ_MAXP + k3] * v;
-                        if (MODE == QEQ_MODE_FINAL) s3 += dw[2 * QEQ_MAXP + k3] * v;
-                    }
-                    y += (double)(w[k1] * w[QEQ_MAXP + k2]) * (double)s;
-                    if (MODE == QEQ_MODE_FINAL) {
-                        du[0] += (double)(dw[k1] * w[QEQ_MAXP + k2]) * (double)s;
-                        du[1] += (double)(w[k1] * dw[QEQ_MAXP + k2]) * (double)s;
-                        du[2] += (double)(w[k1] * w[QEQ_MAXP + k2]) * (double)s3;
-                    }
-                }
+            const float w1 = w[k1], w2 = w[QEQ_MAXP + k2];
+            v[0] = (double)(w1 * w2) * (double)s;
+            if (FIN) {
+                const float* dw = dwts + (size_t)i * 3 * QEQ_MAXP;
+                v[1] = (double)(dw[k1] * w2) * (double)s;
+                v[2] = (double)(w1 * dw[QEQ_MAXP + k2]) * (double)s;
+                v[3] = (double)(w1 * w2) * (double)s3;
             }
         }
-        double fr[3] = {0.0, 0.0, 0.0};
         if (k.parts & QEQ_PART_REAL) {
             const int e1 = rowptr[i + 1];
-            double sr = 0.0;
-            for (int e = rowptr[i]; e < e1; ++e) {
-                double vj = src[col[e]];
-                sr += (double)kval[e] * vj;
-                if (MODE == QEQ_MODE_FINAL) {
-                    float4 d = pdr[e];
-                    double c = (double)d.w * vj;
-                    fr[0] += c * d.x;
-                    fr[1] += c * d.y;
-                    fr[2] += c * d.z;
+            for (int e = rowptr[i] + lane; e < e1; e += 64) {
+                const double vj = src[col[e]];
+                v[0] += (double)kval[e] * vj;
+                if (FIN) {
+                    const float4 d = pdr[e];
+                    const double c = (double)d.w * vj;
+                    v[4] += c * d.x;
+                    v[5] += c * d.y;
+                    v[6] += c * d.z;
                 }
             }
-            y += sr;
         }
+    }
+    v[0] = wave_sum(v[0]);
+    if (FIN) {
+#pragma unroll
+        for (int t = 1; t < 7; ++t) v[t] = wave_sum(v[t]);
+    }
+    if (active && lane == 0) {
+        const double vi = src[i];
+        double y = v[0];
         if (k.parts & QEQ_PART_SELF) y += dself[i] * vi;
         if (MODE == QEQ_MODE_CG) {
             y += Jv[i] * vi;
-            acc[0] = vi * y;
-            acc[1] = y;
+            acc[0] += vi * y;
+            acc[1] += y;
         }
         dst[i] = y;
-        if (MODE == QEQ_MODE_FINAL) {
-            // forces: -dE/dr_i.  du_a = dE_rec/du_a / q_i, with u_a = K_a s_a.
-            const double Kd[3] = {(double)k.K1, (double)k.K2, (double)k.K3};
-            double sg2 = 0.0;
+        if (FIN) {
+            // forces: -dE/dr_i, with u_a = K_a s_a and s = r H^-1
+            double du[3] = {v[1], v[2], v[3]};
             if (k.self_corr && (k.parts & QEQ_PART_SELF)) {
                 // +1/2 q_i^2 d(theta^T Theta theta)/du cancels the mesh self-force
                 for (int a = 0; a < 3; ++a) du[a] -= 0.5 * vi * selfgrad[3 * i + a];
             }
+            const double Kd[3] = {(double)k.K1, (double)k.K2, (double)k.K3};
             for (int c = 0; c < 3; ++c) {
                 double g = 0.0;
                 for (int a = 0; a < 3; ++a) g += Kd[a] * k.Hinv[c * 3 + a] * du[a];
-                forces[3 * i + c] = -vi * g - vi * fr[c];
+                forces[3 * i + c] = -vi * g - vi * v[4 + c];
             }
-            (void)sg2;
-            double J = Jv[i];
-            double gi = y + J * vi + chi_eff[i];
+            const double J = Jv[i];
+            const double gi = y + J * vi + chi_eff[i];
             gvec[i] = gi;
-            acc[0] = vi * y;              // q.E q (no background)
-            acc[1] = chi_raw[i] * vi;     // chi.q
-            acc[2] = J * vi * vi;         // J q^2
-            acc[3] = sig[i] * sig[i] * vi;// sigma^2 q
-            acc[4] = gi;                  // sum of the gradient
+            acc[0] += vi * y;               // q.E q (no background)
+            acc[1] += chi_raw[i] * vi;      // chi.q
+            acc[2] += J * vi * vi;          // J q^2
+            acc[3] += sig[i] * sig[i] * vi; // sigma^2 q
+            acc[4] += gi;                   // sum of the gradient
         }
     }
+    }   // rounds
     if (MODE != QEQ_MODE_MATVEC) {
         block_sum<5>(acc);
         if (threadIdx.x == 0) {
             for (int t = 0; t < 5; ++t) part[blockIdx.x * QEQ_NPART + t] = acc[t];
         }
     }
+    (void)parity;
 }
 
 // q <- q0 (original order, gathered to sorted) or Q/N; partial sum(q).
 __global__ void k_cg_init_q(KParams k, const double* __restrict__ q0, const int* __restrict__ perm,
                             double* __restrict__ q, double* __restrict__ part, CgScalars* sc) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
     double v[1] = {0.0};
     if (i < k.n) {
         double x = q0 ? q0[perm[i]] : k.q_tot / (double)k.n;
@@ -142,23 +156,6 @@ __global__ void k_cg_init_q(KParams k, const double* __restrict__ q0, const int*
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         sc->done = 0;
         sc->iters = 0;
-    }
-}
-
-__global__ void k_cg_project_q(KParams k, double* __restrict__ q, double* __restrict__ p,
-                               const double* __restrict__ part, int nparts) {
-    __shared__ double shift;
-    if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int b = 0; b < nparts; ++b) s += part[b * QEQ_NPART];
-        shift = (k.q_tot - s) / (double)k.n;
-    }
-    __syncthreads();
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < k.n) {
-        double x = q[i] + shift;
-        q[i] = x;
-        p[i] = x;
     }
 }
 
@@ -183,7 +180,17 @@ __device__ __forceinline__ void reduce_strided(const double* part, int nparts, d
     __syncthreads();
 }
 
-// r = -(chi_eff + A q0) projected to zero mean; partial sums for z.
+// shift q onto the constraint plane sum(q) = Q_tot
+__global__ void k_cg_project_q(KParams k, double* __restrict__ q, const double* __restrict__ part,
+                               int nparts) {
+    double tot[1];
+    reduce_strided<1>(part, nparts, tot);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < k.n) q[i] += (k.q_tot - tot[0]) / (double)k.n;
+}
+
+// r = -(chi_eff + A q) with zero mean (y = A q and its partial sums from the
+// preceding matvec); partial sums of D^-1 r, r^2 / D and r^2.
 __global__ void k_cg_init_r(KParams k, const double* __restrict__ y, const double* __restrict__ chi,
                             const double* __restrict__ dinv, double* __restrict__ r,
                             const double* __restrict__ part_in, int nparts, double* __restrict__ part_out,
@@ -191,12 +198,12 @@ __global__ void k_cg_init_r(KParams k, const double* __restrict__ y, const doubl
     double tot[2];
     reduce_strided<2>(part_in, nparts, tot);
     const double shift = (sc->chi_sum + tot[1]) / (double)k.n;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
     double acc[3] = {0.0, 0.0, 0.0};
     if (i < k.n) {
-        double ri = -chi[i] - y[i] + shift;
+        const double ri = -chi[i] - y[i] + shift;
         r[i] = ri;
-        double di = dinv[i];
+        const double di = dinv[i];
         acc[0] = di * ri;
         acc[1] = di * ri * ri;
         acc[2] = ri * ri;
@@ -207,6 +214,7 @@ __global__ void k_cg_init_r(KParams k, const double* __restrict__ y, const doubl
     }
 }
 
+// alpha = r.z / p.A p; q += alpha p; r -= alpha (A p - mean(A p)).
 __global__ void k_cg_update(KParams k, const double* __restrict__ p, const double* __restrict__ y,
                             const double* __restrict__ dinv, double* __restrict__ q, double* __restrict__ r,
                             const double* __restrict__ part_in, int nparts, double* __restrict__ part_out,
@@ -216,13 +224,13 @@ __global__ void k_cg_update(KParams k, const double* __restrict__ p, const doubl
     reduce_strided<2>(part_in, nparts, tot);
     const double alpha = sc->rz[parity] / tot[0];
     const double ymean = tot[1] / (double)k.n;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
     double acc[3] = {0.0, 0.0, 0.0};
     if (i < k.n) {
         q[i] += alpha * p[i];
-        double ri = r[i] - alpha * (y[i] - ymean);
+        const double ri = r[i] - alpha * (y[i] - ymean);
         r[i] = ri;
-        double di = dinv[i];
+        const double di = dinv[i];
         acc[0] = di * ri;
         acc[1] = di * ri * ri;
         acc[2] = ri * ri;
@@ -237,6 +245,9 @@ __global__ void k_cg_update(KParams k, const double* __restrict__ p, const doubl
     }
 }
 
+// c = sum(D^-1 r) / sum(D^-1) projects the preconditioned residual onto sum = 0,
+// r.z = sum(r^2/D) - c sum(D^-1 r), beta = r.z / r.z_old, p = D^-1 (r - c) + beta p;
+// the relative residual ||r|| / ||P chi_eff|| decides convergence.
 __global__ void k_cg_dir(KParams k, const double* __restrict__ r, const double* __restrict__ dinv,
                          double* __restrict__ p, const double* __restrict__ part_in, int nparts,
                          CgScalars* sc, int parity, int init) {
@@ -247,7 +258,7 @@ __global__ void k_cg_dir(KParams k, const double* __restrict__ r, const double* 
     const double rz = tot[1] - c * tot[0];
     const double beta = init ? 0.0 : rz / sc->rz[parity];
     const double res = sc->chi_norm > 0.0 ? sqrt(tot[2]) / sc->chi_norm : sqrt(tot[2]);
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < k.n) p[i] = dinv[i] * (r[i] - c) + beta * p[i];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         sc->rz[parity ^ 1] = rz;
@@ -282,13 +293,13 @@ __global__ void k_final2(KParams k, const double* __restrict__ q_s, const double
     if (threadIdx.x == 0) part_out[blockIdx.x * QEQ_NPART] = acc[0];
 }
 
-__global__ void k_final3(KParams k, const double* __restrict__ part5, const double* __restrict__ part1,
-                         int nparts, const CgScalars* __restrict__ sc, double* __restrict__ out,
-                         double* __restrict__ energies) {
+__global__ void k_final3(KParams k, const double* __restrict__ part5, int nparts5,
+                         const double* __restrict__ part1, int nparts1, const CgScalars* __restrict__ sc,
+                         double* __restrict__ out, double* __restrict__ energies) {
     double tot[5];
-    reduce_strided<5>(part5, nparts, tot);
+    reduce_strided<5>(part5, nparts5, tot);
     double dev[1];
-    reduce_strided<1>(part1, nparts, dev);
+    reduce_strided<1>(part1, nparts1, dev);
     if (threadIdx.x == 0) {
         const double Q = k.q_tot;
         const double S2 = tot[3];
@@ -347,55 +358,60 @@ __global__ void k_perm_out(KParams k, const double* __restrict__ ys, const int* 
 static double* part_buf(qeq_plan* pl, int which) { return pl->part + (size_t)which * pl->nblk_max * QEQ_NPART; }
 
 template <int MODE>
-static void interp_launch(qeq_plan* pl, const double* src, double* dst, double* part) {
-    int nb = nblocks(pl->kp.n);
-    hipLaunchKernelGGL(k_interp<MODE>, dim3(nb), dim3(QEQ_BLOCK), 0, pl->stream, pl->kp, src, dst,
-                       pl->grid_r, pl->home, pl->wts, pl->dwts, pl->rowptr, pl->col, pl->kval, pl->pdr,
-                       pl->dself, pl->Jv, pl->chi_raw, pl->chi, pl->sig, pl->selfgrad, pl->forces_s,
-                       pl->gtmp, part, pl->sc);
+static void interp_launch(qeq_plan* pl, const double* src, double* dst, double* part, int parity) {
+    const int nb = interp_blocks(pl->kp.n);   // one wave per atom
+#define QEQ_INTERP_ARGS                                                                              \
+    dim3(nb), dim3(QEQ_BLOCK), 0, pl->stream, pl->kp, src, dst, pl->grid_r, pl->home, pl->wts,       \
+        pl->dwts, pl->rowptr, pl->col, pl->kval, pl->pdr, pl->dself, pl->Jv, pl->chi_raw, pl->chi,   \
+        pl->sig, pl->selfgrad, pl->forces_s, pl->gtmp, part, pl->sc, parity
+    if (pl->kp.p == 6)
+        hipLaunchKernelGGL((k_interp<MODE, 6>), QEQ_INTERP_ARGS);
+    else
+        hipLaunchKernelGGL((k_interp<MODE, 0>), QEQ_INTERP_ARGS);
+#undef QEQ_INTERP_ARGS
 }
 
 int launch_interp(qeq_plan* pl, const double* src, double* dst, int mode, int parity) {
-    (void)parity;
     double* part = part_buf(pl, 0);
     ProfScope ps(pl, mode == QEQ_MODE_CG ? PK_INTERP : PK_COUNT);
     if (mode == QEQ_MODE_CG)
-        interp_launch<QEQ_MODE_CG>(pl, src, dst, part);
+        interp_launch<QEQ_MODE_CG>(pl, src, dst, part, parity);
     else if (mode == QEQ_MODE_MATVEC)
-        interp_launch<QEQ_MODE_MATVEC>(pl, src, dst, part);
+        interp_launch<QEQ_MODE_MATVEC>(pl, src, dst, part, parity);
     else
-        interp_launch<QEQ_MODE_FINAL>(pl, src, dst, part);
+        interp_launch<QEQ_MODE_FINAL>(pl, src, dst, part, parity);
     return qeq_check(hipGetLastError());
 }
 
 int launch_cg_init_q(qeq_plan* pl, const double* q0) {
-    int nb = nblocks(pl->kp.n);
+    const int nb = nblocks(pl->kp.n);
     hipLaunchKernelGGL(k_cg_init_q, dim3(nb), dim3(QEQ_BLOCK), 0, pl->stream, pl->kp, q0, pl->perm,
                        pl->q, part_buf(pl, 1), pl->sc);
     hipLaunchKernelGGL(k_cg_project_q, dim3(nb), dim3(QEQ_BLOCK), 0, pl->stream, pl->kp, pl->q,
-                       pl->pvec, part_buf(pl, 1), nb);
+                       part_buf(pl, 1), nb);
     return qeq_check(hipGetLastError());
 }
 
 int launch_cg_init_r(qeq_plan* pl) {
-    int nb = nblocks(pl->kp.n);
-    hipLaunchKernelGGL(k_cg_init_r, dim3(nb), dim3(QEQ_BLOCK), 0, pl->stream, pl->kp, pl->y, pl->chi,
-                       pl->dinv, pl->r, part_buf(pl, 0), nb, part_buf(pl, 1), pl->sc);
+    const int nb = nblocks(pl->kp.n, QEQ_VBLOCK);
+    hipLaunchKernelGGL(k_cg_init_r, dim3(nb), dim3(QEQ_VBLOCK), 0, pl->stream, pl->kp, pl->y, pl->chi,
+                       pl->dinv, pl->r, part_buf(pl, 0), interp_blocks(pl->kp.n), part_buf(pl, 1), pl->sc);
     return qeq_check(hipGetLastError());
 }
 
 int launch_cg_update(qeq_plan* pl, int parity) {
-    int nb = nblocks(pl->kp.n);
+    const int nb = nblocks(pl->kp.n, QEQ_VBLOCK);
     ProfScope ps(pl, PK_CG_UPDATE);
-    hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(QEQ_BLOCK), 0, pl->stream, pl->kp, pl->pvec, pl->y,
-                       pl->dinv, pl->q, pl->r, part_buf(pl, 0), nb, part_buf(pl, 1), pl->sc, parity);
+    hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(QEQ_VBLOCK), 0, pl->stream, pl->kp, pl->pvec, pl->y,
+                       pl->dinv, pl->q, pl->r, part_buf(pl, 0), interp_blocks(pl->kp.n), part_buf(pl, 1),
+                       pl->sc, parity);
     return qeq_check(hipGetLastError());
 }
 
 int launch_cg_dir(qeq_plan* pl, int parity, int init) {
-    int nb = nblocks(pl->kp.n);
+    const int nb = nblocks(pl->kp.n, QEQ_VBLOCK);
     ProfScope ps(pl, PK_CG_DIR);
-    hipLaunchKernelGGL(k_cg_dir, dim3(nb), dim3(QEQ_BLOCK), 0, pl->stream, pl->kp, pl->r, pl->dinv,
+    hipLaunchKernelGGL(k_cg_dir, dim3(nb), dim3(QEQ_VBLOCK), 0, pl->stream, pl->kp, pl->r, pl->dinv,
                        pl->pvec, part_buf(pl, 1), nb, pl->sc, parity, init);
     return qeq_check(hipGetLastError());
 }
@@ -404,11 +420,11 @@ int launch_final(qeq_plan* pl, double* q_out, double* energies, double* forces_o
     int nb = nblocks(pl->kp.n);
     double* part = part_buf(pl, 0);
     ProfScope ps(pl, PK_FINAL);
-    interp_launch<QEQ_MODE_FINAL>(pl, pl->q, pl->y, part);
+    interp_launch<QEQ_MODE_FINAL>(pl, pl->q, pl->y, part, 0);
     hipLaunchKernelGGL(k_final2, dim3(nb), dim3(QEQ_BLOCK), 0, pl->stream, pl->kp, pl->q, pl->forces_s,
-                       pl->gtmp, pl->perm, q_out, forces_out, part, nb, part_buf(pl, 1));
-    hipLaunchKernelGGL(k_final3, dim3(1), dim3(QEQ_BLOCK), 0, pl->stream, pl->kp, part, part_buf(pl, 1),
-                       nb, pl->sc, pl->final_dev, energies);
+                       pl->gtmp, pl->perm, q_out, forces_out, part, interp_blocks(pl->kp.n), part_buf(pl, 1));
+    hipLaunchKernelGGL(k_final3, dim3(1), dim3(QEQ_BLOCK), 0, pl->stream, pl->kp, part, interp_blocks(pl->kp.n),
+                       part_buf(pl, 1), nb, pl->sc, pl->final_dev, energies);
     return qeq_check(hipGetLastError());
 }
 
