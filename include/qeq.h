@@ -111,6 +111,22 @@ int qeq_solve(qeq_plan* plan, int32_t n, const double* pos, const double* cell,
               const double* q0, double* q, double* energies, double* forces,
               qeq_stats* stats);
 
+/* Gradient of a loss L(q, E_QEq, E_elec) through the last solve on this plan
+   (SI eq. 4g_force_trick: Lagrange / adjoint route, one extra linear solve
+   with the same operator instead of 3N charge derivatives).
+   dL_dq (n, device, caller order) or NULL for zero; dL_dEqeq, dL_dEelec:
+   scalar weights of the two energies.
+   Outputs (device, caller order, each may be NULL):
+     dL_dchi (n) = -a + dL_dEqeq q,
+     dL_dJ   (n) = -a q + dL_dEqeq q^2 / 2,
+     dL_dpos (n*3) = (dL_dEqeq + dL_dEelec) dE_elec/dr|_q - d(a^T E q)/dr,
+   where [E + diag J, 1; 1^T, 0][a; nu] = [dL_dq + dL_dEelec E q; 0].
+   stats (host) report the adjoint CG.  Needs a preceding successful
+   qeq_solve on the same plan (QEQ_EINVAL otherwise); gradients with respect to
+   sigma and the cell are not provided. */
+int qeq_backward(qeq_plan* plan, const double* dL_dq, double dL_dEqeq, double dL_dEelec,
+                 double* dL_dchi, double* dL_dJ, double* dL_dpos, qeq_stats* stats);
+
 /* y = E v with the plan's particle-mesh operator (no J), for checking the
    matrix-vector product of eq. matvec on its own.  parts is a bit mask:
    1 reciprocal (mesh) part, 2 real-space pair part, 4 self terms (Gaussian

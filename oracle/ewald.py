@@ -332,10 +332,10 @@ def qeq_adjoint(pos, cell, sigma, J, chi, q_tot, dL_dq, dL_dEelec=0.0, dL_dEqeq=
 
         [A 1; 1^T 0][a; nu] = [g; 0],  g = dL/dq + dL/dE_elec * (E q),
 
-    then dL/dchi = -a + dL/dE_QEq * q and
+    then dL/dchi = -a + dL/dE_QEq * q, dL/dJ = -a q + dL/dE_QEq q^2 / 2 and
     dL/dr = (dL/dE_elec + dL/dE_QEq) dE_elec/dr|_q - d(a^T E q)/dr|_{a,q}.
     The term dE_QEq/dq = mu 1 is orthogonal to every feasible dq and drops out.
-    Returns (q, dL_dchi, dL_dpos).
+    Returns (q, dL_dchi, dL_dpos, dL_dJ).
     """
     pos = np.asarray(pos, dtype=np.float64)
     E = coulomb_matrix(pos, cell, sigma, eta=eta)
@@ -345,7 +345,8 @@ def qeq_adjoint(pos, cell, sigma, J, chi, q_tot, dL_dq, dL_dEelec=0.0, dL_dEqeq=
     x = solver(bordered_matrix(A), np.concatenate([g, [0.0]]))
     a = x[:-1]
     dchi = -a + dL_dEqeq * q
+    dJ = -a * q + 0.5 * dL_dEqeq * q * q
     de_dr = energy_gradient_positions(pos, cell, sigma, q, eta=eta)
     bil = energy_gradient_positions(pos, cell, sigma, q, eta=eta, a=a)
     dpos = (dL_dEelec + dL_dEqeq) * de_dr - bil
-    return q, dchi, dpos
+    return q, dchi, dpos, dJ

@@ -408,13 +408,11 @@ int setup_geometry(qeq_plan* pl, const double* pos, const double* sigma, const d
     return QEQ_OK;
 }
 
-int solve_impl(qeq_plan* pl, int n, const double* pos, const double* cell, const double* sigma,
-               const double* J, const double* chi, double q_tot, const double* q0, double* q,
-               double* energies, double* forces, qeq_stats* stats) {
-    if (!pos || !sigma || !J || !chi || !q) return QEQ_EINVAL;
-    pl->tape_valid = false;
-    QEQ_TRY(prepare(pl, n, cell, q_tot));
-    QEQ_TRY(setup_geometry(pl, pos, sigma, J, chi));
+// Projected CG from q0 (or Q/N) to the tolerance, with the true-residual
+// restart, then the final matvec: energies, mu, true residual and forces are
+// computed; q_out / energies / forces_out (caller order) may be NULL.
+int cg_run(qeq_plan* pl, const double* q0, double* q_out, double* energies, double* forces_out,
+           bool* conv_out) {
     const int* done = &pl->sc->done;
     // initial guess (projected onto the constraint plane)
     QEQ_TRY(launch_cg_init_q(pl, q0));
@@ -456,7 +454,7 @@ int solve_impl(qeq_plan* pl, int n, const double* pos, const double* cell, const
         conv = pl->sc_host->done != 0;
         // final matvec on q: energies, mu, true residual, forces; scatter to caller order
         QEQ_TRY(launch_mesh_potential(pl, pl->q, nullptr));
-        QEQ_TRY(launch_final(pl, q, energies, forces));
+        QEQ_TRY(launch_final(pl, q_out, energies, forces_out));
         QEQ_HIP(hipMemcpyAsync(pl->out_host, pl->final_dev, 4 * sizeof(double), hipMemcpyDeviceToHost,
                                pl->stream));
         QEQ_HIP(hipMemcpyAsync(pl->sc_host, pl->sc, sizeof(CgScalars), hipMemcpyDeviceToHost, pl->stream));
@@ -469,6 +467,11 @@ int solve_impl(qeq_plan* pl, int n, const double* pos, const double* cell, const
         QEQ_HIP(hipMemsetAsync(&pl->sc->done, 0, sizeof(int), pl->stream));
     }
     prof_flush(pl, pl->sc_host->iters);
+    *conv_out = conv;
+    return QEQ_OK;
+}
+
+int cg_status(qeq_plan* pl, bool conv, qeq_stats* stats) {
     int status = conv ? QEQ_OK : QEQ_NOT_CONVERGED;
     if (pl->sc_host->err & QEQ_ERRBIT_INPUT) status = QEQ_EINVAL;
     if (!isfinite(pl->out_host[0])) status = status == QEQ_OK ? QEQ_NOT_CONVERGED : status;
@@ -481,7 +484,52 @@ int solve_impl(qeq_plan* pl, int n, const double* pos, const double* cell, const
         stats->e_qeq = pl->out_host[0];
         stats->e_elec = pl->out_host[1];
     }
+    return status;
+}
+
+int solve_impl(qeq_plan* pl, int n, const double* pos, const double* cell, const double* sigma,
+               const double* J, const double* chi, double q_tot, const double* q0, double* q,
+               double* energies, double* forces, qeq_stats* stats) {
+    if (!pos || !sigma || !J || !chi || !q) return QEQ_EINVAL;
+    pl->tape_valid = false;
+    QEQ_TRY(prepare(pl, n, cell, q_tot));
+    QEQ_TRY(setup_geometry(pl, pos, sigma, J, chi));
+    pl->fdst = pl->forces_s;
+    bool conv = false;
+    QEQ_TRY(cg_run(pl, q0, q, energies, forces, &conv));
+    int status = cg_status(pl, conv, stats);
     pl->tape_valid = status >= 0;
+    return status;
+}
+
+// Adjoint of the solve (SI eq. 4g_force_trick, Lagrange route): one more
+// projected CG with the same operator and right-hand side g, then the
+// bilinear position derivative of a^T E q from two mesh potentials.
+int backward_impl(qeq_plan* pl, const double* dL_dq, double dL_dEqeq, double dL_dEelec, double* dL_dchi,
+                  double* dL_dJ, double* dL_dpos, qeq_stats* stats) {
+    if (!pl->tape_valid) return QEQ_EINVAL;
+    if (!isfinite(dL_dEqeq) || !isfinite(dL_dEelec)) return QEQ_EINVAL;
+    const double q_tot = pl->kp.q_tot;
+    QEQ_TRY(launch_adj_rhs(pl, dL_dq, dL_dEelec));
+    // the adjoint system: A a + nu 1 = g, sum(a) = 0
+    // y (= E q of the solve) is part of the tape: the adjoint CG works on a copy
+    std::swap(pl->q, pl->q_adj);
+    std::swap(pl->chi, pl->chi_adj);
+    std::swap(pl->y, pl->y_adj);
+    pl->kp.q_tot = 0.0;
+    pl->fdst = pl->adj_scratch;
+    bool conv = false;
+    int rc = cg_run(pl, nullptr, nullptr, nullptr, nullptr, &conv);
+    std::swap(pl->q, pl->q_adj);
+    std::swap(pl->chi, pl->chi_adj);
+    std::swap(pl->y, pl->y_adj);
+    pl->kp.q_tot = q_tot;
+    pl->fdst = pl->forces_s;
+    QEQ_TRY(rc);
+    int status = cg_status(pl, conv, stats);
+    if (status < 0) return status;
+    QEQ_TRY(launch_adj_gradients(pl, dL_dEqeq, dL_dEelec, dL_dchi, dL_dJ, dL_dpos));
+    QEQ_HIP(hipStreamSynchronize(pl->stream));
     return status;
 }
 
@@ -538,6 +586,12 @@ int qeq_plan_create(qeq_plan** out, const qeq_params* params, int32_t n_atoms_ma
     A(dalloc(&pl->y, n));
     A(dalloc(&pl->forces_s, 3 * n));
     A(dalloc(&pl->gtmp, n));
+    A(dalloc(&pl->q_adj, n));
+    A(dalloc(&pl->y_adj, n));
+    A(dalloc(&pl->chi_adj, n));
+    A(dalloc(&pl->adj_scratch, 3 * n));
+    A(dalloc(&pl->tq, 3 * n));
+    pl->fdst = pl->forces_s;
     A(dalloc(&pl->rowptr, n + 1));
     A(dalloc(&pl->cell_atoms, n));
     A(dalloc(&pl->rowcnt, n + 1));
@@ -569,7 +623,7 @@ int qeq_plan_destroy(qeq_plan* pl) {
     dfree(pl->perm); dfree(pl->key); dfree(pl->frac); dfree(pl->home); dfree(pl->wts); dfree(pl->dwts);
     dfree(pl->sig); dfree(pl->Jv); dfree(pl->chi); dfree(pl->chi_raw); dfree(pl->dself); dfree(pl->dinv);
     dfree(pl->selfgrad); dfree(pl->q); dfree(pl->r); dfree(pl->pvec); dfree(pl->y); dfree(pl->forces_s);
-    dfree(pl->gtmp); dfree(pl->rowptr); dfree(pl->rowcnt); dfree(pl->theta_tab); dfree(pl->part);
+    dfree(pl->gtmp); dfree(pl->q_adj); dfree(pl->y_adj); dfree(pl->chi_adj); dfree(pl->adj_scratch); dfree(pl->tq); dfree(pl->rowptr); dfree(pl->rowcnt); dfree(pl->theta_tab); dfree(pl->part);
     dfree(pl->sc); dfree(pl->final_dev);
     dfree(pl->cell_count); dfree(pl->cell_start); dfree(pl->cell_fill); dfree(pl->cell_atoms);
     dfree(pl->col); dfree(pl->kval); dfree(pl->pdr);
@@ -631,6 +685,17 @@ int qeq_profile_read(qeq_plan* plan, double* total_ms, int64_t* launches, int32_
         }
     }
     return PK_COUNT;
+}
+
+int qeq_backward(qeq_plan* plan, const double* dL_dq, double dL_dEqeq, double dL_dEelec,
+                 double* dL_dchi, double* dL_dJ, double* dL_dpos, qeq_stats* stats) {
+    if (!plan) return QEQ_EINVAL;
+    int rc = backward_impl(plan, dL_dq, dL_dEqeq, dL_dEelec, dL_dchi, dL_dJ, dL_dpos, stats);
+    if (rc < 0 && stats) {
+        memset(stats, 0, sizeof(*stats));
+        stats->status = rc;
+    }
+    return rc;
 }
 
 const char* qeq_strerror(int code) {

@@ -135,6 +135,13 @@ struct qeq_plan {
     double* y = nullptr;
     double* forces_s = nullptr;   // n x 3 (sorted)
     double* gtmp = nullptr;       // n: final gradient vector
+    double* fdst = nullptr;       // where the final matvec writes sorted forces
+    // adjoint (tape of the last solve is q, y = E q, forces_s, geometry, pairs)
+    double* q_adj = nullptr;      // adjoint solution a (sorted)
+    double* y_adj = nullptr;      // matvec output buffer of the adjoint CG
+    double* chi_adj = nullptr;    // -g, the adjoint right-hand side (sorted)
+    double* adj_scratch = nullptr;// n x 3 scratch for the adjoint's final matvec
+    double* tq = nullptr;         // n x 3: sum_g dtheta_i/du phi_q(g)
 
     // real-space cell list and pair list
     int ncell_alloc = 0;
@@ -208,6 +215,7 @@ int launch_cells_and_pairs(qeq_plan* pl);
 int launch_theta(qeq_plan* pl);          // mesh kernel table for the self-correction
 int launch_selfcorr(qeq_plan* pl);
 int launch_scan(qeq_plan* pl, const int* in, int* out, int m);
+int launch_rhs_norm(qeq_plan* pl, const double* b);
 
 // ------------------------------------------------------------------ mesh kernels (mesh.hip)
 // Reciprocal potential of the charges src (sorted, FP64): real grid phi in grid_r.
@@ -225,3 +233,8 @@ int launch_cg_update(qeq_plan* pl, int parity);
 int launch_cg_dir(qeq_plan* pl, int parity, int init);
 int launch_final(qeq_plan* pl, double* q_out, double* energies, double* forces_out);
 int launch_matvec_io(qeq_plan* pl, const double* v_orig, double* y_orig, int stage);
+
+// ------------------------------------------------------------------ adjoint kernels (adjoint.hip)
+int launch_adj_rhs(qeq_plan* pl, const double* dL_dq, double dL_dEelec);
+int launch_adj_gradients(qeq_plan* pl, double dL_dEqeq, double dL_dEelec, double* dL_dchi,
+                         double* dL_dJ, double* dL_dpos);

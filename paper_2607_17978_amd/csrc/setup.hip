@@ -404,6 +404,18 @@ int launch_gather(qeq_plan* pl, const double* pos, const double* sigma, const do
     return qeq_check(hipGetLastError());
 }
 
+// ||P b|| and sum b of a right-hand side whose partial sums (slot 0: sum b,
+// slot 1: sum 1/D) are already in the first partial buffer.
+int launch_rhs_norm(qeq_plan* pl, const double* b) {
+    const int nb = nblocks(pl->kp.n);
+    double* part1 = pl->part;
+    double* part2 = pl->part + (size_t)pl->nblk_max * QEQ_NPART;
+    hipLaunchKernelGGL(k_chi_norm, dim3(nb), dim3(QEQ_BLOCK), 0, pl->stream, pl->kp.n, b, part1, nb, part2);
+    hipLaunchKernelGGL(k_chi_finish, dim3(1), dim3(QEQ_BLOCK), 0, pl->stream, pl->kp.n, part1, part2, nb,
+                       pl->sc);
+    return qeq_check(hipGetLastError());
+}
+
 int launch_cells_and_pairs(qeq_plan* pl) {
     const KParams& k = pl->kp;
     int ncell = k.nc[0] * k.nc[1] * k.nc[2];

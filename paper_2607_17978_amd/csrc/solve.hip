@@ -363,7 +363,7 @@ static void interp_launch(qeq_plan* pl, const double* src, double* dst, double* 
 #define QEQ_INTERP_ARGS                                                                              \
     dim3(nb), dim3(QEQ_BLOCK), 0, pl->stream, pl->kp, src, dst, pl->grid_r, pl->home, pl->wts,       \
         pl->dwts, pl->rowptr, pl->col, pl->kval, pl->pdr, pl->dself, pl->Jv, pl->chi_raw, pl->chi,   \
-        pl->sig, pl->selfgrad, pl->forces_s, pl->gtmp, part, pl->sc, parity
+        pl->sig, pl->selfgrad, pl->fdst, pl->gtmp, part, pl->sc, parity
     if (pl->kp.p == 6)
         hipLaunchKernelGGL((k_interp<MODE, 6>), QEQ_INTERP_ARGS);
     else
@@ -421,7 +421,7 @@ int launch_final(qeq_plan* pl, double* q_out, double* energies, double* forces_o
     double* part = part_buf(pl, 0);
     ProfScope ps(pl, PK_FINAL);
     interp_launch<QEQ_MODE_FINAL>(pl, pl->q, pl->y, part, 0);
-    hipLaunchKernelGGL(k_final2, dim3(nb), dim3(QEQ_BLOCK), 0, pl->stream, pl->kp, pl->q, pl->forces_s,
+    hipLaunchKernelGGL(k_final2, dim3(nb), dim3(QEQ_BLOCK), 0, pl->stream, pl->kp, pl->q, pl->fdst,
                        pl->gtmp, pl->perm, q_out, forces_out, part, interp_blocks(pl->kp.n), part_buf(pl, 1));
     hipLaunchKernelGGL(k_final3, dim3(1), dim3(QEQ_BLOCK), 0, pl->stream, pl->kp, part, interp_blocks(pl->kp.n),
                        part_buf(pl, 1), nb, pl->sc, pl->final_dev, energies);

@@ -84,6 +84,8 @@ def load_library():
     L.qeq_solve.argtypes = [vp, i32, dp, ctypes.POINTER(ctypes.c_double), dp, dp, dp, f64, dp, dp, dp,
                             dp, ctypes.POINTER(Stats)]
     L.qeq_solve.restype = ctypes.c_int
+    L.qeq_backward.argtypes = [vp, dp, f64, f64, dp, dp, dp, ctypes.POINTER(Stats)]
+    L.qeq_backward.restype = ctypes.c_int
     L.qeq_matvec.argtypes = [vp, i32, dp, ctypes.POINTER(ctypes.c_double), dp, dp, dp, i32]
     L.qeq_matvec.restype = ctypes.c_int
     L.qeq_profile.argtypes = [vp, ctypes.c_uint32]
@@ -162,6 +164,8 @@ class Plan:
             raise QEqError(rc, strerror(rc))
         self._h = h
         self.n_max = int(n_max)
+        self.solve_count = 0      # identifies the tape left by the last solve
+        self._last_n = None
 
     def close(self):
         if getattr(self, "_h", None):
@@ -190,9 +194,29 @@ class Plan:
         rc = load_library().qeq_solve(self._h, n, _ptr(pos), cp, _ptr(sigma), _ptr(J), _ptr(chi),
                                       float(q_tot), _ptr(q0), _ptr(q), _ptr(en), _ptr(f),
                                       ctypes.byref(st))
+        self.solve_count += 1
+        self._last_n = n
         if check and rc < 0:
             raise QEqError(rc, strerror(rc))
         return q, en, f, dict(st.as_dict(), rc=rc)
+
+    def backward(self, dL_dq=None, dL_dEqeq=0.0, dL_dEelec=0.0, check=True):
+        """Adjoint gradients (dL/dchi, dL/dJ, dL/dpos, stats) through the last solve."""
+        import torch
+        n = self._last_n
+        if n is None:
+            raise QEqError(QEQ_EINVAL, "backward needs a preceding solve")
+        if dL_dq is not None:
+            _check_dev("dL_dq", dL_dq, n, None, self.device)
+        dchi = torch.empty(n, dtype=torch.float64, device=self.device)
+        dJ = torch.empty(n, dtype=torch.float64, device=self.device)
+        dpos = torch.empty((n, 3), dtype=torch.float64, device=self.device)
+        st = Stats()
+        rc = load_library().qeq_backward(self._h, _ptr(dL_dq), float(dL_dEqeq), float(dL_dEelec),
+                                         _ptr(dchi), _ptr(dJ), _ptr(dpos), ctypes.byref(st))
+        if check and rc < 0:
+            raise QEqError(rc, strerror(rc))
+        return dchi, dJ, dpos, dict(st.as_dict(), rc=rc)
 
     PROFILE_KINDS = ("spread_r2c", "fft_rows_fwd", "fft_cols_green", "fft_rows_inv", "c2r",
                      "interp_pairs", "cg_update", "cg_dir", "final")
@@ -221,3 +245,45 @@ class Plan:
         if rc < 0:
             raise QEqError(rc, strerror(rc))
         return y
+
+
+def _autograd_function():
+    import torch
+
+    class QEqFunction(torch.autograd.Function):
+        """Differentiable QEq solve: (pos, chi, J) -> (q, [E_QEq, E_elec]).
+
+        Forward runs qeq_solve; backward runs the adjoint (qeq_backward) on the
+        same plan.  If another solve used the plan in between, the forward is
+        replayed first to restore the tape.  sigma, the cell and Q_tot are
+        treated as constants.
+        """
+
+        @staticmethod
+        def forward(ctx, pos, chi, J, sigma, plan, cell, q_tot):
+            q, en, _, st = plan.solve(pos.detach(), cell, sigma, J.detach(), chi.detach(), q_tot,
+                                      forces=False)
+            ctx.plan, ctx.cell, ctx.q_tot = plan, cell, q_tot
+            ctx.solve_id = plan.solve_count
+            ctx.save_for_backward(pos.detach(), chi.detach(), J.detach(), sigma)
+            ctx.stats = st
+            return q, en
+
+        @staticmethod
+        def backward(ctx, gq, gen):
+            plan = ctx.plan
+            pos, chi, J, sigma = ctx.saved_tensors
+            if plan.solve_count != ctx.solve_id:
+                plan.solve(pos, ctx.cell, sigma, J, chi, ctx.q_tot, forces=False)
+            dq = gq.contiguous() if gq is not None else None
+            e_qeq = float(gen[0]) if gen is not None else 0.0
+            e_elec = float(gen[1]) if gen is not None else 0.0
+            dchi, dJ, dpos, _ = plan.backward(dq, e_qeq, e_elec)
+            return dpos, dchi, dJ, None, None, None, None
+
+    return QEqFunction
+
+
+def qeq_autograd(pos, chi, J, sigma, plan, cell, q_tot=0.0):
+    """q, energies = QEq(pos, chi, J) with gradients through the adjoint solve."""
+    return _autograd_function().apply(pos, chi, J, sigma, plan, cell, q_tot)

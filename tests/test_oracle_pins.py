@@ -198,6 +198,29 @@ def _small_system(n=8, seed=21):
     return s.pos[idx], s.cell, s.sigma[idx], s.J[idx], s.chi[idx]
 
 
+def test_adjoint_energy_weights_match_finite_differences():
+    """dL/dE_QEq and dL/dE_elec weights (no charge term) against FD of the energies."""
+    pos, cell, sigma, J, chi = _small_system(n=6, seed=9)
+    q_tot = 1.0
+    _, dchi, dpos, dJ = ewald.qeq_adjoint(pos, cell, sigma, J, chi, q_tot, np.zeros(6),
+                                           dL_dEelec=0.7, dL_dEqeq=-1.3)
+
+    def loss(p, c, Jv):
+        r = ewald.qeq_dense(p, cell, sigma, Jv, c, q_tot, forces=False)
+        return 0.7 * r.e_elec - 1.3 * r.e_qeq
+
+    h = 1e-5
+    cp = chi.copy(); cp[1] += h
+    cm = chi.copy(); cm[1] -= h
+    assert abs((loss(pos, cp, J) - loss(pos, cm, J)) / (2 * h) - dchi[1]) < 1e-8
+    jp = J.copy(); jp[3] += h
+    jm = J.copy(); jm[3] -= h
+    assert abs((loss(pos, chi, jp) - loss(pos, chi, jm)) / (2 * h) - dJ[3]) < 1e-8
+    pp = pos.copy(); pp[4, 1] += h
+    pm = pos.copy(); pm[4, 1] -= h
+    assert abs((loss(pp, chi, J) - loss(pm, chi, J)) / (2 * h) - dpos[4, 1]) < 1e-8
+
+
 def test_forces_are_minus_energy_derivative_with_resolved_charges():
     pos, cell, sigma, J, chi = _small_system()
     q_tot = 0.5
@@ -223,13 +246,23 @@ def test_adjoint_gradient_matches_finite_differences():
 
     _, r0 = loss(pos, chi)
     dl_dq = 2 * w * (r0.q - q_ref)
-    _, dchi, dpos = ewald.qeq_adjoint(pos, cell, sigma, J, chi, q_tot, dl_dq, dL_dEelec=1.0)
+    _, dchi, dpos, dJ = ewald.qeq_adjoint(pos, cell, sigma, J, chi, q_tot, dl_dq, dL_dEelec=1.0)
     h = 1e-5
     for i in (0, 4):
         cp = chi.copy(); cp[i] += h
         cm = chi.copy(); cm[i] -= h
         fd = (loss(pos, cp)[0] - loss(pos, cm)[0]) / (2 * h)
         assert abs(fd - dchi[i]) < 1e-8
+
+    def loss_J(Jv):
+        r = ewald.qeq_dense(pos, cell, sigma, Jv, chi, q_tot, forces=False)
+        return np.sum(w * (r.q - q_ref) ** 2) + r.e_elec
+
+    for i in (2, 7):
+        jp = J.copy(); jp[i] += h
+        jm = J.copy(); jm[i] -= h
+        fd = (loss_J(jp) - loss_J(jm)) / (2 * h)
+        assert abs(fd - dJ[i]) < 1e-8
     for (i, c) in [(1, 0), (6, 2)]:
         pp = pos.copy(); pp[i, c] += h
         pm = pos.copy(); pm[i, c] -= h
