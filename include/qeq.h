@@ -135,6 +135,56 @@ int qeq_backward(qeq_plan* plan, const double* dL_dq, double dL_dEqeq, double dL
 int qeq_matvec(qeq_plan* plan, int32_t n, const double* pos, const double* cell,
                const double* sigma, const double* v, double* y, int32_t parts);
 
+/* ------------------------------------------------------------------------
+   Learned warm start (a small per-element network predicts initial charges).
+   ------------------------------------------------------------------------ */
+
+/* Radial descriptors (paper eq. g2 with the SI cosine cutoff, inner radius 0):
+     G_i,mu = sum_{j, images, r_ij < r_cut} exp(-(r_ij - c_mu)^2 / (2 width^2))
+                                           (cos(pi r_ij / r_cut) + 1) / 2,
+   mu < n_feat <= 32, over all neighbours (not element-resolved).  Runs the
+   plan's geometry set-up (which replaces the tape of the last solve), so
+   r_cut must not exceed the plan's real-space cutoff.  centers: host,
+   n_feat doubles.  G: device, n x n_feat floats, caller order. */
+int qeq_descriptors(qeq_plan* plan, int32_t n, const double* pos, const double* cell,
+                    const double* sigma, int32_t n_feat, const double* centers, double width,
+                    double r_cut, float* G);
+
+/* Element networks 16-32-32-1, tanh hidden layers, linear output (SI
+   feed-forward networks), one per element; inputs scaled per element as
+   (G - mean) / (max - min) (SI feature scaling).  Products run on BF16 MFMA
+   (operands rounded to nearest even) with FP32 accumulation; biases, tanh and
+   the output layer in FP32.
+   params: device floats, element e at offset 1664 e, packed as
+     W1[32][16] | b1[32] | W2[32][32] | b2[32] | W3[32] | b3   (1633 used).
+   stats: device floats [n_species][3][16] = mean, min, max per feature.
+   species: device int32 in [0, n_species), n_species <= 4.
+   All calls enqueue on `stream` (a hipStream_t) and do not synchronise.   */
+
+/* Floats of scratch workspace that mlp_train_step / mlp_feature_stats need. */
+int64_t mlp_workspace_floats(int32_t n_species);
+
+/* Per-element mean / min / max of the 16 features over the given atoms. */
+int mlp_feature_stats(const float* G, const int32_t* species, int32_t n, int32_t n_species,
+                      float* stats, float* workspace, void* stream);
+
+/* out[i] (device double) = network of species[i] applied to G[i]; pass out
+   as the q0 of qeq_solve (the solve projects it onto sum = Q_tot, which is
+   the paper's constraint projection of predicted charges). */
+int mlp_forward(const float* G, const int32_t* species, int32_t n, int32_t n_species,
+                const float* params, const float* stats, double* out, void* stream);
+
+/* One training step on the batch: L = 1/2 mean (y - target)^2 (SI loss with
+   the 1/2 prefactor), gradients by a hand-written backward pass (BF16 MFMA,
+   FP32 accumulate), then Adam (beta1 0.9, beta2 0.999, eps 1e-8; SI) with
+   learning rate lr at step `step` (>= 1; step 0 computes loss and gradients
+   only).  loss (device, 1 float) and grad_out (device, like params) may be
+   NULL.  workspace: device, at least mlp_workspace_floats floats. */
+int mlp_train_step(const float* G, const int32_t* species, const double* target, int32_t n,
+                   int32_t n_species, const float* stats, float* params, float* adam_m,
+                   float* adam_v, int32_t step, float lr, float* workspace,
+                   int64_t workspace_floats, float* loss, float* grad_out, void* stream);
+
 /* Per-stage timers (the paper's per-stage timing of a step, here with HIP
    events on the plan's stream).  kind_mask selects which launch kinds are
    bracketed with events during later calls; 0 switches timing off.  Kinds:

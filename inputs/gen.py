@@ -259,3 +259,20 @@ def wrap_positions(pos: np.ndarray, cell: np.ndarray) -> np.ndarray:
     frac = pos @ np.linalg.inv(cell)
     frac -= np.floor(frac)
     return frac @ cell
+
+
+def warmstart_init(seed: int = 1005, n_species: int = 2):
+    """Initial weights of the per-element 16-32-32-1 warm-start networks.
+
+    Xavier-uniform weights, zero biases (paper SI, initialisation section),
+    drawn from default_rng(seed) in the order element, W1 (32x16), W2 (32x32),
+    W3 (1x32).  Returns a list of dicts {W1, b1, W2, b2, W3, b3} per element.
+    """
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n_species):
+        W1 = xavier_uniform(rng, 16, 32)
+        W2 = xavier_uniform(rng, 32, 32)
+        W3 = xavier_uniform(rng, 32, 1)
+        out.append(dict(W1=W1, b1=np.zeros(32), W2=W2, b2=np.zeros(32), W3=W3[0], b3=0.0))
+    return out

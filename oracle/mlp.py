@@ -1,0 +1,137 @@
+"""FP64 oracle for the learned warm start (test infrastructure only).
+
+* ``radial_descriptors`` -- radial symmetry functions of the paper's type-2
+  ACSF (eq. g2; SI "Radial ACSF"): G_i,mu = sum_j exp(-eta_mu (r_ij - R_mu)^2)
+  f_c(r_ij) with the cosine cutoff f_c(r) = (cos(pi r / r_c) + 1) / 2 (SI
+  cutoff functions, inner radius 0), over all periodic images, all neighbours
+  (not element-resolved).
+* ``feature_stats`` / ``scale`` -- per-element feature scaling
+  (G - mean) / (max - min) (SI "Feature scaling").
+* ``forward`` / ``backward`` -- the element network: tanh hidden layers and a
+  linear output (SI "Feed-forward neural networks"; activations), with an
+  optional bf16 rounding of the matrix-product operands at the points where
+  the GPU kernel rounds them, so that both sides take the same rounding
+  decisions and differ only by FP32 vs FP64 accumulation.
+* ``mse_loss`` -- 1/2 mean squared error (SI loss functions, 1/2 prefactor).
+* ``adam`` -- Adam update (SI "Adam": beta1 0.9, beta2 0.999, eps 1e-8).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import matfree
+
+# parameter layout of one element network 16-32-32-1 (row-major weights)
+N_IN, N_H = 16, 32
+OFF_W1, OFF_B1 = 0, 512
+OFF_W2, OFF_B2 = 544, 1568
+OFF_W3, OFF_B3 = 1600, 1632
+N_PARAM = 1633
+STRIDE = 1664          # per-element stride in the packed parameter vector
+
+
+def radial_descriptors(pos, cell, centers, width, r_cut):
+    """G (N x n_mu) with eta_mu = 1 / (2 width^2) and the cosine cutoff."""
+    pos = np.asarray(pos, dtype=np.float64)
+    ii, jj, d = matfree.real_space_pairs(pos, cell, r_cut)
+    r = np.sqrt(np.einsum("ij,ij->i", d, d))
+    fc = 0.5 * (np.cos(math.pi * r / r_cut) + 1.0)
+    eta = 1.0 / (2.0 * width * width)
+    G = np.zeros((pos.shape[0], len(centers)))
+    for m, c in enumerate(centers):
+        G[:, m] = np.bincount(ii, weights=np.exp(-eta * (r - c) ** 2) * fc, minlength=pos.shape[0])
+    return G
+
+
+def feature_stats(G, species, n_species):
+    """(n_species, 3, n_feat): mean, min, max per element."""
+    out = np.zeros((n_species, 3, G.shape[1]))
+    for s in range(n_species):
+        g = G[species == s]
+        out[s, 0], out[s, 1], out[s, 2] = g.mean(0), g.min(0), g.max(0)
+    return out
+
+
+def scale(G, species, stats):
+    mean, mn, mx = stats[species, 0], stats[species, 1], stats[species, 2]
+    rng = np.where(mx - mn > 0, mx - mn, 1.0)
+    return (G - mean) / rng
+
+
+def bf16(x):
+    """Round to bfloat16 (round to nearest even), returned as float64."""
+    f = np.asarray(x, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    lsb = (u >> 16) & 1
+    u = (u + 0x7FFF + lsb) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def unpack(params, s):
+    p = np.asarray(params, dtype=np.float64)[s * STRIDE:(s + 1) * STRIDE]
+    W1 = p[OFF_W1:OFF_W1 + 512].reshape(32, 16)
+    b1 = p[OFF_B1:OFF_B1 + 32]
+    W2 = p[OFF_W2:OFF_W2 + 1024].reshape(32, 32)
+    b2 = p[OFF_B2:OFF_B2 + 32]
+    W3 = p[OFF_W3:OFF_W3 + 32]
+    b3 = p[OFF_B3]
+    return W1, b1, W2, b2, W3, b3
+
+
+def forward(params, X, species, use_bf16=False):
+    """Per-atom output of its element's network and the cache for backward."""
+    rb = bf16 if use_bf16 else (lambda a: np.asarray(a, dtype=np.float64))
+    n = X.shape[0]
+    y = np.zeros(n)
+    cache = {}
+    for s in np.unique(species):
+        m = species == s
+        W1, b1, W2, b2, W3, b3 = unpack(params, s)
+        x = rb(X[m])
+        z1 = x @ rb(W1).T + b1
+        h1 = np.tanh(z1)
+        h1r = rb(h1)
+        z2 = h1r @ rb(W2).T + b2
+        h2 = np.tanh(z2)
+        y[m] = h2 @ W3 + b3
+        cache[s] = (m, x, h1, h1r, h2)
+    return y, cache
+
+
+def backward(params, cache, dy, use_bf16=False):
+    """Gradient of sum(dy * y) with respect to the packed parameters."""
+    rb = bf16 if use_bf16 else (lambda a: np.asarray(a, dtype=np.float64))
+    g = np.zeros_like(np.asarray(params, dtype=np.float64))
+    for s, (m, x, h1, h1r, h2) in cache.items():
+        W1, b1, W2, b2, W3, b3 = unpack(params, s)
+        d = dy[m]
+        gs = g[s * STRIDE:(s + 1) * STRIDE]
+        gs[OFF_W3:OFF_W3 + 32] = h2.T @ d
+        gs[OFF_B3] = d.sum()
+        dz2 = (d[:, None] * W3[None, :]) * (1.0 - h2 * h2)
+        dz2r = rb(dz2)
+        gs[OFF_W2:OFF_W2 + 1024] = (dz2r.T @ h1r).ravel()
+        gs[OFF_B2:OFF_B2 + 32] = dz2.sum(0)
+        dh1 = dz2r @ rb(W2)
+        dz1 = dh1 * (1.0 - h1 * h1)
+        dz1r = rb(dz1)
+        gs[OFF_W1:OFF_W1 + 512] = (dz1r.T @ x).ravel()
+        gs[OFF_B1:OFF_B1 + 32] = dz1.sum(0)
+    return g
+
+
+def mse_loss(y, target):
+    """L = 1/2 mean (y - t)^2 and dL/dy."""
+    r = y - target
+    return 0.5 * np.mean(r * r), r / r.shape[0]
+
+
+def adam(params, grad, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update (step counts from 1); returns new (params, m, v)."""
+    m = b1 * m + (1 - b1) * grad
+    v = b2 * v + (1 - b2) * grad * grad
+    mh = m / (1 - b1 ** step)
+    vh = v / (1 - b2 ** step)
+    return params - lr * mh / (np.sqrt(vh) + eps), m, v

@@ -236,5 +236,8 @@ int launch_matvec_io(qeq_plan* pl, const double* v_orig, double* y_orig, int sta
 
 // ------------------------------------------------------------------ adjoint kernels (adjoint.hip)
 int launch_adj_rhs(qeq_plan* pl, const double* dL_dq, double dL_dEelec);
+
+// ------------------------------------------------------------------ warm start (mlp.hip)
+int launch_descriptors(qeq_plan* pl, int nf, const double* centers, double width, double rc, float* G);
 int launch_adj_gradients(qeq_plan* pl, double dL_dEqeq, double dL_dEelec, double* dL_dchi,
                          double* dL_dJ, double* dL_dpos);

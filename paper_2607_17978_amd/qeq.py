@@ -93,6 +93,18 @@ def load_library():
     L.qeq_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                    i32, i32]
     L.qeq_profile_read.restype = ctypes.c_int
+    L.qeq_descriptors.argtypes = [vp, i32, dp, ctypes.POINTER(ctypes.c_double), dp, i32,
+                                  ctypes.POINTER(ctypes.c_double), f64, f64, dp]
+    L.qeq_descriptors.restype = ctypes.c_int
+    L.mlp_workspace_floats.argtypes = [i32]
+    L.mlp_workspace_floats.restype = ctypes.c_int64
+    L.mlp_feature_stats.argtypes = [dp, dp, i32, i32, dp, dp, vp]
+    L.mlp_feature_stats.restype = ctypes.c_int
+    L.mlp_forward.argtypes = [dp, dp, i32, i32, dp, dp, dp, vp]
+    L.mlp_forward.restype = ctypes.c_int
+    L.mlp_train_step.argtypes = [dp, dp, dp, i32, i32, dp, dp, dp, dp, i32, ctypes.c_float, dp,
+                                 ctypes.c_int64, dp, dp, vp]
+    L.mlp_train_step.restype = ctypes.c_int
     L.qeq_strerror.argtypes = [ctypes.c_int]
     L.qeq_strerror.restype = ctypes.c_char_p
     _lib = L
@@ -218,6 +230,23 @@ class Plan:
             raise QEqError(rc, strerror(rc))
         return dchi, dJ, dpos, dict(st.as_dict(), rc=rc)
 
+    def descriptors(self, pos, cell, sigma, centers, width, r_cut):
+        """Radial descriptors G (n x len(centers), float32, device); see qeq_descriptors."""
+        import torch
+        n = int(pos.shape[0])
+        _check_dev("pos", pos, n, 3, self.device)
+        _check_dev("sigma", sigma, n, None, self.device)
+        c = np.ascontiguousarray(np.asarray(centers, dtype=np.float64))
+        G = torch.empty((n, len(c)), dtype=torch.float32, device=self.device)
+        _, cp = _cell_arg(cell)
+        rc = load_library().qeq_descriptors(self._h, n, _ptr(pos), cp, _ptr(sigma), len(c),
+                                            c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                            float(width), float(r_cut), _ptr(G))
+        self._last_n = None       # the tape of the last solve is gone
+        if rc < 0:
+            raise QEqError(rc, strerror(rc))
+        return G
+
     PROFILE_KINDS = ("spread_r2c", "fft_rows_fwd", "fft_cols_green", "fft_rows_inv", "c2r",
                      "interp_pairs", "cg_update", "cg_dir", "final")
 
@@ -287,3 +316,67 @@ def _autograd_function():
 def qeq_autograd(pos, chi, J, sigma, plan, cell, q_tot=0.0):
     """q, energies = QEq(pos, chi, J) with gradients through the adjoint solve."""
     return _autograd_function().apply(pos, chi, J, sigma, plan, cell, q_tot)
+
+
+MLP_STRIDE = 1664
+MLP_OFFSETS = {"W1": (0, (32, 16)), "b1": (512, (32,)), "W2": (544, (32, 32)), "b2": (1568, (32,)),
+               "W3": (1600, (32,)), "b3": (1632, ())}
+
+
+def pack_mlp_params(nets):
+    """Pack per-element {W1, b1, W2, b2, W3, b3} into the flat layout of include/qeq.h."""
+    p = np.zeros(len(nets) * MLP_STRIDE, dtype=np.float32)
+    for e, net in enumerate(nets):
+        for k, (off, shape) in MLP_OFFSETS.items():
+            a = np.asarray(net[k], dtype=np.float32).reshape(-1)
+            p[e * MLP_STRIDE + off:e * MLP_STRIDE + off + a.size] = a
+    return p
+
+
+class WarmStartNet:
+    """Per-element 16-32-32-1 warm-start networks on the device (mlp_* calls)."""
+
+    def __init__(self, nets, device=None, stream=None):
+        import torch
+        self.n_species = len(nets)
+        self.device = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.params = torch.as_tensor(pack_mlp_params(nets), device=self.device)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.stats = torch.zeros(self.n_species * 3 * 16, dtype=torch.float32, device=self.device)
+        nws = load_library().mlp_workspace_floats(self.n_species)
+        self.workspace = torch.empty(int(nws), dtype=torch.float32, device=self.device)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=self.device)
+        self.step = 0
+
+    def _s(self):
+        return ctypes.c_void_p(self.stream.cuda_stream)
+
+    def fit_scaling(self, G, species):
+        rc = load_library().mlp_feature_stats(_ptr(G), _ptr(species), int(G.shape[0]), self.n_species,
+                                              _ptr(self.stats), _ptr(self.workspace), self._s())
+        if rc < 0:
+            raise QEqError(rc, strerror(rc))
+
+    def predict(self, G, species):
+        import torch
+        out = torch.empty(int(G.shape[0]), dtype=torch.float64, device=self.device)
+        rc = load_library().mlp_forward(_ptr(G), _ptr(species), int(G.shape[0]), self.n_species,
+                                        _ptr(self.params), _ptr(self.stats), _ptr(out), self._s())
+        if rc < 0:
+            raise QEqError(rc, strerror(rc))
+        return out
+
+    def train_step(self, G, species, target, lr=1e-3, update=True, grad_out=None):
+        """One Adam step on the batch (or only loss / gradients if update=False)."""
+        if update:
+            self.step += 1
+        rc = load_library().mlp_train_step(_ptr(G), _ptr(species), _ptr(target), int(G.shape[0]),
+                                           self.n_species, _ptr(self.stats), _ptr(self.params),
+                                           _ptr(self.m), _ptr(self.v), self.step if update else 0,
+                                           float(lr), _ptr(self.workspace), int(self.workspace.numel()),
+                                           _ptr(self.loss), _ptr(grad_out), self._s())
+        if rc < 0:
+            raise QEqError(rc, strerror(rc))
+        return self.loss

@@ -173,3 +173,28 @@ def test_repeat_solves_agree(dev):
     q2 = plan.solve(*args)[0].cpu().numpy()
     assert np.abs(q1 - q2).max() < 1e-9
     plan.close()
+
+
+def test_full_size_32768_matches_oracle(dev):
+    """The benchmark configuration (32,768 atoms, 192^3, tol 1e-6, r_c 11) against
+    the stored FP64 oracle solution (tests/golden/make_n32768_reference.py)."""
+    import os
+    from paper_2607_17978_amd import qeq
+    path = os.path.join(os.path.dirname(__file__), "golden", "n32768_reference.npz")
+    if not os.path.exists(path):
+        pytest.skip("reference not generated")
+    ref = np.load(path)
+    s = gen.system_32k()
+    plan = qeq.Plan(s.n, eta=ETA, r_cut=RC, grid=s.grid, tol=1e-6)
+    q, en, f, st = plan.solve(T(s.pos, dev), s.cell, T(s.sigma, dev), T(s.J, dev), T(s.chi, dev), 0.0)
+    q, en, f = q.cpu().numpy(), en.cpu().numpy(), f.cpu().numpy()
+    dq = np.abs(q - ref["q"]).max()
+    de_q = abs(en[0] - float(ref["e_qeq"])) / abs(float(ref["e_qeq"]))
+    de_e = abs(en[1] - float(ref["e_elec"])) / abs(float(ref["e_elec"]))
+    df = np.sqrt(np.mean((f - ref["forces"]) ** 2)) / np.sqrt(np.mean(ref["forces"] ** 2))
+    print("n32768", st, "dq", dq, "dEqeq", de_q, "dEelec", de_e, "dF", df)
+    assert st["rc"] == 0
+    assert dq <= 1e-5
+    assert de_q <= 1e-6 and de_e <= 1e-6
+    assert df <= 1e-4
+    plan.close()
