@@ -93,6 +93,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--workload", choices=["cold32k", "warmstart"], default="cold32k",
+                    help="cold32k: the default cold-start solve; warmstart: the 131,072-atom "
+                         "trajectory (learned vs cold vs previous-frame start)")
+    ap.add_argument("--frames", type=int, default=200)
+    ap.add_argument("--epochs", type=int, default=30)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported; this build runs on one GPU "
@@ -106,6 +111,8 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.workload == "warmstart":
+        return warmstart_main(args, dev)
     s = gen.system_32k()
     T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
     pos, sig, J, chi = T(s.pos), T(s.sigma), T(s.J), T(s.chi)
@@ -182,6 +189,38 @@ def main():
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
     plan.close()
+
+
+def warmstart_main(args, dev):
+    """One JSON line for the trajectory workload (value = learned-start solve ms)."""
+    from paper_2607_17978_amd import warmstart
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    t0 = time.perf_counter()
+    out = warmstart.run_trajectory(frames=args.frames, epochs=args.epochs, tol=args.tol, device=dev, log=log)
+    wall = time.perf_counter() - t0
+    line = {
+        "metric": METRIC,
+        "value": round(out["learned"]["ms"], 4),
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": out["frames"] - out["train_frames"],
+        "warmup": out["train_frames"],
+        "ms_per_step": round(out["learned"]["ms"], 4),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "learned warm start, 131072-atom trajectory, 320^3 grid, tol 1e-6",
+                   "n_atoms": out["n"], "grid": out["grid"], "frames": out["frames"],
+                   "train_frames": out["train_frames"]},
+        "warmstart": out,
+        "wall_s": round(wall, 1),
+    }
+    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

@@ -276,3 +276,25 @@ def warmstart_init(seed: int = 1005, n_species: int = 2):
         W3 = xavier_uniform(rng, 32, 1)
         out.append(dict(W1=W1, b1=np.zeros(32), W2=W2, b2=np.zeros(32), W3=W3[0], b3=0.0))
     return out
+
+
+def chi_from_descriptors(G, species, weights, scaling=None, y_std=None):
+    """Electronegativities of the trajectory workload from its descriptors.
+
+    chi_i = m_e + 0.05 y_i / y_std with m_e = +0.1 / -0.1 for the two
+    elements and y the fixed random 16-32-1 tanh network (``chi_network_weights``)
+    applied to the descriptors scaled per feature by ``scaling`` = (mean, min,
+    max) over all atoms.  With scaling / y_std None they are taken from this
+    frame (the first frame) and returned, so that later frames reuse them.
+    """
+    W1, b1, W2, b2 = weights
+    G = np.asarray(G, dtype=np.float64)
+    if scaling is None:
+        scaling = (G.mean(0), G.min(0), G.max(0))
+    mean, mn, mx = scaling
+    x = (G - mean) / np.where(mx - mn > 0, mx - mn, 1.0)
+    y = (np.tanh(x @ W1.T + b1) @ W2.T + b2)[:, 0]
+    if y_std is None:
+        y_std = float(y.std())
+    chi = np.asarray(CHI_MEAN_2EL)[species] + CHI_SD * y / y_std
+    return chi, scaling, y_std

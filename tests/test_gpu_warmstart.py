@@ -138,3 +138,17 @@ def test_training_reduces_loss(dev):
     last = float(last.cpu())
     print("loss", first, "->", last)
     assert last < 0.2 * first
+
+
+def test_learned_warm_start_on_small_trajectory(dev):
+    """4,096-atom version of the trajectory workload: the trained network's
+    start needs fewer CG iterations than the cold start, and every start
+    converges to the cold-start charges."""
+    from paper_2607_17978_amd import warmstart
+    out = warmstart.run_trajectory(n=4096, side=17, frames=24, epochs=40, tol=1e-6, device=dev)
+    print(out)
+    for k in ("cold", "prev", "learned"):
+        assert out[k]["all_converged"]
+    assert out["max_dq_vs_cold"] <= 1e-5
+    assert out["learned"]["iters"] < out["cold"]["iters"]
+    assert out["prev"]["iters"] < out["cold"]["iters"]
