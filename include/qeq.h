@@ -81,6 +81,8 @@ typedef struct qeq_stats {   /* host memory */
     double  mu;              /* Lagrange multiplier: (E + diag J) q + chi = mu 1 */
     double  e_qeq;           /* E_QEq at q */
     double  e_elec;          /* E_elec at q */
+    int32_t q0_rejected;     /* 1 if the supplied q0 was worse than the cold start and replaced */
+    int32_t reserved;
 } qeq_stats;
 
 /* Default parameters: eta 2.0, r_cut 11.0, max_spacing 0.8, grid derived,
@@ -97,7 +99,10 @@ int qeq_plan_destroy(qeq_plan* plan);
 /* Solve the QEq problem (eq. 4G_qeq_prime) for one periodic structure.
    pos (n*3), sigma, J, chi (n each): device, read-only.
    q0 (n, device) or NULL: initial guess, projected onto sum = q_tot; NULL
-   starts from q_tot/n.
+   starts from q_tot/n.  A guess that starts farther from the solution than
+   the cold start is discarded in favour of q_tot/n (stats->q0_rejected):
+   for q_tot = 0 in the energy norm CG minimises (E_QEq(q0) >= E_QEq(0)),
+   for charged cells by the projected residual (> ||P chi_eff||).
    q (n, device, out): charges.
    energies (2, device, out) or NULL: [E_QEq, E_elec].
    forces (n*3, device, out) or NULL: -dE_QEq/dr at the solution.  At the
@@ -152,7 +157,8 @@ int qeq_descriptors(qeq_plan* plan, int32_t n, const double* pos, const double* 
 
 /* Element networks 16-32-32-1, tanh hidden layers, linear output (SI
    feed-forward networks), one per element; inputs scaled per element as
-   (G - mean) / (max - min) (SI feature scaling).  Products run on BF16 MFMA
+   (G - mean) / (max - min) (SI feature scaling) and clipped to [-1.5, 1.5]
+   (atoms that leave the training range do not saturate the network).  Products run on BF16 MFMA
    (operands rounded to nearest even) with FP32 accumulation; biases, tanh and
    the output layer in FP32.
    params: device floats, element e at offset 1664 e, packed as

@@ -54,10 +54,19 @@ def feature_stats(G, species, n_species):
     return out
 
 
+CLIP = 1.5
+
+
 def scale(G, species, stats):
+    """(G - mean) / (max - min), clipped to [-1.5, 1.5].
+
+    Training data scale into [-1, 1]; the clip only bounds features of atoms
+    that leave the training range (the extrapolation the paper monitors during
+    MD), which would otherwise saturate the network.
+    """
     mean, mn, mx = stats[species, 0], stats[species, 1], stats[species, 2]
     rng = np.where(mx - mn > 0, mx - mn, 1.0)
-    return (G - mean) / rng
+    return np.clip((G - mean) / rng, -CLIP, CLIP)
 
 
 def bf16(x):

@@ -414,6 +414,7 @@ int setup_geometry(qeq_plan* pl, const double* pos, const double* sigma, const d
 int cg_run(qeq_plan* pl, const double* q0, double* q_out, double* energies, double* forces_out,
            bool* conv_out) {
     const int* done = &pl->sc->done;
+    pl->warm_rejected = false;
     // initial guess (projected onto the constraint plane)
     QEQ_TRY(launch_cg_init_q(pl, q0));
     const int chunk = 8;
@@ -431,6 +432,25 @@ int cg_run(qeq_plan* pl, const double* q0, double* q_out, double* energies, doub
         QEQ_TRY(launch_interp(pl, pl->q, pl->y, QEQ_MODE_CG, 0));
         QEQ_TRY(launch_cg_init_r(pl));
         QEQ_TRY(launch_cg_dir(pl, 1, 1));
+        if (restart == 0 && q0) {
+            // A supplied guess is kept only if it starts closer to the solution
+            // than the cold start in the energy norm that CG minimises: for
+            // Q_tot = 0 the cold start q = 0 has energy 0, so a guess with
+            // E(q0) = 1/2 q0.A q0 + chi_eff.q0 >= 0 is replaced; for charged
+            // cells the relative residual (1 for the cold start) decides.
+            QEQ_TRY(launch_start_energy(pl));
+            QEQ_HIP(hipMemcpyAsync(pl->sc_host, pl->sc, sizeof(CgScalars), hipMemcpyDeviceToHost, pl->stream));
+            QEQ_HIP(hipStreamSynchronize(pl->stream));
+            const bool worse = pl->kp.q_tot == 0.0 ? !(pl->sc_host->e_start < 0.0) : !(pl->sc_host->res <= 1.0);
+            if (worse) {
+                pl->warm_rejected = true;
+                QEQ_TRY(launch_cg_init_q(pl, nullptr));
+                QEQ_TRY(launch_mesh_potential(pl, pl->q, done));
+                QEQ_TRY(launch_interp(pl, pl->q, pl->y, QEQ_MODE_CG, 0));
+                QEQ_TRY(launch_cg_init_r(pl));
+                QEQ_TRY(launch_cg_dir(pl, 1, 1));
+            }
+        }
         conv = false;
         int local = 0;
         while (it < pl->prm.max_iter) {
@@ -483,6 +503,8 @@ int cg_status(qeq_plan* pl, bool conv, qeq_stats* stats) {
         stats->mu = pl->out_host[2];
         stats->e_qeq = pl->out_host[0];
         stats->e_elec = pl->out_host[1];
+        stats->q0_rejected = pl->warm_rejected ? 1 : 0;
+        stats->reserved = 0;
     }
     return status;
 }

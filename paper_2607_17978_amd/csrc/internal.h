@@ -61,6 +61,7 @@ struct CgScalars {
     double dinv_sum;          // sum 1 / D
     double res;               // relative residual after the last update
     double alpha;             // step length of the current iteration
+    double e_start;           // energy of a supplied starting point (constraint plane)
     int iters;
     int done;
     int err;                  // QEQ_ERRBIT_*
@@ -167,6 +168,7 @@ struct qeq_plan {
 
     KParams kp;
     bool tape_valid = false;
+    bool warm_rejected = false;   // the last solve discarded its q0
 
     // per-stage timers
     unsigned prof_mask = 0;
@@ -229,6 +231,7 @@ int launch_write_green(qeq_plan* pl);
 int launch_interp(qeq_plan* pl, const double* src, double* dst, int mode, int parity);
 int launch_cg_init_q(qeq_plan* pl, const double* q0);
 int launch_cg_init_r(qeq_plan* pl);
+int launch_start_energy(qeq_plan* pl);
 int launch_cg_update(qeq_plan* pl, int parity);
 int launch_cg_dir(qeq_plan* pl, int parity, int init);
 int launch_final(qeq_plan* pl, double* q_out, double* energies, double* forces_out);

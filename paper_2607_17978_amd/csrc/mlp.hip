@@ -37,6 +37,7 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 #define MLP_NF 16
 #define MLP_MAXSP 4
 #define MLP_BLOCKS 256          // blocks of the training kernel (partial gradients)
+#define MLP_CLIP 1.5f           // scaled features are clipped to [-1.5, 1.5]
 
 __device__ __forceinline__ short f2bf(float x) {   // round to nearest even
     unsigned u = __float_as_uint(x);
@@ -234,7 +235,10 @@ __global__ __launch_bounds__(256) void k_mlp(const float* __restrict__ G, const 
             float4 gv = mine ? *reinterpret_cast<const float4*>(G + (size_t)a * MLP_NF + 4 * g)
                              : make_float4(0.f, 0.f, 0.f, 0.f);
             const float gx[4] = {gv.x, gv.y, gv.z, gv.w};
-            for (int j = 0; j < 4; ++j) xb[j] = mine ? f2bf((gx[j] - R.mean[j]) * R.inv_rng[j]) : (short)0;
+            // extrapolation guard: scaled features outside the training range are clipped
+            for (int j = 0; j < 4; ++j)
+                xb[j] = mine ? f2bf(fminf(fmaxf((gx[j] - R.mean[j]) * R.inv_rng[j], -MLP_CLIP), MLP_CLIP))
+                             : (short)0;
             // layer 1
             float h1[2][4];
             s4 hb1[2];

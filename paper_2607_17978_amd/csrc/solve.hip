@@ -192,14 +192,14 @@ __global__ void k_cg_project_q(KParams k, double* __restrict__ q, const double* 
 // r = -(chi_eff + A q) with zero mean (y = A q and its partial sums from the
 // preceding matvec); partial sums of D^-1 r, r^2 / D and r^2.
 __global__ void k_cg_init_r(KParams k, const double* __restrict__ y, const double* __restrict__ chi,
-                            const double* __restrict__ dinv, double* __restrict__ r,
-                            const double* __restrict__ part_in, int nparts, double* __restrict__ part_out,
-                            const CgScalars* __restrict__ sc) {
+                            const double* __restrict__ dinv, const double* __restrict__ q,
+                            double* __restrict__ r, const double* __restrict__ part_in, int nparts,
+                            double* __restrict__ part_out, const CgScalars* __restrict__ sc) {
     double tot[2];
     reduce_strided<2>(part_in, nparts, tot);
     const double shift = (sc->chi_sum + tot[1]) / (double)k.n;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    double acc[3] = {0.0, 0.0, 0.0};
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
     if (i < k.n) {
         const double ri = -chi[i] - y[i] + shift;
         r[i] = ri;
@@ -207,11 +207,24 @@ __global__ void k_cg_init_r(KParams k, const double* __restrict__ y, const doubl
         acc[0] = di * ri;
         acc[1] = di * ri * ri;
         acc[2] = ri * ri;
+        acc[3] = chi[i] * q[i];   // for the energy of the starting point
     }
-    block_sum<3>(acc);
+    block_sum<4>(acc);
     if (threadIdx.x == 0) {
-        for (int t = 0; t < 3; ++t) part_out[blockIdx.x * QEQ_NPART + t] = acc[t];
+        for (int t = 0; t < 4; ++t) part_out[blockIdx.x * QEQ_NPART + t] = acc[t];
     }
+}
+
+// Energy of the starting point on the constraint plane, 1/2 q.(A q) + chi_eff.q
+// (up to a constant that is the same for every feasible q), from the partial
+// sums of the initial matvec (slot 0: q.A q) and of k_cg_init_r (slot 3).
+__global__ void k_start_energy(const double* __restrict__ part_mv, int n_mv, const double* __restrict__ part_r,
+                               int n_r, CgScalars* sc) {
+    double a[2] = {0.0, 0.0};
+    for (int b = threadIdx.x; b < n_mv; b += blockDim.x) a[0] += part_mv[b * QEQ_NPART];
+    for (int b = threadIdx.x; b < n_r; b += blockDim.x) a[1] += part_r[b * QEQ_NPART + 3];
+    block_sum<2>(a);
+    if (threadIdx.x == 0) sc->e_start = 0.5 * a[0] + a[1];
 }
 
 // alpha = r.z / p.A p; q += alpha p; r -= alpha (A p - mean(A p)).
@@ -395,7 +408,13 @@ int launch_cg_init_q(qeq_plan* pl, const double* q0) {
 int launch_cg_init_r(qeq_plan* pl) {
     const int nb = nblocks(pl->kp.n, QEQ_VBLOCK);
     hipLaunchKernelGGL(k_cg_init_r, dim3(nb), dim3(QEQ_VBLOCK), 0, pl->stream, pl->kp, pl->y, pl->chi,
-                       pl->dinv, pl->r, part_buf(pl, 0), interp_blocks(pl->kp.n), part_buf(pl, 1), pl->sc);
+                       pl->dinv, pl->q, pl->r, part_buf(pl, 0), interp_blocks(pl->kp.n), part_buf(pl, 1), pl->sc);
+    return qeq_check(hipGetLastError());
+}
+
+int launch_start_energy(qeq_plan* pl) {
+    hipLaunchKernelGGL(k_start_energy, dim3(1), dim3(QEQ_BLOCK), 0, pl->stream, part_buf(pl, 0),
+                       interp_blocks(pl->kp.n), part_buf(pl, 1), nblocks(pl->kp.n, QEQ_VBLOCK), pl->sc);
     return qeq_check(hipGetLastError());
 }
 

@@ -51,6 +51,8 @@ class Stats(ctypes.Structure):
         ("mu", ctypes.c_double),
         ("e_qeq", ctypes.c_double),
         ("e_elec", ctypes.c_double),
+        ("q0_rejected", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
     def as_dict(self):

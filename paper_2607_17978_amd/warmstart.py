@@ -36,7 +36,8 @@ def run_trajectory(n=None, side=None, spacing=None, frames=200, epochs=30, lr=2e
     pos, cell, species, sigma, J = gen.md_initial(n, side, spacing)
     L = side * spacing
     if grid is None:
-        k = gen.grid_dim(L, 0.8)
+        # the 131,072-atom workload is specified on a 320^3 grid (spacing 0.74)
+        k = 320 if n == gen.MD_N else gen.grid_dim(L, 0.8)
         grid = (k, k, k)
     plan = qeq.Plan(n, eta=2.0, r_cut=11.0, grid=grid, tol=tol, max_iter=3000)
     net = qeq.WarmStartNet(gen.warmstart_init(1005, 2), device=dev)
@@ -83,6 +84,8 @@ def run_trajectory(n=None, side=None, spacing=None, frames=200, epochs=30, lr=2e
                 for ep in range(epochs):
                     for f in order(n_train):
                         loss = net.train_step(train_G[f], sp_d, train_q[f], lr=lr)
+                    if log and (ep % 5 == 0 or ep == epochs - 1):
+                        log(f"epoch {ep}: loss {float(loss.cpu()):.3e}")
                 torch.cuda.synchronize()
                 rec["train_s"] = time.perf_counter() - t0
                 rec["train_loss"] = float(loss.cpu())
@@ -99,13 +102,16 @@ def run_trajectory(n=None, side=None, spacing=None, frames=200, epochs=30, lr=2e
         torch.cuda.synchronize()
         t_pred.append((time.perf_counter() - t0) * 1e3)
         q_l, st_l, ms_l = solve(posd, chid, q0=q0)
-        max_dq = max(max_dq, float((q_p - q_c).abs().max()), float((q_l - q_c).abs().max()))
+        dq_p, dq_l = float((q_p - q_c).abs().max()), float((q_l - q_c).abs().max())
+        max_dq = max(max_dq, dq_p, dq_l)
         for k, st, ms in (("cold", st_c, ms_c), ("prev", st_p, ms_p), ("learned", st_l, ms_l)):
-            rec[k].append((st["iters"], ms, st["rc"]))
+            rec[k].append((st["iters"], ms, st["rc"], st["q0_rejected"]))
         q_prev = q_c
         if log:
             log(f"frame {t}: iters cold {st_c['iters']} prev {st_p['iters']} learned {st_l['iters']}; "
-                f"ms {ms_c:.1f} / {ms_p:.1f} / {ms_l:.1f}")
+                f"ms {ms_c:.1f} / {ms_p:.1f} / {ms_l:.1f}; max|dq| prev {dq_p:.1e} learned {dq_l:.1e}; "
+                f"|q0 - q| learned max {float((q0 - q_c).abs().max()):.2e} "
+                f"rms {float((q0 - q_c).pow(2).mean().sqrt()):.2e}")
     plan.close()
     out = {"n": n, "grid": list(grid), "frames": frames, "train_frames": n_train,
            "max_dq_vs_cold": max_dq, "descriptor_ms": float(np.mean(t_desc)),
@@ -115,5 +121,5 @@ def run_trajectory(n=None, side=None, spacing=None, frames=200, epochs=30, lr=2e
     for k in ("cold", "prev", "learned"):
         a = np.array(rec[k], dtype=float)
         out[k] = {"iters": float(a[:, 0].mean()), "ms": float(a[:, 1].mean()),
-                  "all_converged": bool((a[:, 2] == 0).all())}
+                  "all_converged": bool((a[:, 2] == 0).all()), "q0_rejected": int(a[:, 3].sum())}
     return out
