@@ -141,6 +141,50 @@ int qeq_matvec(qeq_plan* plan, int32_t n, const double* pos, const double* cell,
                const double* sigma, const double* v, double* y, int32_t parts);
 
 /* ------------------------------------------------------------------------
+   Batched solve: many independent structures in one persistent launch.
+   ------------------------------------------------------------------------ */
+
+#define QEQ_BATCH_NMAX 1024   /* largest structure of the batched path */
+
+/* Solve eq. 4G_qeq_prime for n_struct independent periodic structures of
+   uneven size (the paper treats structures independently and distributes them
+   over ranks; here one launch with one workgroup per structure at a time, the
+   order longest first).  Structure s owns atoms atom_offsets[s] ..
+   atom_offsets[s+1]-1 of the concatenated arrays.
+   atom_offsets (n_struct + 1, HOST, non-decreasing), cells (n_struct x 9,
+   HOST, rows = lattice vectors), q_tot (n_struct, HOST).
+   pos (3 per atom), sigma, J, chi (1 per atom): DEVICE, read-only.
+   q0 (DEVICE, 1 per atom) or NULL: starting charges, treated per structure as
+   in qeq_solve.  q (DEVICE, out), energies (DEVICE, n_struct x 2 =
+   [E_QEq, E_elec], out, or NULL), forces (DEVICE, 3 per atom, out, or NULL),
+   stats (HOST, n_struct, out, or NULL).
+   Each structure gets its own grid from the plan's max_spacing (or the plan's
+   fixed grid), axis lengths up to 128, and at most QEQ_BATCH_NMAX atoms; the
+   plan's eta, r_cut, spline order, tol, max_iter and self_correction apply to
+   all.  Per-structure failures (invalid input or cell: QEQ_EINVAL; too many
+   atoms, unsupported grid or r_cut above 4 perpendicular widths: QEQ_EPLAN)
+   are reported in stats[s].status and do not stop the other structures; such
+   structures leave q, energies and forces unwritten.  The return value is the
+   most negative per-structure status, else QEQ_NOT_CONVERGED if any structure
+   did not converge, else QEQ_OK.  Does not touch the tape of qeq_solve /
+   qeq_backward other than invalidating it. */
+int qeq_solve_batched(qeq_plan* plan, int32_t n_struct, const int32_t* atom_offsets,
+                      const double* pos, const double* cells, const double* sigma,
+                      const double* J, const double* chi, const double* q_tot,
+                      const double* q0, double* q, double* energies, double* forces,
+                      qeq_stats* stats);
+
+/* Launch shape of qeq_solve_batched: threads per workgroup (256, 512 or 1024),
+   the LDS staging buffer of the FFT passes in complex elements (256 ..
+   16384), and resident workgroups per compute unit (1 .. 8).  Does not change
+   results beyond FP32 rounding order.  Defaults 512, 8192, 1. */
+int qeq_batched_config(qeq_plan* plan, int32_t threads, int32_t fft_elems, int32_t wg_per_cu);
+
+/* Milliseconds of the batched kernels (HIP events) accumulated since the
+   last reset; reset != 0 clears the counter. */
+double qeq_batched_last_ms(qeq_plan* plan, int32_t reset);
+
+/* ------------------------------------------------------------------------
    Learned warm start (a small per-element network predicts initial charges).
    ------------------------------------------------------------------------ */
 

@@ -642,6 +642,7 @@ int qeq_plan_destroy(qeq_plan* pl) {
     for (hipEvent_t e : pl->prof_pool) (void)hipEventDestroy(e);
     pl->prof_pool.clear();
     free_grid(pl);
+    batch_free(pl);
     dfree(pl->perm); dfree(pl->key); dfree(pl->frac); dfree(pl->home); dfree(pl->wts); dfree(pl->dwts);
     dfree(pl->sig); dfree(pl->Jv); dfree(pl->chi); dfree(pl->chi_raw); dfree(pl->dself); dfree(pl->dinv);
     dfree(pl->selfgrad); dfree(pl->q); dfree(pl->r); dfree(pl->pvec); dfree(pl->y); dfree(pl->forces_s);

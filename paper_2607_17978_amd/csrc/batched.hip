@@ -1,0 +1,1331 @@
+// Batched particle-mesh QEq: one persistent launch solves many independent
+// periodic structures of uneven size, each with its own cell, grid and total
+// charge.  Structures are independent (the paper distributes them over ranks
+// for training, "Parallelization"), so a workgroup takes the next structure
+// from a device queue (longest-first order chosen on the host) and runs the
+// whole solve for it:
+//   staging, validation and B-spline weights -> the reciprocal self constant
+//   C_eta (double Ewald split) -> the image-aware pair list (two passes, CSR)
+//   -> the Green table and, from its inverse transform, the mesh
+//   self-correction -> projected Jacobi CG on the particle-mesh matvec ->
+//   final energies, mu, true residual and forces (restart on a residual gap).
+// Each workgroup owns one slot of device scratch for its current structure
+// (grids of at most a few MB stay in L2 / Infinity Cache); FFT lines are
+// staged through LDS.  The transform is the full complex 3-D FFT (five passes:
+// axis 3, axis 2, axis 1 forward + Green + inverse, axis 2, axis 3), whose
+// last pass writes the real potential and clears the complex grid for the
+// next spread.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "internal.h"
+
+namespace qeqb {
+
+constexpr int BQ_KAX = 128;     // longest grid axis of a batched structure
+constexpr int BQ_L = 8;         // lanes per atom in the interpolation and pair loops
+constexpr int BQ_NV = 11;       // per-atom FP64 vectors in a slot
+constexpr int BQ_OVERFLOW = 100;   // internal status: pair list did not fit
+
+enum { V_Q = 0, V_R, V_P, V_Y, V_DINV, V_CHI, V_DSELF, V_G, V_J, V_SIG, V_CHIRAW };
+
+struct BAxis {
+    int K, nst, tw_off, bm_off;
+    int radix[QEQ_FFT_MAXST];
+};
+
+// Per-structure constants prepared on the host.
+struct BStruct {
+    int n, off, npts, pad0;
+    BAxis ax[3];
+    int mm[3], nn[3];           // ranges of the C_eta k-space and lattice sums
+    double H[9], Hinv[9], M[6];
+    double vol, green_pref, bg_pref, q_tot, zeta;
+    double rho[3];              // r_cut / perpendicular width, per axis
+};
+
+struct BStat {
+    int status, iters, restarts, q0_rejected;
+    long long nnz;
+    double rel_resid, true_rel_resid, mu, e_qeq, e_elec, pad;
+};
+
+// Byte offsets inside one workgroup's scratch slot.
+struct BSlot {
+    size_t C, R, G, wts, dwts, home, frac, vec, selfgrad, rowcnt, rowptr, col, kval, pdr, tab, bytes;
+};
+
+struct BArgs {
+    int n_work, p, self_corr, max_iter;
+    double tol, eta, rc2, restart_thr;
+    int nmax, fft_elems;
+    long long pcap;
+    BSlot slot;
+    const BStruct* st;
+    const int* order;
+    int* next;
+    const float2* tw;
+    const float* bmod;
+    const double* pos;
+    const double* sigma;
+    const double* J;
+    const double* chi;
+    const double* q0;
+    double* q_out;
+    double* energies;
+    double* forces;
+    BStat* stats;
+    char* scratch;
+};
+
+// Pointers into the current workgroup's slot.
+struct Slot {
+    float2* C;
+    float* R;
+    float* G;
+    float* wts;
+    float* dwts;
+    int* home;
+    double* frac;
+    double* v;          // BQ_NV vectors of nmax doubles
+    double* selfgrad;
+    int* rowcnt;
+    int* rowptr;
+    int* col;
+    float* kval;
+    float4* pdr;
+    double* tab;
+    int nmax;
+    __device__ double* vec(int k) const { return v + (size_t)k * nmax; }
+};
+
+// ------------------------------------------------------------------ reductions
+// Sum of NV doubles over the workgroup, returned to every thread.
+template <int NV>
+__device__ __forceinline__ void wg_sum(double* v) {
+    __shared__ double bc[NV];
+    block_sum<NV>(v);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) bc[k] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = bc[k];
+    __syncthreads();
+}
+
+// Exclusive prefix sum of cnt[0..n) into out[0..n], out[n] = total.
+template <int NT>
+__device__ void wg_scan(const int* cnt, int* out, int n) {
+    __shared__ int part[NT];
+    const int t = threadIdx.x;
+    const int chunk = (n + NT - 1) / NT;
+    const int lo = min(n, t * chunk), hi = min(n, lo + chunk);
+    int s = 0;
+    for (int a = lo; a < hi; ++a) s += cnt[a];
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < NT; off <<= 1) {
+        int v = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int run = part[t] - s;
+    for (int a = lo; a < hi; ++a) {
+        out[a] = run;
+        run += cnt[a];
+    }
+    if (t == NT - 1) out[n] = part[NT - 1];
+    __syncthreads();
+}
+
+// ------------------------------------------------------------------ FFT
+// complex elements one thread holds in an FFT stage
+template <int NT>
+constexpr int bq_emax() { return NT >= 1024 ? 16 : 32; }
+
+// Stockham stage on ncol = 2^cl2 columns; element (k, c) at buf[k ks + c cs].
+template <int R, int NT>
+__device__ __forceinline__ void bq_stage(float2* buf, int K, int Ns, int cl2, int ks, int cs, const float2* tw,
+                                         bool inv, int tid) {
+    constexpr int nt = NT;
+    constexpr int MAXIT = (bq_emax<NT>() + R - 1) / R;
+    const int per = K / R;
+    const int nitems = per << cl2;
+    const int cm = (1 << cl2) - 1;
+    const int step = K / (Ns * R);
+    float2 v[MAXIT][R];
+#pragma unroll
+    for (int it = 0; it < MAXIT; ++it) {
+        const int item = tid + it * nt;
+        if (item < nitems) {
+            const int c = item & cm, j = item >> cl2;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[it][r] = buf[(j + r * per) * ks + c * cs];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < MAXIT; ++it) {
+        const int item = tid + it * nt;
+        if (item < nitems) {
+            const int c = item & cm, j = item >> cl2;
+            const int k = j % Ns;
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                float2 w = tw[k * r * step];
+                if (inv) w.y = -w.y;
+                v[it][r] = cmul(v[it][r], w);
+            }
+            dft<R>(v[it], inv);
+            const int base = (j - k) * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[(base + r * Ns) * ks + c * cs] = v[it][r];
+        }
+    }
+    __syncthreads();
+}
+
+template <int NT>
+__device__ void bq_fft(float2* buf, const BAxis& ax, int cl2, int ks, int cs, const float2* tw, bool inv, int tid) {
+    int Ns = 1;
+    for (int s = 0; s < ax.nst; ++s) {
+        const int R = ax.radix[s];
+        switch (R) {
+            case 2: bq_stage<2, NT>(buf, ax.K, Ns, cl2, ks, cs, tw, inv, tid); break;
+            case 3: bq_stage<3, NT>(buf, ax.K, Ns, cl2, ks, cs, tw, inv, tid); break;
+            case 4: bq_stage<4, NT>(buf, ax.K, Ns, cl2, ks, cs, tw, inv, tid); break;
+            case 5: bq_stage<5, NT>(buf, ax.K, Ns, cl2, ks, cs, tw, inv, tid); break;
+            default: bq_stage<8, NT>(buf, ax.K, Ns, cl2, ks, cs, tw, inv, tid); break;
+        }
+        Ns *= R;
+    }
+}
+
+// Largest power-of-two number of lines that fits the LDS buffer and the
+// per-thread register budget of a stage.
+template <int NT>
+__device__ __forceinline__ int bq_lines_log2(int K, int pad, int elems) {
+    int l = 0;
+    while ((2 << l) * (K + pad) <= elems && (2 << l) * K <= bq_emax<NT>() * NT) ++l;
+    return l;
+}
+
+// Lines along axis 3 (contiguous rows).  Forward: C -> C.  Inverse: the real
+// part goes to R and C is cleared for the next spread.
+template <int NT>
+__device__ void bq_pass3(const BStruct& S, const Slot& sl, float2* buf, const float2* tw, int elems, bool inv,
+                         int tid) {
+    constexpr int nt = NT;
+    const int K = S.ax[2].K;
+    const int nl = S.ax[0].K * S.ax[1].K;
+    const int cl2 = bq_lines_log2<NT>(K, 1, elems);
+    const int ncol = 1 << cl2, cs = K + 1;
+    for (int L0 = 0; L0 < nl; L0 += ncol) {
+        const int cnt = min(ncol, nl - L0);
+        for (int e = tid; e < ncol * K; e += nt) {
+            const int c = e / K, k = e - c * K;
+            buf[c * cs + k] = c < cnt ? sl.C[(size_t)(L0 + c) * K + k] : make_float2(0.f, 0.f);
+        }
+        __syncthreads();
+        bq_fft<NT>(buf, S.ax[2], cl2, 1, cs, tw, inv, tid);
+        for (int e = tid; e < cnt * K; e += nt) {
+            const int c = e / K, k = e - c * K;
+            const size_t g = (size_t)(L0 + c) * K + k;
+            const float2 x = buf[c * cs + k];
+            if (inv) {
+                sl.R[g] = x.x;
+                sl.C[g] = make_float2(0.f, 0.f);
+            } else {
+                sl.C[g] = x;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+#define BQ_FWD 1
+#define BQ_GREEN 2
+#define BQ_INV 4
+
+// Lines along axis 0 (stride K2 K3) or axis 1 (stride K3); consecutive lines
+// are consecutive in memory, so loads and stores of a batch are coalesced.
+// With BQ_GREEN (axis 0 only) the spectrum is multiplied by the Green table
+// between the forward and the inverse transform.
+template <int NT>
+__device__ void bq_pass_strided(const BStruct& S, const Slot& sl, int axis, int mode, float2* buf,
+                                const float2* tw, int elems, int tid) {
+    constexpr int nt = NT;
+    const int K2 = S.ax[1].K, K3 = S.ax[2].K;
+    const int K = S.ax[axis].K;
+    const int inner = axis == 0 ? K2 * K3 : K3;
+    const size_t kstride = axis == 0 ? (size_t)K2 * K3 : (size_t)K3;
+    const size_t ostride = axis == 0 ? 0 : (size_t)K2 * K3;
+    const int nl = axis == 0 ? K2 * K3 : S.ax[0].K * K3;
+    const int cl2 = bq_lines_log2<NT>(K, 0, elems);
+    const int ncol = 1 << cl2, cm = ncol - 1;
+    for (int L0 = 0; L0 < nl; L0 += ncol) {
+        const int cnt = min(ncol, nl - L0);
+        for (int e = tid; e < (K << cl2); e += nt) {
+            const int k = e >> cl2, c = e & cm;
+            float2 x = make_float2(0.f, 0.f);
+            if (c < cnt) {
+                const int L = L0 + c;
+                const int lo = L / inner;
+                x = sl.C[(size_t)lo * ostride + k * kstride + (L - lo * inner)];
+            }
+            buf[e] = x;
+        }
+        __syncthreads();
+        if (mode & BQ_FWD) bq_fft<NT>(buf, S.ax[axis], cl2, ncol, 1, tw, false, tid);
+        if (mode & BQ_GREEN) {
+            for (int e = tid; e < (K << cl2); e += nt) {
+                const int k = e >> cl2, c = e & cm;
+                if (c < cnt) buf[e] = cscale(buf[e], sl.G[k * kstride + L0 + c]);
+            }
+            __syncthreads();
+        }
+        if (mode & BQ_INV) bq_fft<NT>(buf, S.ax[axis], cl2, ncol, 1, tw, true, tid);
+        for (int e = tid; e < (K << cl2); e += nt) {
+            const int k = e >> cl2, c = e & cm;
+            if (c < cnt) {
+                const int L = L0 + c;
+                const int lo = L / inner;
+                sl.C[(size_t)lo * ostride + k * kstride + (L - lo * inner)] = buf[e];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Green's function of the split times the B-spline moduli (SI "Ewald
+// Summation" Gaussian filter, eq. matvec 4 pi / k^2) on the full complex grid:
+// zero at m = 0 and on the Nyquist planes, as in the single-structure path.
+__device__ __forceinline__ float bq_green(const BStruct& S, double eta, int m1, int m2, int m3, const float* b1,
+                                          const float* b2, const float* b3) {
+    const int K1 = S.ax[0].K, K2 = S.ax[1].K, K3 = S.ax[2].K;
+    if ((m1 | m2 | m3) == 0) return 0.f;
+    if (2 * m1 == K1 || 2 * m2 == K2 || 2 * m3 == K3) return 0.f;
+    const double x1 = m1 <= K1 / 2 ? m1 : m1 - K1;
+    const double x2 = m2 <= K2 / 2 ? m2 : m2 - K2;
+    const double x3 = m3 <= K3 / 2 ? m3 : m3 - K3;
+    const double q = S.M[0] * x1 * x1 + S.M[1] * x2 * x2 + S.M[2] * x3 * x3 +
+                     2.0 * (S.M[3] * x1 * x2 + S.M[4] * x1 * x3 + S.M[5] * x2 * x3);
+    const double k2 = 39.478417604357434475 * q;   // (2 pi)^2
+    const double g = S.green_pref * exp(-0.5 * eta * eta * k2) / k2;
+    return (float)g * b1[m1] * b2[m2] * b3[m3];
+}
+
+// ------------------------------------------------------------------ pairs
+// Images n of the pair (i, j) with |x_a + n_a| <= rho_a on every axis, where
+// x = s_j - s_i is wrapped to [-1/2, 1/2], and |r_j + n H - r_i| < r_cut.
+// EMIT writes K, (r_i - r_j(image), K'/r) and j at out[0..).
+template <bool EMIT>
+__device__ __forceinline__ int bq_pair_images(const BStruct& S, const double* si, const double* sj, bool same,
+                                              double rc2, double eta, double gam, int j, int* col, float* kval,
+                                              float4* pdr, long long at, long long cap) {
+    double x[3];
+    int lo[3], hi[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double d = sj[a] - si[a];
+        d -= rint(d);
+        x[a] = d;
+        lo[a] = (int)ceil(-S.rho[a] - d);
+        hi[a] = (int)floor(S.rho[a] - d);
+    }
+    int c = 0;
+    for (int n1 = lo[0]; n1 <= hi[0]; ++n1)
+        for (int n2 = lo[1]; n2 <= hi[1]; ++n2)
+            for (int n3 = lo[2]; n3 <= hi[2]; ++n3) {
+                if (same && n1 == 0 && n2 == 0 && n3 == 0) continue;
+                const double f0 = x[0] + n1, f1 = x[1] + n2, f2 = x[2] + n3;
+                const double dx = f0 * S.H[0] + f1 * S.H[3] + f2 * S.H[6];
+                const double dy = f0 * S.H[1] + f1 * S.H[4] + f2 * S.H[7];
+                const double dz = f0 * S.H[2] + f1 * S.H[5] + f2 * S.H[8];
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                if (r2 >= rc2) continue;
+                if (EMIT && at + c < cap) {
+                    double K, dKr;
+                    pair_kernel(sqrt(r2), gam, eta, &K, &dKr);
+                    col[at + c] = j;
+                    kval[at + c] = (float)K;
+                    pdr[at + c] = make_float4((float)(-dx), (float)(-dy), (float)(-dz), (float)dKr);
+                }
+                ++c;
+            }
+    return c;
+}
+
+// ------------------------------------------------------------------ matvec
+// Reciprocal potential of the vector src (slot vector), left in sl.R:
+// spread (global atomics on the cleared complex grid) and the five FFT passes.
+template <int NT>
+__device__ void bq_mesh(const BStruct& S, const Slot& sl, const double* src, int p, float2* buf,
+                        const float2 (*tws)[BQ_KAX], int elems) {
+    const int tid = threadIdx.x;
+    const int n = S.n, K2 = S.ax[1].K, K3 = S.ax[2].K, K1 = S.ax[0].K;
+    const int pp = p * p;
+    float* Cf = reinterpret_cast<float*>(sl.C);
+    // the clearing stores of the previous pass reach L2 before the atomics
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    for (int t = tid; t < n * pp; t += NT) {
+        const int i = t / pp, rem = t - i * pp;
+        const int k1 = rem / p, k2 = rem - k1 * p;
+        const int h1 = sl.home[4 * i], h2 = sl.home[4 * i + 1], h3 = sl.home[4 * i + 2];
+        const float* w = sl.wts + (size_t)i * 3 * QEQ_MAXP;
+        int g1 = h1 - k1;
+        if (g1 < 0) g1 += K1;
+        int g2 = h2 - k2;
+        if (g2 < 0) g2 += K2;
+        const float a0 = (float)src[i] * w[k1] * w[QEQ_MAXP + k2];
+        float* row = Cf + 2 * ((size_t)g1 * K2 + g2) * K3;
+        for (int k3 = 0; k3 < p; ++k3) {
+            int g3 = h3 - k3;
+            if (g3 < 0) g3 += K3;
+            unsafeAtomicAdd(row + 2 * g3, a0 * w[2 * QEQ_MAXP + k3]);
+        }
+    }
+    // the atomics complete in L2: wait for them, then drop stale L1 lines
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    bq_pass3<NT>(S, sl, buf, tws[2], elems, false, tid);
+    bq_pass_strided<NT>(S, sl, 1, BQ_FWD, buf, tws[1], elems, tid);
+    bq_pass_strided<NT>(S, sl, 0, BQ_FWD | BQ_GREEN | BQ_INV, buf, tws[0], elems, tid);
+    bq_pass_strided<NT>(S, sl, 1, BQ_INV, buf, tws[1], elems, tid);
+    bq_pass3<NT>(S, sl, buf, tws[2], elems, true, tid);
+}
+
+#define BQ_CG 0
+#define BQ_FINAL 2
+
+// y = (E + diag J) src (CG) or y = E src with forces and energy sums (FINAL),
+// from the potential in sl.R and the pair list; BQ_L lanes per atom.
+// CG: sums[0] = src.y, sums[1] = sum y.  FINAL: sums = q.Eq, chi.q, J q^2,
+// sigma^2 q, sum g, with g = E q + J q + chi_eff stored in V_G.
+template <int NT, int MODE>
+__device__ void bq_interp(const BStruct& S, const Slot& sl, const double* src, double* dst, int p, int self_corr,
+                          double* sp, double* forces, double* sums) {
+    constexpr bool FIN = MODE == BQ_FINAL;
+    const int tid = threadIdx.x;
+    const int n = S.n, K1 = S.ax[0].K, K2 = S.ax[1].K, K3 = S.ax[2].K;
+    for (int i = tid; i < n; i += NT) sp[i] = src[i];
+    __syncthreads();
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    const int l = tid & (BQ_L - 1);
+    const double* J = sl.vec(V_J);
+    const double* dself = sl.vec(V_DSELF);
+    for (int ib = 0; ib < n; ib += NT / BQ_L) {
+        const int i = ib + tid / BQ_L;
+        double v[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        if (i < n) {
+            if (l < p) {
+                const int k1 = l;
+                const int h1 = sl.home[4 * i], h2 = sl.home[4 * i + 1], h3 = sl.home[4 * i + 2];
+                const float* w = sl.wts + (size_t)i * 3 * QEQ_MAXP;
+                const float* dw = sl.dwts + (size_t)i * 3 * QEQ_MAXP;
+                int g1 = h1 - k1;
+                if (g1 < 0) g1 += K1;
+                float s = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+                for (int k2 = 0; k2 < p; ++k2) {
+                    int g2 = h2 - k2;
+                    if (g2 < 0) g2 += K2;
+                    const float* row = sl.R + ((size_t)g1 * K2 + g2) * K3;
+                    float t = 0.f, t3 = 0.f;
+                    for (int k3 = 0; k3 < p; ++k3) {
+                        int g3 = h3 - k3;
+                        if (g3 < 0) g3 += K3;
+                        const float gv = row[g3];
+                        t += w[2 * QEQ_MAXP + k3] * gv;
+                        if (FIN) t3 += dw[2 * QEQ_MAXP + k3] * gv;
+                    }
+                    s += w[QEQ_MAXP + k2] * t;
+                    if (FIN) {
+                        s2 += dw[QEQ_MAXP + k2] * t;
+                        s3 += w[QEQ_MAXP + k2] * t3;
+                    }
+                }
+                v[0] = (double)(w[k1] * s);
+                if (FIN) {
+                    s1 = dw[k1] * s;
+                    v[1] = (double)s1;
+                    v[2] = (double)(w[k1] * s2);
+                    v[3] = (double)(w[k1] * s3);
+                }
+            }
+            const int e1 = sl.rowptr[i + 1];
+            for (int e = sl.rowptr[i] + l; e < e1; e += BQ_L) {
+                const double vj = sp[sl.col[e]];
+                v[0] += (double)sl.kval[e] * vj;
+                if (FIN) {
+                    const float4 d = sl.pdr[e];
+                    const double c = (double)d.w * vj;
+                    v[4] += c * d.x;
+                    v[5] += c * d.y;
+                    v[6] += c * d.z;
+                }
+            }
+        }
+        // reduce over the BQ_L lanes of the atom
+#pragma unroll
+        for (int t = 0; t < (FIN ? 7 : 1); ++t) {
+#pragma unroll
+            for (int off = BQ_L / 2; off > 0; off >>= 1) v[t] += __shfl_xor(v[t], off, 64);
+        }
+        if (i < n && l == 0) {
+            const double vi = sp[i];
+            double y = v[0] + dself[i] * vi;
+            if (MODE == BQ_CG) {
+                y += J[i] * vi;
+                acc[0] += vi * y;
+                acc[1] += y;
+            }
+            dst[i] = y;
+            if (FIN) {
+                double du[3] = {v[1], v[2], v[3]};
+                if (self_corr) {
+                    for (int a = 0; a < 3; ++a) du[a] -= 0.5 * vi * sl.selfgrad[3 * i + a];
+                }
+                const double Kd[3] = {(double)K1, (double)K2, (double)K3};
+                if (forces) {
+                    for (int c = 0; c < 3; ++c) {
+                        double g = 0.0;
+                        for (int a = 0; a < 3; ++a) g += Kd[a] * S.Hinv[c * 3 + a] * du[a];
+                        forces[3 * i + c] = -vi * g - vi * v[4 + c];
+                    }
+                }
+                const double Ji = J[i];
+                const double gi = y + Ji * vi + sl.vec(V_CHI)[i];
+                sl.vec(V_G)[i] = gi;
+                const double sg = sl.vec(V_SIG)[i];
+                acc[0] += vi * y;
+                acc[1] += sl.vec(V_CHIRAW)[i] * vi;
+                acc[2] += Ji * vi * vi;
+                acc[3] += sg * sg * vi;
+                acc[4] += gi;
+            }
+        }
+    }
+    wg_sum<5>(acc);
+    for (int t = 0; t < 5; ++t) sums[t] = acc[t];
+}
+
+// ------------------------------------------------------------------ one structure
+template <int NT>
+__device__ void bq_solve(const BArgs& a, const BStruct& S, int s, const Slot& sl, float2* buf, double* sp,
+                         const float2 (*tws)[BQ_KAX], const float (*bms)[BQ_KAX]) {
+    const int tid = threadIdx.x;
+    const int n = S.n, p = a.p;
+    const int K1 = S.ax[0].K, K2 = S.ax[1].K, K3 = S.ax[2].K;
+    const double Q = S.q_tot;
+    __shared__ int err;
+    if (tid == 0) err = 0;
+    __syncthreads();
+
+    // --- staging: validation, fractional coordinates, spline weights, diagonal
+    double acc[2] = {0.0, 0.0};
+    for (int i = tid; i < n; i += NT) {
+        const int o = S.off + i;
+        const double x[3] = {a.pos[3 * o], a.pos[3 * o + 1], a.pos[3 * o + 2]};
+        const double sg = a.sigma[o], jj = a.J[o], ch = a.chi[o];
+        const bool ok = isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]) && isfinite(ch) && sg > 0.0 &&
+                        jj > 0.0 && isfinite(sg) && isfinite(jj);
+        if (!ok) atomicOr(&err, 1);
+        const int Kd[3] = {K1, K2, K3};
+        for (int ax = 0; ax < 3; ++ax) {
+            double v = x[0] * S.Hinv[0 * 3 + ax] + x[1] * S.Hinv[1 * 3 + ax] + x[2] * S.Hinv[2 * 3 + ax];
+            v -= floor(v);
+            if (!(v >= 0.0 && v < 1.0)) v = 0.0;
+            sl.frac[3 * i + ax] = v;
+            const double u = v * (double)Kd[ax];
+            int h = (int)floor(u);
+            h = h < 0 ? 0 : (h >= Kd[ax] ? Kd[ax] - 1 : h);
+            double c[QEQ_MAXP], dc[QEQ_MAXP];
+            bspline_weights<double>(u - (double)h, p, c, dc);
+            for (int k = 0; k < QEQ_MAXP; ++k) {
+                sl.wts[(i * 3 + ax) * QEQ_MAXP + k] = k < p ? (float)c[k] : 0.f;
+                sl.dwts[(i * 3 + ax) * QEQ_MAXP + k] = k < p ? (float)dc[k] : 0.f;
+            }
+            sl.home[4 * i + ax] = h;
+        }
+        const double rsqpi = 0.56418958354775628695;
+        const double ce = ch + S.bg_pref * Q * sg * sg;
+        sl.vec(V_CHI)[i] = ce;
+        sl.vec(V_CHIRAW)[i] = ch;
+        sl.vec(V_SIG)[i] = sg;
+        sl.vec(V_J)[i] = jj;
+        sl.vec(V_DSELF)[i] = rsqpi / sg - 0.79788456080286535588 / a.eta;
+        const double di = 1.0 / (jj + rsqpi / sg);
+        sl.vec(V_DINV)[i] = di;
+        acc[0] += ce;
+        acc[1] += di;
+    }
+    wg_sum<2>(acc);
+    const double chi_sum = acc[0], dinv_sum = acc[1];
+    double nv[1] = {0.0};
+    for (int i = tid; i < n; i += NT) {
+        const double d = sl.vec(V_CHI)[i] - chi_sum / (double)n;
+        nv[0] += d * d;
+    }
+    wg_sum<1>(nv);
+    const double chi_norm = sqrt(nv[0]);
+
+    // --- C_eta = (4 pi / V) sum_{k != 0} exp(-eta^2 k^2 / 2) / k^2 by a second
+    // split of width zeta: k-space sum with zeta plus the lattice sum of the
+    // difference kernel, minus 2 pi (zeta^2 - eta^2) / V
+    double ce_acc[2] = {0.0, 0.0};
+    {
+        const double X = 6.5 * 1.41421356237309504880;
+        const double zeta = S.zeta, eta = a.eta;
+        const double kmax = X / zeta, rmax = X * zeta;
+        const int w1 = 2 * S.mm[0] + 1, w2 = 2 * S.mm[1] + 1, w3 = 2 * S.mm[2] + 1;
+        const int nk = w1 * w2 * w3;
+        for (int t = tid; t < nk; t += NT) {
+            const int m3 = t % w3 - S.mm[2], m2 = (t / w3) % w2 - S.mm[1], m1 = t / (w3 * w2) - S.mm[0];
+            if (!m1 && !m2 && !m3) continue;
+            double k[3];
+            for (int c = 0; c < 3; ++c)
+                k[c] = 6.283185307179586477 * (S.Hinv[c * 3 + 0] * m1 + S.Hinv[c * 3 + 1] * m2 + S.Hinv[c * 3 + 2] * m3);
+            const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+            if (k2 > kmax * kmax) continue;
+            ce_acc[0] += exp(-0.5 * zeta * zeta * k2) / k2;
+        }
+        const int v1 = 2 * S.nn[0] + 1, v2 = 2 * S.nn[1] + 1, v3 = 2 * S.nn[2] + 1;
+        const int nr = v1 * v2 * v3;
+        const double s2 = 0.70710678118654752440;
+        for (int t = tid; t < nr; t += NT) {
+            const int n3 = t % v3 - S.nn[2], n2 = (t / v3) % v2 - S.nn[1], n1 = t / (v3 * v2) - S.nn[0];
+            double x[3];
+            for (int c = 0; c < 3; ++c) x[c] = n1 * S.H[0 * 3 + c] + n2 * S.H[1 * 3 + c] + n3 * S.H[2 * 3 + c];
+            const double r = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+            if (r > rmax) continue;
+            ce_acc[1] += r < 1e-12 ? 0.79788456080286535588 * (1.0 / eta - 1.0 / zeta)
+                                   : (erf(r * s2 / eta) - erf(r * s2 / zeta)) / r;
+        }
+    }
+    wg_sum<2>(ce_acc);
+    const double c_eta = ce_acc[0] * 4.0 * 3.14159265358979323846 / S.vol + ce_acc[1] -
+                         2.0 * 3.14159265358979323846 * (S.zeta * S.zeta - a.eta * a.eta) / S.vol;
+
+    // --- pair list: count, scan, fill (BQ_L lanes per atom, in j order)
+    const int l = tid & (BQ_L - 1);
+    for (int ib = 0; ib < n; ib += NT / BQ_L) {
+        const int i = ib + tid / BQ_L;
+        int cnt = 0;
+        if (i < n) {
+            const double si[3] = {sl.frac[3 * i], sl.frac[3 * i + 1], sl.frac[3 * i + 2]};
+            for (int j = l; j < n; j += BQ_L) {
+                const double sj[3] = {sl.frac[3 * j], sl.frac[3 * j + 1], sl.frac[3 * j + 2]};
+                cnt += bq_pair_images<false>(S, si, sj, i == j, a.rc2, a.eta, 1.0, j, nullptr, nullptr, nullptr, 0,
+                                             0);
+            }
+        }
+#pragma unroll
+        for (int off = BQ_L / 2; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
+        if (i < n && l == 0) sl.rowcnt[i] = cnt;
+    }
+    __syncthreads();
+    wg_scan<NT>(sl.rowcnt, sl.rowptr, n);
+    const long long nnz = sl.rowptr[n];
+    const bool overflow = nnz > a.pcap;
+    if (!overflow) {
+        for (int ib = 0; ib < n; ib += NT / BQ_L) {
+            const int i = ib + tid / BQ_L;
+            if (i < n) {
+                const double si[3] = {sl.frac[3 * i], sl.frac[3 * i + 1], sl.frac[3 * i + 2]};
+                const double sgi = sl.vec(V_SIG)[i];
+                long long cursor = sl.rowptr[i];
+                for (int jb = 0; jb < n; jb += BQ_L) {
+                    const int j = jb + l;
+                    double sj[3] = {0.0, 0.0, 0.0};
+                    int c = 0;
+                    if (j < n) {
+                        sj[0] = sl.frac[3 * j];
+                        sj[1] = sl.frac[3 * j + 1];
+                        sj[2] = sl.frac[3 * j + 2];
+                        c = bq_pair_images<false>(S, si, sj, i == j, a.rc2, a.eta, 1.0, j, nullptr, nullptr, nullptr,
+                                                  0, 0);
+                    }
+                    int incl = c;
+#pragma unroll
+                    for (int d = 1; d < BQ_L; d <<= 1) {
+                        const int y = __shfl_up(incl, d, BQ_L);
+                        if (l >= d) incl += y;
+                    }
+                    const int total = __shfl(incl, BQ_L - 1, BQ_L);
+                    if (c) {
+                        const double sgj = sl.vec(V_SIG)[j];
+                        bq_pair_images<true>(S, si, sj, i == j, a.rc2, a.eta, sqrt(sgi * sgi + sgj * sgj), j, sl.col,
+                                             sl.kval, sl.pdr, cursor + incl - c, a.pcap);
+                    }
+                    cursor += total;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (overflow || err) {
+        if (tid == 0) {
+            BStat& st = a.stats[s];
+            st.status = overflow ? BQ_OVERFLOW : QEQ_EINVAL;
+            st.nnz = nnz;
+            st.iters = 0;
+        }
+        __syncthreads();
+        return;
+    }
+
+    // --- Green table; the inverse transform of the Green spectrum gives the
+    // mesh kernel Theta around the origin for the self-correction
+    const size_t npts = (size_t)S.npts;
+    for (size_t t = tid; t < npts; t += NT) {
+        const int m3 = (int)(t % K3), m2 = (int)((t / K3) % K2), m1 = (int)(t / ((size_t)K3 * K2));
+        const float g = bq_green(S, a.eta, m1, m2, m3, bms[0], bms[1], bms[2]);
+        sl.G[t] = g;
+        sl.C[t] = make_float2(a.self_corr ? g : 0.f, 0.f);
+    }
+    __syncthreads();
+    if (a.self_corr) {
+        bq_pass_strided<NT>(S, sl, 0, BQ_INV, buf, tws[0], a.fft_elems, tid);
+        bq_pass_strided<NT>(S, sl, 1, BQ_INV, buf, tws[1], a.fft_elems, tid);
+        bq_pass3<NT>(S, sl, buf, tws[2], a.fft_elems, true, tid);
+        const int np = 2 * p - 1;
+        for (int t = tid; t < np * np * np; t += NT) {
+            const int d3 = t % np - (p - 1), d2 = (t / np) % np - (p - 1), d1 = t / (np * np) - (p - 1);
+            const int g1 = d1 < 0 ? d1 + K1 : d1, g2 = d2 < 0 ? d2 + K2 : d2, g3 = d3 < 0 ? d3 + K3 : d3;
+            sl.tab[t] = (double)sl.R[((size_t)g1 * K2 + g2) * K3 + g3];
+        }
+        __syncthreads();
+        for (int i = tid; i < n; i += NT) {
+            const double u[3] = {sl.frac[3 * i] * K1, sl.frac[3 * i + 1] * K2, sl.frac[3 * i + 2] * K3};
+            double v, g[3];
+            mesh_self_term(u, p, sl.tab, &v, g);
+            sl.vec(V_DSELF)[i] += c_eta - v;
+            sl.selfgrad[3 * i] = g[0];
+            sl.selfgrad[3 * i + 1] = g[1];
+            sl.selfgrad[3 * i + 2] = g[2];
+        }
+        __syncthreads();
+    }
+
+    // --- projected Jacobi CG (as in the single-structure solver)
+    double* q = sl.vec(V_Q);
+    double* r = sl.vec(V_R);
+    double* pv = sl.vec(V_P);
+    double* y = sl.vec(V_Y);
+    const double* dinv = sl.vec(V_DINV);
+    const double* chi = sl.vec(V_CHI);
+    double* fout = a.forces ? a.forces + 3 * (size_t)S.off : nullptr;
+    bool use_q0 = a.q0 != nullptr;
+    int q0_rejected = 0;
+    {
+        double sq[1] = {0.0};
+        for (int i = tid; i < n; i += NT) {
+            double x = use_q0 ? a.q0[S.off + i] : Q / (double)n;
+            if (!isfinite(x)) x = Q / (double)n;
+            q[i] = x;
+            sq[0] += x;
+        }
+        wg_sum<1>(sq);
+        for (int i = tid; i < n; i += NT) q[i] += (Q - sq[0]) / (double)n;
+        __syncthreads();
+    }
+    const double restart_thr = a.restart_thr;
+    int it = 0, restarts = 0;
+    bool conv = false;
+    double res = 0.0, tres = 0.0, sums[5];
+    double e_qeq = 0.0, e_elec = 0.0, mu = 0.0;
+    for (;;) {
+        double rz = 0.0;
+        bool done = false;
+        for (int attempt = 0; attempt < 2; ++attempt) {
+            bq_mesh<NT>(S, sl, q, p, buf, tws, a.fft_elems);
+            bq_interp<NT, BQ_CG>(S, sl, q, y, p, a.self_corr, sp, nullptr, sums);
+            const double qAq = sums[0];
+            const double shift = (chi_sum + sums[1]) / (double)n;
+            double t4[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int i = tid; i < n; i += NT) {
+                const double ri = -chi[i] - y[i] + shift;
+                r[i] = ri;
+                t4[0] += dinv[i] * ri;
+                t4[1] += dinv[i] * ri * ri;
+                t4[2] += ri * ri;
+                t4[3] += chi[i] * q[i];
+            }
+            wg_sum<4>(t4);
+            const double c = t4[0] / dinv_sum;
+            rz = t4[1] - c * t4[0];
+            res = chi_norm > 0.0 ? sqrt(t4[2]) / chi_norm : sqrt(t4[2]);
+            for (int i = tid; i < n; i += NT) pv[i] = dinv[i] * (r[i] - c);
+            __syncthreads();
+            done = res <= a.tol || !(res == res);
+            if (restarts == 0 && attempt == 0 && use_q0) {
+                const double e_start = 0.5 * qAq + t4[3];
+                const bool worse = Q == 0.0 ? !(e_start < 0.0) : !(res <= 1.0);
+                if (worse) {
+                    q0_rejected = 1;
+                    for (int i = tid; i < n; i += NT) q[i] = Q / (double)n;
+                    __syncthreads();
+                    continue;
+                }
+            }
+            break;
+        }
+        while (!done && it < a.max_iter) {
+            bq_mesh<NT>(S, sl, pv, p, buf, tws, a.fft_elems);
+            bq_interp<NT, BQ_CG>(S, sl, pv, y, p, a.self_corr, sp, nullptr, sums);
+            const double alpha = rz / sums[0];
+            const double ymean = sums[1] / (double)n;
+            double t3[3] = {0.0, 0.0, 0.0};
+            for (int i = tid; i < n; i += NT) {
+                q[i] += alpha * pv[i];
+                const double ri = r[i] - alpha * (y[i] - ymean);
+                r[i] = ri;
+                t3[0] += dinv[i] * ri;
+                t3[1] += dinv[i] * ri * ri;
+                t3[2] += ri * ri;
+            }
+            wg_sum<3>(t3);
+            ++it;
+            const double c = t3[0] / dinv_sum;
+            const double rz_new = t3[1] - c * t3[0];
+            const double beta = rz_new / rz;
+            rz = rz_new;
+            for (int i = tid; i < n; i += NT) pv[i] = dinv[i] * (r[i] - c) + beta * pv[i];
+            __syncthreads();
+            res = chi_norm > 0.0 ? sqrt(t3[2]) / chi_norm : sqrt(t3[2]);
+            done = res <= a.tol || !(res == res);
+        }
+        conv = done;
+        // final matvec on q: energies, mu, true residual, forces
+        bq_mesh<NT>(S, sl, q, p, buf, tws, a.fft_elems);
+        bq_interp<NT, BQ_FINAL>(S, sl, q, y, p, a.self_corr, sp, fout, sums);
+        const double gmean = sums[4] / (double)n;
+        double dv[1] = {0.0};
+        for (int i = tid; i < n; i += NT) {
+            const double d = sl.vec(V_G)[i] - gmean;
+            dv[0] += d * d;
+        }
+        wg_sum<1>(dv);
+        tres = chi_norm > 0.0 ? sqrt(dv[0]) / chi_norm : sqrt(dv[0]);
+        const double S2 = sums[3];
+        const double e_bg = -0.5 * S.bg_pref * (a.eta * a.eta * Q * Q - 2.0 * Q * S2);
+        e_elec = 0.5 * sums[0] + e_bg;
+        e_qeq = e_elec + sums[1] + 0.5 * sums[2];
+        mu = gmean - S.bg_pref * (a.eta * a.eta * Q - S2);
+        const bool gap = !(tres <= restart_thr);
+        if (!conv || !gap || restarts >= 4 || it >= a.max_iter) {
+            if (conv && gap) conv = false;
+            break;
+        }
+        ++restarts;
+    }
+    for (int i = tid; i < n; i += NT) a.q_out[S.off + i] = q[i];
+    if (tid == 0) {
+        BStat& st = a.stats[s];
+        const bool finite = isfinite(e_qeq);
+        st.status = (conv && finite) ? QEQ_OK : QEQ_NOT_CONVERGED;
+        st.iters = it;
+        st.restarts = restarts;
+        st.q0_rejected = q0_rejected;
+        st.nnz = nnz;
+        st.rel_resid = res;
+        st.true_rel_resid = tres;
+        st.mu = mu;
+        st.e_qeq = e_qeq;
+        st.e_elec = e_elec;
+        if (a.energies) {
+            a.energies[2 * s] = e_qeq;
+            a.energies[2 * s + 1] = e_elec;
+        }
+    }
+    __syncthreads();
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_batched(BArgs a) {
+    extern __shared__ float2 fbuf[];
+    double* sp = reinterpret_cast<double*>(fbuf + a.fft_elems);
+    __shared__ BStruct S;
+    __shared__ float2 tws[3][BQ_KAX];
+    __shared__ float bms[3][BQ_KAX];
+    __shared__ int work;
+    const int tid = threadIdx.x;
+    char* base = a.scratch + (size_t)blockIdx.x * a.slot.bytes;
+    Slot sl;
+    sl.C = reinterpret_cast<float2*>(base + a.slot.C);
+    sl.R = reinterpret_cast<float*>(base + a.slot.R);
+    sl.G = reinterpret_cast<float*>(base + a.slot.G);
+    sl.wts = reinterpret_cast<float*>(base + a.slot.wts);
+    sl.dwts = reinterpret_cast<float*>(base + a.slot.dwts);
+    sl.home = reinterpret_cast<int*>(base + a.slot.home);
+    sl.frac = reinterpret_cast<double*>(base + a.slot.frac);
+    sl.v = reinterpret_cast<double*>(base + a.slot.vec);
+    sl.selfgrad = reinterpret_cast<double*>(base + a.slot.selfgrad);
+    sl.rowcnt = reinterpret_cast<int*>(base + a.slot.rowcnt);
+    sl.rowptr = reinterpret_cast<int*>(base + a.slot.rowptr);
+    sl.col = reinterpret_cast<int*>(base + a.slot.col);
+    sl.kval = reinterpret_cast<float*>(base + a.slot.kval);
+    sl.pdr = reinterpret_cast<float4*>(base + a.slot.pdr);
+    sl.tab = reinterpret_cast<double*>(base + a.slot.tab);
+    sl.nmax = a.nmax;
+    for (;;) {
+        if (tid == 0) work = atomicAdd(a.next, 1);
+        __syncthreads();
+        const int w = work;
+        __syncthreads();
+        if (w >= a.n_work) break;   // uniform: every wave of the workgroup leaves here
+        const int s = a.order[w];
+        const int* src = reinterpret_cast<const int*>(a.st + s);
+        int* dst = reinterpret_cast<int*>(&S);
+        for (int t = tid; t < (int)(sizeof(BStruct) / sizeof(int)); t += NT) dst[t] = src[t];
+        __syncthreads();
+        for (int ax = 0; ax < 3; ++ax) {
+            for (int t = tid; t < S.ax[ax].K; t += NT) {
+                tws[ax][t] = a.tw[S.ax[ax].tw_off + t];
+                bms[ax][t] = a.bmod[S.ax[ax].bm_off + t];
+            }
+        }
+        // the grid must start cleared; later matvecs clear it in their last pass
+        for (size_t t = tid; t < (size_t)S.npts; t += NT) sl.C[t] = make_float2(0.f, 0.f);
+        __syncthreads();
+        bq_solve<NT>(a, S, s, sl, fbuf, sp, tws, bms);
+    }
+}
+
+// ------------------------------------------------------------------ host side
+constexpr double PI_H = 3.14159265358979323846;
+
+bool smooth_235_h(int n) {
+    for (int f : {2, 3, 5})
+        while (n % f == 0) n /= f;
+    return n == 1;
+}
+
+bool radix_plan_h(int K, BAxis* ax) {
+    int n = K, ns = 0;
+    while (n % 5 == 0) { ax->radix[ns++] = 5; n /= 5; }
+    while (n % 3 == 0) { ax->radix[ns++] = 3; n /= 3; }
+    while (n % 8 == 0) { ax->radix[ns++] = 8; n /= 8; }
+    if (n == 4) { ax->radix[ns++] = 4; n = 1; }
+    if (n == 2) { ax->radix[ns++] = 2; n = 1; }
+    if (n != 1 || ns > QEQ_FFT_MAXST) return false;
+    ax->nst = ns;
+    ax->K = K;
+    return true;
+}
+
+// |b(m)|^2 of the order-p cardinal B-spline (Essmann et al.), host FP64.
+void bmod_h(int K, int p, float* out) {
+    double c[QEQ_MAXP + 1] = {0};
+    c[1] = 1.0;
+    for (int nn = 3; nn <= p; ++nn) {
+        const double inv = 1.0 / (nn - 1);
+        for (int k = nn - 1; k >= 1; --k) c[k] = (k * c[k] + (nn - k) * c[k - 1]) * inv;
+        c[0] = 0.0;
+    }
+    for (int m = 0; m < K; ++m) {
+        double re = 0.0, im = 0.0;
+        for (int k = 0; k <= p - 2; ++k) {
+            const double ang = 2.0 * PI_H * (double)m * k / K;
+            re += c[k + 1] * cos(ang);
+            im += c[k + 1] * sin(ang);
+        }
+        const double d = re * re + im * im;
+        out[m] = d > 1e-30 ? (float)(1.0 / d) : 0.f;
+    }
+}
+
+void inv3_h(const double* H, double* Hi, double* det) {
+    const double a = H[0], b = H[1], c = H[2], d = H[3], e = H[4], f = H[5], g = H[6], h = H[7], i = H[8];
+    const double A = e * i - f * h, B = -(d * i - f * g), C = d * h - e * g;
+    const double D = -(b * i - c * h), E = a * i - c * g, F = -(a * h - b * g);
+    const double G = b * f - c * e, Hh = -(a * f - c * d), I = a * e - b * d;
+    *det = a * A + b * B + c * C;
+    const double r = 1.0 / *det;
+    Hi[0] = A * r; Hi[1] = D * r; Hi[2] = G * r;
+    Hi[3] = B * r; Hi[4] = E * r; Hi[5] = Hh * r;
+    Hi[6] = C * r; Hi[7] = F * r; Hi[8] = I * r;
+}
+
+template <typename T>
+int grow(T** p, size_t* cap, size_t count) {
+    if (count <= *cap && *p) return QEQ_OK;
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+    *cap = 0;
+    if (hipMalloc((void**)p, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) return QEQ_ENOMEM;
+    *cap = count;
+    return QEQ_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace qeqb
+
+using namespace qeqb;
+
+// Workspace of the batched path, owned by the plan.
+struct BatchState {
+    char* scratch = nullptr;
+    size_t scratch_cap = 0;
+    BStruct* st = nullptr;
+    size_t st_cap = 0;
+    int* order = nullptr;
+    size_t order_cap = 0;
+    int* next = nullptr;
+    size_t next_cap = 0;
+    BStat* stats = nullptr;
+    size_t stats_cap = 0;
+    float2* tw = nullptr;
+    size_t tw_cap = 0;
+    float* bmod = nullptr;
+    size_t bmod_cap = 0;
+    int threads = 512;
+    int fft_elems = 8192;
+    int wg_per_cu = 1;
+    int n_cu = 0;
+    double last_ms = 0.0;
+};
+
+void batch_free(qeq_plan* pl) {
+    BatchState* b = pl->batch;
+    if (!b) return;
+    if (b->scratch) (void)hipFree(b->scratch);
+    if (b->st) (void)hipFree(b->st);
+    if (b->order) (void)hipFree(b->order);
+    if (b->next) (void)hipFree(b->next);
+    if (b->stats) (void)hipFree(b->stats);
+    if (b->tw) (void)hipFree(b->tw);
+    if (b->bmod) (void)hipFree(b->bmod);
+    delete b;
+    pl->batch = nullptr;
+}
+
+namespace {
+
+BatchState* batch_state(qeq_plan* pl) {
+    if (!pl->batch) {
+        pl->batch = new (std::nothrow) BatchState();
+        if (pl->batch) {
+            int cu = 0;
+            if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, pl->dev) != hipSuccess || cu < 1)
+                cu = 256;
+            pl->batch->n_cu = cu;
+        }
+    }
+    return pl->batch;
+}
+
+template <int NT>
+int launch_batched(const BArgs& a, int grid, size_t smem, hipStream_t stream) {
+    auto fn = k_batched<NT>;
+    if (smem > 65536) {
+        QEQ_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+    }
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(NT), smem, stream, a);
+    return qeq_check(hipGetLastError());
+}
+
+int batched_impl(qeq_plan* pl, int n_struct, const int32_t* offs, const double* pos, const double* cells,
+                 const double* sigma, const double* J, const double* chi, const double* q_tot, const double* q0,
+                 double* q, double* energies, double* forces, qeq_stats* stats) {
+    if (n_struct < 1 || !offs || !pos || !cells || !sigma || !J || !chi || !q_tot || !q) return QEQ_EINVAL;
+    for (int s = 0; s < n_struct; ++s)
+        if (offs[s] < 0 || offs[s + 1] < offs[s]) return QEQ_EINVAL;
+    BatchState* b = batch_state(pl);
+    if (!b) return QEQ_ENOMEM;
+    const qeq_params& prm = pl->prm;
+    const int p = prm.spline_order;
+    const double rc = prm.r_cut;
+    std::vector<BStruct> st(n_struct);
+    std::vector<int> hstatus(n_struct, QEQ_OK);
+    std::vector<int> Ks;                    // distinct axis lengths
+    std::vector<double> cost(n_struct, 0.0);
+    int nmax = 1;
+    size_t kmax = 1;
+    long long pcap = 1;
+    for (int s = 0; s < n_struct; ++s) {
+        BStruct& S = st[s];
+        memset(&S, 0, sizeof(S));
+        const int n = offs[s + 1] - offs[s];
+        S.n = n;
+        S.off = offs[s];
+        const double* cell = cells + 9 * (size_t)s;
+        bool ok = n >= 1 && isfinite(q_tot[s]);
+        for (int t = 0; t < 9; ++t) ok = ok && isfinite(cell[t]);
+        double det = 0.0;
+        if (ok) {
+            inv3_h(cell, S.Hinv, &det);
+            ok = det > 0.0 && isfinite(det);
+        }
+        if (!ok) {
+            hstatus[s] = QEQ_EINVAL;
+            continue;
+        }
+        if (n > QEQ_BATCH_NMAX) {
+            hstatus[s] = QEQ_EPLAN;
+            continue;
+        }
+        for (int t = 0; t < 9; ++t) S.H[t] = cell[t];
+        S.vol = det;
+        double Mm[9];
+        for (int x = 0; x < 3; ++x)
+            for (int y = 0; y < 3; ++y) {
+                double v = 0.0;
+                for (int c = 0; c < 3; ++c) v += S.Hinv[c * 3 + x] * S.Hinv[c * 3 + y];
+                Mm[x * 3 + y] = v;
+            }
+        S.M[0] = Mm[0]; S.M[1] = Mm[4]; S.M[2] = Mm[8];
+        S.M[3] = Mm[1]; S.M[4] = Mm[2]; S.M[5] = Mm[5];
+        double widths[3], lengths[3];
+        int K[3];
+        bool gok = true;
+        for (int x = 0; x < 3; ++x) {
+            widths[x] = 1.0 / sqrt(Mm[x * 3 + x]);
+            lengths[x] = sqrt(cell[3 * x] * cell[3 * x] + cell[3 * x + 1] * cell[3 * x + 1] +
+                              cell[3 * x + 2] * cell[3 * x + 2]);
+            if (prm.grid[0] > 0) {
+                K[x] = prm.grid[x];
+            } else {
+                int m = (int)ceil(lengths[x] / prm.max_spacing - 1e-12);
+                m = std::max(m, 12);
+                m = (m + 3) / 4 * 4;
+                while (!smooth_235_h(m)) m += 4;
+                K[x] = m;
+            }
+            gok = gok && K[x] >= 2 * p && K[x] >= 12 && K[x] <= BQ_KAX && K[x] % 4 == 0 &&
+                  radix_plan_h(K[x], &S.ax[x]);
+            S.rho[x] = rc / widths[x];
+            gok = gok && S.rho[x] <= 4.0;
+        }
+        if (!gok) {
+            hstatus[s] = QEQ_EPLAN;
+            continue;
+        }
+        S.npts = K[0] * K[1] * K[2];
+        S.green_pref = 4.0 * PI_H / det;
+        S.bg_pref = 2.0 * PI_H / det;
+        S.q_tot = q_tot[s];
+        // second split for C_eta (same ranges as the single-structure host sum)
+        S.zeta = std::max(prm.eta, 0.3 * cbrt(det));
+        const double X = 6.5 * sqrt(2.0);
+        const double kmx = X / S.zeta, rmx = X * S.zeta;
+        for (int x = 0; x < 3; ++x) {
+            S.mm[x] = (int)ceil(kmx * lengths[x] / (2 * PI_H)) + 1;
+            S.nn[x] = (int)ceil(rmx / widths[x]) + 1;
+        }
+        for (int x = 0; x < 3; ++x)
+            if (std::find(Ks.begin(), Ks.end(), K[x]) == Ks.end()) Ks.push_back(K[x]);
+        nmax = std::max(nmax, n);
+        kmax = std::max(kmax, (size_t)S.npts);
+        // pair capacity: mean neighbour count of a uniform density plus a
+        // generous Poisson tail
+        const double dens = n / det;
+        const double mean = dens * 4.0 / 3.0 * PI_H * rc * rc * rc;
+        const long long row = (long long)ceil(mean + 6.0 * sqrt(mean) + 16.0);
+        pcap = std::max(pcap, (long long)n * std::min<long long>(row, (long long)n * 27));
+        cost[s] = (double)S.npts * 12.0 + (double)n * (216.0 + mean);
+    }
+    // tables for the distinct axis lengths
+    std::vector<float2> twh;
+    std::vector<float> bmh;
+    std::vector<int> tw_off(Ks.size()), bm_off(Ks.size());
+    for (size_t u = 0; u < Ks.size(); ++u) {
+        const int K = Ks[u];
+        tw_off[u] = (int)twh.size();
+        bm_off[u] = (int)bmh.size();
+        for (int j = 0; j < K; ++j) {
+            const double ang = -2.0 * PI_H * (double)j / (double)K;
+            twh.push_back(make_float2((float)cos(ang), (float)sin(ang)));
+        }
+        std::vector<float> bm(K);
+        bmod_h(K, p, bm.data());
+        bmh.insert(bmh.end(), bm.begin(), bm.end());
+    }
+    std::vector<int> work;
+    for (int s = 0; s < n_struct; ++s) {
+        if (hstatus[s] != QEQ_OK) continue;
+        BStruct& S = st[s];
+        for (int x = 0; x < 3; ++x) {
+            const size_t u = std::find(Ks.begin(), Ks.end(), S.ax[x].K) - Ks.begin();
+            S.ax[x].tw_off = tw_off[u];
+            S.ax[x].bm_off = bm_off[u];
+        }
+        work.push_back(s);
+    }
+    // longest first
+    std::stable_sort(work.begin(), work.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+
+    QEQ_TRY(grow(&b->st, &b->st_cap, (size_t)n_struct));
+    QEQ_TRY(grow(&b->stats, &b->stats_cap, (size_t)n_struct));
+    QEQ_TRY(grow(&b->order, &b->order_cap, std::max<size_t>(work.size(), 1)));
+    QEQ_TRY(grow(&b->next, &b->next_cap, (size_t)1));
+    QEQ_TRY(grow(&b->tw, &b->tw_cap, std::max<size_t>(twh.size(), 1)));
+    QEQ_TRY(grow(&b->bmod, &b->bmod_cap, std::max<size_t>(bmh.size(), 1)));
+    hipStream_t stream = pl->stream;
+    QEQ_HIP(hipMemcpyAsync(b->st, st.data(), sizeof(BStruct) * n_struct, hipMemcpyHostToDevice, stream));
+    if (!twh.empty()) {
+        QEQ_HIP(hipMemcpyAsync(b->tw, twh.data(), sizeof(float2) * twh.size(), hipMemcpyHostToDevice, stream));
+        QEQ_HIP(hipMemcpyAsync(b->bmod, bmh.data(), sizeof(float) * bmh.size(), hipMemcpyHostToDevice, stream));
+    }
+    std::vector<BStat> hst(n_struct);
+    memset(hst.data(), 0, sizeof(BStat) * n_struct);
+    for (int s = 0; s < n_struct; ++s) hst[s].status = hstatus[s];
+    QEQ_HIP(hipMemcpyAsync(b->stats, hst.data(), sizeof(BStat) * n_struct, hipMemcpyHostToDevice, stream));
+
+    const int nt = b->threads;
+    const int elems = b->fft_elems;
+    for (int round = 0; round < 2 && !work.empty(); ++round) {
+        BArgs a;
+        memset(&a, 0, sizeof(a));
+        a.p = p;
+        a.self_corr = prm.self_correction;
+        a.max_iter = prm.max_iter;
+        a.tol = prm.tol;
+        a.eta = prm.eta;
+        a.rc2 = rc * rc;
+        a.restart_thr = 2.0 * std::max(prm.tol, 1e-7);
+        a.nmax = nmax;
+        a.fft_elems = elems;
+        a.pcap = pcap;
+        // slot layout
+        BSlot& L = a.slot;
+        size_t o = 0;
+        L.C = o; o = align256(o + sizeof(float2) * kmax);
+        L.R = o; o = align256(o + sizeof(float) * kmax);
+        L.G = o; o = align256(o + sizeof(float) * kmax);
+        L.wts = o; o = align256(o + sizeof(float) * 3 * QEQ_MAXP * nmax);
+        L.dwts = o; o = align256(o + sizeof(float) * 3 * QEQ_MAXP * nmax);
+        L.home = o; o = align256(o + sizeof(int) * 4 * nmax);
+        L.frac = o; o = align256(o + sizeof(double) * 3 * nmax);
+        L.vec = o; o = align256(o + sizeof(double) * BQ_NV * nmax);
+        L.selfgrad = o; o = align256(o + sizeof(double) * 3 * nmax);
+        L.rowcnt = o; o = align256(o + sizeof(int) * nmax);
+        L.rowptr = o; o = align256(o + sizeof(int) * (nmax + 1));
+        L.col = o; o = align256(o + sizeof(int) * pcap);
+        L.kval = o; o = align256(o + sizeof(float) * pcap);
+        L.pdr = o; o = align256(o + sizeof(float4) * pcap);
+        L.tab = o; o = align256(o + sizeof(double) * (2 * QEQ_MAXP - 1) * (2 * QEQ_MAXP - 1) * (2 * QEQ_MAXP - 1));
+        L.bytes = o;
+        const int grid = (int)std::min<size_t>(work.size(), (size_t)b->n_cu * b->wg_per_cu);
+        QEQ_TRY(grow(&b->scratch, &b->scratch_cap, L.bytes * grid));
+        QEQ_HIP(hipMemcpyAsync(b->order, work.data(), sizeof(int) * work.size(), hipMemcpyHostToDevice, stream));
+        QEQ_HIP(hipMemsetAsync(b->next, 0, sizeof(int), stream));
+        a.n_work = (int)work.size();
+        a.st = b->st;
+        a.order = b->order;
+        a.next = b->next;
+        a.tw = b->tw;
+        a.bmod = b->bmod;
+        a.pos = pos;
+        a.sigma = sigma;
+        a.J = J;
+        a.chi = chi;
+        a.q0 = q0;
+        a.q_out = q;
+        a.energies = energies;
+        a.forces = forces;
+        a.stats = b->stats;
+        a.scratch = b->scratch;
+        const size_t smem = sizeof(float2) * (size_t)elems + sizeof(double) * (size_t)nmax;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        (void)hipEventCreate(&e0);
+        (void)hipEventCreate(&e1);
+        if (e0) (void)hipEventRecord(e0, stream);
+        int rc2 = QEQ_EPLAN;
+        if (nt == 256) rc2 = launch_batched<256>(a, grid, smem, stream);
+        else if (nt == 512) rc2 = launch_batched<512>(a, grid, smem, stream);
+        else if (nt == 1024) rc2 = launch_batched<1024>(a, grid, smem, stream);
+        if (e1) (void)hipEventRecord(e1, stream);
+        if (rc2 != QEQ_OK) {
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+            return rc2;
+        }
+        QEQ_HIP(hipMemcpyAsync(hst.data(), b->stats, sizeof(BStat) * n_struct, hipMemcpyDeviceToHost, stream));
+        QEQ_HIP(hipStreamSynchronize(stream));
+        float ms = 0.f;
+        if (e0 && e1 && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) b->last_ms += ms;
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        // structures whose pair list overflowed go again with the measured size
+        std::vector<int> again;
+        long long need = 0;
+        for (int s : work)
+            if (hst[s].status == BQ_OVERFLOW) {
+                again.push_back(s);
+                need = std::max(need, hst[s].nnz);
+            }
+        work.swap(again);
+        pcap = std::max(pcap, need);
+    }
+    int worst = QEQ_OK;
+    for (int s = 0; s < n_struct; ++s) {
+        int code = hst[s].status;
+        if (code == BQ_OVERFLOW) code = QEQ_ENOMEM;
+        if (stats) {
+            qeq_stats& o = stats[s];
+            memset(&o, 0, sizeof(o));
+            o.status = code;
+            o.iters = hst[s].iters;
+            o.rel_resid = hst[s].rel_resid;
+            o.true_rel_resid = hst[s].true_rel_resid;
+            o.mu = hst[s].mu;
+            o.e_qeq = hst[s].e_qeq;
+            o.e_elec = hst[s].e_elec;
+            o.q0_rejected = hst[s].q0_rejected;
+        }
+        if (code < 0) {
+            if (worst >= 0 || code < worst) worst = code;
+        } else if (code > 0 && worst == QEQ_OK) {
+            worst = code;
+        }
+    }
+    return worst;
+}
+
+}  // namespace
+
+extern "C" {
+
+int qeq_solve_batched(qeq_plan* plan, int32_t n_struct, const int32_t* atom_offsets, const double* pos,
+                      const double* cells, const double* sigma, const double* J, const double* chi,
+                      const double* q_tot, const double* q0, double* q, double* energies, double* forces,
+                      qeq_stats* stats) {
+    if (!plan) return QEQ_EINVAL;
+    plan->tape_valid = false;
+    return batched_impl(plan, n_struct, atom_offsets, pos, cells, sigma, J, chi, q_tot, q0, q, energies, forces,
+                        stats);
+}
+
+int qeq_batched_config(qeq_plan* plan, int32_t threads, int32_t fft_elems, int32_t wg_per_cu) {
+    if (!plan) return QEQ_EINVAL;
+    if (threads != 256 && threads != 512 && threads != 1024) return QEQ_EINVAL;
+    if (fft_elems < 2 * BQ_KAX || fft_elems > 16384 || wg_per_cu < 1 || wg_per_cu > 8) return QEQ_EINVAL;
+    if ((size_t)fft_elems * sizeof(float2) + sizeof(double) * QEQ_BATCH_NMAX > 160 * 1024 - 16 * 1024)
+        return QEQ_EINVAL;
+    BatchState* b = batch_state(plan);
+    if (!b) return QEQ_ENOMEM;
+    b->threads = threads;
+    b->fft_elems = fft_elems;
+    b->wg_per_cu = wg_per_cu;
+    return QEQ_OK;
+}
+
+double qeq_batched_last_ms(qeq_plan* plan, int32_t reset) {
+    if (!plan || !plan->batch) return 0.0;
+    const double v = plan->batch->last_ms;
+    if (reset) plan->batch->last_ms = 0.0;
+    return v;
+}
+
+}  // extern "C"

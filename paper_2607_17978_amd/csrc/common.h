@@ -319,6 +319,75 @@ __device__ __forceinline__ void reduce_partials(const double* part, int nparts, 
     __syncthreads();
 }
 
+// ---------------------------------------------------------------------------
+// Real-space pair kernel K(r) = [erf(r/(sqrt2 gamma)) - erf(r/(sqrt2 eta))]/r
+// (the erfc-difference of the Ewald split for Gaussian charges, SI "Ewald
+// Summation"), gamma = sqrt(sigma_i^2 + sigma_j^2), and K'(r)/r for forces.
+// A series replaces the quotient below r = 1e-4 bohr.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void pair_kernel(double r, double gam, double eta, double* K, double* dKr) {
+    const double two_sqrtpi = 1.12837916709551257390;
+    double a = 0.70710678118654752440 / gam, b = 0.70710678118654752440 / eta;
+    if (r < 1e-4) {
+        *K = two_sqrtpi * ((a - b) - (a * a * a - b * b * b) * r * r / 3.0);
+        *dKr = -two_sqrtpi * 2.0 * (a * a * a - b * b * b) / 3.0;
+        return;
+    }
+    double e = erf(a * r) - erf(b * r);
+    double kv = e / r;
+    double d = (two_sqrtpi * (a * exp(-a * a * r * r) - b * exp(-b * b * r * r)) - kv) / r;
+    *K = kv;
+    *dKr = d / r;
+}
+
+// ---------------------------------------------------------------------------
+// Mesh self-interaction of one atom.  The mesh reproduces the reciprocal self
+// term of atom i as theta_i^T Theta theta_i, which depends on where the atom
+// sits inside its grid cell.  With separable spline weights W_a,
+//   theta_i^T Theta theta_i = sum_d Theta(d) R_1(d_1) R_2(d_2) R_3(d_3),
+//   R_a(d) = sum_{k' - k = d} W_a[k] W_a[k'],  |d_a| <= p - 1,
+// where tab holds Theta(d) on the (2p-1)^3 offsets (d_1 slowest).  Returns the
+// value and its derivative with respect to the grid coordinates u_a.
+// ---------------------------------------------------------------------------
+__device__ inline void mesh_self_term(const double* u, int p, const double* __restrict__ tab, double* val,
+                                      double* grad) {
+    const int np = 2 * p - 1;
+    double R[3][2 * QEQ_MAXP - 1], dR[3][2 * QEQ_MAXP - 1];
+    for (int a = 0; a < 3; ++a) {
+        double w = u[a] - floor(u[a]);
+        double c[QEQ_MAXP], dc[QEQ_MAXP];
+        bspline_weights<double>(w, p, c, dc);
+        for (int d = 0; d < np; ++d) {
+            R[a][d] = 0.0;
+            dR[a][d] = 0.0;
+        }
+        for (int k1 = 0; k1 < p; ++k1)
+            for (int k2 = 0; k2 < p; ++k2) {
+                int d = k2 - k1 + (p - 1);
+                R[a][d] += c[k1] * c[k2];
+                dR[a][d] += dc[k1] * c[k2] + c[k1] * dc[k2];
+            }
+    }
+    double s = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0;
+    for (int a = 0; a < np; ++a)
+        for (int b = 0; b < np; ++b) {
+            double t = 0.0, t1 = 0.0;
+            const double* row = tab + (a * np + b) * np;
+            for (int c = 0; c < np; ++c) {
+                t += row[c] * R[2][c];
+                t1 += row[c] * dR[2][c];
+            }
+            s += R[0][a] * R[1][b] * t;
+            g0 += dR[0][a] * R[1][b] * t;
+            g1 += R[0][a] * dR[1][b] * t;
+            g2 += R[0][a] * R[1][b] * t1;
+        }
+    *val = s;
+    grad[0] = g0;
+    grad[1] = g1;
+    grad[2] = g2;
+}
+
 __device__ __forceinline__ int wrap_idx(int i, int K) {
     i %= K;
     return i < 0 ? i + K : i;

@@ -92,6 +92,8 @@ struct DeviceAxes {
     FftAxis ax[3];
 };
 
+struct BatchState;   // workspace of the batched solver (batched.hip)
+
 struct qeq_plan {
     qeq_params prm;
     int n_max = 0;
@@ -170,6 +172,8 @@ struct qeq_plan {
     bool tape_valid = false;
     bool warm_rejected = false;   // the last solve discarded its q0
 
+    BatchState* batch = nullptr;
+
     // per-stage timers
     unsigned prof_mask = 0;
     int cur_it = -1;
@@ -239,6 +243,9 @@ int launch_matvec_io(qeq_plan* pl, const double* v_orig, double* y_orig, int sta
 
 // ------------------------------------------------------------------ adjoint kernels (adjoint.hip)
 int launch_adj_rhs(qeq_plan* pl, const double* dL_dq, double dL_dEelec);
+
+// ------------------------------------------------------------------ batched solver (batched.hip)
+void batch_free(qeq_plan* pl);
 
 // ------------------------------------------------------------------ warm start (mlp.hip)
 int launch_descriptors(qeq_plan* pl, int nf, const double* centers, double width, double rc, float* G);

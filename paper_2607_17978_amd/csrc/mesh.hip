@@ -122,9 +122,11 @@ __global__ __launch_bounds__(NT) void k_spread_r2c(KParams k, FftAxis ax3, const
         for (int item = tid; item < cnt * p; item += NT) {
             const int c = item / p;
             const int k2 = item - c * p;
+            // row of grid point h2 - k2 inside this tile; a tile narrower than
+            // p - 1 rows also sees candidates whose point lies before it
             int r = ch[2 * c] - k2 - g20;
             if (r < 0) r += K2;
-            if (r >= TW) continue;
+            if (r < 0 || r >= TW) continue;
             const float* cwc = cw + c * SPREAD_CW;
             const float a0 = cwc[0] * cwc[1 + k2];
             const int h3 = ch[2 * c + 1];

@@ -210,26 +210,6 @@ __global__ void k_cell_scatter(int n, const int* __restrict__ home, const int* _
     atoms[start[ck] + atomicAdd(&fill[ck], 1)] = s;
 }
 
-// ---------------------------------------------------------------------------
-// Real-space pair kernel K(r) = [erf(r/(sqrt2 gamma)) - erf(r/(sqrt2 eta))]/r
-// over every periodic image within r_cut (the erfc-difference of the Ewald
-// split for Gaussian charges, SI "Ewald Summation").
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void pair_kernel(double r, double gam, double eta, double* K, double* dKr) {
-    const double two_sqrtpi = 1.12837916709551257390;
-    double a = 0.70710678118654752440 / gam, b = 0.70710678118654752440 / eta;
-    if (r < 1e-4) {
-        *K = two_sqrtpi * ((a - b) - (a * a * a - b * b * b) * r * r / 3.0);
-        *dKr = -two_sqrtpi * 2.0 * (a * a * a - b * b * b) / 3.0;
-        return;
-    }
-    double e = erf(a * r) - erf(b * r);
-    double kv = e / r;
-    double d = (two_sqrtpi * (a * exp(-a * a * r * r) - b * exp(-b * b * r * r)) - kv) / r;
-    *K = kv;
-    *dKr = d / r;
-}
-
 template <bool FILL>
 __global__ void k_pairs(KParams k, const double* __restrict__ frac, const int* __restrict__ home,
                         const double* __restrict__ sig, const int* __restrict__ cell_start,
@@ -314,43 +294,14 @@ __global__ void k_selfcorr(KParams k, const double* __restrict__ frac, const dou
                            double* __restrict__ dself, double* __restrict__ selfgrad) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= k.n) return;
-    const int p = k.p, np = 2 * p - 1;
-    int Kd[3] = {k.K1, k.K2, k.K3};
-    double R[3][2 * QEQ_MAXP - 1], dR[3][2 * QEQ_MAXP - 1];
-    for (int a = 0; a < 3; ++a) {
-        double u = frac[3 * i + a] * (double)Kd[a];
-        double w = u - floor(u);
-        double c[QEQ_MAXP], dc[QEQ_MAXP];
-        bspline_weights<double>(w, p, c, dc);
-        for (int d = 0; d < np; ++d) {
-            R[a][d] = 0.0;
-            dR[a][d] = 0.0;
-        }
-        for (int k1 = 0; k1 < p; ++k1)
-            for (int k2 = 0; k2 < p; ++k2) {
-                int d = k2 - k1 + (p - 1);
-                R[a][d] += c[k1] * c[k2];
-                dR[a][d] += dc[k1] * c[k2] + c[k1] * dc[k2];
-            }
-    }
-    double s = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0;
-    for (int a = 0; a < np; ++a)
-        for (int b = 0; b < np; ++b) {
-            double t = 0.0, t1 = 0.0;
-            const double* row = tab + (a * np + b) * np;
-            for (int c = 0; c < np; ++c) {
-                t += row[c] * R[2][c];
-                t1 += row[c] * dR[2][c];
-            }
-            s += R[0][a] * R[1][b] * t;
-            g0 += dR[0][a] * R[1][b] * t;
-            g1 += R[0][a] * dR[1][b] * t;
-            g2 += R[0][a] * R[1][b] * t1;
-        }
+    const double u[3] = {frac[3 * i] * (double)k.K1, frac[3 * i + 1] * (double)k.K2,
+                         frac[3 * i + 2] * (double)k.K3};
+    double s, g[3];
+    mesh_self_term(u, k.p, tab, &s, g);
     dself[i] += k.c_eta - s;
-    selfgrad[3 * i + 0] = g0;
-    selfgrad[3 * i + 1] = g1;
-    selfgrad[3 * i + 2] = g2;
+    selfgrad[3 * i + 0] = g[0];
+    selfgrad[3 * i + 1] = g[1];
+    selfgrad[3 * i + 2] = g[2];
 }
 
 }  // namespace

@@ -107,6 +107,14 @@ def load_library():
     L.mlp_train_step.argtypes = [dp, dp, dp, i32, i32, dp, dp, dp, dp, i32, ctypes.c_float, dp,
                                  ctypes.c_int64, dp, dp, vp]
     L.mlp_train_step.restype = ctypes.c_int
+    L.qeq_solve_batched.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int32), dp, ctypes.POINTER(ctypes.c_double),
+                                    dp, dp, dp, ctypes.POINTER(ctypes.c_double), dp, dp, dp, dp,
+                                    ctypes.POINTER(Stats)]
+    L.qeq_solve_batched.restype = ctypes.c_int
+    L.qeq_batched_config.argtypes = [vp, i32, i32, i32]
+    L.qeq_batched_config.restype = ctypes.c_int
+    L.qeq_batched_last_ms.argtypes = [vp, i32]
+    L.qeq_batched_last_ms.restype = ctypes.c_double
     L.qeq_strerror.argtypes = [ctypes.c_int]
     L.qeq_strerror.restype = ctypes.c_char_p
     _lib = L
@@ -248,6 +256,47 @@ class Plan:
         if rc < 0:
             raise QEqError(rc, strerror(rc))
         return G
+
+    def solve_batched(self, pos, offsets, cells, sigma, J, chi, q_tot, q0=None, forces=True, check=True):
+        """Solve many structures in one persistent launch (see qeq_solve_batched).
+
+        pos (N_tot x 3), sigma, J, chi (N_tot): device float64; offsets: n_struct + 1
+        ints (host); cells: n_struct x 3 x 3 (host); q_tot: n_struct (host).
+        Returns q (N_tot), energies (n_struct x 2), forces (N_tot x 3 or None),
+        a list of per-structure stats dicts and the return code.
+        """
+        import torch
+        off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int32))
+        ns = off.shape[0] - 1
+        ntot = int(off[-1])
+        for name, t, c in (("pos", pos, 3), ("sigma", sigma, None), ("J", J, None), ("chi", chi, None)):
+            _check_dev(name, t, ntot, c, self.device)
+        if q0 is not None:
+            _check_dev("q0", q0, ntot, None, self.device)
+        cl = np.ascontiguousarray(np.asarray(cells, dtype=np.float64).reshape(ns, 9))
+        qt = np.ascontiguousarray(np.asarray(q_tot, dtype=np.float64).reshape(ns))
+        q = torch.zeros(ntot, dtype=torch.float64, device=self.device)
+        en = torch.zeros((ns, 2), dtype=torch.float64, device=self.device)
+        f = torch.zeros((ntot, 3), dtype=torch.float64, device=self.device) if forces else None
+        st = (Stats * ns)()
+        rc = load_library().qeq_solve_batched(
+            self._h, ns, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _ptr(pos),
+            cl.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _ptr(sigma), _ptr(J), _ptr(chi),
+            qt.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _ptr(q0), _ptr(q), _ptr(en), _ptr(f), st)
+        self._last_n = None       # the tape of the last solve is gone
+        if check and rc < 0 and rc != QEQ_EINVAL and rc != QEQ_EPLAN:
+            raise QEqError(rc, strerror(rc))
+        return q, en, f, [st[k].as_dict() for k in range(ns)], rc
+
+    def batched_config(self, threads=512, fft_elems=8192, wg_per_cu=1):
+        """Launch shape of the batched solver (see qeq_batched_config)."""
+        rc = load_library().qeq_batched_config(self._h, int(threads), int(fft_elems), int(wg_per_cu))
+        if rc != QEQ_OK:
+            raise QEqError(rc, strerror(rc))
+
+    def batched_ms(self, reset=True):
+        """Kernel milliseconds of the batched solves since the last reset."""
+        return load_library().qeq_batched_last_ms(self._h, 1 if reset else 0)
 
     PROFILE_KINDS = ("spread_r2c", "fft_rows_fwd", "fft_cols_green", "fft_rows_inv", "c2r",
                      "interp_pairs", "cg_update", "cg_dir", "final")

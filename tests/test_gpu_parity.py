@@ -35,7 +35,9 @@ def T(a, dev):
 
 def systems():
     out = [gen.system_64(), gen.system_512()]
-    for s in (3, 17, 40):
+    # batch 2 has K2 = 36: axis-2 tiles of 4 rows, narrower than the spline
+    # support, with atoms in the first grid rows (regression case of the spread)
+    for s in (2, 3, 17, 40):
         out.append(gen.batch_structure(s))
     return out
 
