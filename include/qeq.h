@@ -159,7 +159,7 @@ int qeq_matvec(qeq_plan* plan, int32_t n, const double* pos, const double* cell,
    [E_QEq, E_elec], out, or NULL), forces (DEVICE, 3 per atom, out, or NULL),
    stats (HOST, n_struct, out, or NULL).
    Each structure gets its own grid from the plan's max_spacing (or the plan's
-   fixed grid), axis lengths up to 128, and at most QEQ_BATCH_NMAX atoms; the
+   fixed grid), axis lengths up to 64, and at most QEQ_BATCH_NMAX atoms; the
    plan's eta, r_cut, spline order, tol, max_iter and self_correction apply to
    all.  Per-structure failures (invalid input or cell: QEQ_EINVAL; too many
    atoms, unsupported grid or r_cut above 4 perpendicular widths: QEQ_EPLAN)
@@ -174,15 +174,24 @@ int qeq_solve_batched(qeq_plan* plan, int32_t n_struct, const int32_t* atom_offs
                       const double* q0, double* q, double* energies, double* forces,
                       qeq_stats* stats);
 
-/* Launch shape of qeq_solve_batched: threads per workgroup (256, 512 or 1024),
-   the LDS staging buffer of the FFT passes in complex elements (256 ..
-   16384), and resident workgroups per compute unit (1 .. 8).  Does not change
-   results beyond FP32 rounding order.  Defaults 512, 8192, 1. */
-int qeq_batched_config(qeq_plan* plan, int32_t threads, int32_t fft_elems, int32_t wg_per_cu);
+/* Launch shape of qeq_solve_batched: threads per workgroup (256, 512 or 1024)
+   and workgroups per compute unit (1 .. 8; the launch has that many per CU,
+   as many as fit run at once).  Does not change results beyond FP32 rounding
+   order.  Defaults 1024, 1. */
+int qeq_batched_config(qeq_plan* plan, int32_t threads, int32_t wg_per_cu);
 
 /* Milliseconds of the batched kernels (HIP events) accumulated since the
    last reset; reset != 0 clears the counter. */
 double qeq_batched_last_ms(qeq_plan* plan, int32_t reset);
+
+/* Per-structure time breakdown of the last qeq_solve_batched call, measured
+   inside the kernel with the GPU's constant 100 MHz clock by each structure's
+   workgroup: us[s * 8 + k] = microseconds in phase k of structure s, k =
+   0 staging / C_eta, 1 pair list, 2 Green table and mesh self-correction,
+   3 spreading, 4 FFT passes, 5 interpolation and pair product, 6 CG vector
+   updates and reductions, 7 total.  us: host, n_struct x 8 doubles.
+   Returns 8, or QEQ_EINVAL if n_struct exceeds the last call's batch. */
+int qeq_batched_phase_us(qeq_plan* plan, int32_t n_struct, double* us);
 
 /* ------------------------------------------------------------------------
    Learned warm start (a small per-element network predicts initial charges).

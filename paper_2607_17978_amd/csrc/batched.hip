@@ -26,7 +26,8 @@
 
 namespace qeqb {
 
-constexpr int BQ_KAX = 128;     // longest grid axis of a batched structure
+constexpr int BQ_KAX = 64;      // longest grid axis of a batched structure
+constexpr int BQ_LDS = 64 * 65;  // complex elements of the FFT staging buffer
 constexpr int BQ_L = 8;         // lanes per atom in the interpolation and pair loops
 constexpr int BQ_NV = 11;       // per-atom FP64 vectors in a slot
 constexpr int BQ_OVERFLOW = 100;   // internal status: pair list did not fit
@@ -40,7 +41,7 @@ struct BAxis {
 
 // Per-structure constants prepared on the host.
 struct BStruct {
-    int n, off, npts, pad0;
+    int n, off, npts, nhalf;     // atoms, first atom, grid points, half-spectrum points
     BAxis ax[3];
     int mm[3], nn[3];           // ranges of the C_eta k-space and lattice sums
     double H[9], Hinv[9], M[6];
@@ -48,10 +49,30 @@ struct BStruct {
     double rho[3];              // r_cut / perpendicular width, per axis
 };
 
+// Phases of the per-structure time breakdown (wall-clock ticks, 100 MHz).
+enum { PH_SETUP = 0, PH_PAIRS, PH_MESHPREP, PH_SPREAD, PH_FFT, PH_INTERP, PH_VEC, PH_COUNT };
+
 struct BStat {
     int status, iters, restarts, q0_rejected;
     long long nnz;
     double rel_resid, true_rel_resid, mu, e_qeq, e_elec, pad;
+    long long ticks[PH_COUNT + 1];
+};
+
+// Accumulates wall-clock ticks per phase in thread 0 (a read of the constant
+// 100 MHz counter; the per-structure totals go to the stats record).
+struct PhaseClock {
+    long long last;
+    long long acc[PH_COUNT];
+    __device__ void start() {
+        last = wall_clock64();
+        for (int k = 0; k < PH_COUNT; ++k) acc[k] = 0;
+    }
+    __device__ void lap(int ph) {
+        const long long t = wall_clock64();
+        acc[ph] += t - last;
+        last = t;
+    }
 };
 
 // Byte offsets inside one workgroup's scratch slot.
@@ -62,7 +83,7 @@ struct BSlot {
 struct BArgs {
     int n_work, p, self_corr, max_iter;
     double tol, eta, rc2, restart_thr;
-    int nmax, fft_elems;
+    int nmax, pad;
     long long pcap;
     BSlot slot;
     const BStruct* st;
@@ -145,106 +166,97 @@ __device__ void wg_scan(const int* cnt, int* out, int n) {
     __syncthreads();
 }
 
-// ------------------------------------------------------------------ FFT
-// complex elements one thread holds in an FFT stage
-template <int NT>
-constexpr int bq_emax() { return NT >= 1024 ? 16 : 32; }
+// ------------------------------------------------------------------ mesh
+// Layouts in the slot: real grid R[g1][g2][g3]; half spectrum
+// C[g1][g2][m3], m3 = 0 .. K3/2 (contiguous), and the Green table G in the
+// same half layout.  One matvec = five passes, each staging lines in LDS:
+//   A  spread + real-to-complex along axis 3 (D whole g1 planes per batch;
+//      two real rows share one complex transform), written as half spectra;
+//   B  axis 2 forward;  C  axis 1 forward, times G, axis 1 inverse;
+//   D  axis 2 inverse;  E  complex-to-real along axis 3 into R.
+// Transforms of the common lengths are compiled for that length (every index
+// folds to constants); other lengths up to BQ_KAX use the runtime transform.
 
-// Stockham stage on ncol = 2^cl2 columns; element (k, c) at buf[k ks + c cs].
-template <int R, int NT>
-__device__ __forceinline__ void bq_stage(float2* buf, int K, int Ns, int cl2, int ks, int cs, const float2* tw,
-                                         bool inv, int tid) {
-    constexpr int nt = NT;
-    constexpr int MAXIT = (bq_emax<NT>() + R - 1) / R;
-    const int per = K / R;
-    const int nitems = per << cl2;
-    const int cm = (1 << cl2) - 1;
-    const int step = K / (Ns * R);
-    float2 v[MAXIT][R];
-#pragma unroll
-    for (int it = 0; it < MAXIT; ++it) {
-        const int item = tid + it * nt;
-        if (item < nitems) {
-            const int c = item & cm, j = item >> cl2;
-#pragma unroll
-            for (int r = 0; r < R; ++r) v[it][r] = buf[(j + r * per) * ks + c * cs];
-        }
+#define BQ_FOR_EACH_LEN(X) X(24) X(32) X(36) X(40) X(48) X(60) X(64)
+
+// lines per LDS batch and row stride of the staging buffer
+template <int KC> constexpr int bq_nc() { return KC ? 64 : 32; }
+template <int KC> constexpr int bq_ks() { return KC ? 65 : 32; }
+
+template <int KC, int NT, bool INV>
+__device__ __forceinline__ void bq_lines_fft(float2* buf, const BAxis& ax, const float2* tw, int tid) {
+    if constexpr (KC > 0) {
+        fft_ct<KC, bq_nc<KC>(), bq_ks<KC>(), NT, INV>(buf, tw, tid);
+    } else {
+        FftAxis f;
+        f.K = ax.K;
+        f.nst = ax.nst;
+        for (int s = 0; s < QEQ_FFT_MAXST; ++s) f.radix[s] = ax.radix[s];
+        f.tw = nullptr;
+        fft_lds(buf, f, 5, tw, INV, tid, NT);
     }
-    __syncthreads();
-#pragma unroll
-    for (int it = 0; it < MAXIT; ++it) {
-        const int item = tid + it * nt;
-        if (item < nitems) {
-            const int c = item & cm, j = item >> cl2;
-            const int k = j % Ns;
-#pragma unroll
-            for (int r = 1; r < R; ++r) {
-                float2 w = tw[k * r * step];
-                if (inv) w.y = -w.y;
-                v[it][r] = cmul(v[it][r], w);
+}
+
+// Pass A: spread src onto planes [g1a, g1a + D) in LDS (atoms binned by h1),
+// real-to-complex transform of the rows along axis 3, half spectra to C.
+template <int K3C, int NT>
+__device__ void bq_passA(const BStruct& S, const Slot& sl, const double* src, int p, float2* buf,
+                         const float2* tw, const int* hstart, const int* order, int tid) {
+    constexpr int NC = bq_nc<K3C>(), KS = bq_ks<K3C>();
+    const int K1 = S.ax[0].K, K2 = S.ax[1].K;
+    const int K3 = K3C ? K3C : S.ax[2].K;
+    const int K3h = K3 / 2 + 1;
+    const int D = max(1, min(2 * NC / K2, K1 - p + 1));
+    float* bf = reinterpret_cast<float*>(buf);
+    const int Dp = D * p;
+    for (int g1a = 0; g1a < K1; g1a += D) {
+        for (int t = tid; t < K3 * KS; t += NT) buf[t] = make_float2(0.f, 0.f);
+        // candidates: h1 in [g1a, g1a + D + p - 1), wrapped
+        const int end = g1a + D + p - 1;
+        const int lo0 = hstart[g1a], hi0 = hstart[min(end, K1)];
+        const int n0 = hi0 - lo0;
+        const int ncand = n0 + (end > K1 ? hstart[end - K1] : 0);
+        __syncthreads();
+        for (int t = tid; t < ncand * Dp; t += NT) {
+            const int c = t / Dp;
+            const int rem = t - c * Dp;
+            const int j = rem / p, k2 = rem - j * p;
+            const int a = c < n0 ? order[lo0 + c] : order[c - n0];
+            int d = sl.home[4 * a] - g1a;
+            if (d < 0) d += K1;
+            const int k1 = d - j;               // grid plane g1a + j = h1 - k1
+            if (k1 < 0 || k1 >= p || g1a + j >= K1) continue;
+            int g2 = sl.home[4 * a + 1] - k2;
+            if (g2 < 0) g2 += K2;
+            const int h3 = sl.home[4 * a + 2];
+            const float* w = sl.wts + (size_t)a * 3 * QEQ_MAXP;
+            const float a0 = (float)src[a] * w[k1] * w[QEQ_MAXP + k2];
+            const int r = j * K2 + g2;
+            float* col = bf + 2 * (r >> 1) + (r & 1);
+            for (int k3 = 0; k3 < p; ++k3) {
+                int g3 = h3 - k3;
+                if (g3 < 0) g3 += K3;
+                atomicAdd(col + 2 * g3 * KS, a0 * w[2 * QEQ_MAXP + k3]);
             }
-            dft<R>(v[it], inv);
-            const int base = (j - k) * R + k;
-#pragma unroll
-            for (int r = 0; r < R; ++r) buf[(base + r * Ns) * ks + c * cs] = v[it][r];
-        }
-    }
-    __syncthreads();
-}
-
-template <int NT>
-__device__ void bq_fft(float2* buf, const BAxis& ax, int cl2, int ks, int cs, const float2* tw, bool inv, int tid) {
-    int Ns = 1;
-    for (int s = 0; s < ax.nst; ++s) {
-        const int R = ax.radix[s];
-        switch (R) {
-            case 2: bq_stage<2, NT>(buf, ax.K, Ns, cl2, ks, cs, tw, inv, tid); break;
-            case 3: bq_stage<3, NT>(buf, ax.K, Ns, cl2, ks, cs, tw, inv, tid); break;
-            case 4: bq_stage<4, NT>(buf, ax.K, Ns, cl2, ks, cs, tw, inv, tid); break;
-            case 5: bq_stage<5, NT>(buf, ax.K, Ns, cl2, ks, cs, tw, inv, tid); break;
-            default: bq_stage<8, NT>(buf, ax.K, Ns, cl2, ks, cs, tw, inv, tid); break;
-        }
-        Ns *= R;
-    }
-}
-
-// Largest power-of-two number of lines that fits the LDS buffer and the
-// per-thread register budget of a stage.
-template <int NT>
-__device__ __forceinline__ int bq_lines_log2(int K, int pad, int elems) {
-    int l = 0;
-    while ((2 << l) * (K + pad) <= elems && (2 << l) * K <= bq_emax<NT>() * NT) ++l;
-    return l;
-}
-
-// Lines along axis 3 (contiguous rows).  Forward: C -> C.  Inverse: the real
-// part goes to R and C is cleared for the next spread.
-template <int NT>
-__device__ void bq_pass3(const BStruct& S, const Slot& sl, float2* buf, const float2* tw, int elems, bool inv,
-                         int tid) {
-    constexpr int nt = NT;
-    const int K = S.ax[2].K;
-    const int nl = S.ax[0].K * S.ax[1].K;
-    const int cl2 = bq_lines_log2<NT>(K, 1, elems);
-    const int ncol = 1 << cl2, cs = K + 1;
-    for (int L0 = 0; L0 < nl; L0 += ncol) {
-        const int cnt = min(ncol, nl - L0);
-        for (int e = tid; e < ncol * K; e += nt) {
-            const int c = e / K, k = e - c * K;
-            buf[c * cs + k] = c < cnt ? sl.C[(size_t)(L0 + c) * K + k] : make_float2(0.f, 0.f);
         }
         __syncthreads();
-        bq_fft<NT>(buf, S.ax[2], cl2, 1, cs, tw, inv, tid);
-        for (int e = tid; e < cnt * K; e += nt) {
-            const int c = e / K, k = e - c * K;
-            const size_t g = (size_t)(L0 + c) * K + k;
-            const float2 x = buf[c * cs + k];
-            if (inv) {
-                sl.R[g] = x.x;
-                sl.C[g] = make_float2(0.f, 0.f);
+        bq_lines_fft<K3C, NT, false>(buf, S.ax[2], tw, tid);
+        const int rows = min(D, K1 - g1a) * K2;
+        float2* Cb = sl.C + (size_t)g1a * K2 * K3h;
+        for (int t = tid; t < rows * K3h; t += NT) {
+            const int r = t / K3h, m = t - r * K3h;
+            const int pr = r >> 1;
+            const float2 Z = buf[m * KS + pr];
+            float2 Zc = buf[(m == 0 ? 0 : K3 - m) * KS + pr];
+            Zc.y = -Zc.y;
+            float2 X;
+            if ((r & 1) == 0) {
+                X = make_float2(0.5f * (Z.x + Zc.x), 0.5f * (Z.y + Zc.y));
             } else {
-                sl.C[g] = x;
+                const float2 dz = csub(Z, Zc);
+                X = make_float2(0.5f * dz.y, -0.5f * dz.x);
             }
+            Cb[t] = X;
         }
         __syncthreads();
     }
@@ -254,59 +266,124 @@ __device__ void bq_pass3(const BStruct& S, const Slot& sl, float2* buf, const fl
 #define BQ_GREEN 2
 #define BQ_INV 4
 
-// Lines along axis 0 (stride K2 K3) or axis 1 (stride K3); consecutive lines
-// are consecutive in memory, so loads and stores of a batch are coalesced.
-// With BQ_GREEN (axis 0 only) the spectrum is multiplied by the Green table
-// between the forward and the inverse transform.
-template <int NT>
-__device__ void bq_pass_strided(const BStruct& S, const Slot& sl, int axis, int mode, float2* buf,
-                                const float2* tw, int elems, int tid) {
-    constexpr int nt = NT;
-    const int K2 = S.ax[1].K, K3 = S.ax[2].K;
-    const int K = S.ax[axis].K;
-    const int inner = axis == 0 ? K2 * K3 : K3;
-    const size_t kstride = axis == 0 ? (size_t)K2 * K3 : (size_t)K3;
-    const size_t ostride = axis == 0 ? 0 : (size_t)K2 * K3;
-    const int nl = axis == 0 ? K2 * K3 : S.ax[0].K * K3;
-    const int cl2 = bq_lines_log2<NT>(K, 0, elems);
-    const int ncol = 1 << cl2, cm = ncol - 1;
-    for (int L0 = 0; L0 < nl; L0 += ncol) {
-        const int cnt = min(ncol, nl - L0);
-        for (int e = tid; e < (K << cl2); e += nt) {
-            const int k = e >> cl2, c = e & cm;
-            float2 x = make_float2(0.f, 0.f);
-            if (c < cnt) {
-                const int L = L0 + c;
-                const int lo = L / inner;
-                x = sl.C[(size_t)lo * ostride + k * kstride + (L - lo * inner)];
-            }
-            buf[e] = x;
+// Passes B / C / D: lines of the half spectrum along axis 1 (AX = 1, stride
+// K3h, lines (g1, m3)) or axis 0 (AX = 0, stride K2 K3h, lines (g2, m3)).
+// Consecutive lines are consecutive in memory: batches load and store
+// coalesced rows, and each thread keeps one line of the batch.
+template <int KC, int NT, int AX>
+__device__ void bq_pass_lines(const BStruct& S, const Slot& sl, int mode, float2* buf, const float2* tw, int tid) {
+    constexpr int NC = bq_nc<KC>(), KS = bq_ks<KC>();
+    constexpr int CL = NC == 64 ? 6 : 5;
+    static_assert(NT % NC == 0, "lines per batch must divide the workgroup");
+    const int K2 = S.ax[1].K, K3h = S.ax[2].K / 2 + 1;
+    const int K = KC ? KC : S.ax[AX].K;
+    const size_t kstride = AX == 0 ? (size_t)K2 * K3h : (size_t)K3h;
+    const int nl = AX == 0 ? K2 * K3h : S.ax[0].K * K3h;
+    const int c = tid & (NC - 1);
+    const int k0 = tid >> CL;
+    constexpr int KSTEP = NT / NC;
+    for (int L0 = 0; L0 < nl; L0 += NC) {
+        const int L = L0 + c;
+        const bool live = L < nl;
+        size_t base = 0;
+        if (AX == 0) {
+            base = (size_t)L;
+        } else {
+            const int g1 = L / K3h;
+            base = (size_t)g1 * K2 * K3h + (L - g1 * K3h);
         }
+        for (int k = k0; k < K; k += KSTEP)
+            buf[k * KS + c] = live ? sl.C[base + k * kstride] : make_float2(0.f, 0.f);
         __syncthreads();
-        if (mode & BQ_FWD) bq_fft<NT>(buf, S.ax[axis], cl2, ncol, 1, tw, false, tid);
+        if (mode & BQ_FWD) bq_lines_fft<KC, NT, false>(buf, S.ax[AX], tw, tid);
         if (mode & BQ_GREEN) {
-            for (int e = tid; e < (K << cl2); e += nt) {
-                const int k = e >> cl2, c = e & cm;
-                if (c < cnt) buf[e] = cscale(buf[e], sl.G[k * kstride + L0 + c]);
+            if (live)
+                for (int k = k0; k < K; k += KSTEP) buf[k * KS + c] = cscale(buf[k * KS + c], sl.G[base + k * kstride]);
+            __syncthreads();
+        }
+        if (mode & BQ_INV) bq_lines_fft<KC, NT, true>(buf, S.ax[AX], tw, tid);
+        if (live)
+            for (int k = k0; k < K; k += KSTEP) sl.C[base + k * kstride] = buf[k * KS + c];
+        __syncthreads();
+    }
+}
+
+// Pass E: complex-to-real along axis 3 into R.  Two rows a, b of half spectra
+// form Z(m) = X_a(m) + i X_b(m) over the full axis (Hermitian extension); the
+// inverse transform returns row a in the real and row b in the imaginary part.
+template <int K3C, int NT>
+__device__ void bq_passE(const BStruct& S, const Slot& sl, float2* buf, const float2* tw, int tid) {
+    constexpr int NC = bq_nc<K3C>(), KS = bq_ks<K3C>();
+    const int K3 = K3C ? K3C : S.ax[2].K;
+    const int K3h = K3 / 2 + 1;
+    const int nrows = S.ax[0].K * S.ax[1].K;
+    const float* bf = reinterpret_cast<const float*>(buf);
+    for (int r0 = 0; r0 < nrows; r0 += 2 * NC) {
+        for (int half = 0; half < 2; ++half) {
+            for (int t = tid; t < NC * K3h; t += NT) {
+                const int pr = t / K3h, m = t - pr * K3h;
+                const int row = r0 + 2 * pr + half;
+                float2 X = row < nrows ? sl.C[(size_t)row * K3h + m] : make_float2(0.f, 0.f);
+                float2 Xm = make_float2(X.x, -X.y);     // conj, for K3 - m
+                if (half) {
+                    X = make_float2(-X.y, X.x);          // i X
+                    Xm = make_float2(-Xm.y, Xm.x);       // i conj(X)
+                    buf[m * KS + pr] = cadd(buf[m * KS + pr], X);
+                    if (m > 0 && 2 * m < K3) buf[(K3 - m) * KS + pr] = cadd(buf[(K3 - m) * KS + pr], Xm);
+                } else {
+                    buf[m * KS + pr] = X;
+                    if (m > 0 && 2 * m < K3) buf[(K3 - m) * KS + pr] = Xm;
+                }
             }
             __syncthreads();
         }
-        if (mode & BQ_INV) bq_fft<NT>(buf, S.ax[axis], cl2, ncol, 1, tw, true, tid);
-        for (int e = tid; e < (K << cl2); e += nt) {
-            const int k = e >> cl2, c = e & cm;
-            if (c < cnt) {
-                const int L = L0 + c;
-                const int lo = L / inner;
-                sl.C[(size_t)lo * ostride + k * kstride + (L - lo * inner)] = buf[e];
-            }
+        bq_lines_fft<K3C, NT, true>(buf, S.ax[2], tw, tid);
+        const int rows = min(2 * NC, nrows - r0);
+        float* Rb = sl.R + (size_t)r0 * K3;
+        for (int t = tid; t < rows * K3; t += NT) {
+            const int r = t / K3, g3 = t - r * K3;
+            Rb[t] = bf[2 * (g3 * KS + (r >> 1)) + (r & 1)];
         }
         __syncthreads();
     }
 }
 
+// Dispatch on the axis length (compile-time transforms for the common ones).
+template <int NT>
+__device__ void bq_A(const BStruct& S, const Slot& sl, const double* src, int p, float2* buf, const float2* tw,
+                     const int* hstart, const int* order, int tid) {
+    switch (S.ax[2].K) {
+#define X(KK) case KK: bq_passA<KK, NT>(S, sl, src, p, buf, tw, hstart, order, tid); return;
+        BQ_FOR_EACH_LEN(X)
+#undef X
+        default: bq_passA<0, NT>(S, sl, src, p, buf, tw, hstart, order, tid);
+    }
+}
+
+template <int NT>
+__device__ void bq_E(const BStruct& S, const Slot& sl, float2* buf, const float2* tw, int tid) {
+    switch (S.ax[2].K) {
+#define X(KK) case KK: bq_passE<KK, NT>(S, sl, buf, tw, tid); return;
+        BQ_FOR_EACH_LEN(X)
+#undef X
+        default: bq_passE<0, NT>(S, sl, buf, tw, tid);
+    }
+}
+
+template <int NT, int AX>
+__device__ void bq_L(const BStruct& S, const Slot& sl, int mode, float2* buf, const float2* tw, int tid) {
+    switch (S.ax[AX].K) {
+#define X(KK) case KK: bq_pass_lines<KK, NT, AX>(S, sl, mode, buf, tw, tid); return;
+        BQ_FOR_EACH_LEN(X)
+#undef X
+        default: bq_pass_lines<0, NT, AX>(S, sl, mode, buf, tw, tid);
+    }
+}
+
 // Green's function of the split times the B-spline moduli (SI "Ewald
-// Summation" Gaussian filter, eq. matvec 4 pi / k^2) on the full complex grid:
-// zero at m = 0 and on the Nyquist planes, as in the single-structure path.
+// Summation" Gaussian filter, eq. matvec 4 pi / k^2) on the half spectrum
+// (m3 <= K3 / 2): zero at m = 0 and on the Nyquist planes, as in the
+// single-structure path.
 __device__ __forceinline__ float bq_green(const BStruct& S, double eta, int m1, int m2, int m3, const float* b1,
                                           const float* b2, const float* b3) {
     const int K1 = S.ax[0].K, K2 = S.ax[1].K, K3 = S.ax[2].K;
@@ -314,7 +391,7 @@ __device__ __forceinline__ float bq_green(const BStruct& S, double eta, int m1, 
     if (2 * m1 == K1 || 2 * m2 == K2 || 2 * m3 == K3) return 0.f;
     const double x1 = m1 <= K1 / 2 ? m1 : m1 - K1;
     const double x2 = m2 <= K2 / 2 ? m2 : m2 - K2;
-    const double x3 = m3 <= K3 / 2 ? m3 : m3 - K3;
+    const double x3 = m3;
     const double q = S.M[0] * x1 * x1 + S.M[1] * x2 * x2 + S.M[2] * x3 * x3 +
                      2.0 * (S.M[3] * x1 * x2 + S.M[4] * x1 * x3 + S.M[5] * x2 * x3);
     const double k2 = 39.478417604357434475 * q;   // (2 pi)^2
@@ -364,44 +441,18 @@ __device__ __forceinline__ int bq_pair_images(const BStruct& S, const double* si
 }
 
 // ------------------------------------------------------------------ matvec
-// Reciprocal potential of the vector src (slot vector), left in sl.R:
-// spread (global atomics on the cleared complex grid) and the five FFT passes.
+// Reciprocal potential of the vector src (slot vector), left in sl.R.
 template <int NT>
 __device__ void bq_mesh(const BStruct& S, const Slot& sl, const double* src, int p, float2* buf,
-                        const float2 (*tws)[BQ_KAX], int elems) {
+                        const float2 (*tws)[BQ_KAX], const int* hstart, const int* order, PhaseClock& clk) {
     const int tid = threadIdx.x;
-    const int n = S.n, K2 = S.ax[1].K, K3 = S.ax[2].K, K1 = S.ax[0].K;
-    const int pp = p * p;
-    float* Cf = reinterpret_cast<float*>(sl.C);
-    // the clearing stores of the previous pass reach L2 before the atomics
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    for (int t = tid; t < n * pp; t += NT) {
-        const int i = t / pp, rem = t - i * pp;
-        const int k1 = rem / p, k2 = rem - k1 * p;
-        const int h1 = sl.home[4 * i], h2 = sl.home[4 * i + 1], h3 = sl.home[4 * i + 2];
-        const float* w = sl.wts + (size_t)i * 3 * QEQ_MAXP;
-        int g1 = h1 - k1;
-        if (g1 < 0) g1 += K1;
-        int g2 = h2 - k2;
-        if (g2 < 0) g2 += K2;
-        const float a0 = (float)src[i] * w[k1] * w[QEQ_MAXP + k2];
-        float* row = Cf + 2 * ((size_t)g1 * K2 + g2) * K3;
-        for (int k3 = 0; k3 < p; ++k3) {
-            int g3 = h3 - k3;
-            if (g3 < 0) g3 += K3;
-            unsafeAtomicAdd(row + 2 * g3, a0 * w[2 * QEQ_MAXP + k3]);
-        }
-    }
-    // the atomics complete in L2: wait for them, then drop stale L1 lines
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    bq_pass3<NT>(S, sl, buf, tws[2], elems, false, tid);
-    bq_pass_strided<NT>(S, sl, 1, BQ_FWD, buf, tws[1], elems, tid);
-    bq_pass_strided<NT>(S, sl, 0, BQ_FWD | BQ_GREEN | BQ_INV, buf, tws[0], elems, tid);
-    bq_pass_strided<NT>(S, sl, 1, BQ_INV, buf, tws[1], elems, tid);
-    bq_pass3<NT>(S, sl, buf, tws[2], elems, true, tid);
+    bq_A<NT>(S, sl, src, p, buf, tws[2], hstart, order, tid);
+    if (tid == 0) clk.lap(PH_SPREAD);
+    bq_L<NT, 1>(S, sl, BQ_FWD, buf, tws[1], tid);
+    bq_L<NT, 0>(S, sl, BQ_FWD | BQ_GREEN | BQ_INV, buf, tws[0], tid);
+    bq_L<NT, 1>(S, sl, BQ_INV, buf, tws[1], tid);
+    bq_E<NT>(S, sl, buf, tws[2], tid);
+    if (tid == 0) clk.lap(PH_FFT);
 }
 
 #define BQ_CG 0
@@ -521,13 +572,18 @@ __device__ void bq_interp(const BStruct& S, const Slot& sl, const double* src, d
 // ------------------------------------------------------------------ one structure
 template <int NT>
 __device__ void bq_solve(const BArgs& a, const BStruct& S, int s, const Slot& sl, float2* buf, double* sp,
-                         const float2 (*tws)[BQ_KAX], const float (*bms)[BQ_KAX]) {
+                         const float2 (*tws)[BQ_KAX], const float (*bms)[BQ_KAX], int* hcnt, int* hstart,
+                         int* order) {
     const int tid = threadIdx.x;
     const int n = S.n, p = a.p;
     const int K1 = S.ax[0].K, K2 = S.ax[1].K, K3 = S.ax[2].K;
     const double Q = S.q_tot;
     __shared__ int err;
-    if (tid == 0) err = 0;
+    PhaseClock clk;
+    if (tid == 0) {
+        err = 0;
+        clk.start();
+    }
     __syncthreads();
 
     // --- staging: validation, fractional coordinates, spline weights, diagonal
@@ -615,6 +671,7 @@ __device__ void bq_solve(const BArgs& a, const BStruct& S, int s, const Slot& sl
     const double c_eta = ce_acc[0] * 4.0 * 3.14159265358979323846 / S.vol + ce_acc[1] -
                          2.0 * 3.14159265358979323846 * (S.zeta * S.zeta - a.eta * a.eta) / S.vol;
 
+    if (tid == 0) clk.lap(PH_SETUP);
     // --- pair list: count, scan, fill (BQ_L lanes per atom, in j order)
     const int l = tid & (BQ_L - 1);
     for (int ib = 0; ib < n; ib += NT / BQ_L) {
@@ -672,6 +729,7 @@ __device__ void bq_solve(const BArgs& a, const BStruct& S, int s, const Slot& sl
         }
     }
     __syncthreads();
+    if (tid == 0) clk.lap(PH_PAIRS);
     if (overflow || err) {
         if (tid == 0) {
             BStat& st = a.stats[s];
@@ -683,20 +741,40 @@ __device__ void bq_solve(const BArgs& a, const BStruct& S, int s, const Slot& sl
         return;
     }
 
-    // --- Green table; the inverse transform of the Green spectrum gives the
+    // --- atoms binned by h1 (the spread pass takes whole g1 planes)
+    if (tid <= K1) hcnt[tid] = 0;
+    __syncthreads();
+    for (int i = tid; i < n; i += NT) atomicAdd(&hcnt[sl.home[4 * i]], 1);
+    __syncthreads();
+    if (tid == 0) {
+        int run = 0;
+        for (int b = 0; b < K1; ++b) {
+            hstart[b] = run;
+            run += hcnt[b];
+            hcnt[b] = 0;
+        }
+        hstart[K1] = run;
+    }
+    __syncthreads();
+    for (int i = tid; i < n; i += NT) {
+        const int b = sl.home[4 * i];
+        order[hstart[b] + atomicAdd(&hcnt[b], 1)] = i;
+    }
+    // --- Green table on the half spectrum; its inverse transform gives the
     // mesh kernel Theta around the origin for the self-correction
-    const size_t npts = (size_t)S.npts;
-    for (size_t t = tid; t < npts; t += NT) {
-        const int m3 = (int)(t % K3), m2 = (int)((t / K3) % K2), m1 = (int)(t / ((size_t)K3 * K2));
+    const int K3h = K3 / 2 + 1;
+    const size_t nhalf = (size_t)S.nhalf;
+    for (size_t t = tid; t < nhalf; t += NT) {
+        const int m3 = (int)(t % K3h), m2 = (int)((t / K3h) % K2), m1 = (int)(t / ((size_t)K3h * K2));
         const float g = bq_green(S, a.eta, m1, m2, m3, bms[0], bms[1], bms[2]);
         sl.G[t] = g;
-        sl.C[t] = make_float2(a.self_corr ? g : 0.f, 0.f);
+        sl.C[t] = make_float2(g, 0.f);
     }
     __syncthreads();
     if (a.self_corr) {
-        bq_pass_strided<NT>(S, sl, 0, BQ_INV, buf, tws[0], a.fft_elems, tid);
-        bq_pass_strided<NT>(S, sl, 1, BQ_INV, buf, tws[1], a.fft_elems, tid);
-        bq_pass3<NT>(S, sl, buf, tws[2], a.fft_elems, true, tid);
+        bq_L<NT, 0>(S, sl, BQ_INV, buf, tws[0], tid);
+        bq_L<NT, 1>(S, sl, BQ_INV, buf, tws[1], tid);
+        bq_E<NT>(S, sl, buf, tws[2], tid);
         const int np = 2 * p - 1;
         for (int t = tid; t < np * np * np; t += NT) {
             const int d3 = t % np - (p - 1), d2 = (t / np) % np - (p - 1), d1 = t / (np * np) - (p - 1);
@@ -716,6 +794,7 @@ __device__ void bq_solve(const BArgs& a, const BStruct& S, int s, const Slot& sl
         __syncthreads();
     }
 
+    if (tid == 0) clk.lap(PH_MESHPREP);
     // --- projected Jacobi CG (as in the single-structure solver)
     double* q = sl.vec(V_Q);
     double* r = sl.vec(V_R);
@@ -747,8 +826,9 @@ __device__ void bq_solve(const BArgs& a, const BStruct& S, int s, const Slot& sl
         double rz = 0.0;
         bool done = false;
         for (int attempt = 0; attempt < 2; ++attempt) {
-            bq_mesh<NT>(S, sl, q, p, buf, tws, a.fft_elems);
+            bq_mesh<NT>(S, sl, q, p, buf, tws, hstart, order, clk);
             bq_interp<NT, BQ_CG>(S, sl, q, y, p, a.self_corr, sp, nullptr, sums);
+            if (tid == 0) clk.lap(PH_INTERP);
             const double qAq = sums[0];
             const double shift = (chi_sum + sums[1]) / (double)n;
             double t4[4] = {0.0, 0.0, 0.0, 0.0};
@@ -780,8 +860,9 @@ __device__ void bq_solve(const BArgs& a, const BStruct& S, int s, const Slot& sl
             break;
         }
         while (!done && it < a.max_iter) {
-            bq_mesh<NT>(S, sl, pv, p, buf, tws, a.fft_elems);
+            bq_mesh<NT>(S, sl, pv, p, buf, tws, hstart, order, clk);
             bq_interp<NT, BQ_CG>(S, sl, pv, y, p, a.self_corr, sp, nullptr, sums);
+            if (tid == 0) clk.lap(PH_INTERP);
             const double alpha = rz / sums[0];
             const double ymean = sums[1] / (double)n;
             double t3[3] = {0.0, 0.0, 0.0};
@@ -803,11 +884,13 @@ __device__ void bq_solve(const BArgs& a, const BStruct& S, int s, const Slot& sl
             __syncthreads();
             res = chi_norm > 0.0 ? sqrt(t3[2]) / chi_norm : sqrt(t3[2]);
             done = res <= a.tol || !(res == res);
+            if (tid == 0) clk.lap(PH_VEC);
         }
         conv = done;
         // final matvec on q: energies, mu, true residual, forces
-        bq_mesh<NT>(S, sl, q, p, buf, tws, a.fft_elems);
+        bq_mesh<NT>(S, sl, q, p, buf, tws, hstart, order, clk);
         bq_interp<NT, BQ_FINAL>(S, sl, q, y, p, a.self_corr, sp, fout, sums);
+        if (tid == 0) clk.lap(PH_INTERP);
         const double gmean = sums[4] / (double)n;
         double dv[1] = {0.0};
         for (int i = tid; i < n; i += NT) {
@@ -842,6 +925,13 @@ __device__ void bq_solve(const BArgs& a, const BStruct& S, int s, const Slot& sl
         st.mu = mu;
         st.e_qeq = e_qeq;
         st.e_elec = e_elec;
+        clk.lap(PH_VEC);
+        long long tot = 0;
+        for (int k = 0; k < PH_COUNT; ++k) {
+            st.ticks[k] = clk.acc[k];
+            tot += clk.acc[k];
+        }
+        st.ticks[PH_COUNT] = tot;
         if (a.energies) {
             a.energies[2 * s] = e_qeq;
             a.energies[2 * s + 1] = e_elec;
@@ -850,10 +940,14 @@ __device__ void bq_solve(const BArgs& a, const BStruct& S, int s, const Slot& sl
     __syncthreads();
 }
 
-template <int NT>
-__global__ __launch_bounds__(NT) void k_batched(BArgs a) {
+// MINB: workgroups per CU the register allocation must allow (1 or 2).
+template <int NT, int MINB>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MINB > 1 ? NT / 256 * MINB : 1)))
+void k_batched(BArgs a) {
     extern __shared__ float2 fbuf[];
-    double* sp = reinterpret_cast<double*>(fbuf + a.fft_elems);
+    double* sp = reinterpret_cast<double*>(fbuf + BQ_LDS);
+    int* order = reinterpret_cast<int*>(sp + a.nmax);
+    __shared__ int hcnt[BQ_KAX + 1], hstart[BQ_KAX + 1];
     __shared__ BStruct S;
     __shared__ float2 tws[3][BQ_KAX];
     __shared__ float bms[3][BQ_KAX];
@@ -894,10 +988,8 @@ __global__ __launch_bounds__(NT) void k_batched(BArgs a) {
                 bms[ax][t] = a.bmod[S.ax[ax].bm_off + t];
             }
         }
-        // the grid must start cleared; later matvecs clear it in their last pass
-        for (size_t t = tid; t < (size_t)S.npts; t += NT) sl.C[t] = make_float2(0.f, 0.f);
         __syncthreads();
-        bq_solve<NT>(a, S, s, sl, fbuf, sp, tws, bms);
+        bq_solve<NT>(a, S, s, sl, fbuf, sp, tws, bms, hcnt, hstart, order);
     }
 }
 
@@ -989,11 +1081,11 @@ struct BatchState {
     size_t tw_cap = 0;
     float* bmod = nullptr;
     size_t bmod_cap = 0;
-    int threads = 512;
-    int fft_elems = 8192;
+    int threads = 1024;
     int wg_per_cu = 1;
     int n_cu = 0;
     double last_ms = 0.0;
+    std::vector<BStat> last_stats;   // per-structure records of the last call
 };
 
 void batch_free(qeq_plan* pl) {
@@ -1025,9 +1117,9 @@ BatchState* batch_state(qeq_plan* pl) {
     return pl->batch;
 }
 
-template <int NT>
+template <int NT, int MINB>
 int launch_batched(const BArgs& a, int grid, size_t smem, hipStream_t stream) {
-    auto fn = k_batched<NT>;
+    auto fn = k_batched<NT, MINB>;
     if (smem > 65536) {
         QEQ_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
     }
@@ -1051,7 +1143,7 @@ int batched_impl(qeq_plan* pl, int n_struct, const int32_t* offs, const double* 
     std::vector<int> Ks;                    // distinct axis lengths
     std::vector<double> cost(n_struct, 0.0);
     int nmax = 1;
-    size_t kmax = 1;
+    size_t kmax = 1, khalf = 1;
     long long pcap = 1;
     for (int s = 0; s < n_struct; ++s) {
         BStruct& S = st[s];
@@ -1112,6 +1204,7 @@ int batched_impl(qeq_plan* pl, int n_struct, const int32_t* offs, const double* 
             continue;
         }
         S.npts = K[0] * K[1] * K[2];
+        S.nhalf = K[0] * K[1] * (K[2] / 2 + 1);
         S.green_pref = 4.0 * PI_H / det;
         S.bg_pref = 2.0 * PI_H / det;
         S.q_tot = q_tot[s];
@@ -1127,6 +1220,7 @@ int batched_impl(qeq_plan* pl, int n_struct, const int32_t* offs, const double* 
             if (std::find(Ks.begin(), Ks.end(), K[x]) == Ks.end()) Ks.push_back(K[x]);
         nmax = std::max(nmax, n);
         kmax = std::max(kmax, (size_t)S.npts);
+        khalf = std::max(khalf, (size_t)S.nhalf);
         // pair capacity: mean neighbour count of a uniform density plus a
         // generous Poisson tail
         const double dens = n / det;
@@ -1183,7 +1277,6 @@ int batched_impl(qeq_plan* pl, int n_struct, const int32_t* offs, const double* 
     QEQ_HIP(hipMemcpyAsync(b->stats, hst.data(), sizeof(BStat) * n_struct, hipMemcpyHostToDevice, stream));
 
     const int nt = b->threads;
-    const int elems = b->fft_elems;
     for (int round = 0; round < 2 && !work.empty(); ++round) {
         BArgs a;
         memset(&a, 0, sizeof(a));
@@ -1195,14 +1288,13 @@ int batched_impl(qeq_plan* pl, int n_struct, const int32_t* offs, const double* 
         a.rc2 = rc * rc;
         a.restart_thr = 2.0 * std::max(prm.tol, 1e-7);
         a.nmax = nmax;
-        a.fft_elems = elems;
         a.pcap = pcap;
         // slot layout
         BSlot& L = a.slot;
         size_t o = 0;
-        L.C = o; o = align256(o + sizeof(float2) * kmax);
+        L.C = o; o = align256(o + sizeof(float2) * khalf);
         L.R = o; o = align256(o + sizeof(float) * kmax);
-        L.G = o; o = align256(o + sizeof(float) * kmax);
+        L.G = o; o = align256(o + sizeof(float) * khalf);
         L.wts = o; o = align256(o + sizeof(float) * 3 * QEQ_MAXP * nmax);
         L.dwts = o; o = align256(o + sizeof(float) * 3 * QEQ_MAXP * nmax);
         L.home = o; o = align256(o + sizeof(int) * 4 * nmax);
@@ -1236,15 +1328,16 @@ int batched_impl(qeq_plan* pl, int n_struct, const int32_t* offs, const double* 
         a.forces = forces;
         a.stats = b->stats;
         a.scratch = b->scratch;
-        const size_t smem = sizeof(float2) * (size_t)elems + sizeof(double) * (size_t)nmax;
+        const size_t smem = sizeof(float2) * (size_t)BQ_LDS + sizeof(double) * (size_t)nmax + sizeof(int) * (size_t)nmax;
         hipEvent_t e0 = nullptr, e1 = nullptr;
         (void)hipEventCreate(&e0);
         (void)hipEventCreate(&e1);
         if (e0) (void)hipEventRecord(e0, stream);
         int rc2 = QEQ_EPLAN;
-        if (nt == 256) rc2 = launch_batched<256>(a, grid, smem, stream);
-        else if (nt == 512) rc2 = launch_batched<512>(a, grid, smem, stream);
-        else if (nt == 1024) rc2 = launch_batched<1024>(a, grid, smem, stream);
+        const bool two = b->wg_per_cu >= 2;
+        if (nt == 256) rc2 = two ? launch_batched<256, 2>(a, grid, smem, stream) : launch_batched<256, 1>(a, grid, smem, stream);
+        else if (nt == 512) rc2 = two ? launch_batched<512, 2>(a, grid, smem, stream) : launch_batched<512, 1>(a, grid, smem, stream);
+        else if (nt == 1024) rc2 = launch_batched<1024, 1>(a, grid, smem, stream);
         if (e1) (void)hipEventRecord(e1, stream);
         if (rc2 != QEQ_OK) {
             if (e0) (void)hipEventDestroy(e0);
@@ -1268,6 +1361,7 @@ int batched_impl(qeq_plan* pl, int n_struct, const int32_t* offs, const double* 
         work.swap(again);
         pcap = std::max(pcap, need);
     }
+    b->last_stats = hst;
     int worst = QEQ_OK;
     for (int s = 0; s < n_struct; ++s) {
         int code = hst[s].status;
@@ -1307,18 +1401,24 @@ int qeq_solve_batched(qeq_plan* plan, int32_t n_struct, const int32_t* atom_offs
                         stats);
 }
 
-int qeq_batched_config(qeq_plan* plan, int32_t threads, int32_t fft_elems, int32_t wg_per_cu) {
+int qeq_batched_config(qeq_plan* plan, int32_t threads, int32_t wg_per_cu) {
     if (!plan) return QEQ_EINVAL;
     if (threads != 256 && threads != 512 && threads != 1024) return QEQ_EINVAL;
-    if (fft_elems < 2 * BQ_KAX || fft_elems > 16384 || wg_per_cu < 1 || wg_per_cu > 8) return QEQ_EINVAL;
-    if ((size_t)fft_elems * sizeof(float2) + sizeof(double) * QEQ_BATCH_NMAX > 160 * 1024 - 16 * 1024)
-        return QEQ_EINVAL;
+    if (wg_per_cu < 1 || wg_per_cu > 8) return QEQ_EINVAL;
     BatchState* b = batch_state(plan);
     if (!b) return QEQ_ENOMEM;
     b->threads = threads;
-    b->fft_elems = fft_elems;
     b->wg_per_cu = wg_per_cu;
     return QEQ_OK;
+}
+
+int qeq_batched_phase_us(qeq_plan* plan, int32_t n_struct, double* us) {
+    if (!plan || !plan->batch || !us || n_struct < 0) return QEQ_EINVAL;
+    const std::vector<BStat>& v = plan->batch->last_stats;
+    if ((size_t)n_struct > v.size()) return QEQ_EINVAL;
+    for (int s = 0; s < n_struct; ++s)
+        for (int k = 0; k <= PH_COUNT; ++k) us[s * (PH_COUNT + 1) + k] = (double)v[s].ticks[k] * 0.01;
+    return PH_COUNT + 1;
 }
 
 double qeq_batched_last_ms(qeq_plan* plan, int32_t reset) {

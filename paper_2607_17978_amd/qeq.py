@@ -111,8 +111,10 @@ def load_library():
                                     dp, dp, dp, ctypes.POINTER(ctypes.c_double), dp, dp, dp, dp,
                                     ctypes.POINTER(Stats)]
     L.qeq_solve_batched.restype = ctypes.c_int
-    L.qeq_batched_config.argtypes = [vp, i32, i32, i32]
+    L.qeq_batched_config.argtypes = [vp, i32, i32]
     L.qeq_batched_config.restype = ctypes.c_int
+    L.qeq_batched_phase_us.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double)]
+    L.qeq_batched_phase_us.restype = ctypes.c_int
     L.qeq_batched_last_ms.argtypes = [vp, i32]
     L.qeq_batched_last_ms.restype = ctypes.c_double
     L.qeq_strerror.argtypes = [ctypes.c_int]
@@ -288,11 +290,21 @@ class Plan:
             raise QEqError(rc, strerror(rc))
         return q, en, f, [st[k].as_dict() for k in range(ns)], rc
 
-    def batched_config(self, threads=512, fft_elems=8192, wg_per_cu=1):
+    def batched_config(self, threads=1024, wg_per_cu=1):
         """Launch shape of the batched solver (see qeq_batched_config)."""
-        rc = load_library().qeq_batched_config(self._h, int(threads), int(fft_elems), int(wg_per_cu))
+        rc = load_library().qeq_batched_config(self._h, int(threads), int(wg_per_cu))
         if rc != QEQ_OK:
             raise QEqError(rc, strerror(rc))
+
+    BATCH_PHASES = ("setup", "pairs", "mesh_prep", "spread", "fft", "interp", "cg_vec", "total")
+
+    def batched_phase_us(self, n_struct):
+        """n_struct x 8 array of per-structure phase microseconds of the last batched call."""
+        buf = (ctypes.c_double * (8 * n_struct))()
+        rc = load_library().qeq_batched_phase_us(self._h, int(n_struct), buf)
+        if rc < 0:
+            raise QEqError(rc, strerror(rc))
+        return np.array(buf[:], dtype=np.float64).reshape(n_struct, 8)
 
     def batched_ms(self, reset=True):
         """Kernel milliseconds of the batched solves since the last reset."""

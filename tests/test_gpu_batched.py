@@ -97,7 +97,7 @@ def test_batched_equals_single_and_split(dev):
     plan.close()
 
 
-@pytest.mark.parametrize("shape", [(256, 4096, 1), (1024, 16384, 1), (512, 2048, 2)])
+@pytest.mark.parametrize("shape", [(256, 2), (1024, 1), (512, 1)])
 def test_batched_launch_shapes_agree(dev, shape):
     from paper_2607_17978_amd import qeq
     structs = [gen.batch_structure(s) for s in range(8)]
