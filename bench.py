@@ -93,9 +93,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tol", type=float, default=1e-6)
-    ap.add_argument("--workload", choices=["cold32k", "warmstart"], default="cold32k",
+    ap.add_argument("--workload", choices=["cold32k", "warmstart", "batch"], default="cold32k",
                     help="cold32k: the default cold-start solve; warmstart: the 131,072-atom "
-                         "trajectory (learned vs cold vs previous-frame start)")
+                         "trajectory (learned vs cold vs previous-frame start); batch: 1,024 "
+                         "structures in one persistent launch vs one launch sequence per structure")
+    ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="MB",
+                    help="only run a plain device copy of this many MB (10 times) and exit: the "
+                         "reference for scaling FETCH_SIZE / WRITE_SIZE counters")
     ap.add_argument("--frames", type=int, default=200)
     ap.add_argument("--epochs", type=int, default=30)
     args = ap.parse_args()
@@ -111,8 +115,19 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.copy_calibration > 0:
+        n = int(args.copy_calibration * 1e6) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(10):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 10}), flush=True)
+        return
     if args.workload == "warmstart":
         return warmstart_main(args, dev)
+    if args.workload == "batch":
+        return batch_main(args, dev)
     s = gen.system_32k()
     T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
     pos, sig, J, chi = T(s.pos), T(s.sigma), T(s.J), T(s.chi)
@@ -123,7 +138,8 @@ def main():
         d = plan.profile_read(reset=True)
         return [d[k][0] for k in KIND_NAMES], [d[k][1] for k in KIND_NAMES]
 
-    # warm-up with every stage timed, to find the dominant kernel
+    # warm-up with every stage timed (kernels launched one by one), to find
+    # the dominant kernel
     plan.profile((1 << 9) - 1)
     st = None
     for _ in range(max(1, args.warmup)):
@@ -132,8 +148,10 @@ def main():
     avg_all = [m / c if c else 0.0 for m, c in zip(ms_all, cnt_all)]
     mesh_kinds = list(range(6))
     dom = max(mesh_kinds, key=lambda k: ms_all[k])
-    # timed region: only the dominant kernel is bracketed with events
-    plan.profile(1 << dom)
+    # timed region: the production path (CG chunks replayed as HIP graphs,
+    # no timers); one untimed solve captures the graph first
+    plan.profile(0)
+    plan.solve(pos, s.cell, sig, J, chi, s.q_tot)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     iters = []
@@ -142,9 +160,19 @@ def main():
         iters.append(st["iters"])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    # the dominant kernel's launch duration: HIP events on the plan's stream
+    # around each of its launches in eager solves right after the timed region
+    # (events recorded inside a replayed graph cannot be read back)
+    plan.profile(1 << dom)
+    te0 = time.perf_counter()
+    n_eager = max(2, args.steps // 3)
+    for _ in range(n_eager):
+        plan.solve(pos, s.cell, sig, J, chi, s.q_tot)
+    torch.cuda.synchronize()
+    ms_eager = (time.perf_counter() - te0) * 1e3 / n_eager
     ms_dom, cnt_dom = prof_read()
     plan.profile(0)
-    ms_step = (t1 - t0) * 1e3 / args.steps
     nnz = None
     # CSR size is not exported; estimate from the cutoff sphere at this density
     nnz = int(round(s.n * 0.01 * 4.0 / 3.0 * np.pi * 11.0 ** 3))
@@ -184,11 +212,133 @@ def main():
             "stage_us": {KIND_NAMES[k]: round(avg_all[k] * 1e3, 3) for k in range(9)},
         },
         "final_stats": {k: st[k] for k in ("iters", "rel_resid", "true_rel_resid", "e_qeq", "e_elec")},
+        "ms_per_step_eager_launches": round(ms_eager, 4),
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
     plan.close()
+
+
+def batch_flops(structs, stats, p=6):
+    """Algorithmic FP32 flops of one batched solve (per structure: matvecs x
+    (real-to-complex 3-D FFT forward and inverse, Green multiply, spreading,
+    interpolation, pair product) + CG vector work)."""
+    tot = 0.0
+    for s, st in zip(structs, stats):
+        K1, K2, K3 = s.grid
+        npts = K1 * K2 * K3
+        nh = K1 * K2 * (K3 // 2 + 1)
+        n = s.n
+        nnz = n * 0.01 * 4.0 / 3.0 * np.pi * 12.0 ** 3
+        mv = 2 * 2.5 * npts * np.log2(npts) + 6 * nh + 4 * n * p ** 3 + 2 * nnz
+        tot += (st["iters"] + 2) * (mv + 20 * n)
+    return tot
+
+
+def cpu_baseline_batch(structs, budget_s=20.0):
+    """The FP64 matrix-free oracle on a bounded sample of the batch: the first
+    structures in order until the budget is spent, scaled to 1,024 by atoms."""
+    from oracle import matfree
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    t_tot, n_done, k = 0.0, 0, 0
+    while k < len(structs) and t_tot < budget_s:
+        s = structs[k]
+        t0 = time.perf_counter()
+        matfree.qeq_matfree(s.pos, s.cell, s.sigma, s.J, s.chi, s.q_tot, tol=1e-6, forces=True)
+        t_tot += time.perf_counter() - t0
+        n_done += s.n
+        k += 1
+    n_all = sum(s.n for s in structs)
+    return {"value": t_tot * n_all / n_done * 1e3, "unit": "ms", "cores": int(threads), "kind": "oracle",
+            "sample": (f"FP64 matrix-free Ewald oracle, projected CG to 1e-6 with forces, on the first "
+                       f"{k} structures ({n_done} atoms, {t_tot:.1f} s), scaled by atom count to the "
+                       f"{len(structs)} structures ({n_all} atoms)")}
+
+
+def batch_main(args, dev):
+    """One JSON line for the batched workload (value = ms per batched solve)."""
+    import torch
+
+    from inputs import gen
+    from paper_2607_17978_amd import qeq
+
+    structs = gen.batch(1024)
+    T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    offs = np.concatenate([[0], np.cumsum([s.n for s in structs])]).astype(np.int32)
+    cat = lambda f: np.concatenate([getattr(s, f) for s in structs])
+    a = dict(pos=T(cat("pos")), offsets=offs, cells=np.stack([s.cell for s in structs]),
+             sigma=T(cat("sigma")), J=T(cat("J")), chi=T(cat("chi")),
+             q_tot=np.array([s.q_tot for s in structs]))
+    rc_cut = 12.0
+    plan = qeq.Plan(512, eta=2.0, r_cut=rc_cut, tol=args.tol, max_iter=2000)
+    for _ in range(max(1, args.warmup)):
+        plan.solve_batched(**a)
+    plan.batched_ms()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        q, en, f, st, rc = plan.solve_batched(**a)
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    kern_ms = plan.batched_ms() / args.steps
+    phase = plan.batched_phase_us(len(structs)).mean(0)
+    # baseline: one launch sequence per structure (qeq_solve), plans cached per grid
+    plans = {}
+    for s in structs:
+        if s.grid not in plans:
+            plans[s.grid] = qeq.Plan(512, eta=2.0, r_cut=rc_cut, grid=s.grid, tol=args.tol, max_iter=2000)
+    dev_in = [(T(s.pos), T(s.sigma), T(s.J), T(s.chi)) for s in structs]
+    for s, d in list(zip(structs, dev_in))[:16]:
+        plans[s.grid].solve(d[0], s.cell, d[1], d[2], d[3], s.q_tot, forces=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq_iters = []
+    for s, d in zip(structs, dev_in):
+        _, _, _, st1 = plans[s.grid].solve(d[0], s.cell, d[1], d[2], d[3], s.q_tot, forces=True)
+        seq_iters.append(st1["iters"])
+    torch.cuda.synchronize()
+    seq_ms = (time.perf_counter() - t0) * 1e3
+    for pl in plans.values():
+        pl.close()
+    flops = batch_flops(structs, st)
+    achieved = flops / (kern_ms * 1e-3) / 1e12
+    out = {
+        "metric": METRIC,
+        "value": round(ms_step, 4),
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "batched QEq, 1024 triclinic structures (N 32-512, 3 elements, Q in {-1,0,1}), "
+                               "one persistent launch", "n_structures": len(structs), "n_atoms": int(offs[-1]),
+                   "r_cut_bohr": rc_cut, "tol": args.tol, "spline_order": 6,
+                   "grids": "per structure, spacing <= 0.8 bohr (24..60 per axis)"},
+        "structures_per_s": round(len(structs) / (ms_step * 1e-3), 1),
+        "per_structure_launches": {"ms": round(seq_ms, 2), "structures_per_s": round(len(structs) / (seq_ms * 1e-3), 1),
+                                   "speedup_of_batched": round(seq_ms / ms_step, 2),
+                                   "cg_iters_mean": float(np.mean(seq_iters))},
+        "roofline": {"bound": "alu", "kernel": "k_batched", "achieved": round(achieved, 3),
+                     "peak": 157.3, "unit": "TFLOP/s", "frac": round(achieved / 157.3, 5), "traffic": None,
+                     "flops_per_launch": flops, "us_per_launch": round(kern_ms * 1e3, 1)},
+        "phase_us_per_structure": {k: round(v, 1) for k, v in zip(plan.BATCH_PHASES, phase)},
+        "cg_iters_mean": float(np.mean([x["iters"] for x in st])),
+        "all_converged": bool(rc == 0),
+    }
+    plan.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_batch(structs)
+    print(json.dumps(out), flush=True)
 
 
 def warmstart_main(args, dev):

@@ -244,6 +244,14 @@ int mlp_train_step(const float* G, const int32_t* species, const double* target,
                    float* adam_v, int32_t step, float lr, float* workspace,
                    int64_t workspace_floats, float* loss, float* grad_out, void* stream);
 
+/* The CG loop of qeq_solve / qeq_backward runs as a replayed HIP graph of
+   8 iterations (captured on a private stream, launched on the plan's stream,
+   re-captured when the geometry or buffers change); enable = 0 launches every
+   kernel separately instead.  Results are the same either way up to the
+   rounding order of the mesh atomics.  Default on.  While per-stage timers
+   are enabled (qeq_profile) the loop launches kernels one by one. */
+int qeq_use_graphs(qeq_plan* plan, int32_t enable);
+
 /* Per-stage timers (the paper's per-stage timing of a step, here with HIP
    events on the plan's stream).  kind_mask selects which launch kinds are
    bracketed with events during later calls; 0 switches timing off.  Kinds:

@@ -408,6 +408,73 @@ int setup_geometry(qeq_plan* pl, const double* pos, const double* sigma, const d
     return QEQ_OK;
 }
 
+// Bytes that determine the kernels of one CG chunk: the kernel-argument
+// bundle and every buffer the chunk touches.
+void chunk_key(const qeq_plan* pl, std::vector<unsigned char>& key) {
+
+    const void* ptrs[] = {pl->pvec, pl->y, pl->q, pl->r, pl->dinv, pl->part, pl->sc, pl->grid_r, pl->grid_c,
+                          pl->wts, pl->dwts, pl->home, pl->bin_start, pl->rowptr, pl->col, pl->kval, pl->pdr,
+                          pl->dself, pl->Jv, pl->chi_raw, pl->chi, pl->sig, pl->selfgrad, pl->fdst, pl->gtmp,
+                          pl->tw[0], pl->tw[1], pl->tw[2], pl->bmod[0], pl->bmod[1], pl->bmod[2]};
+    key.resize(sizeof(KParams) + sizeof(ptrs) + sizeof(DeviceAxes));
+    unsigned char* k = key.data();
+    memcpy(k, &pl->kp, sizeof(KParams));
+    memcpy(k + sizeof(KParams), ptrs, sizeof(ptrs));
+    memcpy(k + sizeof(KParams) + sizeof(ptrs), &pl->axes, sizeof(DeviceAxes));
+}
+
+void drop_graph(qeq_plan* pl) {
+    if (pl->graph_exec) (void)hipGraphExecDestroy(pl->graph_exec);
+    if (pl->graph) (void)hipGraphDestroy(pl->graph);
+    pl->graph_exec = nullptr;
+    pl->graph = nullptr;
+    pl->graph_key.clear();
+}
+
+// One CG iteration: matvec of the direction, update of q and r, new direction.
+int cg_iteration(qeq_plan* pl, int parity) {
+    const int* done = &pl->sc->done;
+    QEQ_TRY(launch_mesh_potential(pl, pl->pvec, done));
+    QEQ_TRY(launch_interp(pl, pl->pvec, pl->y, QEQ_MODE_CG, parity));
+    QEQ_TRY(launch_cg_update(pl, parity));
+    return launch_cg_dir(pl, parity, 0);
+}
+
+// Capture `chunk` iterations (starting at even parity) into a graph unless the
+// current one was captured with the same arguments.  Every kernel of the loop
+// reads the device flag `done` and returns at once after convergence, so the
+// graph can be replayed whole.
+int ensure_chunk_graph(qeq_plan* pl, int chunk) {
+    std::vector<unsigned char> key;
+    chunk_key(pl, key);
+    if (pl->graph_exec && key == pl->graph_key) return QEQ_OK;
+    drop_graph(pl);
+    if (!pl->cap_stream) QEQ_HIP(hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking));
+    hipStream_t user = pl->stream;
+    pl->stream = pl->cap_stream;
+    int rc = qeq_check(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal));
+    if (rc == QEQ_OK) {
+        for (int t = 0; t < chunk && rc == QEQ_OK; ++t) rc = cg_iteration(pl, t & 1);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(pl->cap_stream, &g);
+        if (rc == QEQ_OK) rc = qeq_check(e);
+        if (rc == QEQ_OK) {
+            rc = qeq_check(hipGraphInstantiate(&pl->graph_exec, g, nullptr, nullptr, 0));
+            pl->graph = g;
+        } else if (g) {
+            (void)hipGraphDestroy(g);
+        }
+    }
+    pl->stream = user;
+    if (rc != QEQ_OK) {
+        drop_graph(pl);
+        return rc;
+    }
+    pl->graph_key.swap(key);
+    return QEQ_OK;
+}
+
+
 // Projected CG from q0 (or Q/N) to the tolerance, with the true-residual
 // restart, then the final matvec: energies, mu, true residual and forces are
 // computed; q_out / energies / forces_out (caller order) may be NULL.
@@ -455,13 +522,18 @@ int cg_run(qeq_plan* pl, const double* q0, double* q_out, double* energies, doub
         int local = 0;
         while (it < pl->prm.max_iter) {
             int m = std::min(chunk, pl->prm.max_iter - it);
-            for (int t = 0; t < m; ++t, ++it, ++local) {
-                int parity = local & 1;
-                pl->cur_it = it;
-                QEQ_TRY(launch_mesh_potential(pl, pl->pvec, done));
-                QEQ_TRY(launch_interp(pl, pl->pvec, pl->y, QEQ_MODE_CG, parity));
-                QEQ_TRY(launch_cg_update(pl, parity));
-                QEQ_TRY(launch_cg_dir(pl, parity, 0));
+            // per-stage timers need eager launches (events recorded inside a
+            // graph cannot be read back with hipEventElapsedTime)
+            if (m == chunk && (local & 1) == 0 && pl->use_graphs && pl->prof_mask == 0) {
+                QEQ_TRY(ensure_chunk_graph(pl, chunk));
+                QEQ_HIP(hipGraphLaunch(pl->graph_exec, pl->stream));
+                it += m;
+                local += m;
+            } else {
+                for (int t = 0; t < m; ++t, ++it, ++local) {
+                    pl->cur_it = it;
+                    QEQ_TRY(cg_iteration(pl, local & 1));
+                }
             }
             pl->cur_it = -1;
             QEQ_HIP(hipMemcpyAsync(pl->sc_host, pl->sc, sizeof(CgScalars), hipMemcpyDeviceToHost,
@@ -641,6 +713,8 @@ int qeq_plan_destroy(qeq_plan* pl) {
     prof_flush(pl, 0);
     for (hipEvent_t e : pl->prof_pool) (void)hipEventDestroy(e);
     pl->prof_pool.clear();
+    drop_graph(pl);
+    if (pl->cap_stream) (void)hipStreamDestroy(pl->cap_stream);
     free_grid(pl);
     batch_free(pl);
     dfree(pl->perm); dfree(pl->key); dfree(pl->frac); dfree(pl->home); dfree(pl->wts); dfree(pl->dwts);
@@ -683,6 +757,14 @@ int qeq_matvec(qeq_plan* plan, int32_t n, const double* pos, const double* cell,
     QEQ_TRY(launch_matvec_io(pl, nullptr, y, 1));
     QEQ_HIP(hipStreamSynchronize(pl->stream));
     pl->kp.parts = 15;
+    return QEQ_OK;
+}
+
+int qeq_use_graphs(qeq_plan* plan, int32_t enable) {
+    if (plan && plan->stream) (void)hipStreamSynchronize(plan->stream);
+    if (!plan) return QEQ_EINVAL;
+    plan->use_graphs = enable != 0;
+    if (!plan->use_graphs) drop_graph(plan);
     return QEQ_OK;
 }
 

@@ -174,6 +174,14 @@ struct qeq_plan {
 
     BatchState* batch = nullptr;
 
+    // the CG loop is replayed as a HIP graph of one chunk of iterations,
+    // captured on a private stream and re-captured when its arguments change
+    bool use_graphs = true;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    std::vector<unsigned char> graph_key;
+
     // per-stage timers
     unsigned prof_mask = 0;
     int cur_it = -1;

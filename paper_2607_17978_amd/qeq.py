@@ -90,6 +90,8 @@ def load_library():
     L.qeq_backward.restype = ctypes.c_int
     L.qeq_matvec.argtypes = [vp, i32, dp, ctypes.POINTER(ctypes.c_double), dp, dp, dp, i32]
     L.qeq_matvec.restype = ctypes.c_int
+    L.qeq_use_graphs.argtypes = [vp, i32]
+    L.qeq_use_graphs.restype = ctypes.c_int
     L.qeq_profile.argtypes = [vp, ctypes.c_uint32]
     L.qeq_profile.restype = ctypes.c_int
     L.qeq_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
@@ -312,6 +314,10 @@ class Plan:
 
     PROFILE_KINDS = ("spread_r2c", "fft_rows_fwd", "fft_cols_green", "fft_rows_inv", "c2r",
                      "interp_pairs", "cg_update", "cg_dir", "final")
+
+    def use_graphs(self, enable=True):
+        """Replay the CG loop as a HIP graph (default) or launch kernels one by one."""
+        load_library().qeq_use_graphs(self._h, 1 if enable else 0)
 
     def profile(self, mask):
         """Bracket the launch kinds in ``mask`` with HIP events (see qeq_profile)."""

@@ -200,3 +200,30 @@ def test_full_size_32768_matches_oracle(dev):
     assert de_q <= 1e-6 and de_e <= 1e-6
     assert df <= 1e-4
     plan.close()
+
+
+def test_graph_replays_match_eager(dev):
+    """The CG loop replayed as a HIP graph gives the eager result on every
+    replay, with other work (matvecs, solves of another system that force a
+    re-capture) in between."""
+    from paper_2607_17978_amd import qeq
+    s = gen.system_512()
+    o = gen.system_64()
+    args = (T(s.pos, dev), s.cell, T(s.sigma, dev), T(s.J, dev), T(s.chi, dev), 0.0)
+    pe = qeq.Plan(s.n, eta=ETA, r_cut=RC, tol=1e-8)
+    pe.use_graphs(False)
+    q_e, en_e, f_e, st_e = pe.solve(*args)
+    pe.close()
+    pg = qeq.Plan(s.n, eta=ETA, r_cut=RC, tol=1e-8)
+    v = T(np.random.default_rng(5).normal(size=s.n), dev)
+    for rep in range(4):
+        q_g, en_g, f_g, st_g = pg.solve(*args)
+        assert st_g["rc"] == 0 and abs(st_g["iters"] - st_e["iters"]) <= 1
+        assert (q_g - q_e).abs().max().item() < 1e-9
+        assert (en_g - en_e).abs().max().item() < 1e-9 * abs(en_e[0].item())
+        assert (f_g - f_e).abs().max().item() < 1e-7
+        torch.cuda.synchronize()
+        pg.matvec(args[0], s.cell, args[2], v)
+        if rep % 2 == 0:
+            pg.solve(T(o.pos, dev), o.cell, T(o.sigma, dev), T(o.J, dev), T(o.chi, dev), 0.0)
+    pg.close()
