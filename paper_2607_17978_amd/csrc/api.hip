@@ -721,7 +721,7 @@ int qeq_plan_destroy(qeq_plan* pl) {
     dfree(pl->sig); dfree(pl->Jv); dfree(pl->chi); dfree(pl->chi_raw); dfree(pl->dself); dfree(pl->dinv);
     dfree(pl->selfgrad); dfree(pl->q); dfree(pl->r); dfree(pl->pvec); dfree(pl->y); dfree(pl->forces_s);
     dfree(pl->gtmp); dfree(pl->q_adj); dfree(pl->y_adj); dfree(pl->chi_adj); dfree(pl->adj_scratch); dfree(pl->tq); dfree(pl->rowptr); dfree(pl->rowcnt); dfree(pl->theta_tab); dfree(pl->part);
-    dfree(pl->sc); dfree(pl->final_dev);
+    dfree(pl->sc); dfree(pl->final_dev); dfree(pl->scan_tmp);
     dfree(pl->cell_count); dfree(pl->cell_start); dfree(pl->cell_fill); dfree(pl->cell_atoms);
     dfree(pl->col); dfree(pl->kval); dfree(pl->pdr);
     if (pl->sc_host) (void)hipHostFree(pl->sc_host);

@@ -160,6 +160,9 @@ struct qeq_plan {
     float4* pdr = nullptr;        // (dx, dy, dz, K'(r)/r)
     long long nnz = 0;
 
+    int* scan_tmp = nullptr;      // chunk totals of the multi-block scan
+    size_t scan_cap = 0;
+
     // reductions
     double* part = nullptr;       // [2][nblk_max][QEQ_NPART]
     int nblk_max = 0;

@@ -70,6 +70,56 @@ __global__ void k_bucket_sort(int nb, const int* __restrict__ start, int* __rest
     }
 }
 
+// Exclusive scan of m ints in three launches: per-block totals of 1024-element
+// chunks, a one-block scan of those totals, then each chunk scanned with its
+// offset.  out[m] = total.
+constexpr int SCAN_CHUNK = 1024;
+
+__global__ __launch_bounds__(256) void k_scan_totals(const int* __restrict__ in, int m, int* __restrict__ tot) {
+    const int base = blockIdx.x * SCAN_CHUNK;
+    int v = 0;
+    for (int t = threadIdx.x; t < SCAN_CHUNK; t += 256) v += base + t < m ? in[base + t] : 0;
+    double d[1] = {(double)v};
+    block_sum<1>(d);
+    if (threadIdx.x == 0) tot[blockIdx.x] = (int)d[0];
+}
+
+__global__ __launch_bounds__(256) void k_scan_chunks(const int* __restrict__ in, int m, const int* __restrict__ tot,
+                                                    int nchunk, int* __restrict__ out) {
+    __shared__ int part[256];
+    __shared__ int offset;
+    const int t = threadIdx.x;
+    {
+        double o[1] = {0.0};
+        for (int b = t; b < (int)blockIdx.x; b += 256) o[0] += (double)tot[b];
+        block_sum<1>(o);
+        if (t == 0) offset = (int)o[0];
+    }
+    // 4 consecutive elements per thread
+    const int base = blockIdx.x * SCAN_CHUNK + 4 * t;
+    int v[4], s = 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        v[u] = base + u < m ? in[base + u] : 0;
+        s += v[u];
+    }
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const int x = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += x;
+        __syncthreads();
+    }
+    int run = offset + part[t] - s;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        if (base + u < m) out[base + u] = run;
+        run += v[u];
+    }
+    if (blockIdx.x == nchunk - 1 && t == 255) out[m] = offset + part[255];
+}
+
 // Exclusive scan of m ints into out[0..m], out[m] = total; one block.
 __global__ void k_scan(const int* __restrict__ in, int* __restrict__ out, int m) {
     __shared__ int part[1024];
@@ -210,64 +260,76 @@ __global__ void k_cell_scatter(int n, const int* __restrict__ home, const int* _
     atoms[start[ck] + atomicAdd(&fill[ck], 1)] = s;
 }
 
+// One wave per atom i: the lanes share the cells of the stencil around i's
+// cell (lane l takes stencil cells l, l + 64, ...), count or write the pairs
+// found there; a wave prefix sum gives each lane its slice of row i, so the
+// row order is fixed (lane-major, cells in stencil order, atoms in cell order).
 template <bool FILL>
-__global__ void k_pairs(KParams k, const double* __restrict__ frac, const int* __restrict__ home,
-                        const double* __restrict__ sig, const int* __restrict__ cell_start,
-                        const int* __restrict__ cell_atoms, int* __restrict__ rowcnt,
-                        const int* __restrict__ rowptr, int* __restrict__ col, float* __restrict__ kval,
-                        float4* __restrict__ pdr) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= k.n) return;
-    double si[3] = {frac[3 * i], frac[3 * i + 1], frac[3 * i + 2]};
-    int ck = home[4 * i + 3];
-    int c3 = ck % k.nc[2];
-    int c2 = (ck / k.nc[2]) % k.nc[1];
-    int c1 = ck / (k.nc[2] * k.nc[1]);
-    double sgi = sig[i];
-    int cnt = 0;
-    int off = FILL ? rowptr[i] : 0;
-    for (int d1 = -k.ns[0]; d1 <= k.ns[0]; ++d1) {
-        int r1 = c1 + d1;
-        int w1 = wrap_idx(r1, k.nc[0]);
-        int sh1 = (r1 - w1) / k.nc[0];
-        for (int d2 = -k.ns[1]; d2 <= k.ns[1]; ++d2) {
-            int r2 = c2 + d2;
-            int w2 = wrap_idx(r2, k.nc[1]);
-            int sh2 = (r2 - w2) / k.nc[1];
-            for (int d3 = -k.ns[2]; d3 <= k.ns[2]; ++d3) {
-                int r3 = c3 + d3;
-                int w3 = wrap_idx(r3, k.nc[2]);
-                int sh3 = (r3 - w3) / k.nc[2];
-                int cell = (w1 * k.nc[1] + w2) * k.nc[2] + w3;
-                bool home_img = (sh1 == 0 && sh2 == 0 && sh3 == 0);
-                for (int t = cell_start[cell]; t < cell_start[cell + 1]; ++t) {
-                    int j = cell_atoms[t];
-                    if (home_img && j == i) continue;
-                    double ds0 = frac[3 * j] + sh1 - si[0];
-                    double ds1 = frac[3 * j + 1] + sh2 - si[1];
-                    double ds2 = frac[3 * j + 2] + sh3 - si[2];
-                    // d = r_j(image) - r_i, Cartesian (row vector ds times H)
-                    double dx = ds0 * k.H[0] + ds1 * k.H[3] + ds2 * k.H[6];
-                    double dy = ds0 * k.H[1] + ds1 * k.H[4] + ds2 * k.H[7];
-                    double dz = ds0 * k.H[2] + ds1 * k.H[5] + ds2 * k.H[8];
-                    double r2v = dx * dx + dy * dy + dz * dz;
-                    if (r2v >= k.rc2) continue;
-                    if (FILL) {
-                        double sj = sig[j];
-                        double K, dKr;
-                        pair_kernel(sqrt(r2v), sqrt(sgi * sgi + sj * sj), k.eta, &K, &dKr);
-                        col[off] = j;
-                        kval[off] = (float)K;
-                        // store r_i - r_j(image) for the force
-                        pdr[off] = make_float4((float)(-dx), (float)(-dy), (float)(-dz), (float)dKr);
-                        ++off;
-                    }
-                    ++cnt;
+__global__ __launch_bounds__(QEQ_BLOCK) void k_pairs(KParams k, const double* __restrict__ frac,
+                                                    const int* __restrict__ home, const double* __restrict__ sig,
+                                                    const int* __restrict__ cell_start,
+                                                    const int* __restrict__ cell_atoms, int* __restrict__ rowcnt,
+                                                    const int* __restrict__ rowptr, int* __restrict__ col,
+                                                    float* __restrict__ kval, float4* __restrict__ pdr) {
+    const int lane = threadIdx.x & 63;
+    const int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (i >= k.n) return;   // uniform across the wave
+    const double si[3] = {frac[3 * i], frac[3 * i + 1], frac[3 * i + 2]};
+    const int ck = home[4 * i + 3];
+    const int c3 = ck % k.nc[2];
+    const int c2 = (ck / k.nc[2]) % k.nc[1];
+    const int c1 = ck / (k.nc[2] * k.nc[1]);
+    const double sgi = sig[i];
+    const int w2 = 2 * k.ns[1] + 1, w3 = 2 * k.ns[2] + 1;
+    const int nst = (2 * k.ns[0] + 1) * w2 * w3;
+    int off = 0;
+    for (int pass = FILL ? 0 : 1; pass < 2; ++pass) {
+        // pass 0 (FILL only): count to find this lane's slice; pass 1: count or write
+        int cnt = 0;
+        for (int t = lane; t < nst; t += 64) {
+            const int d3 = t % w3 - k.ns[2], d2 = (t / w3) % w2 - k.ns[1], d1 = t / (w3 * w2) - k.ns[0];
+            const int r1 = c1 + d1, r2 = c2 + d2, r3 = c3 + d3;
+            const int x1 = wrap_idx(r1, k.nc[0]), x2 = wrap_idx(r2, k.nc[1]), x3 = wrap_idx(r3, k.nc[2]);
+            const int sh1 = (r1 - x1) / k.nc[0], sh2 = (r2 - x2) / k.nc[1], sh3 = (r3 - x3) / k.nc[2];
+            const int cell = (x1 * k.nc[1] + x2) * k.nc[2] + x3;
+            const bool home_img = (sh1 == 0 && sh2 == 0 && sh3 == 0);
+            for (int u = cell_start[cell]; u < cell_start[cell + 1]; ++u) {
+                const int j = cell_atoms[u];
+                if (home_img && j == i) continue;
+                const double ds0 = frac[3 * j] + sh1 - si[0];
+                const double ds1 = frac[3 * j + 1] + sh2 - si[1];
+                const double ds2 = frac[3 * j + 2] + sh3 - si[2];
+                // d = r_j(image) - r_i, Cartesian (row vector ds times H)
+                const double dx = ds0 * k.H[0] + ds1 * k.H[3] + ds2 * k.H[6];
+                const double dy = ds0 * k.H[1] + ds1 * k.H[4] + ds2 * k.H[7];
+                const double dz = ds0 * k.H[2] + ds1 * k.H[5] + ds2 * k.H[8];
+                const double r2v = dx * dx + dy * dy + dz * dz;
+                if (r2v >= k.rc2) continue;
+                if (FILL && pass == 1) {
+                    const double sj = sig[j];
+                    double K, dKr;
+                    pair_kernel(sqrt(r2v), sqrt(sgi * sgi + sj * sj), k.eta, &K, &dKr);
+                    col[off] = j;
+                    kval[off] = (float)K;
+                    // store r_i - r_j(image) for the force
+                    pdr[off] = make_float4((float)(-dx), (float)(-dy), (float)(-dz), (float)dKr);
+                    ++off;
                 }
+                ++cnt;
             }
         }
+        int incl = cnt;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int y = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += y;
+        }
+        if (FILL) {
+            off = rowptr[i] + incl - cnt;
+        } else if (lane == 63) {
+            rowcnt[i] = incl;
+        }
     }
-    if (!FILL) rowcnt[i] = cnt;
 }
 
 // ---------------------------------------------------------------------------
@@ -290,8 +352,13 @@ __global__ void k_theta_extract(KParams k, const float* __restrict__ grid, doubl
     tab[t] = (double)grid[((size_t)g1 * k.K2 + g2) * k.K3 + g3];
 }
 
-__global__ void k_selfcorr(KParams k, const double* __restrict__ frac, const double* __restrict__ tab,
+__global__ void k_selfcorr(KParams k, const double* __restrict__ frac, const double* __restrict__ tab_g,
                            double* __restrict__ dself, double* __restrict__ selfgrad) {
+    // the table is read by every atom: stage it in LDS
+    __shared__ double tab[(2 * QEQ_MAXP - 1) * (2 * QEQ_MAXP - 1) * (2 * QEQ_MAXP - 1)];
+    const int np = 2 * k.p - 1;
+    for (int t = threadIdx.x; t < np * np * np; t += blockDim.x) tab[t] = tab_g[t];
+    __syncthreads();
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= k.n) return;
     const double u[3] = {frac[3 * i] * (double)k.K1, frac[3 * i + 1] * (double)k.K2,
@@ -310,7 +377,20 @@ __global__ void k_selfcorr(KParams k, const double* __restrict__ frac, const dou
 // launchers
 // ---------------------------------------------------------------------------
 int launch_scan(qeq_plan* pl, const int* in, int* out, int m) {
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, pl->stream, in, out, m);
+    const int nchunk = (m + SCAN_CHUNK - 1) / SCAN_CHUNK;
+    if (nchunk <= 4) {
+        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, pl->stream, in, out, m);
+        return qeq_check(hipGetLastError());
+    }
+    if ((size_t)nchunk > pl->scan_cap) {
+        if (pl->scan_tmp) (void)hipFree(pl->scan_tmp);
+        pl->scan_tmp = nullptr;
+        pl->scan_cap = 0;
+        if (hipMalloc((void**)&pl->scan_tmp, sizeof(int) * (size_t)nchunk) != hipSuccess) return QEQ_ENOMEM;
+        pl->scan_cap = (size_t)nchunk;
+    }
+    hipLaunchKernelGGL(k_scan_totals, dim3(nchunk), dim3(256), 0, pl->stream, in, m, pl->scan_tmp);
+    hipLaunchKernelGGL(k_scan_chunks, dim3(nchunk), dim3(256), 0, pl->stream, in, m, pl->scan_tmp, nchunk, out);
     return qeq_check(hipGetLastError());
 }
 
@@ -375,7 +455,8 @@ int launch_cells_and_pairs(qeq_plan* pl) {
                        pl->home, pl->cell_start, pl->cell_fill, pl->cell_atoms);
     hipLaunchKernelGGL(k_bucket_sort, dim3(nblocks(ncell)), dim3(QEQ_BLOCK), 0, pl->stream, ncell,
                        pl->cell_start, pl->cell_atoms);
-    hipLaunchKernelGGL(k_pairs<false>, dim3(nblocks(k.n)), dim3(QEQ_BLOCK), 0, pl->stream, k,
+    const int pair_blocks = nblocks(k.n * 64);   // one wave per atom
+    hipLaunchKernelGGL(k_pairs<false>, dim3(pair_blocks), dim3(QEQ_BLOCK), 0, pl->stream, k,
                        pl->frac, pl->home, pl->sig, pl->cell_start, pl->cell_atoms, pl->rowcnt,
                        pl->rowptr, pl->col, pl->kval, pl->pdr);
     QEQ_TRY(launch_scan(pl, pl->rowcnt, pl->rowptr, k.n));
@@ -398,7 +479,7 @@ int launch_cells_and_pairs(qeq_plan* pl) {
             return QEQ_ENOMEM;
         pl->nnz_cap = cap;
     }
-    hipLaunchKernelGGL(k_pairs<true>, dim3(nblocks(k.n)), dim3(QEQ_BLOCK), 0, pl->stream, k,
+    hipLaunchKernelGGL(k_pairs<true>, dim3(pair_blocks), dim3(QEQ_BLOCK), 0, pl->stream, k,
                        pl->frac, pl->home, pl->sig, pl->cell_start, pl->cell_atoms, pl->rowcnt,
                        pl->rowptr, pl->col, pl->kval, pl->pdr);
     return qeq_check(hipGetLastError());
