@@ -174,9 +174,9 @@ int qeq_solve_batched(qeq_plan* plan, int32_t n_struct, const int32_t* atom_offs
                       const double* q0, double* q, double* energies, double* forces,
                       qeq_stats* stats);
 
-/* Launch shape of qeq_solve_batched: threads per workgroup (256, 512 or 1024)
-   and workgroups per compute unit (1 .. 8; the launch has that many per CU,
-   as many as fit run at once).  Does not change results beyond FP32 rounding
+/* Launch shape of qeq_solve_batched: threads per workgroup (512 or 1024;
+   anything else is QEQ_EINVAL) and workgroups per compute unit (1 .. 8; the
+   launch has that many per CU, as many as fit run at once).  Does not change results beyond FP32 rounding
    order.  Defaults 1024, 1. */
 int qeq_batched_config(qeq_plan* plan, int32_t threads, int32_t wg_per_cu);
 
@@ -269,6 +269,15 @@ int qeq_profile(qeq_plan* plan, uint32_t kind_mask);
    Synchronises the plan's stream. */
 int qeq_profile_read(qeq_plan* plan, double* total_ms, int64_t* launches, int32_t n_kinds,
                      int32_t reset);
+
+/* Average duration (microseconds, *avg_us) of one launch of a single mesh
+   pass, timed with HIP events around `reps` back-to-back launches on the
+   plan's stream with the geometry and charges of the last successful solve:
+   kind 0 = spread + axis-3 R2C FFT (from the solve's q), kind 4 = axis-3 C2R
+   FFT (the other passes work in place and are not offered).  The passes only
+   overwrite the plan's mesh buffers; the tape for qeq_backward stays valid.
+   QEQ_EINVAL without a preceding solve or for another kind. */
+int qeq_time_kernel(qeq_plan* plan, int32_t kind, int32_t reps, double* avg_us);
 
 const char* qeq_strerror(int code);
 

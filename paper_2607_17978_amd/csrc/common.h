@@ -349,31 +349,47 @@ __device__ __forceinline__ void pair_kernel(double r, double gam, double eta, do
 // where tab holds Theta(d) on the (2p-1)^3 offsets (d_1 slowest).  Returns the
 // value and its derivative with respect to the grid coordinates u_a.
 // ---------------------------------------------------------------------------
-__device__ inline void mesh_self_term(const double* u, int p, const double* __restrict__ tab, double* val,
+// PC: the spline order at compile time (every loop unrolls, the arrays stay in
+// registers) or 0 for the order p_rt at run time.
+template <int PC>
+__device__ inline void mesh_self_term(const double* u, int p_rt, const double* __restrict__ tab, double* val,
                                       double* grad) {
+    constexpr int PM = PC ? PC : QEQ_MAXP;
+    constexpr int NPM = 2 * PM - 1;
+    const int p = PC ? PC : p_rt;
     const int np = 2 * p - 1;
-    double R[3][2 * QEQ_MAXP - 1], dR[3][2 * QEQ_MAXP - 1];
+    double R[3][NPM], dR[3][NPM];
+#pragma unroll
     for (int a = 0; a < 3; ++a) {
-        double w = u[a] - floor(u[a]);
+        const double w = u[a] - floor(u[a]);
         double c[QEQ_MAXP], dc[QEQ_MAXP];
         bspline_weights<double>(w, p, c, dc);
-        for (int d = 0; d < np; ++d) {
+#pragma unroll
+        for (int d = 0; d < NPM; ++d) {
             R[a][d] = 0.0;
             dR[a][d] = 0.0;
         }
-        for (int k1 = 0; k1 < p; ++k1)
-            for (int k2 = 0; k2 < p; ++k2) {
-                int d = k2 - k1 + (p - 1);
+#pragma unroll
+        for (int k1 = 0; k1 < PM; ++k1)
+#pragma unroll
+            for (int k2 = 0; k2 < PM; ++k2) {
+                if (!PC && (k1 >= p || k2 >= p)) continue;
+                const int d = k2 - k1 + (p - 1);
                 R[a][d] += c[k1] * c[k2];
                 dR[a][d] += dc[k1] * c[k2] + c[k1] * dc[k2];
             }
     }
     double s = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0;
-    for (int a = 0; a < np; ++a)
-        for (int b = 0; b < np; ++b) {
+#pragma unroll
+    for (int a = 0; a < NPM; ++a)
+#pragma unroll
+        for (int b = 0; b < NPM; ++b) {
+            if (!PC && (a >= np || b >= np)) continue;
             double t = 0.0, t1 = 0.0;
             const double* row = tab + (a * np + b) * np;
-            for (int c = 0; c < np; ++c) {
+#pragma unroll
+            for (int c = 0; c < NPM; ++c) {
+                if (!PC && c >= np) continue;
                 t += row[c] * R[2][c];
                 t1 += row[c] * dR[2][c];
             }

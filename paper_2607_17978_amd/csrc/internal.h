@@ -2,6 +2,7 @@
 // bundle, the plan (device workspace) and the host launchers of every kernel.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -194,13 +195,18 @@ struct qeq_plan {
     long long prof_n[PK_COUNT] = {0};
 };
 
-// Brackets one launch with events when its kind is enabled.
+// Times one launch (or a sequence) when its kind is enabled: the start event
+// goes to the first launch and the stop event to the last one of the scope,
+// both recorded by the dispatches themselves (hipExtLaunchKernelGGL), so the
+// interval is the kernels' own execution time.  Null events when disabled.
 struct ProfScope {
     qeq_plan* pl;
     ProfRec rec;
     bool on;
     ProfScope(qeq_plan* p, int kind);
     ~ProfScope();
+    hipEvent_t start() const { return on ? rec.a : nullptr; }
+    hipEvent_t stop() const { return on ? rec.b : nullptr; }
 };
 void prof_flush(qeq_plan* pl, int live_iters);
 
@@ -240,6 +246,8 @@ int launch_mesh_potential(qeq_plan* pl, const double* src, const int* done);
 size_t qeq_mesh_max_smem(const KParams& k);
 // Inverse transforms only (grid_c already holds a spectrum) -> grid_r.
 int launch_mesh_inverse(qeq_plan* pl);
+// One launch of a single mesh pass (PK_SPREAD_R2C from src, or PK_C2R).
+int launch_mesh_stage(qeq_plan* pl, int kind, const double* src);
 int launch_write_green(qeq_plan* pl);
 
 // ------------------------------------------------------------------ solver kernels (solve.hip)

@@ -365,14 +365,14 @@ int spread_pass(qeq_plan* pl, const double* src, const int* done) {
     ProfScope ps(pl, PK_SPREAD_R2C);
 #define X(KK, TT)                                                                                  \
     if (k.K3 == KK && k.TWS == TT && k.p == 6) {                                                    \
-        hipLaunchKernelGGL((k_spread_r2c<KK, TT, 6>), g, b, sh, pl->stream, k, pl->axes.ax[2], src, \
-                           pl->bin_start, pl->home, pl->wts, pl->grid_c, done);                    \
+        hipExtLaunchKernelGGL((k_spread_r2c<KK, TT, 6>), g, b, sh, pl->stream, ps.start(), ps.stop(), 0, k, \
+                              pl->axes.ax[2], src, pl->bin_start, pl->home, pl->wts, pl->grid_c, done);   \
         return qeq_check(hipGetLastError());                                                       \
     }
     QEQ_FOR_EACH_SPREAD(X)
 #undef X
-    hipLaunchKernelGGL((k_spread_r2c<0, 0, 0>), g, b, sh, pl->stream, k, pl->axes.ax[2], src, pl->bin_start,
-                       pl->home, pl->wts, pl->grid_c, done);
+    hipExtLaunchKernelGGL((k_spread_r2c<0, 0, 0>), g, b, sh, pl->stream, ps.start(), ps.stop(), 0, k,
+                          pl->axes.ax[2], src, pl->bin_start, pl->home, pl->wts, pl->grid_c, done);
     return qeq_check(hipGetLastError());
 }
 
@@ -385,14 +385,14 @@ int rows_pass_t(qeq_plan* pl, const int* done) {
     ProfScope ps(pl, INV ? PK_ROWS_INV : PK_ROWS_FWD);
 #define X(KK, TT)                                                                                  \
     if (k.K2 == KK && k.NR == 16) {                                                                \
-        hipLaunchKernelGGL((k_fft_rows<KK, 16, INV>), g, b, sh, pl->stream, k, pl->axes.ax[1],       \
-                           pl->grid_c, nrows, done);                                              \
+        hipExtLaunchKernelGGL((k_fft_rows<KK, 16, INV>), g, b, sh, pl->stream, ps.start(), ps.stop(), 0, \
+                              k, pl->axes.ax[1], pl->grid_c, nrows, done);                          \
         return qeq_check(hipGetLastError());                                                       \
     }
     QEQ_FOR_EACH_SIZE(X)
 #undef X
-    hipLaunchKernelGGL((k_fft_rows<0, 0, INV>), g, b, sh, pl->stream, k, pl->axes.ax[1], pl->grid_c, nrows,
-                       done);
+    hipExtLaunchKernelGGL((k_fft_rows<0, 0, INV>), g, b, sh, pl->stream, ps.start(), ps.stop(), 0, k,
+                          pl->axes.ax[1], pl->grid_c, nrows, done);
     return qeq_check(hipGetLastError());
 }
 
@@ -407,14 +407,15 @@ int cols_pass(qeq_plan* pl, int mode, double* epart, const int* done) {
     ProfScope ps(pl, PK_COLS_GREEN);
 #define X(KK, TT)                                                                                  \
     if (k.K1 == KK && k.TW == TT) {                                                                \
-        hipLaunchKernelGGL((k_fft_cols<KK, TT>), g, b, sh, pl->stream, k, pl->axes.ax[0], pl->grid_c, \
-                           pl->bmod[0], pl->bmod[1], pl->bmod[2], mode, epart, done);             \
+        hipExtLaunchKernelGGL((k_fft_cols<KK, TT>), g, b, sh, pl->stream, ps.start(), ps.stop(), 0, k,   \
+                              pl->axes.ax[0], pl->grid_c, pl->bmod[0], pl->bmod[1], pl->bmod[2], mode, \
+                              epart, done);                                                          \
         return qeq_check(hipGetLastError());                                                       \
     }
     QEQ_FOR_EACH_SIZE(X)
 #undef X
-    hipLaunchKernelGGL((k_fft_cols<0, 0>), g, b, sh, pl->stream, k, pl->axes.ax[0], pl->grid_c, pl->bmod[0],
-                       pl->bmod[1], pl->bmod[2], mode, epart, done);
+    hipExtLaunchKernelGGL((k_fft_cols<0, 0>), g, b, sh, pl->stream, ps.start(), ps.stop(), 0, k, pl->axes.ax[0],
+                          pl->grid_c, pl->bmod[0], pl->bmod[1], pl->bmod[2], mode, epart, done);
     return qeq_check(hipGetLastError());
 }
 
@@ -425,13 +426,14 @@ int c2r_pass(qeq_plan* pl, const int* done) {
     ProfScope ps(pl, PK_C2R);
 #define X(KK, TT)                                                                                  \
     if (k.K3 == KK && k.TW == TT) {                                                                \
-        hipLaunchKernelGGL((k_c2r<KK, TT>), g, b, sh, pl->stream, k, pl->axes.ax[2], pl->grid_c,      \
-                           pl->grid_r, done);                                                      \
+        hipExtLaunchKernelGGL((k_c2r<KK, TT>), g, b, sh, pl->stream, ps.start(), ps.stop(), 0, k,         \
+                              pl->axes.ax[2], pl->grid_c, pl->grid_r, done);                        \
         return qeq_check(hipGetLastError());                                                       \
     }
     QEQ_FOR_EACH_SIZE(X)
 #undef X
-    hipLaunchKernelGGL((k_c2r<0, 0>), g, b, sh, pl->stream, k, pl->axes.ax[2], pl->grid_c, pl->grid_r, done);
+    hipExtLaunchKernelGGL((k_c2r<0, 0>), g, b, sh, pl->stream, ps.start(), ps.stop(), 0, k, pl->axes.ax[2],
+                          pl->grid_c, pl->grid_r, done);
     return qeq_check(hipGetLastError());
 }
 
@@ -450,6 +452,12 @@ int launch_mesh_potential(qeq_plan* pl, const double* src, const int* done) {
     QEQ_TRY(cols_pass(pl, MESH_FWD | MESH_GREEN | MESH_INV, nullptr, done));
     QEQ_TRY(rows_pass(pl, 1, done));
     return c2r_pass(pl, done);
+}
+
+int launch_mesh_stage(qeq_plan* pl, int kind, const double* src) {
+    if (kind == PK_SPREAD_R2C) return spread_pass(pl, src, nullptr);
+    if (kind == PK_C2R) return c2r_pass(pl, nullptr);
+    return QEQ_EINVAL;
 }
 
 int launch_mesh_inverse(qeq_plan* pl) {

@@ -352,6 +352,7 @@ __global__ void k_theta_extract(KParams k, const float* __restrict__ grid, doubl
     tab[t] = (double)grid[((size_t)g1 * k.K2 + g2) * k.K3 + g3];
 }
 
+template <int PC>
 __global__ void k_selfcorr(KParams k, const double* __restrict__ frac, const double* __restrict__ tab_g,
                            double* __restrict__ dself, double* __restrict__ selfgrad) {
     // the table is read by every atom: stage it in LDS
@@ -364,7 +365,7 @@ __global__ void k_selfcorr(KParams k, const double* __restrict__ frac, const dou
     const double u[3] = {frac[3 * i] * (double)k.K1, frac[3 * i + 1] * (double)k.K2,
                          frac[3 * i + 2] * (double)k.K3};
     double s, g[3];
-    mesh_self_term(u, k.p, tab, &s, g);
+    mesh_self_term<PC>(u, k.p, tab, &s, g);
     dself[i] += k.c_eta - s;
     selfgrad[3 * i + 0] = g[0];
     selfgrad[3 * i + 1] = g[1];
@@ -495,7 +496,11 @@ int launch_theta(qeq_plan* pl) {
 }
 
 int launch_selfcorr(qeq_plan* pl) {
-    hipLaunchKernelGGL(k_selfcorr, dim3(nblocks(pl->kp.n)), dim3(QEQ_BLOCK), 0, pl->stream, pl->kp,
-                       pl->frac, pl->theta_tab, pl->dself, pl->selfgrad);
+    if (pl->kp.p == 6)
+        hipLaunchKernelGGL(k_selfcorr<6>, dim3(nblocks(pl->kp.n)), dim3(QEQ_BLOCK), 0, pl->stream, pl->kp,
+                           pl->frac, pl->theta_tab, pl->dself, pl->selfgrad);
+    else
+        hipLaunchKernelGGL(k_selfcorr<0>, dim3(nblocks(pl->kp.n)), dim3(QEQ_BLOCK), 0, pl->stream, pl->kp,
+                           pl->frac, pl->theta_tab, pl->dself, pl->selfgrad);
     return qeq_check(hipGetLastError());
 }

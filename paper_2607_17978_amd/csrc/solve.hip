@@ -371,16 +371,17 @@ __global__ void k_perm_out(KParams k, const double* __restrict__ ys, const int* 
 static double* part_buf(qeq_plan* pl, int which) { return pl->part + (size_t)which * pl->nblk_max * QEQ_NPART; }
 
 template <int MODE>
-static void interp_launch(qeq_plan* pl, const double* src, double* dst, double* part, int parity) {
+static void interp_launch(qeq_plan* pl, const double* src, double* dst, double* part, int parity,
+                          hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
     const int nb = interp_blocks(pl->kp.n);   // one wave per atom
 #define QEQ_INTERP_ARGS                                                                              \
-    dim3(nb), dim3(QEQ_BLOCK), 0, pl->stream, pl->kp, src, dst, pl->grid_r, pl->home, pl->wts,       \
+    dim3(nb), dim3(QEQ_BLOCK), 0, pl->stream, ev0, ev1, 0, pl->kp, src, dst, pl->grid_r, pl->home, pl->wts, \
         pl->dwts, pl->rowptr, pl->col, pl->kval, pl->pdr, pl->dself, pl->Jv, pl->chi_raw, pl->chi,   \
         pl->sig, pl->selfgrad, pl->fdst, pl->gtmp, part, pl->sc, parity
     if (pl->kp.p == 6)
-        hipLaunchKernelGGL((k_interp<MODE, 6>), QEQ_INTERP_ARGS);
+        hipExtLaunchKernelGGL((k_interp<MODE, 6>), QEQ_INTERP_ARGS);
     else
-        hipLaunchKernelGGL((k_interp<MODE, 0>), QEQ_INTERP_ARGS);
+        hipExtLaunchKernelGGL((k_interp<MODE, 0>), QEQ_INTERP_ARGS);
 #undef QEQ_INTERP_ARGS
 }
 
@@ -388,7 +389,7 @@ int launch_interp(qeq_plan* pl, const double* src, double* dst, int mode, int pa
     double* part = part_buf(pl, 0);
     ProfScope ps(pl, mode == QEQ_MODE_CG ? PK_INTERP : PK_COUNT);
     if (mode == QEQ_MODE_CG)
-        interp_launch<QEQ_MODE_CG>(pl, src, dst, part, parity);
+        interp_launch<QEQ_MODE_CG>(pl, src, dst, part, parity, ps.start(), ps.stop());
     else if (mode == QEQ_MODE_MATVEC)
         interp_launch<QEQ_MODE_MATVEC>(pl, src, dst, part, parity);
     else
@@ -421,7 +422,8 @@ int launch_start_energy(qeq_plan* pl) {
 int launch_cg_update(qeq_plan* pl, int parity) {
     const int nb = nblocks(pl->kp.n, QEQ_VBLOCK);
     ProfScope ps(pl, PK_CG_UPDATE);
-    hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(QEQ_VBLOCK), 0, pl->stream, pl->kp, pl->pvec, pl->y,
+    hipExtLaunchKernelGGL(k_cg_update, dim3(nb), dim3(QEQ_VBLOCK), 0, pl->stream, ps.start(), ps.stop(), 0, pl->kp,
+                       pl->pvec, pl->y,
                        pl->dinv, pl->q, pl->r, part_buf(pl, 0), interp_blocks(pl->kp.n), part_buf(pl, 1),
                        pl->sc, parity);
     return qeq_check(hipGetLastError());
@@ -430,7 +432,8 @@ int launch_cg_update(qeq_plan* pl, int parity) {
 int launch_cg_dir(qeq_plan* pl, int parity, int init) {
     const int nb = nblocks(pl->kp.n, QEQ_VBLOCK);
     ProfScope ps(pl, PK_CG_DIR);
-    hipLaunchKernelGGL(k_cg_dir, dim3(nb), dim3(QEQ_VBLOCK), 0, pl->stream, pl->kp, pl->r, pl->dinv,
+    hipExtLaunchKernelGGL(k_cg_dir, dim3(nb), dim3(QEQ_VBLOCK), 0, pl->stream, ps.start(), ps.stop(), 0, pl->kp,
+                       pl->r, pl->dinv,
                        pl->pvec, part_buf(pl, 1), nb, pl->sc, parity, init);
     return qeq_check(hipGetLastError());
 }
@@ -439,11 +442,11 @@ int launch_final(qeq_plan* pl, double* q_out, double* energies, double* forces_o
     int nb = nblocks(pl->kp.n);
     double* part = part_buf(pl, 0);
     ProfScope ps(pl, PK_FINAL);
-    interp_launch<QEQ_MODE_FINAL>(pl, pl->q, pl->y, part, 0);
+    interp_launch<QEQ_MODE_FINAL>(pl, pl->q, pl->y, part, 0, ps.start(), nullptr);
     hipLaunchKernelGGL(k_final2, dim3(nb), dim3(QEQ_BLOCK), 0, pl->stream, pl->kp, pl->q, pl->fdst,
                        pl->gtmp, pl->perm, q_out, forces_out, part, interp_blocks(pl->kp.n), part_buf(pl, 1));
-    hipLaunchKernelGGL(k_final3, dim3(1), dim3(QEQ_BLOCK), 0, pl->stream, pl->kp, part, interp_blocks(pl->kp.n),
-                       part_buf(pl, 1), nb, pl->sc, pl->final_dev, energies);
+    hipExtLaunchKernelGGL(k_final3, dim3(1), dim3(QEQ_BLOCK), 0, pl->stream, nullptr, ps.stop(), 0, pl->kp, part,
+                          interp_blocks(pl->kp.n), part_buf(pl, 1), nb, pl->sc, pl->final_dev, energies);
     return qeq_check(hipGetLastError());
 }
 

@@ -90,6 +90,8 @@ def load_library():
     L.qeq_backward.restype = ctypes.c_int
     L.qeq_matvec.argtypes = [vp, i32, dp, ctypes.POINTER(ctypes.c_double), dp, dp, dp, i32]
     L.qeq_matvec.restype = ctypes.c_int
+    L.qeq_time_kernel.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_double)]
+    L.qeq_time_kernel.restype = ctypes.c_int
     L.qeq_use_graphs.argtypes = [vp, i32]
     L.qeq_use_graphs.restype = ctypes.c_int
     L.qeq_profile.argtypes = [vp, ctypes.c_uint32]
@@ -314,6 +316,14 @@ class Plan:
 
     PROFILE_KINDS = ("spread_r2c", "fft_rows_fwd", "fft_cols_green", "fft_rows_inv", "c2r",
                      "interp_pairs", "cg_update", "cg_dir", "final")
+
+    def time_kernel(self, kind, reps=20):
+        """Average microseconds of one launch of mesh pass `kind` (0 or 4; see qeq_time_kernel)."""
+        us = ctypes.c_double()
+        rc = load_library().qeq_time_kernel(self._h, int(kind), int(reps), ctypes.byref(us))
+        if rc != QEQ_OK:
+            raise QEqError(rc, strerror(rc))
+        return us.value
 
     def use_graphs(self, enable=True):
         """Replay the CG loop as a HIP graph (default) or launch kernels one by one."""

@@ -97,7 +97,11 @@ def test_batched_equals_single_and_split(dev):
     plan.close()
 
 
-@pytest.mark.parametrize("shape", [(256, 2), (1024, 1), (512, 1)])
+@pytest.mark.parametrize("shape", [
+    pytest.param((256, 2), marks=pytest.mark.skip(
+        reason="256-thread workgroups are disabled: a run of this shape ended in a GPU fault whose cause "
+               "has not been found; qeq_batched_config rejects 256")),
+    (1024, 1), (512, 1), (512, 2)])
 def test_batched_launch_shapes_agree(dev, shape):
     from paper_2607_17978_amd import qeq
     structs = [gen.batch_structure(s) for s in range(8)]
@@ -108,6 +112,17 @@ def test_batched_launch_shapes_agree(dev, shape):
     q1, _, _, st, rc = plan.solve_batched(**a)
     assert rc == 0
     assert np.abs(q1.cpu().numpy() - q0).max() < 1e-6
+    plan.close()
+
+
+def test_batched_config_rejects_disabled_shapes(dev):
+    """Host-side check only: the disabled 256-thread shape is refused before any launch."""
+    from paper_2607_17978_amd import qeq
+    plan = qeq.Plan(64, eta=ETA, r_cut=RC)
+    for shape in ((256, 1), (256, 2), (128, 1), (512, 0), (512, 9)):
+        with pytest.raises(qeq.QEqError):
+            plan.batched_config(*shape)
+    plan.batched_config(512, 2)
     plan.close()
 
 
