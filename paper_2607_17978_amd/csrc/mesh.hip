@@ -8,9 +8,11 @@
 // Passes (each one read and one write of the grid, transforms in LDS):
 //   1. spread + R2C along axis 3  : block = (g1, tile of TW rows g2).  The
 //      atoms whose spline support reaches the tile are staged in LDS, their
-//      weights accumulated into the tile with LDS atomics, two real rows are
-//      packed into one complex FFT and the half spectra written transposed so
-//      that m2 becomes contiguous.
+//      weights accumulated into the tile in 64-bit fixed point with integer
+//      LDS atomics (exact, order-independent sums; FP32 LDS atomics run at a
+//      fraction of the integer rate on gfx950), converted to FP32, two real
+//      rows packed into one complex FFT and the half spectra written
+//      transposed so that m2 becomes contiguous.
 //   2. C2C along axis 2 (rows contiguous), NR rows per block.
 //   3. C2C along axis 1 (stride K2) on tiles of TW columns: forward FFT,
 //      multiplication by G(m) computed on the fly, inverse FFT, in one pass.
@@ -50,19 +52,23 @@ __global__ __launch_bounds__(NT) void k_spread_r2c(KParams k, FftAxis ax3, const
     const int TW = TWC ? TWC : k.TWS;
     const int p = PC ? PC : k.p;
     const int ncol = TW >> 1;
+    // LDS: twiddles | accumulator acc[g3][row] (int64; the FFT buffer
+    // buf[g3][pr] (complex) aliases its first half once converted) | staging
     float2* tw = sm;
+    long long* acc = reinterpret_cast<long long*>(sm + K3);
     float2* buf = sm + K3;
-    float* cw = reinterpret_cast<float*>(buf + K3 * ncol);   // [SPREAD_CAND][SPREAD_CW]
+    float* cw = reinterpret_cast<float*>(acc + K3 * TW);                // [SPREAD_CAND][SPREAD_CW]
     int* ch = reinterpret_cast<int*>(cw + SPREAD_CAND * SPREAD_CW);   // [SPREAD_CAND][2]
     __shared__ int seg_lo[2 * QEQ_MAXP], seg_off[2 * QEQ_MAXP + 1], seg_k1[2 * QEQ_MAXP];
     __shared__ int nseg;
+    __shared__ float sh_scale;
     const int tid = threadIdx.x;
     const int g1 = blockIdx.x / k.ntile_s;
     const int g20 = (blockIdx.x - g1 * k.ntile_s) * TW;
     const int K1 = k.K1, K2 = k.K2;
 
     for (int t = tid; t < K3; t += NT) tw[t] = ax3.tw[t];
-    for (int t = tid; t < K3 * ncol; t += NT) buf[t] = make_float2(0.f, 0.f);
+    for (int t = tid; t < K3 * TW; t += NT) acc[t] = 0;
     // candidate segments: for each k1, homes h1 = g1 + k1 and h2 in [g20, g20 + TW + p - 1)
     // (two pieces when the h2 range wraps); lanes k1 < p fetch their bounds in parallel
     __shared__ int seg_len[2 * QEQ_MAXP];
@@ -99,6 +105,27 @@ __global__ __launch_bounds__(NT) void k_spread_r2c(KParams k, FftAxis ax3, const
     }
     __syncthreads();
     const int ncand = seg_off[nseg];
+    // Fixed-point scale: every grid value of the tile is a sum over the
+    // candidates of src times a weight product <= 1, taken at most once per
+    // candidate, so |value| <= S = sum |src|; with scale = 2^(60 - e),
+    // S < 2^e, every partial sum stays below 2^60 in magnitude.
+    {
+        double v[1] = {0.0};
+        for (int cidx = tid; cidx < ncand; cidx += NT) {
+            int sg = 0;
+            while (cidx >= seg_off[sg + 1]) ++sg;
+            v[0] += fabs(src[seg_lo[sg] + (cidx - seg_off[sg])]);
+        }
+        block_sum<1>(v);
+        if (tid == 0) {
+            int e = 0;
+            (void)frexp(v[0] > 0.0 ? v[0] : 1.0, &e);   // v < 2^e
+            sh_scale = ldexpf(1.0f, max(-126, min(126, 60 - e)));
+        }
+        __syncthreads();
+    }
+    const float scale = sh_scale;
+    unsigned long long* acc_u = reinterpret_cast<unsigned long long*>(acc);
     for (int base = 0; base < ncand; base += SPREAD_CAND) {
         const int cnt = min(SPREAD_CAND, ncand - base);
         if (tid < cnt) {
@@ -109,7 +136,7 @@ __global__ __launch_bounds__(NT) void k_spread_r2c(KParams k, FftAxis ax3, const
             const int k1 = seg_k1[sg];
             const float* w = wts + (size_t)a * 3 * QEQ_MAXP;
             float* dstw = cw + tid * SPREAD_CW;
-            dstw[0] = (float)src[a] * w[k1];
+            dstw[0] = (float)src[a] * w[k1] * scale;
             for (int kk = 0; kk < p; ++kk) {
                 dstw[1 + kk] = w[QEQ_MAXP + kk];
                 dstw[1 + QEQ_MAXP + kk] = w[2 * QEQ_MAXP + kk];
@@ -130,13 +157,49 @@ __global__ __launch_bounds__(NT) void k_spread_r2c(KParams k, FftAxis ax3, const
             const float* cwc = cw + c * SPREAD_CW;
             const float a0 = cwc[0] * cwc[1 + k2];
             const int h3 = ch[2 * c + 1];
-            float* col = reinterpret_cast<float*>(buf) + (r >> 1) * 2 + (r & 1);
 #pragma unroll
             for (int k3 = 0; k3 < (PC ? PC : QEQ_MAXP); ++k3) {
                 if (!PC && k3 >= p) break;
                 int g3 = h3 - k3;
                 if (g3 < 0) g3 += K3;
-                atomicAdd(col + 2 * g3 * ncol, a0 * cwc[1 + QEQ_MAXP + k3]);
+                const long long v = __float2ll_rn(a0 * cwc[1 + QEQ_MAXP + k3]);
+                atomicAdd(acc_u + g3 * TW + r, (unsigned long long)v);
+            }
+        }
+        __syncthreads();
+    }
+    // fixed point -> FP32, packed two real rows per complex column
+    {
+        const float inv = 1.0f / scale;
+        constexpr int PER = KC > 0 && TWC > 0 ? (KC * (TWC / 2) + NT - 1) / NT : 1;
+        if constexpr (KC > 0 && TWC > 0) {
+            float2 v[PER];
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const int e = tid + u * NT;
+                if (e < KC * (TWC / 2)) {
+                    const int g3 = e / (TWC / 2), pr = e - g3 * (TWC / 2);
+                    v[u] = make_float2((float)acc[g3 * TWC + 2 * pr] * inv, (float)acc[g3 * TWC + 2 * pr + 1] * inv);
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const int e = tid + u * NT;
+                if (e < KC * (TWC / 2)) buf[e] = v[u];
+            }
+        } else {
+            // runtime sizes: convert through registers one chunk of NT at a time
+            for (int e0 = 0; e0 < K3 * ncol; e0 += NT) {
+                const int e = e0 + tid;
+                float2 v = make_float2(0.f, 0.f);
+                if (e < K3 * ncol) {
+                    const int g3 = e / ncol, pr = e - g3 * ncol;
+                    v = make_float2((float)acc[g3 * TW + 2 * pr] * inv, (float)acc[g3 * TW + 2 * pr + 1] * inv);
+                }
+                __syncthreads();
+                if (e < K3 * ncol) buf[e] = v;
+                __syncthreads();
             }
         }
         __syncthreads();
@@ -205,20 +268,23 @@ __global__ __launch_bounds__(NT) void k_fft_rows(KParams k, FftAxis ax2, float2*
 //   G(m) = (4 pi / V) exp(-eta^2 k^2 / 2) / k^2 |b_1(m_1)|^2 |b_2(m_2)|^2 |b_3(m_3)|^2,
 // k = 2 pi H^{-1} m; G = 0 at m = 0 and on the Nyquist planes (where the
 // half-spectrum symmetry of a triclinic cell is ambiguous; the Gaussian there
-// is below 1e-14 for grids at the supported spacings).
+// is below 1e-14 for grids at the supported spacings).  Evaluated in FP32: it
+// multiplies an FP32 spectrum, and FP32 exp / divide keep its relative error
+// at a few ulp.
 __device__ __forceinline__ float green_value(const KParams& k, int m1, int m2, int m3,
                                              const float* __restrict__ b1, const float* __restrict__ b2,
                                              const float* __restrict__ b3) {
     if ((m1 | m2 | m3) == 0) return 0.f;
     if (2 * m1 == k.K1 || 2 * m2 == k.K2 || 2 * m3 == k.K3) return 0.f;
-    const double x1 = m1 <= k.K1 / 2 ? m1 : m1 - k.K1;
-    const double x2 = m2 <= k.K2 / 2 ? m2 : m2 - k.K2;
-    const double x3 = m3;
-    const double q = k.M[0] * x1 * x1 + k.M[1] * x2 * x2 + k.M[2] * x3 * x3 +
-                     2.0 * (k.M[3] * x1 * x2 + k.M[4] * x1 * x3 + k.M[5] * x2 * x3);
-    const double k2 = 39.478417604357434475 * q;   // (2 pi)^2
-    const double g = k.green_pref * exp(-0.5 * k.eta * k.eta * k2) / k2;
-    return (float)g * b1[m1] * b2[m2] * b3[m3];
+    const float x1 = (float)(m1 <= k.K1 / 2 ? m1 : m1 - k.K1);
+    const float x2 = (float)(m2 <= k.K2 / 2 ? m2 : m2 - k.K2);
+    const float x3 = (float)m3;
+    const float q = (float)k.M[0] * x1 * x1 + (float)k.M[1] * x2 * x2 + (float)k.M[2] * x3 * x3 +
+                    2.0f * ((float)k.M[3] * x1 * x2 + (float)k.M[4] * x1 * x3 + (float)k.M[5] * x2 * x3);
+    const float k2 = 39.478417604357434475f * q;   // (2 pi)^2
+    const float eta = (float)k.eta;
+    const float g = (float)k.green_pref * expf(-0.5f * eta * eta * k2) / k2;
+    return g * b1[m1] * b2[m2] * b3[m3];
 }
 
 // ------------------------------------------------------------------ pass 3
@@ -345,7 +411,7 @@ __global__ void k_write_green(KParams k, float2* __restrict__ C, const float* __
 }
 
 size_t smem_spread(const KParams& k) {
-    return sizeof(float2) * ((size_t)k.K3 + (size_t)k.K3 * (k.TWS / 2)) +
+    return sizeof(float2) * (size_t)k.K3 + sizeof(long long) * (size_t)k.K3 * k.TWS +
            SPREAD_CAND * (SPREAD_CW * sizeof(float) + 2 * sizeof(int));
 }
 size_t smem_rows(const KParams& k) { return sizeof(float2) * ((size_t)k.K2 + (size_t)k.K2 * (k.NR + 1)); }
@@ -363,14 +429,21 @@ int spread_pass(qeq_plan* pl, const double* src, const int* done) {
     dim3 g(k.K1 * k.ntile_s), b(NT);
     const size_t sh = smem_spread(k);
     ProfScope ps(pl, PK_SPREAD_R2C);
+    // the int64 accumulator of long axes can exceed the default 64 KB window
 #define X(KK, TT)                                                                                  \
     if (k.K3 == KK && k.TWS == TT && k.p == 6) {                                                    \
+        if (sh > 65536)                                                                            \
+            QEQ_HIP(hipFuncSetAttribute((const void*)k_spread_r2c<KK, TT, 6>,                      \
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));     \
         hipExtLaunchKernelGGL((k_spread_r2c<KK, TT, 6>), g, b, sh, pl->stream, ps.start(), ps.stop(), 0, k, \
                               pl->axes.ax[2], src, pl->bin_start, pl->home, pl->wts, pl->grid_c, done);   \
         return qeq_check(hipGetLastError());                                                       \
     }
     QEQ_FOR_EACH_SPREAD(X)
 #undef X
+    if (sh > 65536)
+        QEQ_HIP(hipFuncSetAttribute((const void*)k_spread_r2c<0, 0, 0>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)sh));
     hipExtLaunchKernelGGL((k_spread_r2c<0, 0, 0>), g, b, sh, pl->stream, ps.start(), ps.stop(), 0, k,
                           pl->axes.ax[2], src, pl->bin_start, pl->home, pl->wts, pl->grid_c, done);
     return qeq_check(hipGetLastError());
