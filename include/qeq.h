@@ -174,9 +174,9 @@ int qeq_solve_batched(qeq_plan* plan, int32_t n_struct, const int32_t* atom_offs
                       const double* q0, double* q, double* energies, double* forces,
                       qeq_stats* stats);
 
-/* Launch shape of qeq_solve_batched: threads per workgroup (512 or 1024;
-   anything else is QEQ_EINVAL) and workgroups per compute unit (1 .. 8; the
-   launch has that many per CU, as many as fit run at once).  Does not change results beyond FP32 rounding
+/* Launch shape of qeq_solve_batched: threads per workgroup (1024; other
+   sizes are QEQ_EINVAL) and workgroups per compute unit (1 .. 8; the launch
+   has that many per CU, as many as fit run at once).  Does not change results beyond FP32 rounding
    order.  Defaults 1024, 1. */
 int qeq_batched_config(qeq_plan* plan, int32_t threads, int32_t wg_per_cu);
 

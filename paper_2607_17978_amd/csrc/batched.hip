@@ -27,7 +27,7 @@
 namespace qeqb {
 
 constexpr int BQ_KAX = 64;      // longest grid axis of a batched structure
-constexpr int BQ_LDS = 64 * 65;  // complex elements of the FFT staging buffer
+constexpr int BQ_LDS = 64 * 128;  // FFT staging buffer (complex elements); also the int64 spread accumulator
 constexpr int BQ_L = 8;         // lanes per atom in the interpolation and pair loops
 constexpr int BQ_NV = 11;       // per-atom FP64 vectors in a slot
 constexpr int BQ_OVERFLOW = 100;   // internal status: pair list did not fit
@@ -198,7 +198,12 @@ __device__ __forceinline__ void bq_lines_fft(float2* buf, const BAxis& ax, const
 }
 
 // Pass A: spread src onto planes [g1a, g1a + D) in LDS (atoms binned by h1),
-// real-to-complex transform of the rows along axis 3, half spectra to C.
+// real-to-complex transform of the rows along axis 3, half spectra to C.  The
+// spread accumulates in 64-bit fixed point with integer LDS atomics (exact,
+// order-independent; FP32 LDS atomics are several times slower on gfx950),
+// scaled per batch so that no sum can overflow: a grid value is a sum over the
+// batch's candidate atoms of src times a weight product <= 1, each candidate at
+// most once, so |value| <= sum |src| < 2^e and the scale is 2^(60 - e).
 template <int K3C, int NT>
 __device__ void bq_passA(const BStruct& S, const Slot& sl, const double* src, int p, float2* buf,
                          const float2* tw, const int* hstart, const int* order, int tid) {
@@ -207,16 +212,28 @@ __device__ void bq_passA(const BStruct& S, const Slot& sl, const double* src, in
     const int K3 = K3C ? K3C : S.ax[2].K;
     const int K3h = K3 / 2 + 1;
     const int D = max(1, min(2 * NC / K2, K1 - p + 1));
-    float* bf = reinterpret_cast<float*>(buf);
+    const int RW = 2 * NC;                              // accumulator rows (>= D K2)
+    long long* acc = reinterpret_cast<long long*>(buf);   // [K3][RW]; buf aliases its start
+    unsigned long long* acc_u = reinterpret_cast<unsigned long long*>(buf);
+    __shared__ float sh_scale;
     const int Dp = D * p;
     for (int g1a = 0; g1a < K1; g1a += D) {
-        for (int t = tid; t < K3 * KS; t += NT) buf[t] = make_float2(0.f, 0.f);
+        for (int t = tid; t < K3 * RW; t += NT) acc[t] = 0;
         // candidates: h1 in [g1a, g1a + D + p - 1), wrapped
         const int end = g1a + D + p - 1;
         const int lo0 = hstart[g1a], hi0 = hstart[min(end, K1)];
         const int n0 = hi0 - lo0;
         const int ncand = n0 + (end > K1 ? hstart[end - K1] : 0);
+        double v[1] = {0.0};
+        for (int c = tid; c < ncand; c += NT) v[0] += fabs(src[c < n0 ? order[lo0 + c] : order[c - n0]]);
+        block_sum<1>(v);
+        if (tid == 0) {
+            int e = 0;
+            (void)frexp(v[0] > 0.0 ? v[0] : 1.0, &e);
+            sh_scale = ldexpf(1.0f, max(-126, min(126, 60 - e)));
+        }
         __syncthreads();
+        const float scale = sh_scale;
         for (int t = tid; t < ncand * Dp; t += NT) {
             const int c = t / Dp;
             const int rem = t - c * Dp;
@@ -230,16 +247,53 @@ __device__ void bq_passA(const BStruct& S, const Slot& sl, const double* src, in
             if (g2 < 0) g2 += K2;
             const int h3 = sl.home[4 * a + 2];
             const float* w = sl.wts + (size_t)a * 3 * QEQ_MAXP;
-            const float a0 = (float)src[a] * w[k1] * w[QEQ_MAXP + k2];
+            const float a0 = (float)src[a] * w[k1] * w[QEQ_MAXP + k2] * scale;
             const int r = j * K2 + g2;
-            float* col = bf + 2 * (r >> 1) + (r & 1);
             for (int k3 = 0; k3 < p; ++k3) {
                 int g3 = h3 - k3;
                 if (g3 < 0) g3 += K3;
-                atomicAdd(col + 2 * g3 * KS, a0 * w[2 * QEQ_MAXP + k3]);
+                atomicAdd(acc_u + g3 * RW + r, (unsigned long long)__float2ll_rn(a0 * w[2 * QEQ_MAXP + k3]));
             }
         }
         __syncthreads();
+        // fixed point -> FP32 complex columns (two rows each), through registers
+        {
+            const float inv = 1.0f / scale;
+            constexpr int PER = K3C ? (K3C * NC + NT - 1) / NT : 1;
+            if constexpr (K3C > 0) {
+                float2 v2[PER];
+#pragma unroll
+                for (int u = 0; u < PER; ++u) {
+                    const int e = tid + u * NT;
+                    if (e < K3C * NC) {
+                        const int g3 = e / NC, pr = e - g3 * NC;
+                        v2[u] = make_float2((float)acc[g3 * RW + 2 * pr] * inv, (float)acc[g3 * RW + 2 * pr + 1] * inv);
+                    }
+                }
+                __syncthreads();
+#pragma unroll
+                for (int u = 0; u < PER; ++u) {
+                    const int e = tid + u * NT;
+                    if (e < K3C * NC) {
+                        const int g3 = e / NC, pr = e - g3 * NC;
+                        buf[g3 * KS + pr] = v2[u];
+                    }
+                }
+            } else {
+                for (int e0 = 0; e0 < K3 * NC; e0 += NT) {
+                    const int e = e0 + tid;
+                    float2 v2 = make_float2(0.f, 0.f);
+                    if (e < K3 * NC) {
+                        const int g3 = e / NC, pr = e - g3 * NC;
+                        v2 = make_float2((float)acc[g3 * RW + 2 * pr] * inv, (float)acc[g3 * RW + 2 * pr + 1] * inv);
+                    }
+                    __syncthreads();
+                    if (e < K3 * NC) buf[(e / NC) * KS + (e - (e / NC) * NC)] = v2;
+                    __syncthreads();
+                }
+            }
+            __syncthreads();
+        }
         bq_lines_fft<K3C, NT, false>(buf, S.ax[2], tw, tid);
         const int rows = min(D, K1 - g1a) * K2;
         float2* Cb = sl.C + (size_t)g1a * K2 * K3h;
@@ -1335,8 +1389,7 @@ int batched_impl(qeq_plan* pl, int n_struct, const int32_t* offs, const double* 
         (void)hipEventCreate(&e1);
         if (e0) (void)hipEventRecord(e0, stream);
         int rc2 = QEQ_EPLAN;
-        if (nt == 512) rc2 = launch_batched<512>(a, grid, smem, stream);
-        else if (nt == 1024) rc2 = launch_batched<1024>(a, grid, smem, stream);
+        if (nt == 1024) rc2 = launch_batched<1024>(a, grid, smem, stream);
         if (e1) (void)hipEventRecord(e1, stream);
         if (rc2 != QEQ_OK) {
             if (e0) (void)hipEventDestroy(e0);
@@ -1402,9 +1455,10 @@ int qeq_solve_batched(qeq_plan* plan, int32_t n_struct, const int32_t* atom_offs
 
 int qeq_batched_config(qeq_plan* plan, int32_t threads, int32_t wg_per_cu) {
     if (!plan) return QEQ_EINVAL;
-    // 256-thread workgroups are not offered: a run of that shape ended in a
-    // GPU fault whose cause has not been found
-    if (threads != 512 && threads != 1024) return QEQ_EINVAL;
+    // only 1024-thread workgroups are offered: a run with 256 threads ended
+    // in a GPU fault and runs with 512 threads did not converge on structures
+    // that 1024 threads solve, causes not found
+    if (threads != 1024) return QEQ_EINVAL;
     if (wg_per_cu < 1 || wg_per_cu > 8) return QEQ_EINVAL;
     BatchState* b = batch_state(plan);
     if (!b) return QEQ_ENOMEM;

@@ -101,7 +101,10 @@ def test_batched_equals_single_and_split(dev):
     pytest.param((256, 2), marks=pytest.mark.skip(
         reason="256-thread workgroups are disabled: a run of this shape ended in a GPU fault whose cause "
                "has not been found; qeq_batched_config rejects 256")),
-    (1024, 1), (512, 1), (512, 2)])
+    pytest.param((512, 1), marks=pytest.mark.skip(
+        reason="512-thread workgroups are disabled: with the fixed-point spread they returned "
+               "NOT_CONVERGED on structures the 1024-thread shape solves; cause not found")),
+    (1024, 1), (1024, 2)])
 def test_batched_launch_shapes_agree(dev, shape):
     from paper_2607_17978_amd import qeq
     structs = [gen.batch_structure(s) for s in range(8)]
@@ -119,10 +122,10 @@ def test_batched_config_rejects_disabled_shapes(dev):
     """Host-side check only: the disabled 256-thread shape is refused before any launch."""
     from paper_2607_17978_amd import qeq
     plan = qeq.Plan(64, eta=ETA, r_cut=RC)
-    for shape in ((256, 1), (256, 2), (128, 1), (512, 0), (512, 9)):
+    for shape in ((256, 1), (256, 2), (128, 1), (512, 1), (1024, 0), (1024, 9)):
         with pytest.raises(qeq.QEqError):
             plan.batched_config(*shape)
-    plan.batched_config(512, 2)
+    plan.batched_config(1024, 2)
     plan.close()
 
 
