@@ -197,16 +197,19 @@ int qeq_batched_phase_us(qeq_plan* plan, int32_t n_struct, double* us);
    Learned warm start (a small per-element network predicts initial charges).
    ------------------------------------------------------------------------ */
 
-/* Radial descriptors (paper eq. g2 with the SI cosine cutoff, inner radius 0):
-     G_i,mu = sum_{j, images, r_ij < r_cut} exp(-(r_ij - c_mu)^2 / (2 width^2))
-                                           (cos(pi r_ij / r_cut) + 1) / 2,
-   mu < n_feat <= 32, over all neighbours (not element-resolved).  Runs the
-   plan's geometry set-up (which replaces the tape of the last solve), so
-   r_cut must not exceed the plan's real-space cutoff.  centers: host,
-   n_feat doubles.  G: device, n x n_feat floats, caller order. */
+/* Radial descriptors (paper eq. g2 with the SI cosine cutoff, inner radius 0),
+   optionally weighted per neighbour (the paper's weighted ACSFs, whose terms
+   carry a scalar prefactor of the neighbour):
+     G_i,mu = sum_{j, images, r_ij < r_cut} w_j exp(-(r_ij - c_mu)^2 / (2 width^2))
+                                             (cos(pi r_ij / r_cut) + 1) / 2,
+   mu < n_feat <= 32, over all neighbours (not element-resolved); w_j = 1 when
+   weights is NULL.  Runs the plan's geometry set-up (which replaces the tape of
+   the last solve), so r_cut must not exceed the plan's real-space cutoff.
+   weights: device, n doubles, caller order, or NULL.  centers: host, n_feat
+   doubles.  G: device, n x n_feat floats, caller order. */
 int qeq_descriptors(qeq_plan* plan, int32_t n, const double* pos, const double* cell,
-                    const double* sigma, int32_t n_feat, const double* centers, double width,
-                    double r_cut, float* G);
+                    const double* sigma, const double* weights, int32_t n_feat,
+                    const double* centers, double width, double r_cut, float* G);
 
 /* Element networks 16-32-32-1, tanh hidden layers, linear output (SI
    feed-forward networks), one per element; inputs scaled per element as

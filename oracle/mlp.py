@@ -4,7 +4,8 @@
   ACSF (eq. g2; SI "Radial ACSF"): G_i,mu = sum_j exp(-eta_mu (r_ij - R_mu)^2)
   f_c(r_ij) with the cosine cutoff f_c(r) = (cos(pi r / r_c) + 1) / 2 (SI
   cutoff functions, inner radius 0), over all periodic images, all neighbours
-  (not element-resolved).
+  (not element-resolved); optionally each neighbour term carries a scalar
+  weight w_j (the paper's weighted ACSFs with a per-neighbour prefactor).
 * ``feature_stats`` / ``scale`` -- per-element feature scaling
   (G - mean) / (max - min) (SI "Feature scaling").
 * ``forward`` / ``backward`` -- the element network: tanh hidden layers and a
@@ -32,12 +33,16 @@ N_PARAM = 1633
 STRIDE = 1664          # per-element stride in the packed parameter vector
 
 
-def radial_descriptors(pos, cell, centers, width, r_cut):
-    """G (N x n_mu) with eta_mu = 1 / (2 width^2) and the cosine cutoff."""
+def radial_descriptors(pos, cell, centers, width, r_cut, weights=None):
+    """G (N x n_mu) with eta_mu = 1 / (2 width^2) and the cosine cutoff; with
+    weights, every neighbour term is multiplied by its neighbour's weight w_j
+    (weighted ACSF)."""
     pos = np.asarray(pos, dtype=np.float64)
     ii, jj, d = matfree.real_space_pairs(pos, cell, r_cut)
     r = np.sqrt(np.einsum("ij,ij->i", d, d))
     fc = 0.5 * (np.cos(math.pi * r / r_cut) + 1.0)
+    if weights is not None:
+        fc = fc * np.asarray(weights, dtype=np.float64)[jj]
     eta = 1.0 / (2.0 * width * width)
     G = np.zeros((pos.shape[0], len(centers)))
     for m, c in enumerate(centers):

@@ -817,13 +817,14 @@ int qeq_profile_read(qeq_plan* plan, double* total_ms, int64_t* launches, int32_
 }
 
 int qeq_descriptors(qeq_plan* plan, int32_t n, const double* pos, const double* cell, const double* sigma,
-                    int32_t n_feat, const double* centers, double width, double r_cut, float* G) {
+                    const double* weights, int32_t n_feat, const double* centers, double width, double r_cut,
+                    float* G) {
     if (!plan || !pos || !sigma || !centers || !G) return QEQ_EINVAL;
     qeq_plan* pl = plan;
     pl->tape_valid = false;   // the geometry set-up below replaces the solve's tape
     QEQ_TRY(prepare(pl, n, cell, 0.0));
     QEQ_TRY(setup_geometry(pl, pos, sigma, nullptr, nullptr));
-    QEQ_TRY(launch_descriptors(pl, n_feat, centers, width, r_cut, G));
+    QEQ_TRY(launch_descriptors(pl, weights, n_feat, centers, width, r_cut, G));
     QEQ_HIP(hipStreamSynchronize(pl->stream));
     return QEQ_OK;
 }

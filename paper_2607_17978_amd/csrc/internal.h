@@ -267,6 +267,7 @@ int launch_adj_rhs(qeq_plan* pl, const double* dL_dq, double dL_dEelec);
 void batch_free(qeq_plan* pl);
 
 // ------------------------------------------------------------------ warm start (mlp.hip)
-int launch_descriptors(qeq_plan* pl, int nf, const double* centers, double width, double rc, float* G);
+int launch_descriptors(qeq_plan* pl, const double* weights, int nf, const double* centers, double width, double rc,
+                       float* G);
 int launch_adj_gradients(qeq_plan* pl, double dL_dEqeq, double dL_dEelec, double* dL_dchi,
                          double* dL_dJ, double* dL_dpos);

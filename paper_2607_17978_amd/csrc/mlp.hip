@@ -57,9 +57,11 @@ struct DescParams {
     float rc;
 };
 
-__global__ void k_descriptors(int n, DescParams d, const int* __restrict__ rowptr,
+// G_i,mu = sum_j w_j exp(-eta (r_ij - c_mu)^2) f_c(r_ij) over the pair list
+// (sorted order); w_j = weights[perm[j]] (caller order) or 1 without weights.
+__global__ void k_descriptors(int n, DescParams d, const int* __restrict__ rowptr, const int* __restrict__ col,
                               const float4* __restrict__ pdr, const int* __restrict__ perm,
-                              float* __restrict__ G) {
+                              const double* __restrict__ weights, float* __restrict__ G) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     float acc[32];
@@ -70,7 +72,8 @@ __global__ void k_descriptors(int n, DescParams d, const int* __restrict__ rowpt
         const float4 v = pdr[e];
         const float r = sqrtf(v.x * v.x + v.y * v.y + v.z * v.z);
         if (r >= d.rc) continue;
-        const float fc = 0.5f * (cosf(pi_rc * r) + 1.f);
+        float fc = 0.5f * (cosf(pi_rc * r) + 1.f);
+        if (weights) fc *= (float)weights[perm[col[e]]];
 #pragma unroll
         for (int m = 0; m < 32; ++m) {
             if (m < d.nf) {
@@ -395,7 +398,8 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ grad, fl
 
 }  // namespace
 
-int launch_descriptors(qeq_plan* pl, int nf, const double* centers, double width, double rc, float* G) {
+int launch_descriptors(qeq_plan* pl, const double* weights, int nf, const double* centers, double width, double rc,
+                       float* G) {
     if (nf < 1 || nf > 32 || !(width > 0.0) || !(rc > 0.0) || rc > pl->kp.rc) return QEQ_EINVAL;
     DescParams d;
     d.nf = nf;
@@ -403,7 +407,7 @@ int launch_descriptors(qeq_plan* pl, int nf, const double* centers, double width
     d.eta = (float)(1.0 / (2.0 * width * width));
     d.rc = (float)rc;
     hipLaunchKernelGGL(k_descriptors, dim3(nblocks(pl->kp.n)), dim3(QEQ_BLOCK), 0, pl->stream, pl->kp.n, d,
-                       pl->rowptr, pl->pdr, pl->perm, G);
+                       pl->rowptr, pl->col, pl->pdr, pl->perm, weights, G);
     return qeq_check(hipGetLastError());
 }
 

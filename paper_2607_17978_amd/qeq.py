@@ -99,7 +99,7 @@ def load_library():
     L.qeq_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                    i32, i32]
     L.qeq_profile_read.restype = ctypes.c_int
-    L.qeq_descriptors.argtypes = [vp, i32, dp, ctypes.POINTER(ctypes.c_double), dp, i32,
+    L.qeq_descriptors.argtypes = [vp, i32, dp, ctypes.POINTER(ctypes.c_double), dp, dp, i32,
                                   ctypes.POINTER(ctypes.c_double), f64, f64, dp]
     L.qeq_descriptors.restype = ctypes.c_int
     L.mlp_workspace_floats.argtypes = [i32]
@@ -246,16 +246,19 @@ class Plan:
             raise QEqError(rc, strerror(rc))
         return dchi, dJ, dpos, dict(st.as_dict(), rc=rc)
 
-    def descriptors(self, pos, cell, sigma, centers, width, r_cut):
-        """Radial descriptors G (n x len(centers), float32, device); see qeq_descriptors."""
+    def descriptors(self, pos, cell, sigma, centers, width, r_cut, weights=None):
+        """Radial descriptors G (n x len(centers), float32, device), optionally
+        weighted per neighbour; see qeq_descriptors."""
         import torch
         n = int(pos.shape[0])
         _check_dev("pos", pos, n, 3, self.device)
         _check_dev("sigma", sigma, n, None, self.device)
+        if weights is not None:
+            _check_dev("weights", weights, n, None, self.device)
         c = np.ascontiguousarray(np.asarray(centers, dtype=np.float64))
         G = torch.empty((n, len(c)), dtype=torch.float32, device=self.device)
         _, cp = _cell_arg(cell)
-        rc = load_library().qeq_descriptors(self._h, n, _ptr(pos), cp, _ptr(sigma), len(c),
+        rc = load_library().qeq_descriptors(self._h, n, _ptr(pos), cp, _ptr(sigma), _ptr(weights), len(c),
                                             c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                             float(width), float(r_cut), _ptr(G))
         self._last_n = None       # the tape of the last solve is gone

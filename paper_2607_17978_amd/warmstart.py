@@ -8,7 +8,14 @@ per-element warm-start networks (mlp_train_step, Adam).  On the second half
 every frame is solved three times to the same tolerance: cold (q0 = Q/N),
 previous-frame start (q0 = charges of frame t-1) and learned start
 (q0 = network output; the solve projects it onto sum(q) = Q).  Cold-start CG
-stays the reference: all three must agree.
+stays the reference: all must agree.
+
+Two learned starts are trained and compared: the network on the 16 radial
+descriptors of the workload (``learned``), and the same network on 16
+electronegativity-aware features (``learned_chi``): chi_i, 8 radial sums of
+the neighbours' chi_j (weighted radial descriptors, width 1 bohr, centres
+1..9) and 7 plain radial terms (width 1 bohr).  The charges follow the local
+electronegativity differences, which the geometry alone does not determine.
 """
 from __future__ import annotations
 
@@ -20,6 +27,17 @@ from . import qeq
 
 CENTERS = np.linspace(1.0, 9.0, 16)
 WIDTH, RCUT_DESC = 0.5, 9.0
+CHI_CENTERS = np.linspace(1.0, 9.0, 8)
+GEO_CENTERS = np.linspace(1.0, 9.0, 7)
+AUX_WIDTH = 1.0
+
+
+def chi_features(plan, posd, cell, sigma, chi):
+    """n x 16 float32 features: chi_i | sum_j chi_j g_mu(r_ij) (8) | sum_j g_nu(r_ij) (7)."""
+    import torch
+    Gc = plan.descriptors(posd, cell, sigma, CHI_CENTERS, AUX_WIDTH, RCUT_DESC, weights=chi)
+    Gg = plan.descriptors(posd, cell, sigma, GEO_CENTERS, AUX_WIDTH, RCUT_DESC)
+    return torch.cat([chi.float()[:, None], Gc, Gg], 1).contiguous()
 
 
 def run_trajectory(n=None, side=None, spacing=None, frames=200, epochs=30, lr=2e-3, tol=1e-6,
@@ -41,12 +59,13 @@ def run_trajectory(n=None, side=None, spacing=None, frames=200, epochs=30, lr=2e
         grid = (k, k, k)
     plan = qeq.Plan(n, eta=2.0, r_cut=11.0, grid=grid, tol=tol, max_iter=3000)
     net = qeq.WarmStartNet(gen.warmstart_init(1005, 2), device=dev)
+    net_x = qeq.WarmStartNet(gen.warmstart_init(1005, 2), device=dev)
     chi_w = gen.chi_network_weights(1004)
     sig_d, J_d, sp_d = T(sigma), T(J), T(species, torch.int32)
     n_train = frames // 2
     scaling = y_std = None
-    train_G, train_q = [], []
-    rec = {"cold": [], "prev": [], "learned": []}
+    train_G, train_X, train_q = [], [], []
+    rec = {"cold": [], "prev": [], "learned": [], "learned_chi": []}
     q_prev = None
 
     def solve(posd, chid, q0=None):
@@ -56,7 +75,7 @@ def run_trajectory(n=None, side=None, spacing=None, frames=200, epochs=30, lr=2e
         torch.cuda.synchronize()
         return q, st, (time.perf_counter() - t0) * 1e3
 
-    t_desc, t_pred, max_dq = [], [], 0.0
+    t_desc, t_feat, t_pred, t_pred_x, max_dq = [], [], [], [], 0.0
     for t in range(frames):
         if t > 0:
             pos = pos + gen.md_displacement(t - 1, n)
@@ -68,29 +87,37 @@ def run_trajectory(n=None, side=None, spacing=None, frames=200, epochs=30, lr=2e
         t_desc.append((time.perf_counter() - t0) * 1e3)
         chi, scaling, y_std = gen.chi_from_descriptors(G.cpu().numpy(), species, chi_w, scaling, y_std)
         chid = T(chi)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        X = chi_features(plan, posd, cell, sig_d, chid)
+        torch.cuda.synchronize()
+        t_feat.append((time.perf_counter() - t0) * 1e3)
         if t < n_train:
             q, st, ms = solve(posd, chid)
             train_G.append(G)
+            train_X.append(X)
             train_q.append(q)
             q_prev = q
             if log:
                 log(f"frame {t} (train): cold {st['iters']} it {ms:.1f} ms")
             if t == n_train - 1:
-                Gall = torch.cat(train_G)
                 spall = sp_d.repeat(n_train)
-                net.fit_scaling(Gall, spall)
-                t0 = time.perf_counter()
-                order = np.random.default_rng(1006).permutation
-                for ep in range(epochs):
-                    for f in order(n_train):
-                        loss = net.train_step(train_G[f], sp_d, train_q[f], lr=lr)
-                    if log and (ep % 5 == 0 or ep == epochs - 1):
-                        log(f"epoch {ep}: loss {float(loss.cpu()):.3e}")
-                torch.cuda.synchronize()
-                rec["train_s"] = time.perf_counter() - t0
-                rec["train_loss"] = float(loss.cpu())
+                for key, nt_, feats in (("", net, train_G), ("_chi", net_x, train_X)):
+                    Gall = torch.cat(feats)
+                    nt_.fit_scaling(Gall, spall)
+                    del Gall
+                    t0 = time.perf_counter()
+                    order = np.random.default_rng(1006).permutation
+                    for ep in range(epochs):
+                        for f in order(n_train):
+                            loss = nt_.train_step(feats[f], sp_d, train_q[f], lr=lr)
+                        if log and (ep % 5 == 0 or ep == epochs - 1):
+                            log(f"net{key} epoch {ep}: loss {float(loss.cpu()):.3e}")
+                    torch.cuda.synchronize()
+                    rec["train_s" + key] = time.perf_counter() - t0
+                    rec["train_loss" + key] = float(loss.cpu())
                 rec["train_steps"] = epochs * n_train
-                del Gall, spall
+                del spall
                 if log:
                     log(f"trained {epochs} epochs in {rec['train_s']:.1f} s, loss {rec['train_loss']:.3e}")
             continue
@@ -102,24 +129,42 @@ def run_trajectory(n=None, side=None, spacing=None, frames=200, epochs=30, lr=2e
         torch.cuda.synchronize()
         t_pred.append((time.perf_counter() - t0) * 1e3)
         q_l, st_l, ms_l = solve(posd, chid, q0=q0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        q0x = net_x.predict(X, sp_d)
+        torch.cuda.synchronize()
+        t_pred_x.append((time.perf_counter() - t0) * 1e3)
+        q_x, st_x, ms_x = solve(posd, chid, q0=q0x)
         dq_p, dq_l = float((q_p - q_c).abs().max()), float((q_l - q_c).abs().max())
-        max_dq = max(max_dq, dq_p, dq_l)
-        for k, st, ms in (("cold", st_c, ms_c), ("prev", st_p, ms_p), ("learned", st_l, ms_l)):
+        dq_x = float((q_x - q_c).abs().max())
+        max_dq = max(max_dq, dq_p, dq_l, dq_x)
+        for k, st, ms in (("cold", st_c, ms_c), ("prev", st_p, ms_p), ("learned", st_l, ms_l),
+                          ("learned_chi", st_x, ms_x)):
             rec[k].append((st["iters"], ms, st["rc"], st["q0_rejected"]))
         q_prev = q_c
         if log:
-            log(f"frame {t}: iters cold {st_c['iters']} prev {st_p['iters']} learned {st_l['iters']}; "
-                f"ms {ms_c:.1f} / {ms_p:.1f} / {ms_l:.1f}; max|dq| prev {dq_p:.1e} learned {dq_l:.1e}; "
-                f"|q0 - q| learned max {float((q0 - q_c).abs().max()):.2e} "
-                f"rms {float((q0 - q_c).pow(2).mean().sqrt()):.2e}")
+            log(f"frame {t}: iters cold {st_c['iters']} prev {st_p['iters']} learned {st_l['iters']} "
+                f"learned_chi {st_x['iters']}; ms {ms_c:.1f} / {ms_p:.1f} / {ms_l:.1f} / {ms_x:.1f}; "
+                f"max|dq| {max(dq_p, dq_l, dq_x):.1e}; rms |q0 - q| learned "
+                f"{float((q0 - q_c).pow(2).mean().sqrt()):.2e} learned_chi "
+                f"{float((q0x - q_c).pow(2).mean().sqrt()):.2e}")
     plan.close()
     out = {"n": n, "grid": list(grid), "frames": frames, "train_frames": n_train,
            "max_dq_vs_cold": max_dq, "descriptor_ms": float(np.mean(t_desc)),
+           "chi_feature_ms": float(np.mean(t_feat)),
            "predict_ms": float(np.mean(t_pred)) if t_pred else None,
+           "predict_chi_ms": float(np.mean(t_pred_x)) if t_pred_x else None,
            "train_s": rec.get("train_s"), "train_loss": rec.get("train_loss"),
+           "train_s_chi": rec.get("train_s_chi"), "train_loss_chi": rec.get("train_loss_chi"),
            "train_steps": rec.get("train_steps")}
-    for k in ("cold", "prev", "learned"):
+    for k in ("cold", "prev", "learned", "learned_chi"):
         a = np.array(rec[k], dtype=float)
         out[k] = {"iters": float(a[:, 0].mean()), "ms": float(a[:, 1].mean()),
                   "all_converged": bool((a[:, 2] == 0).all()), "q0_rejected": int(a[:, 3].sum())}
+    # inference charged to the learned starts: the network, plus for the
+    # chi-aware start the two feature calls that the workload's own
+    # descriptors (needed for chi anyway) do not provide
+    out["learned"]["ms_with_inference"] = out["learned"]["ms"] + (out["predict_ms"] or 0.0)
+    out["learned_chi"]["ms_with_inference"] = (out["learned_chi"]["ms"] + out["chi_feature_ms"] +
+                                               (out["predict_chi_ms"] or 0.0))
     return out

@@ -348,3 +348,30 @@ def test_pins_catch_planted_mistakes(monkeypatch):
     e1 = 0.5 * q @ no_bg(pos, cell, sigma, eta=1.2) @ q
     e2 = 0.5 * q @ no_bg(pos, cell, sigma, eta=2.8) @ q
     assert abs(e1 - e2) > 1e-3
+
+
+def test_weighted_descriptors_linear_in_weights():
+    """Weighted radial descriptors: unit weights give the plain ones, and the
+    sum over an element partition of the weights gives the total (each
+    neighbour term carries exactly its own weight)."""
+    from oracle import mlp as omlp
+    s = gen.system_64()
+    c = np.linspace(1.0, 9.0, 8)
+    G = omlp.radial_descriptors(s.pos, s.cell, c, 0.7, 8.0)
+    assert np.abs(omlp.radial_descriptors(s.pos, s.cell, c, 0.7, 8.0, weights=np.ones(s.n)) - G).max() < 1e-14
+    parts = [omlp.radial_descriptors(s.pos, s.cell, c, 0.7, 8.0, weights=(s.species == e).astype(float))
+             for e in (0, 1)]
+    assert np.abs(parts[0] + parts[1] - G).max() < 1e-12
+    w = np.random.default_rng(2).normal(size=s.n)
+    Gw = omlp.radial_descriptors(s.pos, s.cell, c, 0.7, 8.0, weights=w)
+    # brute force for atom 0 over images within the cutoff
+    L = s.cell[0, 0]
+    d = s.pos - s.pos[0]
+    ref = np.zeros(len(c))
+    for sh in np.array(np.meshgrid([-1, 0, 1], [-1, 0, 1], [-1, 0, 1])).T.reshape(-1, 3):
+        dd = d + sh * L
+        r = np.linalg.norm(dd, axis=1)
+        m = (r < 8.0) & (r > 1e-12)
+        fc = 0.5 * (np.cos(np.pi * r[m] / 8.0) + 1.0)
+        ref += (w[m][:, None] * np.exp(-(r[m][:, None] - c) ** 2 / (2 * 0.49)) * fc[:, None]).sum(0)
+    assert np.abs(Gw[0] - ref).max() < 1e-12
