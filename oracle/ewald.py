@@ -350,3 +350,90 @@ def qeq_adjoint(pos, cell, sigma, J, chi, q_tot, dL_dq, dL_dEelec=0.0, dL_dEqeq=
     bil = energy_gradient_positions(pos, cell, sigma, q, eta=eta, a=a)
     dpos = (dL_dEelec + dL_dEqeq) * de_dr - bil
     return q, dchi, dpos, dJ
+
+
+# ---------------------------------------------------------------------------
+# Virial (strain derivative of the energy)
+# ---------------------------------------------------------------------------
+
+def background_energy(cell, sigma, q, eta):
+    """E_bg = (1/2) q^T B q with B_ij = -(2 pi / V)(eta^2 - sigma_i^2 - sigma_j^2)."""
+    vol, _, _, _ = cell_geometry(cell)
+    q = np.asarray(q, dtype=np.float64)
+    qt = q.sum()
+    return -(math.pi / vol) * (eta * eta * qt * qt - 2.0 * qt * np.sum(q * sigma * sigma))
+
+
+def kspace_strain_factor(kvec, k2, eta):
+    """d ln(e^{-eta^2 k^2/2} / (V k^2)) / d eps_ab, per k: -delta_ab + 2 (1/k^2 + eta^2/2) k_a k_b.
+
+    Under r -> (1 + eps) r every k.r is unchanged, so k -> (1 + eps)^{-T} k
+    and d(k^2)/d eps_ab = -2 k_a k_b, while dV/d eps_ab = V delta_ab.
+    """
+    c = 2.0 * (1.0 / k2 + 0.5 * eta * eta)
+    return -np.eye(3)[None, :, :] + c[:, None, None] * kvec[:, :, None] * kvec[:, None, :]
+
+
+def virial(pos, cell, sigma, q, eta=None):
+    """W_ab = -dE_elec/d eps_ab at fixed q (3 x 3, symmetric).
+
+    The strain acts on positions and lattice vectors alike (r -> (1 + eps) r,
+    fractional coordinates fixed).  The SI's Stress Tensor subsection defines
+    the stress as sigma = (1/V) dE/d eps and the virial handed to an MD code
+    as -V sigma, which is this W; the Electrostatics Solvers section obtains
+    it from the same Fourier-space machinery as the forces.  Term by term from
+    the same Ewald split as ``coulomb_matrix``:
+
+      real space  -(1/2) sum_{i,j,n} q_i q_j K'(r)/r d_a d_b,  d = r_i - r_j + n.H,
+      k space     -sum_k E_k [-delta_ab + 2 (1/k^2 + eta^2/2) k_a k_b],
+                  E_k = (1/2) (4 pi / V) e^{-eta^2 k^2/2} / k^2 |S(k)|^2,
+      self        none (no length enters it),
+      background  E_bg delta_ab (E_bg is proportional to 1/V).
+
+    The total does not depend on eta (pinned by the tests).
+    """
+    pos = np.asarray(pos, dtype=np.float64)
+    sigma = np.asarray(sigma, dtype=np.float64)
+    q = np.asarray(q, dtype=np.float64)
+    H = np.asarray(cell, dtype=np.float64)
+    n = pos.shape[0]
+    vol, _, _, _ = cell_geometry(H)
+    gmax = SQRT2 * float(sigma.max())
+    if eta is None:
+        eta = default_eta(n, vol, gmax)
+    r_max, k_max = default_cutoffs(eta, gmax)
+    W = np.zeros((3, 3))
+    # real space
+    sig2 = sigma * sigma
+    gam = np.sqrt(sig2[:, None] + sig2[None, :])
+    dr0 = pos[:, None, :] - pos[None, :, :]
+    eye = np.eye(n, dtype=bool)
+    qq = q[:, None] * q[None, :]
+    for s in lattice_shifts(H, r_max):
+        d = dr0 + s @ H
+        r = np.sqrt(np.einsum("ijk,ijk->ij", d, d))
+        mask = r < r_max
+        if (s == 0).all():
+            mask &= ~eye
+        if not mask.any():
+            continue
+        c = np.zeros((n, n))
+        c[mask] = qq[mask] * pair_kernel_deriv(r[mask], gam[mask], eta) / r[mask]
+        W -= 0.5 * np.einsum("ij,ija,ijb->ab", c, d, d)
+    # k space (half space, weights doubled)
+    kvec, k2 = half_space_kvectors(H, k_max)
+    w = kspace_weights(k2, vol, eta)
+    for s, kc, cs, sn in _kspace_tables(pos, kvec):
+        ww = w[s:s + cs.shape[1]]
+        Cq, Sq = q @ cs, q @ sn
+        ek = 0.5 * ww * (Cq * Cq + Sq * Sq)
+        W -= np.einsum("k,kab->ab", ek, kspace_strain_factor(kc, k2[s:s + kc.shape[0]], eta))
+    # background
+    W += background_energy(H, sigma, q, eta) * np.eye(3)
+    return W
+
+
+def strained(pos, cell, F):
+    """Positions and cell after the homogeneous deformation r -> F r (rows are vectors)."""
+    F = np.asarray(F, dtype=np.float64)
+    return np.asarray(pos, dtype=np.float64) @ F.T, np.asarray(cell, dtype=np.float64) @ F.T

@@ -179,6 +179,27 @@ class EwaldOperator:
         return g
 
 
+def _virial_method(self, q):
+    """W_ab = -dE_elec/d eps_ab at fixed q (same terms as ``ewald.virial``)."""
+    q = np.asarray(q, dtype=np.float64)
+    ii, jj, d, r, gam = self._pairs
+    c = q[ii] * q[jj] * ewald.pair_kernel_deriv(r, gam, self.eta) / r
+    W = -0.5 * np.einsum("e,ea,eb->ab", c, d, d)
+    S = self.structure_factor(q)
+    ek = 0.5 * self.W * (S.real ** 2 + S.imag ** 2)        # zero where the weight is
+    k = self.kvec
+    k2 = np.einsum("...i,...i->...", k, k)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        cf = np.where(ek != 0.0, 2.0 * (1.0 / k2 + 0.5 * self.eta ** 2), 0.0)
+    kf = k.reshape(-1, 3)
+    W += ek.sum() * np.eye(3) - np.einsum("m,ma,mb->ab", (ek * cf).ravel(), kf, kf)
+    W += ewald.background_energy(self.cell, self.sigma, q, self.eta) * np.eye(3)
+    return W
+
+
+EwaldOperator.virial = _virial_method
+
+
 def projected_cg(apply_A, diag, chi, q_tot, tol=1e-12, max_iter=5000, q0=None, rhs=None):
     """Jacobi-preconditioned CG for min 1/2 q^T A q + chi.q on sum(q) = Q_tot.
 

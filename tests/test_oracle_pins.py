@@ -375,3 +375,129 @@ def test_weighted_descriptors_linear_in_weights():
         fc = 0.5 * (np.cos(np.pi * r[m] / 8.0) + 1.0)
         ref += (w[m][:, None] * np.exp(-(r[m][:, None] - c) ** 2 / (2 * 0.49)) * fc[:, None]).sum(0)
     assert np.abs(Gw[0] - ref).max() < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Virial W = -dE/d eps (strain of positions and cell at fixed fractional
+# coordinates)
+# ---------------------------------------------------------------------------
+
+def _energy_at_strain(pos, cell, sigma, q, F):
+    p2, c2 = ewald.strained(pos, cell, F)
+    return 0.5 * q @ ewald.coulomb_matrix(p2, c2, sigma) @ q
+
+
+def _strain_fd(fn, h=1e-5):
+    """-d fn(F)/dF_ab at F = 1 by central differences, every (a, b)."""
+    W = np.zeros((3, 3))
+    for a in range(3):
+        for b in range(3):
+            Fp, Fm = np.eye(3), np.eye(3)
+            Fp[a, b] += h
+            Fm[a, b] -= h
+            W[a, b] = -(fn(Fp) - fn(Fm)) / (2 * h)
+    return W
+
+
+def _charges(n, q_tot, seed):
+    q = np.random.default_rng(seed).normal(0, 0.4, n)
+    return q + (q_tot - q.sum()) / n
+
+
+@pytest.mark.parametrize("q_tot", [0.0, 1.0])
+def test_virial_is_minus_strain_derivative(q_tot):
+    """All nine components against finite differences of the dense Ewald
+    energy under r -> F r (non-symmetric F, so the antisymmetric part, zero by
+    rotation invariance, is checked too)."""
+    pos, cell, sigma, _, _, _ = small_triclinic(n=6, seed=7)
+    q = _charges(6, q_tot, 4)
+    W = ewald.virial(pos, cell, sigma, q)
+    fd = _strain_fd(lambda F: _energy_at_strain(pos, cell, sigma, q, F))
+    scale = np.abs(W).max()
+    assert np.abs(W - W.T).max() < 1e-13 * scale
+    assert np.abs(W - fd).max() < 1e-8 * scale
+
+
+def test_virial_eta_invariant():
+    pos, cell, sigma, _, _, _ = small_triclinic(n=6, seed=8)
+    q = _charges(6, -1.0, 5)
+    Ws = [ewald.virial(pos, cell, sigma, q, eta=e) for e in (1.2, 1.9, 2.8)]
+    for W in Ws[1:]:
+        assert np.abs(W - Ws[0]).max() < 1e-12 * np.abs(Ws[0]).max()
+
+
+def test_virial_point_charge_homogeneity():
+    """Rock salt with sigma -> 0: past the (length-independent) self energies
+    the energy is a lattice sum of 1/r, homogeneous of degree -1 in length, so
+    tr W = E_elec - sum q^2/(2 sigma sqrt pi); cubic symmetry makes W
+    isotropic."""
+    a = 6.0
+    pos, q = [], []
+    for i in range(2):
+        for j in range(2):
+            for k in range(2):
+                pos.append([i * a / 2, j * a / 2, k * a / 2])
+                q.append((-1.0) ** (i + j + k))
+    pos, q = np.array(pos), np.array(q)
+    sig = np.full(8, 0.05)
+    W = ewald.virial(pos, np.eye(3) * a, sig, q, eta=0.8)
+    E = ewald.coulomb_matrix(pos, np.eye(3) * a, sig, eta=0.8)
+    e_point = 0.5 * q @ E @ q - np.sum(q * q / (2 * sig * SQRTPI))
+    assert abs(np.trace(W) - e_point) < 1e-11 * abs(e_point)
+    assert np.abs(W - np.trace(W) / 3 * np.eye(3)).max() < 1e-11 * abs(e_point)
+
+
+def test_qeq_virial_is_total_strain_derivative():
+    """At the QEq solution the virial of E_elec at fixed q equals
+    -dE_QEq/d eps with the charges re-solved at every strained geometry
+    (stationarity on the constraint plane; J and chi do not depend on it)."""
+    pos, cell, sigma, J, chi = _small_system(n=7, seed=13)
+    q_tot = 0.5
+    r = ewald.qeq_dense(pos, cell, sigma, J, chi, q_tot, forces=False)
+    W = ewald.virial(pos, cell, sigma, r.q)
+
+    def e_qeq(F):
+        p2, c2 = ewald.strained(pos, cell, F)
+        return ewald.qeq_dense(p2, c2, sigma, J, chi, q_tot, forces=False).e_qeq
+
+    fd = _strain_fd(e_qeq)
+    assert np.abs(W - fd).max() < 1e-8 * np.abs(W).max()
+
+
+@pytest.mark.parametrize("which", ["64", "tri"])
+def test_matfree_virial_matches_dense(which):
+    if which == "64":
+        s = gen.system_64()
+        q = _charges(s.n, 0.0, 6)
+    else:
+        s = gen.batch_structure(7)
+        q = _charges(s.n, s.q_tot, 6)
+    Wd = ewald.virial(s.pos, s.cell, s.sigma, q)
+    Wm = matfree.EwaldOperator(s.pos, s.cell, s.sigma).virial(q)
+    assert np.abs(Wm - Wd).max() < 1e-11 * np.abs(Wd).max()
+
+
+def test_virial_pins_catch_planted_mistakes(monkeypatch):
+    pos, cell, sigma, _, _, _ = small_triclinic(n=6, seed=7)
+    q = _charges(6, 1.0, 4)
+    fd = _strain_fd(lambda F: _energy_at_strain(pos, cell, sigma, q, F))
+    scale = np.abs(fd).max()
+
+    def err():
+        return np.abs(ewald.virial(pos, cell, sigma, q) - fd).max() / scale
+
+    assert err() < 1e-8
+    # (1) the screening Gaussian's own strain dependence left out
+    orig = ewald.kspace_strain_factor
+    monkeypatch.setattr(ewald, "kspace_strain_factor", lambda k, k2, e: orig(k, k2, 0.0))
+    assert err() > 1e-3
+    monkeypatch.setattr(ewald, "kspace_strain_factor", orig)
+    # (2) the volume derivative of the k-space prefactor dropped
+    monkeypatch.setattr(ewald, "kspace_strain_factor", lambda k, k2, e: orig(k, k2, e) + np.eye(3))
+    assert err() > 1e-3
+    monkeypatch.setattr(ewald, "kspace_strain_factor", orig)
+    # (3) the background's volume dependence dropped (charged cell)
+    orig_bg = ewald.background_energy
+    monkeypatch.setattr(ewald, "background_energy", lambda *a: 0.0)
+    assert err() > 1e-3
+    monkeypatch.setattr(ewald, "background_energy", orig_bg)
