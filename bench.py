@@ -212,6 +212,16 @@ def main():
         ms_eager = (time.perf_counter() - te0) * 1e3 / n_eager
         ms_dom, cnt_dom = prof_read()
         plan.profile(0)
+    # virial of the last solve (not part of the timed step): first call for the
+    # cell (builds the strain tables of the self-correction), then steady state
+    torch.cuda.synchronize()
+    tv0 = time.perf_counter()
+    plan.virial()
+    tv1 = time.perf_counter()
+    for _ in range(5):
+        plan.virial()
+    tv2 = time.perf_counter()
+    virial_ms = {"first_call": round((tv1 - tv0) * 1e3, 3), "per_call": round((tv2 - tv1) * 1e3 / 5, 3)}
     nnz = None
     # CSR size is not exported; estimate from the cutoff sphere at this density
     nnz = int(round(s.n * 0.01 * 4.0 / 3.0 * np.pi * 11.0 ** 3))
@@ -252,6 +262,7 @@ def main():
         },
         "final_stats": {k: st[k] for k in ("iters", "rel_resid", "true_rel_resid", "e_qeq", "e_elec")},
         "ms_per_step_eager_launches": None if ms_eager is None else round(ms_eager, 4),
+        "virial_ms": virial_ms,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()

@@ -132,6 +132,24 @@ int qeq_solve(qeq_plan* plan, int32_t n, const double* pos, const double* cell,
 int qeq_backward(qeq_plan* plan, const double* dL_dq, double dL_dEqeq, double dL_dEelec,
                  double* dL_dchi, double* dL_dJ, double* dL_dpos, qeq_stats* stats);
 
+/* Virial of the last solve on this plan (SI "Stress Tensor": the stress is
+   sigma = (1/V) dE/d eps and the virial an MD code takes is -V sigma):
+     virial (9 doubles, device, out, row-major) W_ab = -dE/d eps_ab
+   for the homogeneous strain r -> (1 + eps) r of positions and lattice
+   vectors (fractional coordinates fixed); symmetric.  E is the plan's
+   discretised E_elec at the solution charges: mesh energy, real-space pairs,
+   mesh self-correction, background (charged cells).  At the QEq solution
+   this also equals -dE_QEq/d eps with the charges re-equilibrated, since
+   E_QEq is stationary on sum(q) = Q and J, chi do not depend on the
+   geometry.  The stress is -W / V with V = |det cell|.
+   Needs a preceding successful qeq_solve on the plan (QEQ_EINVAL otherwise,
+   also after qeq_matvec or qeq_descriptors, which replace the geometry).
+   Runs one charge spread and two forward transform passes, the pair list and
+   per-atom terms; the first call for a cell also builds six strain tables of
+   the mesh self-correction (six inverse mesh transforms).  Synchronises the
+   plan's stream. */
+int qeq_virial(qeq_plan* plan, double* virial);
+
 /* y = E v with the plan's particle-mesh operator (no J), for checking the
    matrix-vector product of eq. matvec on its own.  parts is a bit mask:
    1 reciprocal (mesh) part, 2 real-space pair part, 4 self terms (Gaussian

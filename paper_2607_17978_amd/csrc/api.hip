@@ -207,6 +207,65 @@ double reciprocal_self_constant(const double* H, const double* Hinv, double vol,
     return ks + rs - 2 * PI * (zeta * zeta - eta * eta) / vol;
 }
 
+}  // namespace
+
+// d C_eta / d eps_ab for the strain r -> (1 + eps) r, term by term from the
+// zeta split above: each k-space term (4 pi / V) e^{-zeta^2 k^2/2} / k^2
+// changes by the factor -delta + 2 (1/k^2 + zeta^2/2) k_a k_b, each lattice
+// term f(|x|) by f'(r) x_a x_b / r, and -2 pi (zeta^2 - eta^2) / V by
+// +2 pi (zeta^2 - eta^2) / V delta.  Order 00, 11, 22, 01, 02, 12.
+void reciprocal_self_strain(const double* H, const double* Hinv, double vol, double eta, double dC[6]) {
+    static const int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
+    double widths[3], lengths[3];
+    for (int a = 0; a < 3; ++a) {
+        double n2 = 0.0, l2 = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            n2 += Hinv[c * 3 + a] * Hinv[c * 3 + a];
+            l2 += H[a * 3 + c] * H[a * 3 + c];
+        }
+        widths[a] = 1.0 / sqrt(n2);
+        lengths[a] = sqrt(l2);
+    }
+    const double zeta = std::max(eta, 0.3 * cbrt(vol));
+    const double X = 6.5 * sqrt(2.0);
+    for (int c = 0; c < 6; ++c) dC[c] = 0.0;
+    const double kmax = X / zeta;
+    int mm[3];
+    for (int a = 0; a < 3; ++a) mm[a] = (int)ceil(kmax * lengths[a] / (2 * PI)) + 1;
+    for (int m1 = -mm[0]; m1 <= mm[0]; ++m1)
+        for (int m2 = -mm[1]; m2 <= mm[1]; ++m2)
+            for (int m3 = -mm[2]; m3 <= mm[2]; ++m3) {
+                if (!m1 && !m2 && !m3) continue;
+                double k[3];
+                for (int c = 0; c < 3; ++c)
+                    k[c] = 2 * PI * (Hinv[c * 3 + 0] * m1 + Hinv[c * 3 + 1] * m2 + Hinv[c * 3 + 2] * m3);
+                const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+                if (k2 > kmax * kmax) continue;
+                const double e = 4 * PI / vol * exp(-0.5 * zeta * zeta * k2) / k2;
+                const double cf = 2.0 * (1.0 / k2 + 0.5 * zeta * zeta);
+                for (int c = 0; c < 6; ++c) dC[c] += e * ((c < 3 ? -1.0 : 0.0) + cf * k[ia[c]] * k[ib[c]]);
+            }
+    const double rmax = X * zeta;
+    const double a = 0.70710678118654752440 / eta, b = 0.70710678118654752440 / zeta;
+    int nn[3];
+    for (int t = 0; t < 3; ++t) nn[t] = (int)ceil(rmax / widths[t]) + 1;
+    for (int n1 = -nn[0]; n1 <= nn[0]; ++n1)
+        for (int n2 = -nn[1]; n2 <= nn[1]; ++n2)
+            for (int n3 = -nn[2]; n3 <= nn[2]; ++n3) {
+                if (!n1 && !n2 && !n3) continue;
+                double x[3];
+                for (int c = 0; c < 3; ++c) x[c] = n1 * H[0 * 3 + c] + n2 * H[1 * 3 + c] + n3 * H[2 * 3 + c];
+                const double r = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+                if (r > rmax) continue;
+                const double f = (erf(a * r) - erf(b * r)) / r;
+                const double fp = (2.0 / sqrt(PI) * (a * exp(-a * a * r * r) - b * exp(-b * b * r * r)) - f) / r;
+                for (int c = 0; c < 6; ++c) dC[c] += fp * x[ia[c]] * x[ib[c]] / r;
+            }
+    for (int c = 0; c < 3; ++c) dC[c] += 2 * PI * (zeta * zeta - eta * eta) / vol;
+}
+
+namespace {
+
 void free_grid(qeq_plan* pl) {
     for (int a = 0; a < 3; ++a) {
         dfree(pl->tw[a]);
@@ -219,6 +278,7 @@ void free_grid(qeq_plan* pl) {
     dfree(pl->bin_fill);
     pl->K[0] = pl->K[1] = pl->K[2] = 0;
     pl->theta_valid = false;
+    pl->strain_valid = false;
 }
 
 int ensure_grid(qeq_plan* pl, const int K[3]) {
@@ -259,6 +319,7 @@ int ensure_grid(qeq_plan* pl, const int K[3]) {
     pl->K[1] = K[1];
     pl->K[2] = K[2];
     pl->theta_valid = false;
+    pl->strain_valid = false;
     return QEQ_OK;
 }
 
@@ -384,6 +445,7 @@ int prepare(qeq_plan* pl, int n, const double* cell, double q_tot) {
     if (!same_cell || !pl->theta_valid) {
         pl->c_eta = reciprocal_self_constant(k.H, k.Hinv, det, k.eta);
         pl->theta_valid = false;
+        pl->strain_valid = false;
     }
     k.c_eta = pl->c_eta;
     if (k.self_corr && !pl->theta_valid) {
@@ -722,6 +784,7 @@ int qeq_plan_destroy(qeq_plan* pl) {
     dfree(pl->sig); dfree(pl->Jv); dfree(pl->chi); dfree(pl->chi_raw); dfree(pl->dself); dfree(pl->dinv);
     dfree(pl->selfgrad); dfree(pl->q); dfree(pl->r); dfree(pl->pvec); dfree(pl->y); dfree(pl->forces_s);
     dfree(pl->gtmp); dfree(pl->q_adj); dfree(pl->y_adj); dfree(pl->chi_adj); dfree(pl->adj_scratch); dfree(pl->tq); dfree(pl->rowptr); dfree(pl->rowcnt); dfree(pl->theta_tab); dfree(pl->part);
+    dfree(pl->strain_tab); dfree(pl->vir_part);
     dfree(pl->sc); dfree(pl->final_dev); dfree(pl->scan_tmp);
     dfree(pl->cell_count); dfree(pl->cell_start); dfree(pl->cell_fill); dfree(pl->cell_atoms);
     dfree(pl->col); dfree(pl->kval); dfree(pl->pdr);
@@ -838,6 +901,11 @@ int qeq_backward(qeq_plan* plan, const double* dL_dq, double dL_dEqeq, double dL
         stats->status = rc;
     }
     return rc;
+}
+
+int qeq_virial(qeq_plan* plan, double* virial) {
+    if (!plan) return QEQ_EINVAL;
+    return virial_impl(plan, virial);
 }
 
 const char* qeq_strerror(int code) {

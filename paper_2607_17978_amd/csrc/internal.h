@@ -118,6 +118,13 @@ struct qeq_plan {
     bool theta_valid = false;
     double c_eta = 0.0;
     double* theta_tab = nullptr;                    // (2p-1)^3 mesh kernel values
+    // virial: strain derivatives of the self-correction (d C_eta / d eps and
+    // the six tables d Theta / d eps_ab), valid for the same cell as theta_tab
+    bool strain_valid = false;
+    double dc_eta[6] = {0, 0, 0, 0, 0, 0};
+    double* strain_tab = nullptr;                   // 6 x (2p-1)^3
+    double* vir_part = nullptr;                     // partial sums of the virial kernels
+    size_t vir_cap = 0;                             // doubles
 
     // per-atom (sorted order unless noted)
     int* perm = nullptr;
@@ -237,6 +244,15 @@ int launch_gather(qeq_plan* pl, const double* pos, const double* sigma, const do
 int launch_cells_and_pairs(qeq_plan* pl);
 int launch_theta(qeq_plan* pl);          // mesh kernel table for the self-correction
 int launch_selfcorr(qeq_plan* pl);
+// the six d Theta / d eps_ab tables (6 x (2p-1)^3) for the virial
+int launch_theta_strain(qeq_plan* pl, double* tabs);
+// per block [sum q^2 theta^T dTheta_ab theta (6; 0 if tabs is null), sum q^2,
+// sum q sigma^2]; nblocks(n) blocks of QEQ_NPART
+int launch_self_strain(qeq_plan* pl, const double* tabs, double* part);
+// d C_eta / d eps_ab (host, order 00, 11, 22, 01, 02, 12)
+void reciprocal_self_strain(const double* H, const double* Hinv, double vol, double eta, double dC[6]);
+// qeq_virial
+int virial_impl(qeq_plan* pl, double* virial);
 int launch_scan(qeq_plan* pl, const int* in, int* out, int m);
 int launch_rhs_norm(qeq_plan* pl, const double* b);
 
@@ -249,6 +265,12 @@ int launch_mesh_inverse(qeq_plan* pl);
 // One launch of a single mesh pass (PK_SPREAD_R2C from src, or PK_C2R).
 int launch_mesh_stage(qeq_plan* pl, int kind, const double* src);
 int launch_write_green(qeq_plan* pl);
+// G(m) d ln G / d eps_ab (component comp of 00, 11, 22, 01, 02, 12) into grid_c.
+int launch_write_green_strain(qeq_plan* pl, int comp);
+// Mesh virial partials of the charges src: spread, forward transforms and per
+// block [sum e, sum e c k_a k_b]; mesh_virial_blocks() blocks of QEQ_NPART.
+int launch_mesh_virial(qeq_plan* pl, const double* src, double* part);
+int mesh_virial_blocks(const KParams& k);
 
 // ------------------------------------------------------------------ solver kernels (solve.hip)
 int launch_interp(qeq_plan* pl, const double* src, double* dst, int mode, int parity);

@@ -410,6 +410,108 @@ __global__ void k_write_green(KParams k, float2* __restrict__ C, const float* __
     C[t] = make_float2(green_value(k, m1, m2, m3, b1, b2, b3), 0.f);
 }
 
+// Strain factor of one mode: under r -> (1 + eps) r (fractional coordinates
+// fixed) k -> (1 + eps)^-T k and V -> (1 + tr eps) V, so
+//   d ln G(m) / d eps_ab = -delta_ab + 2 (1/k^2 + eta^2/2) k_a k_b
+// (the B-spline moduli do not change).  kv = 2 pi H^-1 m, returns k^2.
+__device__ __forceinline__ float mode_kvec(const KParams& k, int m1, int m2, int m3, float kv[3]) {
+    const float x1 = (float)(m1 <= k.K1 / 2 ? m1 : m1 - k.K1);
+    const float x2 = (float)(m2 <= k.K2 / 2 ? m2 : m2 - k.K2);
+    const float x3 = (float)m3;
+    float k2 = 0.f;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        kv[c] = 6.283185307179586477f * ((float)k.Hinv[c * 3] * x1 + (float)k.Hinv[c * 3 + 1] * x2 +
+                                         (float)k.Hinv[c * 3 + 2] * x3);
+        k2 += kv[c] * kv[c];
+    }
+    return k2;
+}
+
+// Component order of symmetric 3x3 tensors: 00, 11, 22, 01, 02, 12.
+__device__ __forceinline__ void sym_pair(int comp, int& a, int& b) {
+    a = comp < 3 ? comp : (comp == 5 ? 1 : 0);
+    b = comp < 3 ? comp : (comp == 3 ? 1 : 2);
+}
+
+// G(m) d ln G / d eps_ab on the half spectrum: its inverse transform is the
+// strain derivative of the mesh kernel Theta (for the self-correction term).
+__global__ void k_write_green_strain(KParams k, float2* __restrict__ C, const float* __restrict__ b1,
+                                     const float* __restrict__ b2, const float* __restrict__ b3, int comp) {
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t total = (size_t)k.K3h * k.K1 * k.K2;
+    if (t >= total) return;
+    const int m2 = (int)(t % k.K2);
+    const int m1 = (int)((t / k.K2) % k.K1);
+    const int m3 = (int)(t / ((size_t)k.K2 * k.K1));
+    const float g = green_value(k, m1, m2, m3, b1, b2, b3);
+    float v = 0.f;
+    if (g != 0.f) {
+        float kv[3];
+        const float k2 = mode_kvec(k, m1, m2, m3, kv);
+        const float eta = (float)k.eta;
+        int a, b;
+        sym_pair(comp, a, b);
+        v = g * ((a == b ? -1.f : 0.f) + 2.f * (1.f / k2 + 0.5f * eta * eta) * kv[a] * kv[b]);
+    }
+    C[t] = make_float2(v, 0.f);
+}
+
+// Virial of the reciprocal mesh energy E = 1/2 sum_m G(m) |Q(m)|^2: the
+// axis-1 forward transform of a column tile (the grid already transformed
+// along axes 3 and 2), then per mode e = G |Q|^2 (doubled off the m3 = 0
+// plane) and per block the sums of e and of e c k_a k_b, c = 2 (1/k^2 + eta^2/2);
+// W = 1/2 (sum e) delta - 1/2 sum e c k k.  The grid is left as it is.
+template <int KC, int TWC>
+__global__ __launch_bounds__(NT) void k_cols_virial(KParams k, FftAxis ax1, const float2* __restrict__ C,
+                                                   const float* __restrict__ b1, const float* __restrict__ b2,
+                                                   const float* __restrict__ b3, double* __restrict__ part) {
+    extern __shared__ float2 sm[];
+    const int K1 = KC ? KC : k.K1;
+    const int TW = TWC ? TWC : k.TW;
+    const int twl = ilog2_dev(TW);
+    float2* tw = sm;
+    float2* buf = sm + K1;
+    const int tid = threadIdx.x;
+    const int K2 = k.K2;
+    const int m3 = blockIdx.x / k.ntile;
+    const int g20 = (blockIdx.x - m3 * k.ntile) * TW;
+    for (int t = tid; t < K1; t += NT) tw[t] = ax1.tw[t];
+    const float2* base = C + (size_t)m3 * K1 * K2 + g20;
+    for (int t = tid; t < K1 * TW; t += NT) {
+        const int c = t & (TW - 1), g1 = t >> twl;
+        buf[t] = base[(size_t)g1 * K2 + c];
+    }
+    __syncthreads();
+    if constexpr (KC > 0 && TWC > 0)
+        fft_ct<KC, TWC, TWC, NT, false>(buf, tw, tid);
+    else
+        fft_lds(buf, ax1, twl, tw, false, tid, NT);
+    double v[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const float mult = (m3 == 0) ? 1.f : 2.f;
+    const float eta = (float)k.eta;
+    for (int t = tid; t < K1 * TW; t += NT) {
+        const int c = t & (TW - 1), m1 = t >> twl;
+        const float g = green_value(k, m1, g20 + c, m3, b1, b2, b3);
+        if (g == 0.f) continue;
+        const float2 x = buf[t];
+        float kv[3];
+        const float k2 = mode_kvec(k, m1, g20 + c, m3, kv);
+        const float e = g * mult * (x.x * x.x + x.y * x.y);
+        const float ec = e * 2.f * (1.f / k2 + 0.5f * eta * eta);
+        v[0] += (double)e;
+        v[1] += (double)(ec * kv[0] * kv[0]);
+        v[2] += (double)(ec * kv[1] * kv[1]);
+        v[3] += (double)(ec * kv[2] * kv[2]);
+        v[4] += (double)(ec * kv[0] * kv[1]);
+        v[5] += (double)(ec * kv[0] * kv[2]);
+        v[6] += (double)(ec * kv[1] * kv[2]);
+    }
+    block_sum<7>(v);
+    if (tid == 0)
+        for (int u = 0; u < 7; ++u) part[(size_t)blockIdx.x * QEQ_NPART + u] = v[u];
+}
+
 size_t smem_spread(const KParams& k) {
     return sizeof(float2) * (size_t)k.K3 + sizeof(long long) * (size_t)k.K3 * k.TWS +
            SPREAD_CAND * (SPREAD_CW * sizeof(float) + 2 * sizeof(int));
@@ -492,6 +594,23 @@ int cols_pass(qeq_plan* pl, int mode, double* epart, const int* done) {
     return qeq_check(hipGetLastError());
 }
 
+int cols_virial_pass(qeq_plan* pl, double* part) {
+    const KParams& k = pl->kp;
+    dim3 g(k.K3h * k.ntile), b(NT);
+    const size_t sh = smem_cols(k);
+#define X(KK, TT)                                                                                  \
+    if (k.K1 == KK && k.TW == TT) {                                                                \
+        hipLaunchKernelGGL((k_cols_virial<KK, TT>), g, b, sh, pl->stream, k, pl->axes.ax[0], pl->grid_c, \
+                           pl->bmod[0], pl->bmod[1], pl->bmod[2], part);                            \
+        return qeq_check(hipGetLastError());                                                       \
+    }
+    QEQ_FOR_EACH_SIZE(X)
+#undef X
+    hipLaunchKernelGGL((k_cols_virial<0, 0>), g, b, sh, pl->stream, k, pl->axes.ax[0], pl->grid_c, pl->bmod[0],
+                       pl->bmod[1], pl->bmod[2], part);
+    return qeq_check(hipGetLastError());
+}
+
 int c2r_pass(qeq_plan* pl, const int* done) {
     const KParams& k = pl->kp;
     dim3 g(k.K1 * k.ntile), b(NT);
@@ -545,4 +664,20 @@ int launch_write_green(qeq_plan* pl) {
     hipLaunchKernelGGL(k_write_green, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, pl->stream, k,
                        pl->grid_c, pl->bmod[0], pl->bmod[1], pl->bmod[2]);
     return qeq_check(hipGetLastError());
+}
+
+int launch_write_green_strain(qeq_plan* pl, int comp) {
+    const KParams& k = pl->kp;
+    const size_t total = (size_t)k.K3h * k.K1 * k.K2;
+    hipLaunchKernelGGL(k_write_green_strain, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, pl->stream, k,
+                       pl->grid_c, pl->bmod[0], pl->bmod[1], pl->bmod[2], comp);
+    return qeq_check(hipGetLastError());
+}
+
+int mesh_virial_blocks(const KParams& k) { return k.K3h * k.ntile; }
+
+int launch_mesh_virial(qeq_plan* pl, const double* src, double* part) {
+    QEQ_TRY(spread_pass(pl, src, nullptr));
+    QEQ_TRY(rows_pass(pl, 0, nullptr));
+    return cols_virial_pass(pl, part);
 }

@@ -372,6 +372,51 @@ __global__ void k_selfcorr(KParams k, const double* __restrict__ frac, const dou
     selfgrad[3 * i + 2] = g[2];
 }
 
+// Virial of the self-correction: per atom theta_i^T dTheta_ab theta_i for the
+// six strain components (one table staged in LDS at a time), weighted by q^2;
+// also sum q^2 and sum q sigma^2 for the C_eta and background terms.
+template <int PC>
+__global__ __launch_bounds__(QEQ_BLOCK) void k_self_strain(KParams k, const double* __restrict__ frac,
+                                                          const double* __restrict__ tabs,
+                                                          const double* __restrict__ q,
+                                                          const double* __restrict__ sig,
+                                                          double* __restrict__ part) {
+    __shared__ double tab[(2 * QEQ_MAXP - 1) * (2 * QEQ_MAXP - 1) * (2 * QEQ_MAXP - 1)];
+    const int np = 2 * k.p - 1;
+    const int np3 = np * np * np;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool act = i < k.n;
+    double acc[QEQ_NPART];
+#pragma unroll
+    for (int t = 0; t < QEQ_NPART; ++t) acc[t] = 0.0;
+    const double qi = act ? q[i] : 0.0;
+    if (tabs) {
+        double u[3] = {0.0, 0.0, 0.0};
+        if (act) {
+            u[0] = frac[3 * i] * (double)k.K1;
+            u[1] = frac[3 * i + 1] * (double)k.K2;
+            u[2] = frac[3 * i + 2] * (double)k.K3;
+        }
+        for (int comp = 0; comp < 6; ++comp) {
+            __syncthreads();
+            for (int t = threadIdx.x; t < np3; t += blockDim.x) tab[t] = tabs[(size_t)comp * np3 + t];
+            __syncthreads();
+            if (act) {
+                double s, g[3];
+                mesh_self_term<PC>(u, k.p, tab, &s, g);
+                acc[comp] = qi * qi * s;
+            }
+        }
+    }
+    if (act) {
+        acc[6] = qi * qi;
+        acc[7] = qi * sig[i] * sig[i];
+    }
+    block_sum<QEQ_NPART>(acc);
+    if (threadIdx.x == 0)
+        for (int t = 0; t < QEQ_NPART; ++t) part[(size_t)blockIdx.x * QEQ_NPART + t] = acc[t];
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -502,5 +547,29 @@ int launch_selfcorr(qeq_plan* pl) {
     else
         hipLaunchKernelGGL(k_selfcorr<0>, dim3(nblocks(pl->kp.n)), dim3(QEQ_BLOCK), 0, pl->stream, pl->kp,
                            pl->frac, pl->theta_tab, pl->dself, pl->selfgrad);
+    return qeq_check(hipGetLastError());
+}
+
+int launch_theta_strain(qeq_plan* pl, double* tabs) {
+    const int np = 2 * pl->kp.p - 1;
+    const int np3 = np * np * np;
+    for (int comp = 0; comp < 6; ++comp) {
+        QEQ_TRY(launch_write_green_strain(pl, comp));
+        QEQ_TRY(launch_mesh_inverse(pl));
+        hipLaunchKernelGGL(k_theta_extract, dim3(nblocks(np3)), dim3(QEQ_BLOCK), 0, pl->stream, pl->kp,
+                           pl->grid_r, tabs + (size_t)comp * np3);
+        QEQ_TRY(qeq_check(hipGetLastError()));
+    }
+    return QEQ_OK;
+}
+
+int launch_self_strain(qeq_plan* pl, const double* tabs, double* part) {
+    const KParams& k = pl->kp;
+    if (k.p == 6)
+        hipLaunchKernelGGL(k_self_strain<6>, dim3(nblocks(k.n)), dim3(QEQ_BLOCK), 0, pl->stream, k, pl->frac, tabs,
+                           pl->q, pl->sig, part);
+    else
+        hipLaunchKernelGGL(k_self_strain<0>, dim3(nblocks(k.n)), dim3(QEQ_BLOCK), 0, pl->stream, k, pl->frac, tabs,
+                           pl->q, pl->sig, part);
     return qeq_check(hipGetLastError());
 }

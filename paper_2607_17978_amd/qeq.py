@@ -88,6 +88,8 @@ def load_library():
     L.qeq_solve.restype = ctypes.c_int
     L.qeq_backward.argtypes = [vp, dp, f64, f64, dp, dp, dp, ctypes.POINTER(Stats)]
     L.qeq_backward.restype = ctypes.c_int
+    L.qeq_virial.argtypes = [vp, dp]
+    L.qeq_virial.restype = ctypes.c_int
     L.qeq_matvec.argtypes = [vp, i32, dp, ctypes.POINTER(ctypes.c_double), dp, dp, dp, i32]
     L.qeq_matvec.restype = ctypes.c_int
     L.qeq_time_kernel.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_double)]
@@ -245,6 +247,18 @@ class Plan:
         if check and rc < 0:
             raise QEqError(rc, strerror(rc))
         return dchi, dJ, dpos, dict(st.as_dict(), rc=rc)
+
+    def virial(self):
+        """Virial W = -dE/d eps (3 x 3 float64 on the device) of the last solve;
+        the stress is -W / V (see qeq_virial)."""
+        import torch
+        if self._last_n is None:
+            raise QEqError(QEQ_EINVAL, "virial needs a preceding solve")
+        W = torch.empty((3, 3), dtype=torch.float64, device=self.device)
+        rc = load_library().qeq_virial(self._h, _ptr(W))
+        if rc < 0:
+            raise QEqError(rc, strerror(rc))
+        return W
 
     def descriptors(self, pos, cell, sigma, centers, width, r_cut, weights=None):
         """Radial descriptors G (n x len(centers), float32, device), optionally

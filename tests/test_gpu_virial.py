@@ -1,0 +1,129 @@
+"""Virial W = -dE/d eps of the GPU solve against the FP64 oracle.
+
+The oracle's virial (oracle.ewald.virial, oracle.matfree) is pinned by strain
+finite differences and split-width invariance (test_oracle_pins).  The GPU
+virial is a sum of force-like terms (pair derivatives, the mesh energy
+weighted by k k, the self-correction's strain derivative), so it takes the
+forces' relative bar: 1e-4 in the Frobenius norm.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from inputs import gen
+from oracle import ewald
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+ETA = 2.0
+TOL_W = 1e-4
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2607_17978_amd import qeq
+    qeq.load_library()
+    return torch.device("cuda", 0)
+
+
+def T(a, dev, dt=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+
+
+def rel_fro(W, ref):
+    return np.linalg.norm(W - ref) / np.linalg.norm(ref)
+
+
+def gpu_virial(dev, s, rc, self_correction=True, tol=1e-8):
+    from paper_2607_17978_amd import qeq
+    plan = qeq.Plan(s.n, eta=ETA, r_cut=rc, grid=s.grid, tol=tol, self_correction=self_correction)
+    q, en, f, st = plan.solve(T(s.pos, dev), s.cell, T(s.sigma, dev), T(s.J, dev), T(s.chi, dev), s.q_tot)
+    assert st["rc"] == 0
+    W = plan.virial().cpu().numpy()
+    plan.close()
+    return W, q.cpu().numpy()
+
+
+@pytest.mark.parametrize("which,rc", [("n64", 11.0), ("batch3", 12.0), ("batch17", 12.0), ("batch40", 12.0)])
+def test_virial_matches_oracle(dev, which, rc):
+    s = gen.system_64() if which == "n64" else gen.batch_structure(int(which[5:]))
+    W, q = gpu_virial(dev, s, rc)
+    ref = ewald.qeq_dense(s.pos, s.cell, s.sigma, s.J, s.chi, s.q_tot, forces=False)
+    Wref = ewald.virial(s.pos, s.cell, s.sigma, ref.q)
+    err = rel_fro(W, Wref)
+    print(which, s.n, s.grid, "q_tot", s.q_tot, "W rel err", err, "dq", np.abs(q - ref.q).max())
+    print(W)
+    print(Wref)
+    assert np.abs(W - W.T).max() == 0.0
+    assert err <= TOL_W
+
+
+def test_virial_without_self_correction(dev):
+    """With the mesh self-correction switched off the plan's energy (and so
+    its virial) carries the uncorrected mesh self-interaction; both stay
+    within the bar of the oracle, and the correction moves W by less than it."""
+    s = gen.batch_structure(17)
+    W1, _ = gpu_virial(dev, s, 12.0, self_correction=True)
+    W0, _ = gpu_virial(dev, s, 12.0, self_correction=False)
+    ref = ewald.qeq_dense(s.pos, s.cell, s.sigma, s.J, s.chi, s.q_tot, forces=False)
+    Wref = ewald.virial(s.pos, s.cell, s.sigma, ref.q)
+    print("with", rel_fro(W1, Wref), "without", rel_fro(W0, Wref), "difference", rel_fro(W0, W1))
+    assert rel_fro(W0, Wref) <= TOL_W
+    assert 0.0 < rel_fro(W0, W1) <= TOL_W
+
+
+def test_virial_cached_tables_follow_the_cell(dev):
+    """Repeated calls agree exactly; a solve on another cell and back gives the
+    first value again (the strain tables are rebuilt for each cell)."""
+    from paper_2607_17978_amd import qeq
+    a, b = gen.batch_structure(3), gen.batch_structure(5)
+    plan = qeq.Plan(512, eta=ETA, r_cut=12.0, grid=(48, 48, 48), tol=1e-8)
+
+    def run(s):
+        plan.solve(T(s.pos, dev), s.cell, T(s.sigma, dev), T(s.J, dev), T(s.chi, dev), s.q_tot)
+        return plan.virial().cpu().numpy()
+
+    w1 = run(a)
+    w1b = plan.virial().cpu().numpy()
+    wb = run(b)
+    w2 = run(a)
+    assert np.array_equal(w1, w1b)
+    assert np.array_equal(w1, w2)
+    assert not np.allclose(w1, wb)
+    plan.close()
+
+
+def test_virial_needs_a_solve(dev):
+    from paper_2607_17978_amd import qeq
+    s = gen.system_64()
+    plan = qeq.Plan(s.n, eta=ETA, r_cut=11.0, grid=s.grid)
+    with pytest.raises(qeq.QEqError):
+        plan.virial()
+    plan.solve(T(s.pos, dev), s.cell, T(s.sigma, dev), T(s.J, dev), T(s.chi, dev), 0.0)
+    plan.virial()
+    plan.matvec(T(s.pos, dev), s.cell, T(s.sigma, dev), T(np.ones(s.n), dev))
+    with pytest.raises(qeq.QEqError):
+        plan.virial()
+    lib = qeq.load_library()
+    assert lib.qeq_virial(None, None) == qeq.QEQ_EINVAL
+    plan.close()
+
+
+def test_full_size_32768_virial_matches_oracle(dev):
+    """The benchmark configuration (32,768 atoms, 192^3, tol 1e-6, r_c 11)
+    against the stored matrix-free oracle virial at the oracle's charges."""
+    path = os.path.join(os.path.dirname(__file__), "golden", "n32768_reference.npz")
+    ref = np.load(path) if os.path.exists(path) else None
+    if ref is None or "virial" not in ref.files:
+        pytest.skip("reference not generated")
+    s = gen.system_32k()
+    W, _ = gpu_virial(dev, s, 11.0, tol=1e-6)
+    err = rel_fro(W, ref["virial"])
+    print("n32768 W rel err", err)
+    print(W)
+    print(ref["virial"])
+    assert err <= TOL_W
