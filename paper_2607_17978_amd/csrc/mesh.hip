@@ -7,8 +7,9 @@
 //   half spectrum  C[m3][m1][m2]           (m2 contiguous, m3 = 0 .. K3/2)
 // Passes (each one read and one write of the grid, transforms in LDS):
 //   1. spread + R2C along axis 3  : block = (g1, tile of TW rows g2).  The
-//      atoms whose spline support reaches the tile are staged in LDS, their
-//      weights accumulated into the tile in 64-bit fixed point with integer
+//      atoms whose spline support reaches the tile are held in registers (one
+//      per thread), their weights accumulated into the tile in 64-bit fixed
+//      point with integer
 //      LDS atomics (exact, order-independent sums; FP32 LDS atomics run at a
 //      fraction of the integer rate on gfx950), converted to FP32, two real
 //      rows packed into one complex FFT and the half spectra written
@@ -32,8 +33,6 @@ namespace {
 #define MESH_INV 4
 #define MESH_ENERGY 8
 
-#define SPREAD_CAND 128        // candidate atoms staged in LDS per round
-#define SPREAD_CW (2 * QEQ_MAXP + 1)
 
 constexpr int NT = QEQ_FFT_THREADS;
 
@@ -53,12 +52,10 @@ __global__ __launch_bounds__(NT) void k_spread_r2c(KParams k, FftAxis ax3, const
     const int p = PC ? PC : k.p;
     const int ncol = TW >> 1;
     // LDS: twiddles | accumulator acc[g3][row] (int64; the FFT buffer
-    // buf[g3][pr] (complex) aliases its first half once converted) | staging
+    // buf[g3][pr] (complex) aliases its first half once converted)
     float2* tw = sm;
     long long* acc = reinterpret_cast<long long*>(sm + K3);
     float2* buf = sm + K3;
-    float* cw = reinterpret_cast<float*>(acc + K3 * TW);                // [SPREAD_CAND][SPREAD_CW]
-    int* ch = reinterpret_cast<int*>(cw + SPREAD_CAND * SPREAD_CW);   // [SPREAD_CAND][2]
     __shared__ int seg_lo[2 * QEQ_MAXP], seg_off[2 * QEQ_MAXP + 1], seg_k1[2 * QEQ_MAXP];
     __shared__ int nseg;
     __shared__ float sh_scale;
@@ -105,16 +102,49 @@ __global__ __launch_bounds__(NT) void k_spread_r2c(KParams k, FftAxis ax3, const
     }
     __syncthreads();
     const int ncand = seg_off[nseg];
+    // Candidate c of a round is held by thread c in registers: its source
+    // value times the axis-1 weight, the axis-2 and axis-3 weights and its home
+    // indices (no LDS staging, so more blocks fit per CU).
+    constexpr int PM = PC ? PC : QEQ_MAXP;
+    float a0 = 0.f, w2[PM], w3[PM];
+    int h2 = 0, h3 = 0;
+    double asrc = 0.0;
+    auto load_cand = [&](int cidx) {
+        int sg = 0;
+        while (cidx >= seg_off[sg + 1]) ++sg;
+        const int a = seg_lo[sg] + (cidx - seg_off[sg]);
+        const float* w = wts + (size_t)a * 3 * QEQ_MAXP;
+        const double sv = src[a];
+        asrc = fabs(sv);
+        a0 = (float)sv * w[seg_k1[sg]];
+#pragma unroll
+        for (int kk = 0; kk < PM; ++kk) {
+            if (!PC && kk >= p) break;
+            w2[kk] = w[QEQ_MAXP + kk];
+            w3[kk] = w[2 * QEQ_MAXP + kk];
+        }
+        h2 = home[4 * a + 1];
+        h3 = home[4 * a + 2];
+    };
     // Fixed-point scale: every grid value of the tile is a sum over the
     // candidates of src times a weight product <= 1, taken at most once per
     // candidate, so |value| <= S = sum |src|; with scale = 2^(60 - e),
-    // S < 2^e, every partial sum stays below 2^60 in magnitude.
+    // S < 2^e, every partial sum stays below 2^60 in magnitude.  One round:
+    // S from the registers; more rounds: a pass over the sources first.
+    const bool one_round = ncand <= NT;
     {
         double v[1] = {0.0};
-        for (int cidx = tid; cidx < ncand; cidx += NT) {
-            int sg = 0;
-            while (cidx >= seg_off[sg + 1]) ++sg;
-            v[0] += fabs(src[seg_lo[sg] + (cidx - seg_off[sg])]);
+        if (one_round) {
+            if (tid < ncand) {
+                load_cand(tid);
+                v[0] = asrc;
+            }
+        } else {
+            for (int cidx = tid; cidx < ncand; cidx += NT) {
+                int sg = 0;
+                while (cidx >= seg_off[sg + 1]) ++sg;
+                v[0] += fabs(src[seg_lo[sg] + (cidx - seg_off[sg])]);
+            }
         }
         block_sum<1>(v);
         if (tid == 0) {
@@ -126,48 +156,31 @@ __global__ __launch_bounds__(NT) void k_spread_r2c(KParams k, FftAxis ax3, const
     }
     const float scale = sh_scale;
     unsigned long long* acc_u = reinterpret_cast<unsigned long long*>(acc);
-    for (int base = 0; base < ncand; base += SPREAD_CAND) {
-        const int cnt = min(SPREAD_CAND, ncand - base);
-        if (tid < cnt) {
-            const int cidx = base + tid;
-            int sg = 0;
-            while (cidx >= seg_off[sg + 1]) ++sg;
-            const int a = seg_lo[sg] + (cidx - seg_off[sg]);
-            const int k1 = seg_k1[sg];
-            const float* w = wts + (size_t)a * 3 * QEQ_MAXP;
-            float* dstw = cw + tid * SPREAD_CW;
-            dstw[0] = (float)src[a] * w[k1] * scale;
-            for (int kk = 0; kk < p; ++kk) {
-                dstw[1 + kk] = w[QEQ_MAXP + kk];
-                dstw[1 + QEQ_MAXP + kk] = w[2 * QEQ_MAXP + kk];
-            }
-            ch[2 * tid] = home[4 * a + 1];
-            ch[2 * tid + 1] = home[4 * a + 2];
-        }
-        __syncthreads();
-        // one item = (candidate, k2): a row of p consecutive g3 points
-        for (int item = tid; item < cnt * p; item += NT) {
-            const int c = item / p;
-            const int k2 = item - c * p;
-            // row of grid point h2 - k2 inside this tile; a tile narrower than
-            // p - 1 rows also sees candidates whose point lies before it
-            int r = ch[2 * c] - k2 - g20;
-            if (r < 0) r += K2;
-            if (r < 0 || r >= TW) continue;
-            const float* cwc = cw + c * SPREAD_CW;
-            const float a0 = cwc[0] * cwc[1 + k2];
-            const int h3 = ch[2 * c + 1];
+    for (int base = 0; base < ncand; base += NT) {
+        const int cidx = base + tid;
+        if (cidx < ncand) {
+            if (!one_round) load_cand(cidx);
+            const float as = a0 * scale;
 #pragma unroll
-            for (int k3 = 0; k3 < (PC ? PC : QEQ_MAXP); ++k3) {
-                if (!PC && k3 >= p) break;
-                int g3 = h3 - k3;
-                if (g3 < 0) g3 += K3;
-                const long long v = __float2ll_rn(a0 * cwc[1 + QEQ_MAXP + k3]);
-                atomicAdd(acc_u + g3 * TW + r, (unsigned long long)v);
+            for (int k2 = 0; k2 < PM; ++k2) {
+                if (!PC && k2 >= p) break;
+                // row of grid point h2 - k2 inside this tile; a tile narrower
+                // than p - 1 rows also sees candidates whose point lies before it
+                int r = h2 - k2 - g20;
+                if (r < 0) r += K2;
+                if (r < 0 || r >= TW) continue;
+                const float a1 = as * w2[k2];
+#pragma unroll
+                for (int k3 = 0; k3 < PM; ++k3) {
+                    if (!PC && k3 >= p) break;
+                    int g3 = h3 - k3;
+                    if (g3 < 0) g3 += K3;
+                    atomicAdd(acc_u + g3 * TW + r, (unsigned long long)__float2ll_rn(a1 * w3[k3]));
+                }
             }
         }
-        __syncthreads();
     }
+    __syncthreads();
     // fixed point -> FP32, packed two real rows per complex column
     {
         const float inv = 1.0f / scale;
@@ -513,8 +526,7 @@ __global__ __launch_bounds__(NT) void k_cols_virial(KParams k, FftAxis ax1, cons
 }
 
 size_t smem_spread(const KParams& k) {
-    return sizeof(float2) * (size_t)k.K3 + sizeof(long long) * (size_t)k.K3 * k.TWS +
-           SPREAD_CAND * (SPREAD_CW * sizeof(float) + 2 * sizeof(int));
+    return sizeof(float2) * (size_t)k.K3 + sizeof(long long) * (size_t)k.K3 * k.TWS;
 }
 size_t smem_rows(const KParams& k) { return sizeof(float2) * ((size_t)k.K2 + (size_t)k.K2 * (k.NR + 1)); }
 size_t smem_cols(const KParams& k) { return sizeof(float2) * ((size_t)k.K1 + (size_t)k.K1 * k.TW); }

@@ -17,10 +17,11 @@ namespace {
 
 // y_i = sum_g theta_i(g) phi(g) + sum_j K_ij v_j + d_i v_i (+ J_i v_i)
 // and, in FINAL mode, the force on atom i.  One wave per atom: lane
-// (k1, k2) < p^2 gathers one row of p consecutive grid values along axis 3,
-// all 64 lanes then stride over the atom's pair-list row; the partial sums
-// are reduced across the wave.  (One thread per atom would leave the chip
-// with a few hundred waves and 216 dependent gathers each.)
+// (k2, k3) < p^2 gathers the p grid values along axis 1 at that (k2, k3)
+// (adjacent lanes read adjacent addresses), all 64 lanes then stride over the
+// atom's pair-list row; the partial sums are reduced across the wave.  (One
+// thread per atom would leave the chip with a few hundred waves and 216
+// dependent gathers each.)
 template <int MODE, int PC>
 __global__ __launch_bounds__(QEQ_BLOCK) void k_interp(
     KParams k, const double* __restrict__ src, double* __restrict__ dst, const float* __restrict__ grid,
@@ -47,31 +48,35 @@ __global__ __launch_bounds__(QEQ_BLOCK) void k_interp(
     const bool active = i < k.n;
     if (active) {
         if ((k.parts & QEQ_PART_RECIP) && lane < p * p) {
-            const int k1 = lane / p, k2 = lane - (lane / p) * p;
+            // lane (k2, k3), k3 fastest: the lanes of one k2 read p
+            // consecutive grid values, so each load instruction touches p
+            // short runs instead of p^2 scattered rows; k1 is the loop
+            const int k2 = lane / p, k3 = lane - (lane / p) * p;
             const int h1 = home[4 * i], h2 = home[4 * i + 1], h3 = home[4 * i + 2];
             const float* w = wts + (size_t)i * 3 * QEQ_MAXP;
-            int g1 = h1 - k1;
-            if (g1 < 0) g1 += k.K1;
+            const float* dw = dwts + (size_t)i * 3 * QEQ_MAXP;
             int g2 = h2 - k2;
             if (g2 < 0) g2 += k.K2;
-            const float* row = grid + ((size_t)g1 * k.K2 + g2) * k.K3;
-            float s = 0.f, s3 = 0.f;
+            int g3 = h3 - k3;
+            if (g3 < 0) g3 += k.K3;
+            const size_t plane = (size_t)k.K2 * k.K3;
+            const float* colp = grid + (size_t)g2 * k.K3 + g3;
+            float s = 0.f, s1 = 0.f;
 #pragma unroll
-            for (int k3 = 0; k3 < (PC ? PC : QEQ_MAXP); ++k3) {
-                if (!PC && k3 >= p) break;
-                int g3 = h3 - k3;
-                if (g3 < 0) g3 += k.K3;
-                const float gv = row[g3];
-                s += w[2 * QEQ_MAXP + k3] * gv;
-                if (FIN) s3 += dwts[(size_t)i * 3 * QEQ_MAXP + 2 * QEQ_MAXP + k3] * gv;
+            for (int k1 = 0; k1 < (PC ? PC : QEQ_MAXP); ++k1) {
+                if (!PC && k1 >= p) break;
+                int g1 = h1 - k1;
+                if (g1 < 0) g1 += k.K1;
+                const float gv = colp[(size_t)g1 * plane];
+                s += w[k1] * gv;
+                if (FIN) s1 += dw[k1] * gv;
             }
-            const float w1 = w[k1], w2 = w[QEQ_MAXP + k2];
-            v[0] = (double)(w1 * w2) * (double)s;
+            const float w2 = w[QEQ_MAXP + k2], w3 = w[2 * QEQ_MAXP + k3];
+            v[0] = (double)(w2 * w3) * (double)s;
             if (FIN) {
-                const float* dw = dwts + (size_t)i * 3 * QEQ_MAXP;
-                v[1] = (double)(dw[k1] * w2) * (double)s;
-                v[2] = (double)(w1 * dw[QEQ_MAXP + k2]) * (double)s;
-                v[3] = (double)(w1 * w2) * (double)s3;
+                v[1] = (double)(w2 * w3) * (double)s1;
+                v[2] = (double)(dw[QEQ_MAXP + k2] * w3) * (double)s;
+                v[3] = (double)(w2 * dw[2 * QEQ_MAXP + k3]) * (double)s;
             }
         }
         if (k.parts & QEQ_PART_REAL) {
