@@ -273,6 +273,14 @@ int mlp_train_step(const float* G, const int32_t* species, const double* target,
    are enabled (qeq_profile) the loop launches kernels one by one. */
 int qeq_use_graphs(qeq_plan* plan, int32_t enable);
 
+/* Where a g1 slab of the half spectrum (K2 (K3/2 + 1) complex values) fits
+   in the LDS of one compute unit (grids 96^3 and 192^3 with K1 >= 64), the
+   inverse axis-2 transform and the axis-3 complex-to-real transform run as one
+   pass (eq. matvec's back-transform without the intermediate grid round
+   trip); enable = 0 runs them as two passes.  Both give the same potential
+   up to FP32 rounding.  Default on. */
+int qeq_use_fused_inverse(qeq_plan* plan, int32_t enable);
+
 /* Per-stage timers (the paper's per-stage timing of a step, here with HIP
    events on the plan's stream).  kind_mask selects which launch kinds are
    bracketed with events during later calls; 0 switches timing off.  Kinds:

@@ -832,6 +832,14 @@ int qeq_use_graphs(qeq_plan* plan, int32_t enable) {
     return QEQ_OK;
 }
 
+int qeq_use_fused_inverse(qeq_plan* plan, int32_t enable) {
+    if (!plan) return QEQ_EINVAL;
+    if (plan->stream) (void)hipStreamSynchronize(plan->stream);
+    plan->fused_inverse = enable != 0;
+    drop_graph(plan);
+    return QEQ_OK;
+}
+
 int qeq_time_kernel(qeq_plan* plan, int32_t kind, int32_t reps, double* avg_us) {
     if (!plan || !avg_us || reps < 1) return QEQ_EINVAL;
     if (!plan->tape_valid || (kind != PK_SPREAD_R2C && kind != PK_C2R)) return QEQ_EINVAL;

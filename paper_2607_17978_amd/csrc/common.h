@@ -204,7 +204,7 @@ __device__ __forceinline__ void fft_lds(float2* buf, const FftAxis& ax, int ncol
 // count, the LDS row stride and the thread count fixed at compile time: every
 // index computation folds to shifts and multiplications by constants, only
 // the radices the length needs are instantiated, and register arrays are
-// sized exactly.  Element (k, c) lives at buf[k * KS + c], c < NCOL <= KS.
+// sized exactly.  Element (k, c) lives at buf[k * KS + c * CS].
 // ---------------------------------------------------------------------------
 constexpr int ct_radix_at(int K, int s) {
     int n = K, idx = 0;
@@ -216,7 +216,7 @@ constexpr int ct_radix_at(int K, int s) {
     return 0;
 }
 
-template <int K, int R, int NS, int NCOL, int KS, int NTHR, bool INV>
+template <int K, int R, int NS, int NCOL, int KS, int NTHR, bool INV, int CS = 1>
 __device__ __forceinline__ void fft_stage_ct(float2* buf, const float2* tw, int tid) {
     constexpr int PER = K / R;
     constexpr int NITEMS = PER * NCOL;
@@ -229,7 +229,7 @@ __device__ __forceinline__ void fft_stage_ct(float2* buf, const float2* tw, int 
         if (NITEMS % NTHR == 0 || item < NITEMS) {
             const int c = item % NCOL, j = item / NCOL;
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[it][r] = buf[(j + r * PER) * KS + c];
+            for (int r = 0; r < R; ++r) v[it][r] = buf[(j + r * PER) * KS + c * CS];
         }
     }
     __syncthreads();
@@ -250,18 +250,20 @@ __device__ __forceinline__ void fft_stage_ct(float2* buf, const float2* tw, int 
             dft<R>(v[it], INV);
             const int base = (j - kk) * R + kk;
 #pragma unroll
-            for (int r = 0; r < R; ++r) buf[(base + r * NS) * KS + c] = v[it][r];
+            for (int r = 0; r < R; ++r) buf[(base + r * NS) * KS + c * CS] = v[it][r];
         }
     }
     __syncthreads();
 }
 
-template <int K, int NCOL, int KS, int NTHR, bool INV, int S = 0, int NS = 1>
+// CS: stride between columns (1 = interleaved columns; a transposed layout
+// has KS = 1 and CS = the row length).
+template <int K, int NCOL, int KS, int NTHR, bool INV, int S = 0, int NS = 1, int CS = 1>
 __device__ __forceinline__ void fft_ct(float2* buf, const float2* tw, int tid) {
     constexpr int R = ct_radix_at(K, S);
     if constexpr (R != 0) {
-        fft_stage_ct<K, R, NS, NCOL, KS, NTHR, INV>(buf, tw, tid);
-        fft_ct<K, NCOL, KS, NTHR, INV, S + 1, NS * R>(buf, tw, tid);
+        fft_stage_ct<K, R, NS, NCOL, KS, NTHR, INV, CS>(buf, tw, tid);
+        fft_ct<K, NCOL, KS, NTHR, INV, S + 1, NS * R, CS>(buf, tw, tid);
     }
 }
 

@@ -184,6 +184,7 @@ struct qeq_plan {
     bool warm_rejected = false;   // the last solve discarded its q0
 
     BatchState* batch = nullptr;
+    bool fused_inverse = true;    // fused inverse axis-2 + complex-to-real slab pass where it fits
 
     // the CG loop is replayed as a HIP graph of one chunk of iterations,
     // captured on a private stream and re-captured when its arguments change

@@ -412,6 +412,76 @@ __global__ __launch_bounds__(NT) void k_c2r(KParams k, FftAxis ax3, const float2
     }
 }
 
+// ------------------------------------------------------------------ passes 4 + 5 fused
+// Inverse axis-2 and axis-3 complex-to-real transforms of one g1 slab in LDS,
+// for grids whose slab half spectrum K2 (K3/2 + 1) fits (one block per CU):
+//   load C[m3][g1][m2] as X[m2][m3] (row stride KS = K3/2 + 1),
+//   inverse FFT along m2 for all K3/2 + 1 columns -> X[g2][m3],
+//   each row g2: the real inverse DFT of length N = K3 from its half spectrum
+//   as one complex inverse FFT of length N/2, in place:
+//     E[k] = X[k] + conj X[N/2 - k],  O[k] = e^{2 pi i k/N} (X[k] - conj X[N/2 - k]),
+//     z = IFFT_{N/2}(E + i O),  x[2n] = Re z[n],  x[2n + 1] = Im z[n]
+//   (both IFFT(E) and IFFT(O) are real because the line is),
+//   store R[g1][g2][g3] as pairs.  Saves the grid round trip between the two
+//   separate passes.
+constexpr int SLAB_NT = 1024;
+
+template <int K2C, int K3C>
+__global__ __launch_bounds__(SLAB_NT) void k_slab_inv(KParams k, FftAxis ax2, FftAxis ax3,
+                                                     const float2* __restrict__ C, float* __restrict__ R,
+                                                     const int* __restrict__ done) {
+    if (done && *done) return;
+    constexpr int K3H = K3C / 2 + 1;
+    constexpr int KS = K3H;
+    constexpr int NH = K3C / 2;
+    constexpr int NQ = NH / 2 + 1;
+    extern __shared__ float2 sm[];
+    float2* tw2 = sm;            // K2C: e^{-2 pi i j / K2}
+    float2* tw3 = tw2 + K2C;     // K3C: e^{-2 pi i j / K3}
+    float2* twh = tw3 + K3C;     // NH:  e^{-2 pi i j / NH}
+    float2* X = twh + NH;        // K2C x KS
+    const int tid = threadIdx.x;
+    const int g1 = blockIdx.x;
+    const int K1 = k.K1;
+    for (int t = tid; t < K2C; t += SLAB_NT) tw2[t] = ax2.tw[t];
+    for (int t = tid; t < K3C; t += SLAB_NT) tw3[t] = ax3.tw[t];
+    for (int t = tid; t < NH; t += SLAB_NT) twh[t] = ax3.tw[2 * t];
+    for (int t = tid; t < K3H * K2C; t += SLAB_NT) {
+        const int m3 = t / K2C, m2 = t - m3 * K2C;
+        X[m2 * KS + m3] = C[((size_t)m3 * K1 + g1) * K2C + m2];
+    }
+    __syncthreads();
+    fft_ct<K2C, K3H, KS, SLAB_NT, true>(X, tw2, tid);
+    // pairs (k, N/2 - k), k <= N/4: one thread reads both and writes both
+    for (int t = tid; t < K2C * NQ; t += SLAB_NT) {
+        const int g2 = t / NQ, kk = t - g2 * NQ;
+        float2* row = X + g2 * KS;
+        const int kp = NH - kk;
+        const float2 a = row[kk], b = row[kp];
+        float2 z[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const float2 xk = h ? b : a, xq = h ? a : b;   // X[idx], X[N/2 - idx]
+            const int idx = h ? kp : kk;
+            const float2 cq = make_float2(xq.x, -xq.y);
+            const float2 e = cadd(xk, cq);
+            float2 w = tw3[idx];
+            w.y = -w.y;
+            const float2 o = cmul(csub(xk, cq), w);
+            z[h] = make_float2(e.x - o.y, e.y + o.x);
+        }
+        row[kk] = z[0];
+        if (kp < NH && kp != kk) row[kp] = z[1];
+    }
+    __syncthreads();
+    fft_ct<NH, K2C, 1, SLAB_NT, true, 0, 1, KS>(X, twh, tid);
+    float2* R2 = reinterpret_cast<float2*>(R) + (size_t)g1 * K2C * NH;
+    for (int t = tid; t < K2C * NH; t += SLAB_NT) {
+        const int g2 = t / NH, n = t - g2 * NH;
+        R2[t] = X[g2 * KS + n];
+    }
+}
+
 __global__ void k_write_green(KParams k, float2* __restrict__ C, const float* __restrict__ b1,
                               const float* __restrict__ b2, const float* __restrict__ b3) {
     const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -641,6 +711,47 @@ int c2r_pass(qeq_plan* pl, const int* done) {
     return qeq_check(hipGetLastError());
 }
 
+size_t smem_slab(int K2, int K3) {
+    return sizeof(float2) * ((size_t)K2 + K3 + K3 / 2 + (size_t)K2 * (K3 / 2 + 1));
+}
+
+// Lengths with a fused slab kernel; the slab must fit the LDS of one CU.
+#define QEQ_FOR_EACH_SLAB(X) X(96, 96) X(192, 192)
+
+bool slab_available(const qeq_plan* pl) {
+    const KParams& k = pl->kp;
+    if (!pl->fused_inverse || k.K1 < 64) return false;
+#define X(A, B) if (k.K2 == A && k.K3 == B) return true;
+    QEQ_FOR_EACH_SLAB(X)
+#undef X
+    return false;
+}
+
+int slab_inv_pass(qeq_plan* pl, const int* done) {
+    const KParams& k = pl->kp;
+    ProfScope ps(pl, PK_C2R);
+#define X(A, B)                                                                                    \
+    if (k.K2 == A && k.K3 == B) {                                                                  \
+        const size_t sh = smem_slab(A, B);                                                         \
+        QEQ_HIP(hipFuncSetAttribute((const void*)k_slab_inv<A, B>,                                 \
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));         \
+        hipExtLaunchKernelGGL((k_slab_inv<A, B>), dim3(k.K1), dim3(SLAB_NT), sh, pl->stream, ps.start(), \
+                              ps.stop(), 0, k, pl->axes.ax[1], pl->axes.ax[2], pl->grid_c, pl->grid_r, done); \
+        return qeq_check(hipGetLastError());                                                       \
+    }
+    QEQ_FOR_EACH_SLAB(X)
+#undef X
+    return QEQ_EPLAN;
+}
+
+// Inverse transforms after the axis-1 pass: the fused slab kernel where it
+// applies, else the inverse axis-2 pass and the complex-to-real pass.
+int inverse_tail(qeq_plan* pl, const int* done) {
+    if (slab_available(pl)) return slab_inv_pass(pl, done);
+    QEQ_TRY(rows_pass(pl, 1, done));
+    return c2r_pass(pl, done);
+}
+
 }  // namespace
 
 size_t qeq_mesh_max_smem(const KParams& k) {
@@ -654,20 +765,18 @@ int launch_mesh_potential(qeq_plan* pl, const double* src, const int* done) {
     QEQ_TRY(spread_pass(pl, src, done));
     QEQ_TRY(rows_pass(pl, 0, done));
     QEQ_TRY(cols_pass(pl, MESH_FWD | MESH_GREEN | MESH_INV, nullptr, done));
-    QEQ_TRY(rows_pass(pl, 1, done));
-    return c2r_pass(pl, done);
+    return inverse_tail(pl, done);
 }
 
 int launch_mesh_stage(qeq_plan* pl, int kind, const double* src) {
     if (kind == PK_SPREAD_R2C) return spread_pass(pl, src, nullptr);
-    if (kind == PK_C2R) return c2r_pass(pl, nullptr);
+    if (kind == PK_C2R) return slab_available(pl) ? slab_inv_pass(pl, nullptr) : c2r_pass(pl, nullptr);
     return QEQ_EINVAL;
 }
 
 int launch_mesh_inverse(qeq_plan* pl) {
     QEQ_TRY(cols_pass(pl, MESH_INV, nullptr, nullptr));
-    QEQ_TRY(rows_pass(pl, 1, nullptr));
-    return c2r_pass(pl, nullptr);
+    return inverse_tail(pl, nullptr);
 }
 
 int launch_write_green(qeq_plan* pl) {

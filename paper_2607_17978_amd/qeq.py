@@ -94,6 +94,8 @@ def load_library():
     L.qeq_matvec.restype = ctypes.c_int
     L.qeq_time_kernel.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_double)]
     L.qeq_time_kernel.restype = ctypes.c_int
+    L.qeq_use_fused_inverse.argtypes = [vp, i32]
+    L.qeq_use_fused_inverse.restype = ctypes.c_int
     L.qeq_use_graphs.argtypes = [vp, i32]
     L.qeq_use_graphs.restype = ctypes.c_int
     L.qeq_profile.argtypes = [vp, ctypes.c_uint32]
@@ -345,6 +347,10 @@ class Plan:
     def use_graphs(self, enable=True):
         """Replay the CG loop as a HIP graph (default) or launch kernels one by one."""
         load_library().qeq_use_graphs(self._h, 1 if enable else 0)
+
+    def use_fused_inverse(self, enable=True):
+        """Fused inverse axis-2 + complex-to-real slab pass where it fits (default) or two passes."""
+        load_library().qeq_use_fused_inverse(self._h, 1 if enable else 0)
 
     def profile(self, mask):
         """Bracket the launch kinds in ``mask`` with HIP events (see qeq_profile)."""

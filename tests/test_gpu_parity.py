@@ -227,3 +227,46 @@ def test_graph_replays_match_eager(dev):
         if rep % 2 == 0:
             pg.solve(T(o.pos, dev), o.cell, T(o.sigma, dev), T(o.J, dev), T(o.chi, dev), 0.0)
     pg.close()
+
+
+@pytest.mark.parametrize("which", ["n4096", "n32768"])
+def test_fused_inverse_matches_two_passes(dev, which):
+    """The fused slab pass (inverse axis-2 + complex-to-real in one kernel,
+    96^3 and 192^3 grids) gives the potential of the two separate passes."""
+    from paper_2607_17978_amd import qeq
+    s = gen.system_4096() if which == "n4096" else gen.system_32k()
+    plan = qeq.Plan(s.n, eta=ETA, r_cut=RC, grid=s.grid, tol=1e-8)
+    v = T(np.random.default_rng(9).normal(size=s.n), dev)
+    args = (T(s.pos, dev), s.cell, T(s.sigma, dev))
+    y1 = plan.matvec(*args, v, parts=qeq.PART_RECIP).cpu().numpy()
+    plan.use_fused_inverse(False)
+    y0 = plan.matvec(*args, v, parts=qeq.PART_RECIP).cpu().numpy()
+    err = np.abs(y1 - y0).max() / np.abs(y0).max()
+    print(which, "fused vs two passes, rel max diff", err)
+    assert err <= 1e-5
+    if which == "n4096":
+        solve_args = (T(s.pos, dev), s.cell, T(s.sigma, dev), T(s.J, dev), T(s.chi, dev), 0.0)
+        q0 = plan.solve(*solve_args)[0].cpu().numpy()
+        plan.use_fused_inverse(True)
+        q1 = plan.solve(*solve_args)[0].cpu().numpy()
+        assert np.abs(q1 - q0).max() <= 1e-7
+    plan.close()
+
+
+def test_n4096_matches_matfree_oracle(dev):
+    """96^3 grid (fused slab pass) against the FP64 matrix-free oracle."""
+    from oracle import matfree
+    from paper_2607_17978_amd import qeq
+    s = gen.system_4096()
+    ref = matfree.qeq_matfree(s.pos, s.cell, s.sigma, s.J, s.chi, 0.0, tol=1e-10, forces=True)
+    plan = qeq.Plan(s.n, eta=ETA, r_cut=RC, grid=s.grid, tol=1e-7)
+    q, en, f, st = plan.solve(T(s.pos, dev), s.cell, T(s.sigma, dev), T(s.J, dev), T(s.chi, dev), 0.0)
+    q, en, f = q.cpu().numpy(), en.cpu().numpy(), f.cpu().numpy()
+    dq = np.abs(q - ref.q).max()
+    de_q = abs(en[0] - ref.e_qeq) / abs(ref.e_qeq)
+    de_e = abs(en[1] - ref.e_elec) / abs(ref.e_elec)
+    df = np.sqrt(np.mean((f - ref.forces) ** 2)) / np.sqrt(np.mean(ref.forces ** 2))
+    print("n4096", st, "dq", dq, "dEqeq", de_q, "dEelec", de_e, "dF", df)
+    assert st["rc"] == 0
+    assert dq <= 1e-5 and de_q <= 1e-6 and de_e <= 1e-6 and df <= 1e-4
+    plan.close()
