@@ -268,6 +268,19 @@ __device__ __forceinline__ void fft_ct(float2* buf, const float2* tw, int tid) {
 }
 
 // ---------------------------------------------------------------------------
+// Workgroups are dispatched to the 8 XCDs round-robin (block b runs on XCD
+// b mod 8), and each XCD has its own L2.  Renumbering the blocks so that the
+// blocks of one XCD cover one contiguous range of work keeps neighbouring
+// tiles or atoms, which read the same cache lines, in the same L2.  A
+// bijection of [0, nb) for any nb.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+    const int x = b & 7, j = b >> 3;
+    const int q = nb >> 3, r = nb & 7;
+    return x * q + (x < r ? x : r) + j;
+}
+
+// ---------------------------------------------------------------------------
 // FP64 block reductions (wave64 shuffles, then LDS across waves)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double wave_sum(double v) {

@@ -60,8 +60,9 @@ __global__ __launch_bounds__(NT) void k_spread_r2c(KParams k, FftAxis ax3, const
     __shared__ int nseg;
     __shared__ float sh_scale;
     const int tid = threadIdx.x;
-    const int g1 = blockIdx.x / k.ntile_s;
-    const int g20 = (blockIdx.x - g1 * k.ntile_s) * TW;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int g1 = blk / k.ntile_s;
+    const int g20 = (blk - g1 * k.ntile_s) * TW;
     const int K1 = k.K1, K2 = k.K2;
 
     for (int t = tid; t < K3; t += NT) tw[t] = ax3.tw[t];

@@ -272,7 +272,7 @@ __global__ __launch_bounds__(QEQ_BLOCK) void k_pairs(KParams k, const double* __
                                                     const int* __restrict__ rowptr, int* __restrict__ col,
                                                     float* __restrict__ kval, float4* __restrict__ pdr) {
     const int lane = threadIdx.x & 63;
-    const int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int i = (xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) >> 6;
     if (i >= k.n) return;   // uniform across the wave
     const double si[3] = {frac[3 * i], frac[3 * i + 1], frac[3 * i + 2]};
     const int ck = home[4 * i + 3];

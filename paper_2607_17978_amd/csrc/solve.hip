@@ -42,7 +42,7 @@ __global__ __launch_bounds__(QEQ_BLOCK) void k_interp(
     // waves stride over atoms; the loop trip count is uniform across the block
     const int rounds = (k.n + nwaves - 1) / nwaves;
     for (int rnd = 0; rnd < rounds; ++rnd) {
-    const int i = rnd * nwaves + ((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const int i = rnd * nwaves + ((xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) >> 6);
     // per-lane partials: y, du[3] (reciprocal gradient / q), fr[3] (pair gradient / q)
     double v[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     const bool active = i < k.n;
