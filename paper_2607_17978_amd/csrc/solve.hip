@@ -47,49 +47,93 @@ __global__ __launch_bounds__(QEQ_BLOCK) void k_interp(
     double v[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     const bool active = i < k.n;
     if (active) {
-        if ((k.parts & QEQ_PART_RECIP) && lane < p * p) {
-            // lane (k2, k3), k3 fastest: the lanes of one k2 read p
-            // consecutive grid values, so each load instruction touches p
-            // short runs instead of p^2 scattered rows; k1 is the loop
-            const int k2 = lane / p, k3 = lane - (lane / p) * p;
-            const int h1 = home[4 * i], h2 = home[4 * i + 1], h3 = home[4 * i + 2];
-            const float* w = wts + (size_t)i * 3 * QEQ_MAXP;
-            const float* dw = dwts + (size_t)i * 3 * QEQ_MAXP;
+        // Loads are issued in three dependent levels so that their latencies
+        // overlap (the memory counter retires loads in issue order): the row
+        // bounds and home indices; then the first 64 pairs' columns and
+        // kernel values, the lane's grid line and weights; then the source
+        // values of those columns.  Arithmetic follows.
+        constexpr int PM = PC ? PC : QEQ_MAXP;
+        const bool do_recip = (k.parts & QEQ_PART_RECIP) && lane < p * p;
+        const bool do_real = (k.parts & QEQ_PART_REAL) != 0;
+        const int e0 = rowptr[i], e1 = rowptr[i + 1];
+        const int h1 = home[4 * i], h2 = home[4 * i + 1], h3 = home[4 * i + 2];
+        const int ef = e0 + lane;
+        const bool has_pair = do_real && ef < e1;
+        int cj = 0;
+        float kv = 0.f;
+        float4 d = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (has_pair) {
+            cj = col[ef];
+            kv = kval[ef];
+            if (FIN) d = pdr[ef];
+        }
+        // lane (k2, k3), k3 fastest: the lanes of one k2 read p consecutive
+        // grid values, so each load instruction touches p short runs instead
+        // of p^2 scattered rows; k1 runs along the lane's line
+        const int k2 = lane / p, k3 = lane - (lane / p) * p;
+        const float* w = wts + (size_t)i * 3 * QEQ_MAXP;
+        const float* dw = dwts + (size_t)i * 3 * QEQ_MAXP;
+        float gv[PM], wk[PM], dwk[PM];
+        float w2 = 0.f, w3 = 0.f, dw2 = 0.f, dw3 = 0.f;
+        if (do_recip) {
             int g2 = h2 - k2;
             if (g2 < 0) g2 += k.K2;
             int g3 = h3 - k3;
             if (g3 < 0) g3 += k.K3;
             const size_t plane = (size_t)k.K2 * k.K3;
             const float* colp = grid + (size_t)g2 * k.K3 + g3;
-            float s = 0.f, s1 = 0.f;
 #pragma unroll
-            for (int k1 = 0; k1 < (PC ? PC : QEQ_MAXP); ++k1) {
+            for (int k1 = 0; k1 < PM; ++k1) {
                 if (!PC && k1 >= p) break;
                 int g1 = h1 - k1;
                 if (g1 < 0) g1 += k.K1;
-                const float gv = colp[(size_t)g1 * plane];
-                s += w[k1] * gv;
-                if (FIN) s1 += dw[k1] * gv;
+                gv[k1] = colp[(size_t)g1 * plane];
+                wk[k1] = w[k1];
+                if (FIN) dwk[k1] = dw[k1];
             }
-            const float w2 = w[QEQ_MAXP + k2], w3 = w[2 * QEQ_MAXP + k3];
+            w2 = w[QEQ_MAXP + k2];
+            w3 = w[2 * QEQ_MAXP + k3];
+            if (FIN) {
+                dw2 = dw[QEQ_MAXP + k2];
+                dw3 = dw[2 * QEQ_MAXP + k3];
+            }
+        }
+        const double vj = has_pair ? src[cj] : 0.0;
+        if (do_recip) {
+            float s = 0.f, s1 = 0.f;
+#pragma unroll
+            for (int k1 = 0; k1 < PM; ++k1) {
+                if (!PC && k1 >= p) break;
+                s += wk[k1] * gv[k1];
+                if (FIN) s1 += dwk[k1] * gv[k1];
+            }
             v[0] = (double)(w2 * w3) * (double)s;
             if (FIN) {
                 v[1] = (double)(w2 * w3) * (double)s1;
-                v[2] = (double)(dw[QEQ_MAXP + k2] * w3) * (double)s;
-                v[3] = (double)(w2 * dw[2 * QEQ_MAXP + k3]) * (double)s;
+                v[2] = (double)(dw2 * w3) * (double)s;
+                v[3] = (double)(w2 * dw3) * (double)s;
             }
         }
-        if (k.parts & QEQ_PART_REAL) {
-            const int e1 = rowptr[i + 1];
-            for (int e = rowptr[i] + lane; e < e1; e += 64) {
-                const double vj = src[col[e]];
-                v[0] += (double)kval[e] * vj;
+        if (has_pair) {
+            v[0] += (double)kv * vj;
+            if (FIN) {
+                const double c = (double)d.w * vj;
+                v[4] += c * d.x;
+                v[5] += c * d.y;
+                v[6] += c * d.z;
+            }
+        }
+        // rows of more than 64 pairs
+        if (do_real) {
+            for (int e = ef + 64; e < e1; e += 64) {
+                const double vje = src[col[e]];
+                v[0] += (double)kval[e] * vje;
                 if (FIN) {
-                    const float4 d = pdr[e];
-                    const double c = (double)d.w * vj;
-                    v[4] += c * d.x;
-                    v[5] += c * d.y;
-                    v[6] += c * d.z;
+                    const float4 de = pdr[e];
+                    const double c = (double)de.w * vje;
+                    v[4] += c * de.x;
+                    v[5] += c * de.y;
+                    v[6] += c * de.z;
                 }
             }
         }
