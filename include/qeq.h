@@ -281,6 +281,24 @@ int qeq_use_graphs(qeq_plan* plan, int32_t enable);
    up to FP32 rounding.  Default on. */
 int qeq_use_fused_inverse(qeq_plan* plan, int32_t enable);
 
+/* Preconditioner of the projected CG in qeq_solve / qeq_backward.
+   k_cut <= 0 (default): Jacobi, D_i = J_i + 1/(sigma_i sqrt(pi)).
+   k_cut > 0 (bohr^-1): spectral preconditioner for the long-wavelength
+   Coulomb modes whose eigenvalues make the iteration count grow with N
+   (the Electrostatics Solvers section's observation).  The exact plane-wave
+   Coulomb part at the reciprocal vectors 0 < |k| <= k_cut (at most the 384
+   nearest, half space) is added to the Jacobi diagonal as a low-rank term,
+     M = D' + Phi W Phi^T,  W = diag(2 (4 pi / V) / k^2),
+     Phi = [F_i(k) cos(k.r_i) | F_i(k) sin(k.r_i)],  F_i(k) = exp(-sigma_i^2 k^2 / 2),
+     D' = D - diag(Phi W Phi^T),
+   and applied by the Woodbury identity with the small inverse built once per
+   geometry.  The converged charges are the same as with Jacobi (the solve
+   tolerance applies unchanged); k_cut ~ 0.2 bohr^-1 cuts the cold-start
+   iterations of a 32,768-atom cell from 57 to about 20.  If the geometry
+   falls outside the range where the construction is safe (D' <= 0.1 D or a
+   weakly dominant small matrix) the solve uses Jacobi.  QEQ_EINVAL for NaN. */
+int qeq_use_spectral_preconditioner(qeq_plan* plan, double k_cut);
+
 /* Per-stage timers (the paper's per-stage timing of a step, here with HIP
    events on the plan's stream).  kind_mask selects which launch kinds are
    bracketed with events during later calls; 0 switches timing off.  Kinds:

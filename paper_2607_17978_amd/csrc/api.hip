@@ -478,7 +478,10 @@ void chunk_key(const qeq_plan* pl, std::vector<unsigned char>& key) {
     const void* ptrs[] = {pl->pvec, pl->y, pl->q, pl->r, pl->dinv, pl->part, pl->sc, pl->grid_r, pl->grid_c,
                           pl->wts, pl->dwts, pl->home, pl->bin_start, pl->rowptr, pl->col, pl->kval, pl->pdr,
                           pl->dself, pl->Jv, pl->chi_raw, pl->chi, pl->sig, pl->selfgrad, pl->fdst, pl->gtmp,
-                          pl->tw[0], pl->tw[1], pl->tw[2], pl->bmod[0], pl->bmod[1], pl->bmod[2]};
+                          pl->tw[0], pl->tw[1], pl->tw[2], pl->bmod[0], pl->bmod[1], pl->bmod[2],
+                          pl->spc_active ? (const void*)pl->spc_mats : nullptr, pl->spc_wvec, pl->spc_m1,
+                          pl->spc_atom, pl->spc_dpinv, pl->spc_tpart, pl->spc_s, pl->spc_scal,
+                          (const void*)(size_t)pl->spc_nm};
     key.resize(sizeof(KParams) + sizeof(ptrs) + sizeof(DeviceAxes));
     unsigned char* k = key.data();
     memcpy(k, &pl->kp, sizeof(KParams));
@@ -495,12 +498,20 @@ void drop_graph(qeq_plan* pl) {
 }
 
 // One CG iteration: matvec of the direction, update of q and r, new direction.
+// Search direction from the current residual: Jacobi, or the spectral
+// preconditioner when it was built for this geometry.
+int next_direction(qeq_plan* pl, int parity, int init) {
+    if (!pl->spc_active) return launch_cg_dir(pl, parity, init);
+    QEQ_TRY(spc_apply(pl, pl->r, &pl->sc->done));
+    return spc_direction(pl, parity, init);
+}
+
 int cg_iteration(qeq_plan* pl, int parity) {
     const int* done = &pl->sc->done;
     QEQ_TRY(launch_mesh_potential(pl, pl->pvec, done));
     QEQ_TRY(launch_interp(pl, pl->pvec, pl->y, QEQ_MODE_CG, parity));
     QEQ_TRY(launch_cg_update(pl, parity));
-    return launch_cg_dir(pl, parity, 0);
+    return next_direction(pl, parity, 0);
 }
 
 // Capture `chunk` iterations (starting at even parity) into a graph unless the
@@ -561,7 +572,7 @@ int cg_run(qeq_plan* pl, const double* q0, double* q_out, double* energies, doub
         QEQ_TRY(launch_mesh_potential(pl, pl->q, done));
         QEQ_TRY(launch_interp(pl, pl->q, pl->y, QEQ_MODE_CG, 0));
         QEQ_TRY(launch_cg_init_r(pl));
-        QEQ_TRY(launch_cg_dir(pl, 1, 1));
+        QEQ_TRY(next_direction(pl, 1, 1));
         if (restart == 0 && q0) {
             // A supplied guess is kept only if it starts closer to the solution
             // than the cold start in the energy norm that CG minimises: for
@@ -578,7 +589,7 @@ int cg_run(qeq_plan* pl, const double* q0, double* q_out, double* energies, doub
                 QEQ_TRY(launch_mesh_potential(pl, pl->q, done));
                 QEQ_TRY(launch_interp(pl, pl->q, pl->y, QEQ_MODE_CG, 0));
                 QEQ_TRY(launch_cg_init_r(pl));
-                QEQ_TRY(launch_cg_dir(pl, 1, 1));
+                QEQ_TRY(next_direction(pl, 1, 1));
             }
         }
         conv = false;
@@ -651,6 +662,7 @@ int solve_impl(qeq_plan* pl, int n, const double* pos, const double* cell, const
     pl->tape_valid = false;
     QEQ_TRY(prepare(pl, n, cell, q_tot));
     QEQ_TRY(setup_geometry(pl, pos, sigma, J, chi));
+    QEQ_TRY(spc_setup(pl));
     pl->fdst = pl->forces_s;
     bool conv = false;
     QEQ_TRY(cg_run(pl, q0, q, energies, forces, &conv));
@@ -785,6 +797,7 @@ int qeq_plan_destroy(qeq_plan* pl) {
     dfree(pl->selfgrad); dfree(pl->q); dfree(pl->r); dfree(pl->pvec); dfree(pl->y); dfree(pl->forces_s);
     dfree(pl->gtmp); dfree(pl->q_adj); dfree(pl->y_adj); dfree(pl->chi_adj); dfree(pl->adj_scratch); dfree(pl->tq); dfree(pl->rowptr); dfree(pl->rowcnt); dfree(pl->theta_tab); dfree(pl->part);
     dfree(pl->strain_tab); dfree(pl->vir_part);
+    spc_free(pl);
     dfree(pl->sc); dfree(pl->final_dev); dfree(pl->scan_tmp);
     dfree(pl->cell_count); dfree(pl->cell_start); dfree(pl->cell_fill); dfree(pl->cell_atoms);
     dfree(pl->col); dfree(pl->kval); dfree(pl->pdr);
@@ -829,6 +842,16 @@ int qeq_use_graphs(qeq_plan* plan, int32_t enable) {
     if (!plan) return QEQ_EINVAL;
     plan->use_graphs = enable != 0;
     if (!plan->use_graphs) drop_graph(plan);
+    return QEQ_OK;
+}
+
+int qeq_use_spectral_preconditioner(qeq_plan* plan, double k_cut) {
+    if (!plan || !(k_cut == k_cut)) return QEQ_EINVAL;
+    if (plan->stream) (void)hipStreamSynchronize(plan->stream);
+    plan->spc_kc = k_cut > 0.0 ? k_cut : 0.0;
+    plan->spc_active = false;
+    plan->tape_valid = false;
+    drop_graph(plan);
     return QEQ_OK;
 }
 

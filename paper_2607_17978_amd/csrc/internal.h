@@ -184,6 +184,27 @@ struct qeq_plan {
     bool warm_rejected = false;   // the last solve discarded its q0
 
     BatchState* batch = nullptr;
+
+    // spectral (small-k Woodbury) preconditioner; spc_kc <= 0 keeps Jacobi
+    double spc_kc = 0.0;
+    bool spc_active = false;      // built for the current geometry
+    int spc_nm = 0;               // modes (half space)
+    int spc_cap_m = 0;            // allocated modes
+    int spc_cap_n = 0;            // allocated atoms
+    int4* spc_modes = nullptr;    // integer triplets m, k = 2 pi H^-1 m
+    float* spc_k2 = nullptr;      // |k|^2
+    float* spc_winv = nullptr;    // 1 / w_k
+    float* spc_wk = nullptr;      // w_k
+    float4* spc_atom = nullptr;   // (s1, s2, s3, sigma^2) per atom, sorted
+    double* spc_dpinv = nullptr;  // 1 / D' per atom
+    double* spc_mats = nullptr;   // 6 dense (2m)^2 matrices: G, E, E2, P, Q, S
+    double* spc_gpart = nullptr;  // split partial sums of G
+    double* spc_tpart = nullptr;  // split partial sums of Phi^T u
+    double* spc_s = nullptr;      // S t
+    double* spc_wvec = nullptr;   // M^-1 r
+    double* spc_m1 = nullptr;     // M^-1 1
+    double* spc_ones = nullptr;   // all ones
+    double* spc_scal = nullptr;   // [0] sum(M^-1 1), [1] ||E||_F^2, [2] min D'/D
     bool fused_inverse = true;    // fused inverse axis-2 + complex-to-real slab pass where it fits
 
     // the CG loop is replayed as a HIP graph of one chunk of iterations,
@@ -254,6 +275,11 @@ int launch_self_strain(qeq_plan* pl, const double* tabs, double* part);
 void reciprocal_self_strain(const double* H, const double* Hinv, double vol, double eta, double dC[6]);
 // qeq_virial
 int virial_impl(qeq_plan* pl, double* virial);
+// spectral preconditioner (spectral.hip)
+int spc_setup(qeq_plan* pl);                          // after the geometry set-up
+int spc_apply(qeq_plan* pl, const double* r, const int* done);   // spc_wvec = M^-1 r, partials
+int spc_direction(qeq_plan* pl, int parity, int init);            // p from spc_wvec
+void spc_free(qeq_plan* pl);
 int launch_scan(qeq_plan* pl, const int* in, int* out, int m);
 int launch_rhs_norm(qeq_plan* pl, const double* b);
 
