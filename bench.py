@@ -141,6 +141,9 @@ def main():
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="MB",
                     help="only run a plain device copy of this many MB (10 times) and exit: the "
                          "reference for scaling FETCH_SIZE / WRITE_SIZE counters")
+    ap.add_argument("--spectral-kc", type=float, default=0.2, metavar="BOHR^-1",
+                    help="also time the solve with the spectral preconditioner at this cutoff "
+                         "(0 = skip); the headline value stays the Jacobi solve of the workload")
     ap.add_argument("--frames", type=int, default=200)
     ap.add_argument("--epochs", type=int, default=30)
     args = ap.parse_args()
@@ -231,6 +234,26 @@ def main():
         plan.virial()
     tv2 = time.perf_counter()
     virial_ms = {"first_call": round((tv1 - tv0) * 1e3, 3), "per_call": round((tv2 - tv1) * 1e3 / 5, 3)}
+    spectral = None
+    if args.spectral_kc > 0.0:
+        # the same solve with the spectral preconditioner (own plan and graph)
+        plan_s = qeq.Plan(s.n, eta=2.0, r_cut=11.0, grid=s.grid, spline_order=6, tol=args.tol,
+                          max_iter=2000, self_correction=True, stream=stream)
+        plan_s.use_spectral_preconditioner(args.spectral_kc)
+        for _ in range(max(2, args.warmup)):
+            plan_s.solve(pos, s.cell, sig, J, chi, s.q_tot)
+        torch.cuda.synchronize()
+        ts0 = time.perf_counter()
+        its = []
+        for _ in range(args.steps):
+            _, _, _, sts = plan_s.solve(pos, s.cell, sig, J, chi, s.q_tot)
+            its.append(sts["iters"])
+        torch.cuda.synchronize()
+        ms_s = (time.perf_counter() - ts0) * 1e3 / args.steps
+        spectral = {"k_cut_per_bohr": args.spectral_kc, "ms_per_step": round(ms_s, 4),
+                    "cg_iters": int(np.median(its)), "speedup_vs_jacobi": round(ms_step / ms_s, 3),
+                    "rel_resid": sts["rel_resid"], "true_rel_resid": sts["true_rel_resid"]}
+        plan_s.close()
     nnz = None
     # CSR size is not exported; estimate from the cutoff sphere at this density
     nnz = int(round(s.n * 0.01 * 4.0 / 3.0 * np.pi * 11.0 ** 3))
@@ -276,6 +299,7 @@ def main():
         "final_stats": {k: st[k] for k in ("iters", "rel_resid", "true_rel_resid", "e_qeq", "e_elec")},
         "ms_per_step_eager_launches": None if ms_eager is None else round(ms_eager, 4),
         "virial_ms": virial_ms,
+        "spectral_preconditioner": spectral,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
@@ -412,7 +436,8 @@ def warmstart_main(args, dev):
         print(msg, file=sys.stderr, flush=True)
 
     t0 = time.perf_counter()
-    out = warmstart.run_trajectory(frames=args.frames, epochs=args.epochs, tol=args.tol, device=dev, log=log)
+    out = warmstart.run_trajectory(frames=args.frames, epochs=args.epochs, tol=args.tol, device=dev, log=log,
+                                   spectral_kc=args.spectral_kc)
     wall = time.perf_counter() - t0
     line = {
         "metric": METRIC,

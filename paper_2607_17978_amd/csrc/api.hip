@@ -481,7 +481,8 @@ void chunk_key(const qeq_plan* pl, std::vector<unsigned char>& key) {
                           pl->tw[0], pl->tw[1], pl->tw[2], pl->bmod[0], pl->bmod[1], pl->bmod[2],
                           pl->spc_active ? (const void*)pl->spc_mats : nullptr, pl->spc_wvec, pl->spc_m1,
                           pl->spc_atom, pl->spc_dpinv, pl->spc_tpart, pl->spc_s, pl->spc_scal,
-                          (const void*)(size_t)pl->spc_nm};
+                          pl->spc_sd, pl->spc_psi, (const void*)(size_t)pl->spc_nm,
+                          (const void*)(size_t)pl->spc_npad};
     key.resize(sizeof(KParams) + sizeof(ptrs) + sizeof(DeviceAxes));
     unsigned char* k = key.data();
     memcpy(k, &pl->kp, sizeof(KParams));

@@ -195,11 +195,19 @@ struct qeq_plan {
     float* spc_k2 = nullptr;      // |k|^2
     float* spc_winv = nullptr;    // 1 / w_k
     float* spc_wk = nullptr;      // w_k
+    int spc_ncp = 0;              // table rows (2 nm padded to the tile)
+    int spc_npad = 0;             // table columns (atoms padded)
+    int spc_fsplit = 0;           // atom splits of t = Psi^T u
     float4* spc_atom = nullptr;   // (s1, s2, s3, sigma^2) per atom, sorted
     double* spc_dpinv = nullptr;  // 1 / D' per atom
+    float* spc_sd = nullptr;      // D'^-1/2 per atom
+    float* spc_u = nullptr;       // D'^-1/2 r per atom (padded)
+    unsigned short* spc_psi = nullptr;   // bf16 table Psi, spc_ncp rows of spc_npad atoms
     double* spc_mats = nullptr;   // 6 dense (2m)^2 matrices: G, E, E2, P, Q, S
-    double* spc_gpart = nullptr;  // split partial sums of G
-    double* spc_tpart = nullptr;  // split partial sums of Phi^T u
+    float* spc_gpart = nullptr;   // split partial sums of Psi^T Psi
+    double* spc_tpart = nullptr;  // split partial sums of Psi^T u
+    double* spc_t = nullptr;      // Psi^T u
+    double* spc_kpart = nullptr;  // k-split partial products of the dense series
     double* spc_s = nullptr;      // S t
     double* spc_wvec = nullptr;   // M^-1 r
     double* spc_m1 = nullptr;     // M^-1 1

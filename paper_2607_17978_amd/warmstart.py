@@ -41,7 +41,7 @@ def chi_features(plan, posd, cell, sigma, chi):
 
 
 def run_trajectory(n=None, side=None, spacing=None, frames=200, epochs=30, lr=2e-3, tol=1e-6,
-                   grid=None, log=None, device=None):
+                   grid=None, log=None, device=None, spectral_kc=0.0):
     import torch
 
     from inputs import gen
@@ -58,6 +58,11 @@ def run_trajectory(n=None, side=None, spacing=None, frames=200, epochs=30, lr=2e
         k = 320 if n == gen.MD_N else gen.grid_dim(L, 0.8)
         grid = (k, k, k)
     plan = qeq.Plan(n, eta=2.0, r_cut=11.0, grid=grid, tol=tol, max_iter=3000)
+    # a second plan with the spectral preconditioner (its own captured CG graph)
+    plan_s = None
+    if spectral_kc > 0.0:
+        plan_s = qeq.Plan(n, eta=2.0, r_cut=11.0, grid=grid, tol=tol, max_iter=3000)
+        plan_s.use_spectral_preconditioner(spectral_kc)
     net = qeq.WarmStartNet(gen.warmstart_init(1005, 2), device=dev)
     net_x = qeq.WarmStartNet(gen.warmstart_init(1005, 2), device=dev)
     chi_w = gen.chi_network_weights(1004)
@@ -65,13 +70,16 @@ def run_trajectory(n=None, side=None, spacing=None, frames=200, epochs=30, lr=2e
     n_train = frames // 2
     scaling = y_std = None
     train_G, train_X, train_q = [], [], []
-    rec = {"cold": [], "prev": [], "learned": [], "learned_chi": []}
+    variants = ["cold", "prev", "learned", "learned_chi"]
+    if plan_s is not None:
+        variants += ["cold_spectral", "prev_spectral", "learned_chi_spectral"]
+    rec = {k: [] for k in variants}
     q_prev = None
 
-    def solve(posd, chid, q0=None):
+    def solve(posd, chid, q0=None, pl=None):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        q, en, _, st = plan.solve(posd, cell, sig_d, J_d, chid, 0.0, q0=q0, forces=False)
+        q, en, _, st = (pl or plan).solve(posd, cell, sig_d, J_d, chid, 0.0, q0=q0, forces=False)
         torch.cuda.synchronize()
         return q, st, (time.perf_counter() - t0) * 1e3
 
@@ -138,17 +146,25 @@ def run_trajectory(n=None, side=None, spacing=None, frames=200, epochs=30, lr=2e
         dq_p, dq_l = float((q_p - q_c).abs().max()), float((q_l - q_c).abs().max())
         dq_x = float((q_x - q_c).abs().max())
         max_dq = max(max_dq, dq_p, dq_l, dq_x)
-        for k, st, ms in (("cold", st_c, ms_c), ("prev", st_p, ms_p), ("learned", st_l, ms_l),
-                          ("learned_chi", st_x, ms_x)):
+        runs = [("cold", st_c, ms_c), ("prev", st_p, ms_p), ("learned", st_l, ms_l),
+                ("learned_chi", st_x, ms_x)]
+        if plan_s is not None:
+            for k, q0s in (("cold_spectral", None), ("prev_spectral", q_prev), ("learned_chi_spectral", q0x)):
+                q_s, st_s, ms_s = solve(posd, chid, q0=q0s, pl=plan_s)
+                max_dq = max(max_dq, float((q_s - q_c).abs().max()))
+                runs.append((k, st_s, ms_s))
+        for k, st, ms in runs:
             rec[k].append((st["iters"], ms, st["rc"], st["q0_rejected"]))
         q_prev = q_c
         if log:
-            log(f"frame {t}: iters cold {st_c['iters']} prev {st_p['iters']} learned {st_l['iters']} "
-                f"learned_chi {st_x['iters']}; ms {ms_c:.1f} / {ms_p:.1f} / {ms_l:.1f} / {ms_x:.1f}; "
-                f"max|dq| {max(dq_p, dq_l, dq_x):.1e}; rms |q0 - q| learned "
+            log(f"frame {t}: iters " + " ".join(f"{k} {st['iters']}" for k, st, _ in runs) +
+                "; ms " + " / ".join(f"{ms:.1f}" for _, _, ms in runs) + "; "
+                f"max|dq| {max_dq:.1e}; rms |q0 - q| learned "
                 f"{float((q0 - q_c).pow(2).mean().sqrt()):.2e} learned_chi "
                 f"{float((q0x - q_c).pow(2).mean().sqrt()):.2e}")
     plan.close()
+    if plan_s is not None:
+        plan_s.close()
     out = {"n": n, "grid": list(grid), "frames": frames, "train_frames": n_train,
            "max_dq_vs_cold": max_dq, "descriptor_ms": float(np.mean(t_desc)),
            "chi_feature_ms": float(np.mean(t_feat)),
@@ -157,7 +173,9 @@ def run_trajectory(n=None, side=None, spacing=None, frames=200, epochs=30, lr=2e
            "train_s": rec.get("train_s"), "train_loss": rec.get("train_loss"),
            "train_s_chi": rec.get("train_s_chi"), "train_loss_chi": rec.get("train_loss_chi"),
            "train_steps": rec.get("train_steps")}
-    for k in ("cold", "prev", "learned", "learned_chi"):
+    if plan_s is not None:
+        out["spectral_kc"] = spectral_kc
+    for k in variants:
         a = np.array(rec[k], dtype=float)
         out[k] = {"iters": float(a[:, 0].mean()), "ms": float(a[:, 1].mean()),
                   "all_converged": bool((a[:, 2] == 0).all()), "q0_rejected": int(a[:, 3].sum())}
@@ -165,6 +183,7 @@ def run_trajectory(n=None, side=None, spacing=None, frames=200, epochs=30, lr=2e
     # chi-aware start the two feature calls that the workload's own
     # descriptors (needed for chi anyway) do not provide
     out["learned"]["ms_with_inference"] = out["learned"]["ms"] + (out["predict_ms"] or 0.0)
-    out["learned_chi"]["ms_with_inference"] = (out["learned_chi"]["ms"] + out["chi_feature_ms"] +
-                                               (out["predict_chi_ms"] or 0.0))
+    for k in ("learned_chi", "learned_chi_spectral"):
+        if k in out:
+            out[k]["ms_with_inference"] = out[k]["ms"] + out["chi_feature_ms"] + (out["predict_chi_ms"] or 0.0)
     return out
