@@ -21,6 +21,9 @@ Workloads (sizes and distributions follow the benchmark configurations):
 * ``adjoint_targets`` -- loss weights w ~ U(0,1) and reference charges
   Q_ref ~ N(0, 0.2) for the differentiated workload.
 * ``md_frames`` -- the 131,072-atom trajectory lattice and its displacements.
+* ``cluster_system`` -- an isolated cluster (no cell) for non-periodic QEq:
+  the N sites of a simple-cubic lattice at density 0.01 bohr^-3 nearest to the
+  origin, jittered, two elements 50/50, a chosen total charge.
 """
 from __future__ import annotations
 
@@ -298,3 +301,34 @@ def chi_from_descriptors(G, species, weights, scaling=None, y_std=None):
         y_std = float(y.std())
     chi = np.asarray(CHI_MEAN_2EL)[species] + CHI_SD * y / y_std
     return chi, scaling, y_std
+
+
+# ---------------------------------------------------------------------------
+# Isolated clusters (non-periodic QEq)
+# ---------------------------------------------------------------------------
+CLUSTER_SPACING = 100.0 ** (1.0 / 3.0)   # bohr: density 0.01 bohr^-3
+
+
+def cluster_system(n: int, q_tot: float = 0.0, seed: int = 1007, jitter: float = 0.6) -> System:
+    """n atoms of a jittered simple-cubic lattice cut to a near-spherical cluster.
+
+    Sites are the n lattice points (spacing 4.6416 bohr) nearest the origin,
+    ordered by distance then x, y, z index (deterministic); draw order:
+    element permutation (exact 50/50 split), jitter U(-jitter, jitter) per
+    axis, chi noise.  sigma / J / chi means as the two-element workloads.
+    ``cell`` and ``grid`` are None: the system is isolated.
+    """
+    rng = np.random.default_rng(seed)
+    m = int(math.ceil((3.0 * n / (4.0 * math.pi)) ** (1.0 / 3.0))) + 2
+    idx = np.arange(-m, m + 1)
+    g = np.stack(np.meshgrid(idx, idx, idx, indexing="ij"), axis=-1).reshape(-1, 3)
+    r2 = (g * g).sum(1)
+    order = np.lexsort((g[:, 2], g[:, 1], g[:, 0], r2))
+    sites = g[order[:n]].astype(np.float64) * CLUSTER_SPACING
+    species = rng.permutation(np.array([0] * (n // 2) + [1] * (n - n // 2), dtype=np.int32))
+    pos = sites + rng.uniform(-jitter, jitter, size=(n, 3))
+    noise = rng.normal(0.0, CHI_SD, size=n)
+    sigma = np.asarray(SIGMA_2EL)[species]
+    J = np.asarray(J_2EL)[species]
+    chi = np.asarray(CHI_MEAN_2EL)[species] + noise
+    return System(pos, None, species.astype(np.int32), sigma, J, chi, float(q_tot), None, f"cluster_n{n}")

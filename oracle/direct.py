@@ -11,6 +11,12 @@
   plane sum(q) = Q_tot by pairwise charge-transfer line searches (eq.
   qeq_energy; the constraint of eq. 4G_qeq_prime), with no linear solve.
 * ``two_atom_charges``    -- closed-form solution for two atoms.
+* ``qeq_nonperiodic``     -- QEq of an isolated system (no cell): the bordered
+  system of eq. 4G_qeq_prime with the paper's non-periodic kernel written
+  out, charges by Gaussian elimination (or projected CG on the same dense
+  matrix for large N), energies of eq. qeq_energy and analytic forces
+  F_k = -q_k sum_j q_j K'(r_kj) (r_k - r_j) / r_kj (the SI force expression
+  at constant chi and J).
 """
 from __future__ import annotations
 
@@ -22,6 +28,28 @@ from scipy.special import erf
 SQRTPI = math.sqrt(math.pi)
 
 
+def nonperiodic_kernel(r, gamma):
+    """K(r) = erf(r / (sqrt2 gamma)) / r, with its r -> 0 limit sqrt(2/pi) / gamma.
+
+    Below 1e-4 bohr the series 2a/sqrt(pi) (1 - (a r)^2 / 3), a = 1/(sqrt2 gamma).
+    """
+    r = np.asarray(r, dtype=np.float64)
+    a = 1.0 / (math.sqrt(2.0) * np.asarray(gamma, dtype=np.float64))
+    small = r < 1e-4
+    rs = np.where(small, 1.0, r)
+    return np.where(small, 2.0 / SQRTPI * a * (1.0 - (a * r) ** 2 / 3.0), erf(a * rs) / rs)
+
+
+def nonperiodic_kernel_deriv(r, gamma):
+    """dK/dr of ``nonperiodic_kernel``: (2a/sqrt(pi)) exp(-(a r)^2) / r - K / r (0 at r = 0)."""
+    r = np.asarray(r, dtype=np.float64)
+    a = 1.0 / (math.sqrt(2.0) * np.asarray(gamma, dtype=np.float64))
+    small = r < 1e-4
+    rs = np.where(small, 1.0, r)
+    d = (2.0 / SQRTPI * a * np.exp(-(a * rs) ** 2) - erf(a * rs) / rs) / rs
+    return np.where(small, -4.0 / (3.0 * SQRTPI) * a ** 3 * r, d)
+
+
 def nonperiodic_matrix(pos, sigma):
     """E_ii = 1/(sigma_i sqrt(pi)), E_ij = erf(r_ij/(sqrt2 gamma_ij))/r_ij."""
     pos = np.asarray(pos, dtype=np.float64)
@@ -30,11 +58,48 @@ def nonperiodic_matrix(pos, sigma):
     r = np.sqrt((d * d).sum(-1))
     gam = np.sqrt(sigma[:, None] ** 2 + sigma[None, :] ** 2)
     n = pos.shape[0]
-    E = np.zeros((n, n))
-    off = ~np.eye(n, dtype=bool)
-    E[off] = erf(r[off] / (math.sqrt(2.0) * gam[off])) / r[off]
+    E = nonperiodic_kernel(r, gam)
     E[np.diag_indices(n)] = 1.0 / (sigma * SQRTPI)
     return E
+
+
+def nonperiodic_gradient(pos, sigma, q):
+    """d/dr_k of E_elec = 1/2 q^T E q: sum_j q_k q_j K'(r_kj) (r_k - r_j) / r_kj."""
+    pos = np.asarray(pos, dtype=np.float64)
+    sigma = np.asarray(sigma, dtype=np.float64)
+    q = np.asarray(q, dtype=np.float64)
+    d = pos[:, None, :] - pos[None, :, :]
+    r = np.sqrt((d * d).sum(-1))
+    gam = np.sqrt(sigma[:, None] ** 2 + sigma[None, :] ** 2)
+    np.fill_diagonal(r, 1.0)
+    w = nonperiodic_kernel_deriv(r, gam) / r
+    np.fill_diagonal(w, 0.0)
+    w *= np.outer(q, q)
+    return (w[:, :, None] * d).sum(1)
+
+
+def qeq_nonperiodic(pos, sigma, J, chi, q_tot, forces=True, method="dense", tol=1e-12):
+    """QEq of an isolated system: charges, mu, E_QEq, E_elec and forces.
+
+    method="dense": the bordered system by the oracle's Gaussian elimination;
+    method="cg": Jacobi-projected CG on the same dense matrix (large N).
+    Forces are -dE_QEq/dr at the solution = -dE_elec/dr at fixed q.
+    """
+    from . import ewald, matfree
+    J = np.asarray(J, dtype=np.float64)
+    chi = np.asarray(chi, dtype=np.float64)
+    E = nonperiodic_matrix(pos, sigma)
+    if method == "dense":
+        q, lam = ewald.solve_qeq(E, J, chi, q_tot)
+        mu = -lam
+    else:
+        A = E + np.diag(J)
+        q, mu, _, _ = matfree.projected_cg(lambda v: A @ v, np.diag(A).copy(), chi, q_tot, tol=tol)
+    e_qeq, e_elec = ewald.qeq_energy(E, J, chi, q)
+    res = ewald.QEqResult(q=q, mu=mu, lam=-mu, e_qeq=e_qeq, e_elec=e_elec, E=E)
+    if forces:
+        res["forces"] = -nonperiodic_gradient(pos, sigma, q)
+    return res
 
 
 def planewave_energy(q, pos, cell, sigma, k_max=None):
