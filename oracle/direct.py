@@ -72,7 +72,11 @@ def nonperiodic_gradient(pos, sigma, q):
     r = np.sqrt((d * d).sum(-1))
     gam = np.sqrt(sigma[:, None] ** 2 + sigma[None, :] ** 2)
     np.fill_diagonal(r, 1.0)
-    w = nonperiodic_kernel_deriv(r, gam) / r
+    # K'(r) / r; below 1e-4 bohr its limit -4 a^3 / (3 sqrt(pi)) (finite at r = 0)
+    a = 1.0 / (math.sqrt(2.0) * gam)
+    small = r < 1e-4
+    rs = np.where(small, 1.0, r)
+    w = np.where(small, -4.0 / (3.0 * SQRTPI) * a ** 3, nonperiodic_kernel_deriv(rs, gam) / rs)
     np.fill_diagonal(w, 0.0)
     w *= np.outer(q, q)
     return (w[:, :, None] * d).sum(1)

@@ -176,3 +176,20 @@ def test_planted_force_mistake_is_caught(monkeypatch):
     fd = -(ep - em) / (2 * h)
     assert abs(fd - base.forces[0, 0]) < 1e-9
     assert abs(fd - bad.forces[0, 0]) > 1e-6
+
+
+def test_coincident_atoms_finite():
+    """Coincident atoms: the kernel takes its r -> 0 limit, forces stay finite
+    and still match finite differences of the re-solved energy."""
+    s = gen.cluster_system(12, q_tot=0.0, seed=77)
+    s.pos[1] = s.pos[0]
+    res = direct.qeq_nonperiodic(s.pos, s.sigma, s.J, s.chi, 0.0)
+    assert np.all(np.isfinite(res.forces)) and np.all(np.isfinite(res.q))
+    h = 1e-5
+    for i, c in ((3, 0), (5, 2)):
+        e = []
+        for sgn in (1, -1):
+            p = s.pos.copy()
+            p[i, c] += sgn * h
+            e.append(direct.qeq_nonperiodic(p, s.sigma, s.J, s.chi, 0.0, forces=False).e_qeq)
+        assert abs(-(e[0] - e[1]) / (2 * h) - res.forces[i, c]) < 1e-9
