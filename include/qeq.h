@@ -116,6 +116,23 @@ int qeq_solve(qeq_plan* plan, int32_t n, const double* pos, const double* cell,
               const double* q0, double* q, double* energies, double* forces,
               qeq_stats* stats);
 
+/* Solve the QEq problem (eq. 4G_qeq_prime) for one isolated (non-periodic)
+   system: a molecule or cluster in any total-charge state (the paper's
+   motivation for 4G potentials of non-periodic systems).  The Coulomb
+   operator is the paper's kernel between normalised Gaussians with no
+   images, E_ii = 1/(sigma_i sqrt(pi)), E_ij = erf(r_ij/(sqrt2 gamma_ij))/r_ij
+   (Electrostatics and Charge Equilibration section), summed directly over
+   all pairs: O(n^2) work per CG product, no grid, no cutoff, no background.
+   Arguments, ownership, q0 handling, outputs and errors as qeq_solve; there
+   is no cell and the plan's grid, eta and r_cut are unused (tol and
+   max_iter apply).  Positions may lie anywhere (coincident atoms are
+   allowed: the kernel takes its r -> 0 limit).  The call leaves no tape:
+   qeq_backward and qeq_virial return QEQ_EINVAL until the next periodic
+   solve. */
+int qeq_solve_nonperiodic(qeq_plan* plan, int32_t n, const double* pos, const double* sigma,
+                          const double* J, const double* chi, double q_tot, const double* q0,
+                          double* q, double* energies, double* forces, qeq_stats* stats);
+
 /* Gradient of a loss L(q, E_QEq, E_elec) through the last solve on this plan
    (SI eq. 4g_force_trick: Lagrange / adjoint route, one extra linear solve
    with the same operator instead of 3N charge derivatives).

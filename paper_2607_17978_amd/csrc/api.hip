@@ -482,7 +482,8 @@ void chunk_key(const qeq_plan* pl, std::vector<unsigned char>& key) {
                           pl->spc_active ? (const void*)pl->spc_mats : nullptr, pl->spc_wvec, pl->spc_m1,
                           pl->spc_atom, pl->spc_dpinv, pl->spc_tpart, pl->spc_s, pl->spc_scal,
                           pl->spc_sd, pl->spc_psi, (const void*)(size_t)pl->spc_nm,
-                          (const void*)(size_t)pl->spc_npad};
+                          (const void*)(size_t)pl->spc_npad, (const void*)(size_t)pl->direct, pl->np_pos,
+                          pl->np_ypart, (const void*)(size_t)pl->np_nsplit, (const void*)(size_t)pl->np_tps};
     key.resize(sizeof(KParams) + sizeof(ptrs) + sizeof(DeviceAxes));
     unsigned char* k = key.data();
     memcpy(k, &pl->kp, sizeof(KParams));
@@ -507,10 +508,16 @@ int next_direction(qeq_plan* pl, int parity, int init) {
     return spc_direction(pl, parity, init);
 }
 
+// y = A src with the CG partial sums: the particle-mesh operator, or the
+// direct pair sum of an isolated system.
+int cg_matvec(qeq_plan* pl, const double* src, int parity) {
+    if (pl->direct) return launch_np_matvec(pl, src, pl->y, QEQ_MODE_CG);
+    QEQ_TRY(launch_mesh_potential(pl, src, &pl->sc->done));
+    return launch_interp(pl, src, pl->y, QEQ_MODE_CG, parity);
+}
+
 int cg_iteration(qeq_plan* pl, int parity) {
-    const int* done = &pl->sc->done;
-    QEQ_TRY(launch_mesh_potential(pl, pl->pvec, done));
-    QEQ_TRY(launch_interp(pl, pl->pvec, pl->y, QEQ_MODE_CG, parity));
+    QEQ_TRY(cg_matvec(pl, pl->pvec, parity));
     QEQ_TRY(launch_cg_update(pl, parity));
     return next_direction(pl, parity, 0);
 }
@@ -570,8 +577,7 @@ int cg_run(qeq_plan* pl, const double* q0, double* q_out, double* energies, doub
     const double restart_thr = 2.0 * std::max(pl->prm.tol, 1e-7);
     for (int restart = 0;; ++restart) {
         // residual of the current q and the first direction
-        QEQ_TRY(launch_mesh_potential(pl, pl->q, done));
-        QEQ_TRY(launch_interp(pl, pl->q, pl->y, QEQ_MODE_CG, 0));
+        QEQ_TRY(cg_matvec(pl, pl->q, 0));
         QEQ_TRY(launch_cg_init_r(pl));
         QEQ_TRY(next_direction(pl, 1, 1));
         if (restart == 0 && q0) {
@@ -587,8 +593,7 @@ int cg_run(qeq_plan* pl, const double* q0, double* q_out, double* energies, doub
             if (worse) {
                 pl->warm_rejected = true;
                 QEQ_TRY(launch_cg_init_q(pl, nullptr));
-                QEQ_TRY(launch_mesh_potential(pl, pl->q, done));
-                QEQ_TRY(launch_interp(pl, pl->q, pl->y, QEQ_MODE_CG, 0));
+                QEQ_TRY(cg_matvec(pl, pl->q, 0));
                 QEQ_TRY(launch_cg_init_r(pl));
                 QEQ_TRY(next_direction(pl, 1, 1));
             }
@@ -620,8 +625,13 @@ int cg_run(qeq_plan* pl, const double* q0, double* q_out, double* energies, doub
         QEQ_HIP(hipStreamSynchronize(pl->stream));
         conv = pl->sc_host->done != 0;
         // final matvec on q: energies, mu, true residual, forces; scatter to caller order
-        QEQ_TRY(launch_mesh_potential(pl, pl->q, nullptr));
-        QEQ_TRY(launch_final(pl, q_out, energies, forces_out));
+        if (pl->direct) {
+            QEQ_TRY(launch_np_matvec(pl, pl->q, pl->y, QEQ_MODE_FINAL));
+            QEQ_TRY(launch_final_tail(pl, q_out, energies, forces_out));
+        } else {
+            QEQ_TRY(launch_mesh_potential(pl, pl->q, nullptr));
+            QEQ_TRY(launch_final(pl, q_out, energies, forces_out));
+        }
         QEQ_HIP(hipMemcpyAsync(pl->out_host, pl->final_dev, 4 * sizeof(double), hipMemcpyDeviceToHost,
                                pl->stream));
         QEQ_HIP(hipMemcpyAsync(pl->sc_host, pl->sc, sizeof(CgScalars), hipMemcpyDeviceToHost, pl->stream));
@@ -661,6 +671,7 @@ int solve_impl(qeq_plan* pl, int n, const double* pos, const double* cell, const
                double* energies, double* forces, qeq_stats* stats) {
     if (!pos || !sigma || !J || !chi || !q) return QEQ_EINVAL;
     pl->tape_valid = false;
+    pl->direct = false;
     QEQ_TRY(prepare(pl, n, cell, q_tot));
     QEQ_TRY(setup_geometry(pl, pos, sigma, J, chi));
     QEQ_TRY(spc_setup(pl));
@@ -799,6 +810,7 @@ int qeq_plan_destroy(qeq_plan* pl) {
     dfree(pl->gtmp); dfree(pl->q_adj); dfree(pl->y_adj); dfree(pl->chi_adj); dfree(pl->adj_scratch); dfree(pl->tq); dfree(pl->rowptr); dfree(pl->rowcnt); dfree(pl->theta_tab); dfree(pl->part);
     dfree(pl->strain_tab); dfree(pl->vir_part);
     spc_free(pl);
+    np_free(pl);
     dfree(pl->sc); dfree(pl->final_dev); dfree(pl->scan_tmp);
     dfree(pl->cell_count); dfree(pl->cell_start); dfree(pl->cell_fill); dfree(pl->cell_atoms);
     dfree(pl->col); dfree(pl->kval); dfree(pl->pdr);
@@ -820,12 +832,38 @@ int qeq_solve(qeq_plan* plan, int32_t n, const double* pos, const double* cell, 
     return rc;
 }
 
+int qeq_solve_nonperiodic(qeq_plan* plan, int32_t n, const double* pos, const double* sigma, const double* J,
+                          const double* chi, double q_tot, const double* q0, double* q, double* energies,
+                          double* forces, qeq_stats* stats) {
+    if (!plan) return QEQ_EINVAL;
+    qeq_plan* pl = plan;
+    int rc = QEQ_EINVAL;
+    if (pos && sigma && J && chi && q) {
+        pl->tape_valid = false;   // the adjoint and the virial follow periodic solves only
+        pl->spc_active = false;
+        rc = np_setup(pl, n, pos, sigma, J, chi, q_tot);
+        if (rc == QEQ_OK) {
+            pl->direct = true;
+            pl->fdst = pl->forces_s;
+            bool conv = false;
+            rc = cg_run(pl, q0, q, energies, forces, &conv);
+            if (rc == QEQ_OK) rc = cg_status(pl, conv, stats);
+        }
+    }
+    if (rc < 0 && stats) {
+        memset(stats, 0, sizeof(*stats));
+        stats->status = rc;
+    }
+    return rc;
+}
+
 int qeq_matvec(qeq_plan* plan, int32_t n, const double* pos, const double* cell, const double* sigma,
                const double* v, double* y, int32_t parts) {
     if (!plan || !pos || !sigma || !v || !y) return QEQ_EINVAL;
     if (parts < 0 || parts > 15) return QEQ_EINVAL;
     qeq_plan* pl = plan;
     pl->tape_valid = false;
+    pl->direct = false;
     QEQ_TRY(prepare(pl, n, cell, 0.0));
     QEQ_TRY(setup_geometry(pl, pos, sigma, nullptr, nullptr));
     pl->kp.parts = parts;

@@ -213,6 +213,14 @@ struct qeq_plan {
     double* spc_m1 = nullptr;     // M^-1 1
     double* spc_ones = nullptr;   // all ones
     double* spc_scal = nullptr;   // [0] sum(M^-1 1), [1] ||E||_F^2, [2] min D'/D
+    // non-periodic solve (direct pair sum); direct = the last solve's mode
+    bool direct = false;
+    int np_cap = 0;               // atoms allocated
+    int np_nsplit = 0;            // atom splits of the pair sum
+    int np_tps = 0;               // tiles of 256 atoms per split
+    double* np_pos = nullptr;     // double4 (x, y, z, sigma^2) per atom
+    double* np_ypart = nullptr;   // [split][atom] partial products
+    double* np_fpart = nullptr;   // [split][atom][3] partial force sums
     bool fused_inverse = true;    // fused inverse axis-2 + complex-to-real slab pass where it fits
 
     // the CG loop is replayed as a HIP graph of one chunk of iterations,
@@ -288,6 +296,12 @@ int spc_setup(qeq_plan* pl);                          // after the geometry set-
 int spc_apply(qeq_plan* pl, const double* r, const int* done);   // spc_wvec = M^-1 r, partials
 int spc_direction(qeq_plan* pl, int parity, int init);            // p from spc_wvec
 void spc_free(qeq_plan* pl);
+// non-periodic solve (direct.hip)
+int np_setup(qeq_plan* pl, int n, const double* pos, const double* sigma, const double* J, const double* chi,
+             double q_tot);
+int launch_np_matvec(qeq_plan* pl, const double* src, double* dst, int mode);   // QEQ_MODE_CG / FINAL
+void np_free(qeq_plan* pl);
+int launch_final_tail(qeq_plan* pl, double* q_out, double* energies, double* forces_out);
 int launch_scan(qeq_plan* pl, const int* in, int* out, int m);
 int launch_rhs_norm(qeq_plan* pl, const double* b);
 

@@ -487,15 +487,28 @@ int launch_cg_dir(qeq_plan* pl, int parity, int init) {
     return qeq_check(hipGetLastError());
 }
 
+static void final_tail(qeq_plan* pl, double* q_out, double* energies, double* forces_out, hipEvent_t ev1) {
+    const int nb = nblocks(pl->kp.n);
+    double* part = part_buf(pl, 0);
+    hipLaunchKernelGGL(k_final2, dim3(nb), dim3(QEQ_BLOCK), 0, pl->stream, pl->kp, pl->q, pl->fdst,
+                       pl->gtmp, pl->perm, q_out, forces_out, part, interp_blocks(pl->kp.n), part_buf(pl, 1));
+    hipExtLaunchKernelGGL(k_final3, dim3(1), dim3(QEQ_BLOCK), 0, pl->stream, nullptr, ev1, 0, pl->kp, part,
+                          interp_blocks(pl->kp.n), part_buf(pl, 1), nb, pl->sc, pl->final_dev, energies);
+}
+
 int launch_final(qeq_plan* pl, double* q_out, double* energies, double* forces_out) {
-    int nb = nblocks(pl->kp.n);
     double* part = part_buf(pl, 0);
     ProfScope ps(pl, PK_FINAL);
     interp_launch<QEQ_MODE_FINAL>(pl, pl->q, pl->y, part, 0, ps.start(), nullptr);
-    hipLaunchKernelGGL(k_final2, dim3(nb), dim3(QEQ_BLOCK), 0, pl->stream, pl->kp, pl->q, pl->fdst,
-                       pl->gtmp, pl->perm, q_out, forces_out, part, interp_blocks(pl->kp.n), part_buf(pl, 1));
-    hipExtLaunchKernelGGL(k_final3, dim3(1), dim3(QEQ_BLOCK), 0, pl->stream, nullptr, ps.stop(), 0, pl->kp, part,
-                          interp_blocks(pl->kp.n), part_buf(pl, 1), nb, pl->sc, pl->final_dev, energies);
+    final_tail(pl, q_out, energies, forces_out, ps.stop());
+    return qeq_check(hipGetLastError());
+}
+
+// Energies, mu, true residual and the scatter to caller order from partial
+// sums of a final product that another operator (the direct pair sum) wrote
+// in the same slots.
+int launch_final_tail(qeq_plan* pl, double* q_out, double* energies, double* forces_out) {
+    final_tail(pl, q_out, energies, forces_out, nullptr);
     return qeq_check(hipGetLastError());
 }
 

@@ -86,6 +86,8 @@ def load_library():
     L.qeq_solve.argtypes = [vp, i32, dp, ctypes.POINTER(ctypes.c_double), dp, dp, dp, f64, dp, dp, dp,
                             dp, ctypes.POINTER(Stats)]
     L.qeq_solve.restype = ctypes.c_int
+    L.qeq_solve_nonperiodic.argtypes = [vp, i32, dp, dp, dp, dp, f64, dp, dp, dp, dp, ctypes.POINTER(Stats)]
+    L.qeq_solve_nonperiodic.restype = ctypes.c_int
     L.qeq_backward.argtypes = [vp, dp, f64, f64, dp, dp, dp, ctypes.POINTER(Stats)]
     L.qeq_backward.restype = ctypes.c_int
     L.qeq_virial.argtypes = [vp, dp]
@@ -230,6 +232,27 @@ class Plan:
                                       ctypes.byref(st))
         self.solve_count += 1
         self._last_n = n
+        if check and rc < 0:
+            raise QEqError(rc, strerror(rc))
+        return q, en, f, dict(st.as_dict(), rc=rc)
+
+    def solve_nonperiodic(self, pos, sigma, J, chi, q_tot=0.0, q0=None, forces=True, check=True):
+        """Isolated system (no cell): charges, [E_QEq, E_elec], forces (or None), stats."""
+        import torch
+        n = int(pos.shape[0])
+        for name, t, c in (("pos", pos, 3), ("sigma", sigma, None), ("J", J, None), ("chi", chi, None)):
+            _check_dev(name, t, n, c, self.device)
+        if q0 is not None:
+            _check_dev("q0", q0, n, None, self.device)
+        q = torch.empty(n, dtype=torch.float64, device=self.device)
+        en = torch.empty(2, dtype=torch.float64, device=self.device)
+        f = torch.empty((n, 3), dtype=torch.float64, device=self.device) if forces else None
+        st = Stats()
+        rc = load_library().qeq_solve_nonperiodic(self._h, n, _ptr(pos), _ptr(sigma), _ptr(J), _ptr(chi),
+                                                  float(q_tot), _ptr(q0), _ptr(q), _ptr(en), _ptr(f),
+                                                  ctypes.byref(st))
+        self.solve_count += 1
+        self._last_n = None   # no tape: backward / virial need a periodic solve
         if check and rc < 0:
             raise QEqError(rc, strerror(rc))
         return q, en, f, dict(st.as_dict(), rc=rc)
