@@ -134,10 +134,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tol", type=float, default=1e-6)
-    ap.add_argument("--workload", choices=["cold32k", "warmstart", "batch"], default="cold32k",
+    ap.add_argument("--workload", choices=["cold32k", "warmstart", "batch", "nonperiodic"], default="cold32k",
                     help="cold32k: the default cold-start solve; warmstart: the 131,072-atom "
                          "trajectory (learned vs cold vs previous-frame start); batch: 1,024 "
-                         "structures in one persistent launch vs one launch sequence per structure")
+                         "structures in one persistent launch vs one launch sequence per structure; "
+                         "nonperiodic: an isolated 16,384-atom cluster (direct pair sum)")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="MB",
                     help="only run a plain device copy of this many MB (10 times) and exit: the "
                          "reference for scaling FETCH_SIZE / WRITE_SIZE counters")
@@ -172,6 +173,8 @@ def main():
         return warmstart_main(args, dev)
     if args.workload == "batch":
         return batch_main(args, dev)
+    if args.workload == "nonperiodic":
+        return nonperiodic_main(args, dev)
     s = gen.system_32k()
     T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
     pos, sig, J, chi = T(s.pos), T(s.sigma), T(s.J), T(s.chi)
@@ -426,6 +429,86 @@ def batch_main(args, dev):
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_batch(structs)
     print(json.dumps(out), flush=True)
+
+
+# Arithmetic per pair of the direct pair-sum product, counted from the kernel
+# source (FMA = 2): FP64 differences and squared distance (3 + 5), FP64
+# accumulation (2); FP32 width term, rsqrt, sqrt, products (6), erf (about
+# 15 with its rational approximation) and the division (about 4).
+NP_FLOP_PER_PAIR = 35.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+
+
+def cpu_baseline_nonperiodic(n_target, budget_s=30.0):
+    """FP64 oracle (dense erf matrix + projected CG to 1e-6) on 2,048- and
+    4,096-atom clusters of the same recipe; t = a N^b evaluated at n_target."""
+    from inputs import gen
+    from oracle import direct
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    times = {}
+    for n in (2048, 4096):
+        s = gen.cluster_system(n, q_tot=1.0, seed=1009)
+        t0 = time.perf_counter()
+        direct.qeq_nonperiodic(s.pos, s.sigma, s.J, s.chi, 1.0, method="cg", tol=1e-6)
+        times[n] = time.perf_counter() - t0
+        if sum(times.values()) > budget_s:
+            break
+    ns = sorted(times)
+    b = np.log(times[ns[-1]] / times[ns[0]]) / np.log(ns[-1] / ns[0]) if len(ns) > 1 else float("nan")
+    est = times[ns[-1]] * (n_target / ns[-1]) ** b
+    return {"value": est * 1e3, "unit": "ms", "cores": int(threads), "kind": "oracle",
+            "sample": (f"FP64 non-periodic oracle (dense erf matrix, projected CG to 1e-6, forces) on "
+                       f"2048- and 4096-atom clusters ({times[ns[0]]:.2f} s, {times[ns[-1]]:.2f} s); "
+                       f"t = a N^b fit (b = {b:.2f}) evaluated at N = {n_target}")}
+
+
+def nonperiodic_main(args, dev):
+    """One JSON line for the isolated-cluster workload (value = ms per solve)."""
+    import torch
+
+    from inputs import gen
+    from paper_2607_17978_amd import qeq
+
+    n = 16384
+    s = gen.cluster_system(n, q_tot=1.0, seed=1009)
+    T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    pos, sig, J, chi = T(s.pos), T(s.sigma), T(s.J), T(s.chi)
+    plan = qeq.Plan(n, tol=args.tol, max_iter=3000, stream=torch.cuda.current_stream())
+    for _ in range(max(1, args.warmup)):
+        _, _, _, st = plan.solve_nonperiodic(pos, sig, J, chi, s.q_tot)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = []
+    for _ in range(args.steps):
+        _, _, _, st = plan.solve_nonperiodic(pos, sig, J, chi, s.q_tot)
+        its.append(st["iters"])
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    us_prod = plan.time_kernel(9, reps=20)   # one CG product: pair kernel + epilogue
+    pairs = float(n) * (n - 1)
+    tflops = pairs * NP_FLOP_PER_PAIR / (us_prod * 1e-6) / 1e12
+    out = {
+        "metric": METRIC, "value": round(ms, 4), "unit": "ms", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "non-periodic QEq solve, isolated 16384-atom cluster, Q = +1, direct pair sum",
+                   "n_atoms": n, "q_tot": 1.0, "tol": args.tol, "cg_iters": int(np.median(its)),
+                   "precision": "f32 kernel values, f64 differences, sums and CG"},
+        "roofline": {"bound": "alu", "kernel": "np_pairs (CG product)", "achieved": round(tflops, 2),
+                     "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(tflops / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
+                     "flop_per_pair": NP_FLOP_PER_PAIR, "us_per_launch": round(us_prod, 3),
+                     "pairs_per_s": round(pairs / (us_prod * 1e-6), 1)},
+        "final_stats": {k: st[k] for k in ("iters", "rel_resid", "true_rel_resid", "e_qeq", "e_elec")},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_nonperiodic(n)
+    print(json.dumps(out), flush=True)
+    plan.close()
 
 
 def warmstart_main(args, dev):

@@ -340,7 +340,10 @@ int qeq_profile_read(qeq_plan* plan, double* total_ms, int64_t* launches, int32_
    kind 0 = spread + axis-3 R2C FFT (from the solve's q), kind 4 = axis-3 C2R
    FFT (the other passes work in place and are not offered).  The passes only
    overwrite the plan's mesh buffers; the tape for qeq_backward stays valid.
-   QEQ_EINVAL without a preceding solve or for another kind. */
+   kind 9 = one CG product of the direct pair sum (pair kernel + epilogue)
+   on the charges of the last qeq_solve_nonperiodic call.
+   QEQ_EINVAL without a preceding solve of the matching kind or for another
+   kind. */
 int qeq_time_kernel(qeq_plan* plan, int32_t kind, int32_t reps, double* avg_us);
 
 const char* qeq_strerror(int code);

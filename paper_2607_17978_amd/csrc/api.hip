@@ -672,6 +672,7 @@ int solve_impl(qeq_plan* pl, int n, const double* pos, const double* cell, const
     if (!pos || !sigma || !J || !chi || !q) return QEQ_EINVAL;
     pl->tape_valid = false;
     pl->direct = false;
+    pl->np_valid = false;
     QEQ_TRY(prepare(pl, n, cell, q_tot));
     QEQ_TRY(setup_geometry(pl, pos, sigma, J, chi));
     QEQ_TRY(spc_setup(pl));
@@ -840,6 +841,7 @@ int qeq_solve_nonperiodic(qeq_plan* plan, int32_t n, const double* pos, const do
     int rc = QEQ_EINVAL;
     if (pos && sigma && J && chi && q) {
         pl->tape_valid = false;   // the adjoint and the virial follow periodic solves only
+        pl->np_valid = false;
         pl->spc_active = false;
         rc = np_setup(pl, n, pos, sigma, J, chi, q_tot);
         if (rc == QEQ_OK) {
@@ -848,6 +850,7 @@ int qeq_solve_nonperiodic(qeq_plan* plan, int32_t n, const double* pos, const do
             bool conv = false;
             rc = cg_run(pl, q0, q, energies, forces, &conv);
             if (rc == QEQ_OK) rc = cg_status(pl, conv, stats);
+            pl->np_valid = rc >= 0;
         }
     }
     if (rc < 0 && stats) {
@@ -904,16 +907,22 @@ int qeq_use_fused_inverse(qeq_plan* plan, int32_t enable) {
 
 int qeq_time_kernel(qeq_plan* plan, int32_t kind, int32_t reps, double* avg_us) {
     if (!plan || !avg_us || reps < 1) return QEQ_EINVAL;
-    if (!plan->tape_valid || (kind != PK_SPREAD_R2C && kind != PK_C2R)) return QEQ_EINVAL;
+    const bool direct = kind == PK_COUNT;   // the isolated solve's pair-sum product
+    if (direct ? !(plan->direct && plan->np_valid)
+               : (!plan->tape_valid || (kind != PK_SPREAD_R2C && kind != PK_C2R)))
+        return QEQ_EINVAL;
     qeq_plan* pl = plan;
+    auto stage = [&]() {
+        return direct ? launch_np_matvec(pl, pl->q, pl->y, QEQ_MODE_MATVEC) : launch_mesh_stage(pl, kind, pl->q);
+    };
     hipEvent_t e0 = nullptr, e1 = nullptr;
     QEQ_HIP(hipEventCreate(&e0));
     int rc = qeq_check(hipEventCreate(&e1));
     const unsigned mask = pl->prof_mask;
     pl->prof_mask = 0;
-    if (rc == QEQ_OK) rc = launch_mesh_stage(pl, kind, pl->q);   // warm caches and code
+    if (rc == QEQ_OK) rc = stage();   // warm caches and code
     if (rc == QEQ_OK) rc = qeq_check(hipEventRecord(e0, pl->stream));
-    for (int r = 0; r < reps && rc == QEQ_OK; ++r) rc = launch_mesh_stage(pl, kind, pl->q);
+    for (int r = 0; r < reps && rc == QEQ_OK; ++r) rc = stage();
     if (rc == QEQ_OK) rc = qeq_check(hipEventRecord(e1, pl->stream));
     if (rc == QEQ_OK) rc = qeq_check(hipEventSynchronize(e1));
     float ms = 0.f;

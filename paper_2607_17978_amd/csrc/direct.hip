@@ -237,6 +237,7 @@ int launch_np_matvec(qeq_plan* pl, const double* src, double* dst, int mode) {
     const int ntiles = (n + NP_TILE - 1) / NP_TILE;
     const dim3 grid(ntiles, pl->np_nsplit);
     const double4* npos = (const double4*)pl->np_pos;
+    // QEQ_MODE_MATVEC: the CG product without the convergence flag (timing)
     const int* done = mode == QEQ_MODE_CG ? &pl->sc->done : nullptr;
     double* part = pl->part;
     if (mode == QEQ_MODE_FINAL) {

@@ -215,6 +215,7 @@ struct qeq_plan {
     double* spc_scal = nullptr;   // [0] sum(M^-1 1), [1] ||E||_F^2, [2] min D'/D
     // non-periodic solve (direct pair sum); direct = the last solve's mode
     bool direct = false;
+    bool np_valid = false;        // q and the pair-sum buffers of the last isolated solve
     int np_cap = 0;               // atoms allocated
     int np_nsplit = 0;            // atom splits of the pair sum
     int np_tps = 0;               // tiles of 256 atoms per split
