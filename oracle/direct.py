@@ -177,3 +177,10 @@ def two_atom_charges(E, J, chi):
     den = J[0] + J[1] + E[0, 0] + E[1, 1] - 2.0 * E[0, 1]
     q1 = num / den
     return np.array([q1, -q1])
+
+
+def element_potentials_nonperiodic(pos, sigma, q, species, n_elem):
+    """Gamma_i^z of an isolated system: sum over atoms j != i of element z of
+    erf(r_ij / (sqrt2 gamma_ij)) / r_ij q_j (the paper's kernel)."""
+    from . import ewald
+    return ewald._element_potentials_from(nonperiodic_matrix(pos, sigma), sigma, q, species, n_elem)

@@ -437,3 +437,31 @@ def strained(pos, cell, F):
     """Positions and cell after the homogeneous deformation r -> F r (rows are vectors)."""
     F = np.asarray(F, dtype=np.float64)
     return np.asarray(pos, dtype=np.float64) @ F.T, np.asarray(cell, dtype=np.float64) @ F.T
+
+
+# ---------------------------------------------------------------------------
+# Element-resolved electrostatic potentials (ee4G embedding features)
+# ---------------------------------------------------------------------------
+
+def element_potentials(pos, cell, sigma, q, species, n_elem, eta=None):
+    """Gamma_i^z: potential at atom i of the charges of element z, without the
+    atom's own Gaussian self term (Electrostatics and Charge Equilibration
+    section: the ee4G variant appends element-specific electrostatic
+    potentials at each site, computed from the equilibrated charges).
+
+    Gamma[:, z] = E (q * [s = z]) - [s_i = z] q_i / (sigma_i sqrt(pi)), with E
+    the periodic Coulomb matrix (images, background) of ``coulomb_matrix``.
+    """
+    E = coulomb_matrix(pos, cell, sigma, eta=eta)
+    return _element_potentials_from(E, sigma, q, species, n_elem)
+
+
+def _element_potentials_from(E, sigma, q, species, n_elem):
+    q = np.asarray(q, dtype=np.float64)
+    species = np.asarray(species)
+    sigma = np.asarray(sigma, dtype=np.float64)
+    out = np.zeros((q.shape[0], n_elem))
+    for z in range(n_elem):
+        m = (species == z).astype(np.float64)
+        out[:, z] = E @ (q * m) - m * q / (sigma * SQRTPI)
+    return out
