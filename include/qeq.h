@@ -133,6 +133,26 @@ int qeq_solve_nonperiodic(qeq_plan* plan, int32_t n, const double* pos, const do
                           const double* J, const double* chi, double q_tot, const double* q0,
                           double* q, double* energies, double* forces, qeq_stats* stats);
 
+/* Element-resolved electrostatic potentials of the last solve on this plan:
+   the embedding features of the paper's ee4G variant (Electrostatics and
+   Charge Equilibration section: element-specific potentials at each atomic
+   site from the equilibrated charges, appended to the feature vector).
+     gamma[i * n_elem + z] = sum_j E_ij q_j [species_j = z]
+                             - [species_i = z] q_i / (sigma_i sqrt(pi)),
+   i.e. the potential at atom i of the charges of element z without the
+   atom's own Gaussian self term; E is the Coulomb operator of that solve
+   (qeq_solve: periodic images, mesh, pairs, self and background terms;
+   qeq_solve_nonperiodic: the direct pair sum).  Summed over z and completed
+   with q_i/(sigma_i sqrt(pi)) + J_i q_i + chi_eff,i it gives the Lagrange
+   multiplier mu at every atom (the stationarity of the solve).
+   species (n, int32, device, caller order): element index of each atom;
+   atoms outside [0, n_elem) belong to no channel.  n_elem in [1, 16].
+   gamma (n * n_elem, FP64, device, caller order, out).
+   Cost: n_elem operator products.  The tape for qeq_backward / qeq_virial is
+   kept.  QEQ_EINVAL without a preceding successful solve (or after
+   qeq_matvec / qeq_solve_batched, which replace it) or for bad arguments. */
+int qeq_element_potentials(qeq_plan* plan, const int32_t* species, int32_t n_elem, double* gamma);
+
 /* Gradient of a loss L(q, E_QEq, E_elec) through the last solve on this plan
    (SI eq. 4g_force_trick: Lagrange / adjoint route, one extra linear solve
    with the same operator instead of 3N charge derivatives).

@@ -812,6 +812,7 @@ int qeq_plan_destroy(qeq_plan* pl) {
     dfree(pl->strain_tab); dfree(pl->vir_part);
     spc_free(pl);
     np_free(pl);
+    if (pl->elem_buf) (void)hipFree(pl->elem_buf);
     dfree(pl->sc); dfree(pl->final_dev); dfree(pl->scan_tmp);
     dfree(pl->cell_count); dfree(pl->cell_start); dfree(pl->cell_fill); dfree(pl->cell_atoms);
     dfree(pl->col); dfree(pl->kval); dfree(pl->pdr);
@@ -858,6 +859,11 @@ int qeq_solve_nonperiodic(qeq_plan* plan, int32_t n, const double* pos, const do
         stats->status = rc;
     }
     return rc;
+}
+
+int qeq_element_potentials(qeq_plan* plan, const int32_t* species, int32_t n_elem, double* gamma) {
+    if (!plan) return QEQ_EINVAL;
+    return element_potentials_impl(plan, species, n_elem, gamma);
 }
 
 int qeq_matvec(qeq_plan* plan, int32_t n, const double* pos, const double* cell, const double* sigma,

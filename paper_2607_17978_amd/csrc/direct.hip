@@ -170,6 +170,7 @@ __global__ void k_np_finish(int n, int nsplit, const double* __restrict__ src, c
             acc[4] = gi;
         }
     }
+    if (MODE == QEQ_MODE_ELEC) return;   // uniform per launch: no partial sums
     block_sum<5>(acc);
     if (threadIdx.x == 0)
         for (int t = 0; t < 5; ++t) part[blockIdx.x * QEQ_NPART + t] = acc[t];
@@ -246,6 +247,12 @@ int launch_np_matvec(qeq_plan* pl, const double* src, double* dst, int mode) {
         hipLaunchKernelGGL(k_np_finish<QEQ_MODE_FINAL>, dim3(nblocks(n)), dim3(QEQ_BLOCK), 0, pl->stream, n,
                            pl->np_nsplit, src, pl->np_ypart, pl->np_fpart, pl->dself, pl->Jv, pl->chi_raw, pl->chi,
                            pl->sig, dst, pl->fdst, pl->gtmp, part, done);
+    } else if (mode == QEQ_MODE_ELEC) {
+        hipLaunchKernelGGL(k_np_pairs<false>, grid, dim3(NP_TILE), 0, pl->stream, n, pl->np_tps, npos, src,
+                           pl->np_ypart, pl->np_fpart, nullptr);
+        hipLaunchKernelGGL(k_np_finish<QEQ_MODE_ELEC>, dim3(nblocks(n)), dim3(QEQ_BLOCK), 0, pl->stream, n,
+                           pl->np_nsplit, src, pl->np_ypart, pl->np_fpart, pl->dself, pl->Jv, pl->chi_raw, pl->chi,
+                           pl->sig, dst, pl->fdst, pl->gtmp, part, nullptr);
     } else {
         hipLaunchKernelGGL(k_np_pairs<false>, grid, dim3(NP_TILE), 0, pl->stream, n, pl->np_tps, npos, src,
                            pl->np_ypart, pl->np_fpart, done);

@@ -23,6 +23,8 @@
 #define QEQ_MODE_CG 0         // y = (E + diag J) p over the selected parts
 #define QEQ_MODE_MATVEC 1     // y = E v over the selected parts (no J)
 #define QEQ_MODE_FINAL 2      // y = E q, forces, energy partials
+#define QEQ_MODE_ELEC 3       // direct pair sum only: y = E v (no J, no partial sums)
+#define QEQ_MAX_ELEMENTS 16   // element channels of qeq_element_potentials
 
 #define QEQ_PART_RECIP 1
 #define QEQ_PART_REAL 2
@@ -222,6 +224,7 @@ struct qeq_plan {
     double* np_pos = nullptr;     // double4 (x, y, z, sigma^2) per atom
     double* np_ypart = nullptr;   // [split][atom] partial products
     double* np_fpart = nullptr;   // [split][atom][3] partial force sums
+    double* elem_buf = nullptr;   // 2 n_max: element source and product (caller order)
     bool fused_inverse = true;    // fused inverse axis-2 + complex-to-real slab pass where it fits
 
     // the CG loop is replayed as a HIP graph of one chunk of iterations,
@@ -303,6 +306,8 @@ int np_setup(qeq_plan* pl, int n, const double* pos, const double* sigma, const 
 int launch_np_matvec(qeq_plan* pl, const double* src, double* dst, int mode);   // QEQ_MODE_CG / FINAL
 void np_free(qeq_plan* pl);
 int launch_final_tail(qeq_plan* pl, double* q_out, double* energies, double* forces_out);
+// element-resolved potentials (embed.hip)
+int element_potentials_impl(qeq_plan* pl, const int32_t* species, int n_elem, double* out);
 int launch_scan(qeq_plan* pl, const int* in, int* out, int m);
 int launch_rhs_norm(qeq_plan* pl, const double* b);
 

@@ -88,6 +88,8 @@ def load_library():
     L.qeq_solve.restype = ctypes.c_int
     L.qeq_solve_nonperiodic.argtypes = [vp, i32, dp, dp, dp, dp, f64, dp, dp, dp, dp, ctypes.POINTER(Stats)]
     L.qeq_solve_nonperiodic.restype = ctypes.c_int
+    L.qeq_element_potentials.argtypes = [vp, vp, i32, dp]
+    L.qeq_element_potentials.restype = ctypes.c_int
     L.qeq_backward.argtypes = [vp, dp, f64, f64, dp, dp, dp, ctypes.POINTER(Stats)]
     L.qeq_backward.restype = ctypes.c_int
     L.qeq_virial.argtypes = [vp, dp]
@@ -256,6 +258,21 @@ class Plan:
         if check and rc < 0:
             raise QEqError(rc, strerror(rc))
         return q, en, f, dict(st.as_dict(), rc=rc)
+
+    def element_potentials(self, species, n_elem):
+        """Gamma (n x n_elem float64, device): potentials at each atom of the
+        charges of each element, without the atom's own self term (ee4G
+        embedding features; see qeq_element_potentials)."""
+        import torch
+        n = int(species.shape[0])
+        if species.device != self.device or species.dtype != torch.int32 or not species.is_contiguous():
+            raise QEqError(QEQ_EINVAL, "species must be a contiguous int32 tensor on the plan's device")
+        out = torch.empty((n, int(n_elem)), dtype=torch.float64, device=self.device)
+        rc = load_library().qeq_element_potentials(self._h, ctypes.c_void_p(species.data_ptr()), int(n_elem),
+                                                   _ptr(out))
+        if rc != QEQ_OK:
+            raise QEqError(rc, strerror(rc))
+        return out
 
     def backward(self, dL_dq=None, dL_dEqeq=0.0, dL_dEelec=0.0, check=True):
         """Adjoint gradients (dL/dchi, dL/dJ, dL/dpos, stats) through the last solve."""

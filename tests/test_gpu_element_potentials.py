@@ -1,0 +1,112 @@
+"""Element-resolved potentials Gamma_i^z (ee4G embedding features) on the GPU.
+
+Compared with the FP64 oracle evaluated at the GPU's own charges (so that the
+comparison isolates the potential, not the solve): periodic 64-atom cell with
+two elements, a triclinic charged three-element batch member, an isolated
+517-atom cluster; at full size (32,768 atoms) the stationarity sum rule
+sum_z Gamma_i^z + q_i/(sigma_i sqrt(pi)) + J_i q_i + chi_i = mu.  The tape of
+the solve stays valid (backward and virial unchanged), and calls without a
+solve are refused.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from inputs import gen
+from oracle import direct, ewald
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+ETA = 2.0
+SQRTPI = math.sqrt(math.pi)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2607_17978_amd import qeq
+    qeq.load_library()
+    return torch.device("cuda", 0)
+
+
+def T(a, dev, dt=None):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dt or torch.float64, device=dev)
+
+
+@pytest.mark.parametrize("which", ["n64", "batch17"])
+def test_periodic_matches_oracle(dev, which):
+    from paper_2607_17978_amd import qeq
+    if which == "n64":
+        s, rc, ne = gen.system_64(), 11.0, 2
+    else:
+        s, rc, ne = gen.batch_structure(17), 12.0, 3
+    plan = qeq.Plan(s.n, eta=ETA, r_cut=rc, grid=s.grid, tol=1e-8)
+    q, _, _, st = plan.solve(T(s.pos, dev), s.cell, T(s.sigma, dev), T(s.J, dev), T(s.chi, dev), s.q_tot)
+    G = plan.element_potentials(T(s.species, dev, torch.int32), ne).cpu().numpy()
+    qn = q.cpu().numpy()
+    ref = ewald.element_potentials(s.pos, s.cell, s.sigma, qn, s.species, ne)
+    scale = np.abs(ref).max()
+    err = np.abs(G - ref).max() / scale
+    print(which, "max rel err", err, "scale", scale)
+    assert err <= 2e-5
+    plan.close()
+
+
+def test_nonperiodic_matches_oracle(dev):
+    from paper_2607_17978_amd import qeq
+    s = gen.cluster_system(517, q_tot=1.0)
+    plan = qeq.Plan(s.n, tol=1e-8)
+    q, _, _, st = plan.solve_nonperiodic(T(s.pos, dev), T(s.sigma, dev), T(s.J, dev), T(s.chi, dev), 1.0)
+    G = plan.element_potentials(T(s.species, dev, torch.int32), 2).cpu().numpy()
+    ref = direct.element_potentials_nonperiodic(s.pos, s.sigma, q.cpu().numpy(), s.species, 2)
+    err = np.abs(G - ref).max() / np.abs(ref).max()
+    print("cluster517 max rel err", err)
+    assert err <= 1e-6
+    plan.close()
+
+
+def test_sum_rule_full_size(dev):
+    """32,768 atoms: the potentials of all elements reproduce mu at every atom
+    up to the solve's residual."""
+    from paper_2607_17978_amd import qeq
+    s = gen.system_32k()
+    plan = qeq.Plan(s.n, eta=ETA, r_cut=11.0, grid=s.grid, tol=1e-7)
+    q, _, _, st = plan.solve(T(s.pos, dev), s.cell, T(s.sigma, dev), T(s.J, dev), T(s.chi, dev), s.q_tot)
+    G = plan.element_potentials(T(s.species, dev, torch.int32), 2).cpu().numpy()
+    qn = q.cpu().numpy()
+    lhs = G.sum(1) + qn / (s.sigma * SQRTPI) + s.J * qn + s.chi
+    pchi = np.linalg.norm(s.chi - s.chi.mean())
+    dev_ = np.linalg.norm(lhs - lhs.mean()) / pchi
+    print("n32768 sum rule: relative deviation", dev_, "mean - mu", lhs.mean() - st["mu"])
+    assert dev_ <= 5e-6 and abs(lhs.mean() - st["mu"]) <= 1e-6
+    plan.close()
+
+
+def test_tape_kept_and_refusals(dev):
+    from paper_2607_17978_amd import qeq
+    s = gen.system_64()
+    sp = T(s.species, dev, torch.int32)
+    plan = qeq.Plan(s.n, eta=ETA, r_cut=11.0, grid=s.grid, tol=1e-8)
+    with pytest.raises(qeq.QEqError):
+        plan.element_potentials(sp, 2)   # no solve yet
+    plan.solve(T(s.pos, dev), s.cell, T(s.sigma, dev), T(s.J, dev), T(s.chi, dev), s.q_tot)
+    g = T(np.random.default_rng(1).normal(size=s.n), dev)
+    d1 = [t.cpu().numpy() for t in plan.backward(g, 0.3, 0.7)[:3]]
+    w1 = plan.virial().cpu().numpy()
+    G1 = plan.element_potentials(sp, 2)
+    d2 = [t.cpu().numpy() for t in plan.backward(g, 0.3, 0.7)[:3]]
+    w2 = plan.virial().cpu().numpy()
+    G2 = plan.element_potentials(sp, 2)
+    for a, b in zip(d1, d2):
+        assert np.abs(a - b).max() <= 1e-12 * max(1.0, np.abs(a).max())
+    assert np.abs(w1 - w2).max() <= 1e-12 * np.abs(w1).max()
+    assert torch.equal(G1, G2)
+    with pytest.raises(qeq.QEqError):
+        plan.element_potentials(sp, 0)
+    plan.matvec(T(s.pos, dev), s.cell, T(s.sigma, dev), T(np.ones(s.n), dev))
+    with pytest.raises(qeq.QEqError):
+        plan.element_potentials(sp, 2)   # the matvec replaced the solve's tape
+    plan.close()
