@@ -39,8 +39,8 @@ KIND_NAMES = ["spread_r2c", "fft_rows_fwd", "fft_cols_green", "fft_rows_inv", "c
 # that source the traffic is reported as null until it is measured again.
 MEASURED_TRAFFIC = {
     "spread_r2c": {"kernel": "k_spread_r2c", "file": "paper_2607_17978_amd/csrc/mesh.hip",
-                   "source_sha256_16": "a2b77708a56e59a5",
-                   "fetch_kib": 5831.9375, "fetch_scale": 2.0, "write_kib": 27936.0, "write_scale": 1.0},
+                   "source_sha256_16": "74cfb27206d190dd",
+                   "fetch_kib": 2447.875, "fetch_scale": 2.0, "write_kib": 27936.0, "write_scale": 1.0},
 }
 
 
