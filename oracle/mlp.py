@@ -149,3 +149,21 @@ def adam(params, grad, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     mh = m / (1 - b1 ** step)
     vh = v / (1 - b2 ** step)
     return params - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+def charge_loss_through_qeq(params, X, species, pos, cell, sigma, J, q_tot, q_ref, use_bf16=False):
+    """4G charge training: electronegativities from the element networks, charges
+    from the QEq solve, loss L = mean_i (q_i - q_ref,i)^2 and its parameter
+    gradient by the chain rule dL/dtheta = sum_i dL/dchi_i dchi_i/dtheta, with
+    dL/dchi from the adjoint of the solve (SI 4G section: the charges depend on
+    chi through the linear system; eq. 4g_force_trick's Lagrange route).
+    Returns (L, dL/dtheta, q, dL/dchi).
+    """
+    from . import ewald
+    chi, cache = forward(params, X, species, use_bf16=use_bf16)
+    E = ewald.coulomb_matrix(pos, cell, sigma)
+    q, _ = ewald.solve_qeq(E, J, chi, q_tot)
+    r = q - np.asarray(q_ref, dtype=np.float64)
+    L = float(np.mean(r * r))
+    _, dchi, _, _ = ewald.qeq_adjoint(pos, cell, sigma, J, chi, q_tot, 2.0 * r / r.shape[0])
+    return L, backward(params, cache, dchi, use_bf16=use_bf16), q, dchi
