@@ -1,0 +1,127 @@
+"""4G charge training through the QEq solve (workflow over the C ABI).
+
+In a 4G-HDNNP the element networks predict electronegativities chi_i from the
+atomic environment; the charges follow from the QEq solve, and the networks
+are fitted so that those charges match reference charges (the paper's 4G
+charge training; the SI's Lagrange route differentiates through the linear
+system).  Here one training step on a structure is
+
+    chi = net(G)                     element networks (mlp_forward, BF16 MFMA)
+    q   = QEq(chi)                   qeq_solve
+    L   = mean_i (q_i - q_ref,i)^2
+    dL/dchi                          qeq_backward (one adjoint solve)
+    Adam step with dL/dtheta = sum_i dL/dchi_i dchi_i/dtheta
+
+The last line reuses the network's own training kernel, whose loss is
+1/2 mean (y - t)^2: with the target t = chi - n dL/dchi its output gradient
+(y - t)/n is exactly dL/dchi, so mlp_train_step back-propagates the QEq
+gradient through the network and applies Adam.
+
+The workload: a 4,096-atom subset of a simple-cubic lattice (density 0.01
+bohr^-3) moving as in the trajectory workload; reference charges are QEq
+charges of a hidden "teacher" electronegativity model (the fixed random
+network on radial descriptors of the trajectory workload); the student sees
+the same 16 radial descriptors.  The element-mean electronegativity (the
+method without a chi network) is the baseline the trained network must beat.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+from . import qeq
+from .warmstart import CENTERS, RCUT_DESC, WIDTH
+
+
+def charge_step(plan, net, G, species, pos, cell, sigma, J, q_ref, q_tot=0.0, lr=2e-3, update=True,
+                grad_out=None):
+    """One training step (or only the gradient with update=False, into
+    grad_out).  Returns (loss, q, dL/dchi, solve stats, adjoint stats)."""
+    n = int(G.shape[0])
+    chi = net.predict(G, species)
+    q, _, _, st = plan.solve(pos, cell, sigma, J, chi, q_tot, forces=False)
+    r = q - q_ref
+    loss = float((r * r).mean())
+    dchi, _, _, st_b = plan.backward(2.0 * r / n, 0.0, 0.0)
+    net.train_step(G, species, chi - n * dchi, lr=lr, update=update, grad_out=grad_out)
+    return loss, q, dchi, st, st_b
+
+
+def init_networks(n_species=2, seed=1011, chi_means=(0.1, -0.1)):
+    """Xavier weights, output weights scaled by 0.1 and output biases at the
+    element means: an untrained network starts near the element-mean model."""
+    from inputs import gen
+    nets = gen.warmstart_init(seed, n_species)
+    for e, net in enumerate(nets):
+        net["W3"] = 0.1 * np.asarray(net["W3"])
+        net["b3"] = chi_means[e]
+    return nets
+
+
+def run_chi_training(n=4096, side=17, train_frames=8, test_frames=4, epochs=40, lr=2e-3, tol=1e-8,
+                     device=None, log=None):
+    import torch
+
+    from inputs import gen
+
+    spacing = gen.MD_SPACING
+    dev = device or torch.device("cuda", torch.cuda.current_device())
+    T = lambda a, dt=torch.float64: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+    pos, cell, species, sigma, J = gen.md_initial(n, side, spacing, seed=1010)
+    k = gen.grid_dim(side * spacing, 0.8)
+    plan = qeq.Plan(n, eta=2.0, r_cut=11.0, grid=(k, k, k), tol=tol, max_iter=3000)
+    chi_w = gen.chi_network_weights(1004)
+    sig_d, J_d, sp_d = T(sigma), T(J), T(species, torch.int32)
+    frames = []
+    scaling = y_std = None
+    for t in range(train_frames + test_frames):
+        if t > 0:
+            pos = pos + gen.md_displacement(t - 1, n, seed=1010)
+        posd = T(gen.wrap_positions(pos, cell))
+        G = plan.descriptors(posd, cell, sig_d, CENTERS, WIDTH, RCUT_DESC)
+        chi, scaling, y_std = gen.chi_from_descriptors(G.cpu().numpy(), species, chi_w, scaling, y_std)
+        q_ref, _, _, st = plan.solve(posd, cell, sig_d, J_d, T(chi), 0.0, forces=False)
+        frames.append((posd, G, q_ref))
+    train, test = frames[:train_frames], frames[train_frames:]
+
+    # the method without a chi network: one electronegativity per element
+    chi_base = T(np.asarray(gen.CHI_MEAN_2EL)[species])
+
+    def rms(qa, qb):
+        return float((qa - qb).pow(2).mean().sqrt())
+
+    base = float(np.mean([rms(plan.solve(p, cell, sig_d, J_d, chi_base, 0.0, forces=False)[0], qr)
+                          for p, _, qr in test]))
+    net = qeq.WarmStartNet(init_networks(), device=dev)
+    net.fit_scaling(torch.cat([g for _, g, _ in train]), sp_d.repeat(train_frames))
+
+    def test_rms():
+        errs = []
+        for p, g, qr in test:
+            q, _, _, _ = plan.solve(p, cell, sig_d, J_d, net.predict(g, sp_d), 0.0, forces=False)
+            errs.append(rms(q, qr))
+        return float(np.mean(errs))
+
+    init = test_rms()
+    order = np.random.default_rng(1012).permutation
+    hist, step_ms = [], []
+    for ep in range(epochs):
+        losses = []
+        for f in order(train_frames):
+            p, g, qr = train[f]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            loss, _, _, st, st_b = charge_step(plan, net, g, sp_d, p, cell, sig_d, J_d, qr, lr=lr)
+            torch.cuda.synchronize()
+            step_ms.append((time.perf_counter() - t0) * 1e3)
+            losses.append(loss)
+        hist.append(float(np.mean(losses)))
+        if log and (ep % 10 == 0 or ep == epochs - 1):
+            log(f"epoch {ep}: train loss {hist[-1]:.3e}")
+    final = test_rms()
+    plan.close()
+    return {"n": n, "grid": [k, k, k], "train_frames": train_frames, "test_frames": test_frames,
+            "epochs": epochs, "rms_element_means": base, "rms_untrained": init, "rms_trained": final,
+            "train_loss_first": hist[0], "train_loss_last": hist[-1],
+            "ms_per_step": float(np.median(step_ms))}
