@@ -134,11 +134,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tol", type=float, default=1e-6)
-    ap.add_argument("--workload", choices=["cold32k", "warmstart", "batch", "nonperiodic"], default="cold32k",
+    ap.add_argument("--workload", choices=["cold32k", "warmstart", "batch", "nonperiodic", "adjoint"],
+                    default="cold32k",
                     help="cold32k: the default cold-start solve; warmstart: the 131,072-atom "
                          "trajectory (learned vs cold vs previous-frame start); batch: 1,024 "
                          "structures in one persistent launch vs one launch sequence per structure; "
-                         "nonperiodic: an isolated 16,384-atom cluster (direct pair sum)")
+                         "nonperiodic: an isolated 16,384-atom cluster (direct pair sum); adjoint: "
+                         "the differentiated 32,768-atom workload (forward solve + adjoint backward)")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="MB",
                     help="only run a plain device copy of this many MB (10 times) and exit: the "
                          "reference for scaling FETCH_SIZE / WRITE_SIZE counters")
@@ -175,6 +177,8 @@ def main():
         return batch_main(args, dev)
     if args.workload == "nonperiodic":
         return nonperiodic_main(args, dev)
+    if args.workload == "adjoint":
+        return adjoint_main(args, dev)
     s = gen.system_32k()
     T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
     pos, sig, J, chi = T(s.pos), T(s.sigma), T(s.J), T(s.chi)
@@ -509,6 +513,62 @@ def nonperiodic_main(args, dev):
         out["cpu_baseline"] = cpu_baseline_nonperiodic(n)
     print(json.dumps(out), flush=True)
     plan.close()
+
+
+def adjoint_main(args, dev):
+    """Differentiated workload: L = sum w (q - Q_ref)^2 + E_elec on the 32,768-atom
+    system; one step = forward solve + adjoint backward (dL/dchi, dL/dJ,
+    dL/dr), Jacobi and spectral preconditioner.  value = ms per Jacobi step."""
+    import torch
+
+    from inputs import gen
+    from paper_2607_17978_amd import qeq
+
+    s = gen.system_32k()
+    w, q_ref = gen.adjoint_targets(s.n)
+    T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    pos, sig, J, chi, wd, qrd = T(s.pos), T(s.sigma), T(s.J), T(s.chi), T(w), T(q_ref)
+    res = {}
+    for name, kc in (("jacobi", 0.0), ("spectral", args.spectral_kc)):
+        if name == "spectral" and kc <= 0.0:
+            continue
+        plan = qeq.Plan(s.n, eta=2.0, r_cut=11.0, grid=s.grid, tol=args.tol, max_iter=3000,
+                        stream=torch.cuda.current_stream())
+        plan.use_spectral_preconditioner(kc)
+
+        def step():
+            q, en, f, st = plan.solve(pos, s.cell, sig, J, chi, s.q_tot)
+            out = plan.backward(2.0 * wd * (q - qrd), 0.0, 1.0)
+            return st, out[3]
+
+        for _ in range(max(1, args.warmup)):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            st, stb = step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            plan.solve(pos, s.cell, sig, J, chi, s.q_tot)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        res[name] = {"ms_per_step": round((t1 - t0) * 1e3 / args.steps, 4),
+                     "forward_ms": round((t2 - t1) * 1e3 / args.steps, 4),
+                     "backward_ms": round(((t1 - t0) - (t2 - t1)) * 1e3 / args.steps, 4),
+                     "forward_iters": st["iters"], "adjoint_iters": stb["iters"]}
+        plan.close()
+    ms = res["jacobi"]["ms_per_step"]
+    out = {
+        "metric": METRIC, "value": ms, "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "differentiated QEq, 32768-atom lattice, L = sum w (q - Qref)^2 + E_elec, "
+                               "forward solve + adjoint backward (dL/dchi, dL/dJ, dL/dr)",
+                   "n_atoms": s.n, "grid": list(s.grid), "tol": args.tol},
+        "preconditioners": res,
+    }
+    print(json.dumps(out), flush=True)
 
 
 def warmstart_main(args, dev):

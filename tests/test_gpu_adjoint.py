@@ -126,3 +126,40 @@ def test_autograd_function(dev):
     assert np.abs(J.grad.cpu().numpy() - dJ).max() <= 1e-5
     assert rel_rms(pos.grad.cpu().numpy(), dpos) <= 1e-4
     plan.close()
+
+
+def test_full_size_directional_derivatives(dev):
+    """32,768 atoms (the differentiated workload at its full size): the adjoint
+    gradients against central differences of the loss along random directions
+    in chi and in the positions, every loss from a fresh GPU solve."""
+    from paper_2607_17978_amd import qeq
+    s = gen.system_32k()
+    w, q_ref = gen.adjoint_targets(s.n)
+    wd, qrd = T(w, dev), T(q_ref, dev)
+    plan = qeq.Plan(s.n, eta=ETA, r_cut=RC, grid=s.grid, tol=1e-9, max_iter=3000)
+
+    def loss(pos, chi):
+        q, en, _, st = plan.solve(T(pos, dev), s.cell, T(s.sigma, dev), T(s.J, dev), T(chi, dev), s.q_tot,
+                                  forces=False)
+        assert st["rc"] == 0
+        return float((wd * (q - qrd) ** 2).sum()) + float(en[1]), q
+
+    L0, q = loss(s.pos, s.chi)
+    dchi, dJ, dpos, st = plan.backward(2.0 * wd * (q - qrd), 0.0, 1.0)
+    assert st["rc"] == 0
+    dchi, dpos = dchi.cpu().numpy(), dpos.cpu().numpy()
+    rng = np.random.default_rng(11)
+    for kind, h in (("chi", 1e-3), ("pos", 1e-3)):
+        d = rng.normal(size=s.n if kind == "chi" else (s.n, 3))
+        if kind == "chi":
+            lp, _ = loss(s.pos, s.chi + h * d)
+            lm, _ = loss(s.pos, s.chi - h * d)
+            an = float((dchi * d).sum())
+        else:
+            lp, _ = loss(s.pos + h * d, s.chi)
+            lm, _ = loss(s.pos - h * d, s.chi)
+            an = float((dpos * d).sum())
+        fd = (lp - lm) / (2 * h)
+        print(kind, "fd", fd, "adjoint", an, "rel", abs(fd - an) / abs(fd))
+        assert abs(fd - an) <= 1e-3 * abs(fd)
+    plan.close()
