@@ -167,3 +167,24 @@ def charge_loss_through_qeq(params, X, species, pos, cell, sigma, J, q_tot, q_re
     L = float(np.mean(r * r))
     _, dchi, _, _ = ewald.qeq_adjoint(pos, cell, sigma, J, chi, q_tot, 2.0 * r / r.shape[0])
     return L, backward(params, cache, dchi, use_bf16=use_bf16), q, dchi
+
+
+def charge_loss_through_qeq_chi_j(params_chi, params_j, X, species, pos, cell, sigma, j_elem, j_scale, q_tot,
+                                  q_ref, use_bf16=False):
+    """As ``charge_loss_through_qeq`` with a second set of element networks for
+    the hardness, J_i = j_elem_i exp(j_scale y_i) (positive, as J > 0 requires),
+    y the J network's output.  dL/dJ from the same adjoint solve
+    (dL/dJ_i = -a_i q_i), chained through the exponential.
+    Returns (L, dL/dtheta_chi, dL/dtheta_J, q)."""
+    from . import ewald
+    chi, cache_c = forward(params_chi, X, species, use_bf16=use_bf16)
+    y, cache_j = forward(params_j, X, species, use_bf16=use_bf16)
+    J = np.asarray(j_elem, dtype=np.float64) * np.exp(j_scale * y)
+    E = ewald.coulomb_matrix(pos, cell, sigma)
+    q, _ = ewald.solve_qeq(E, J, chi, q_tot)
+    r = q - np.asarray(q_ref, dtype=np.float64)
+    L = float(np.mean(r * r))
+    _, dchi, _, dJ = ewald.qeq_adjoint(pos, cell, sigma, J, chi, q_tot, 2.0 * r / r.shape[0])
+    g_chi = backward(params_chi, cache_c, dchi, use_bf16=use_bf16)
+    g_j = backward(params_j, cache_j, dJ * J * j_scale, use_bf16=use_bf16)
+    return L, g_chi, g_j, q

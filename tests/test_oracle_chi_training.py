@@ -57,3 +57,34 @@ def test_planted_adjoint_sign_is_caught():
         chi, cache = omlp.forward(p, X, s.species)
         return L, omlp.backward(p, cache, -dchi), q, -dchi
     assert fd_check(wrong) > 0.5
+
+
+def test_hardness_network_gradient_matches_finite_differences():
+    """J_i = J_e exp(0.2 y_i) from a second set of networks: the chain rule
+    through dL/dJ of the adjoint against central differences."""
+    s, X, p, q_ref = setup()
+    _, _, pj, _ = setup(seed=3)
+    pj = pj.copy()
+    for e in range(2):
+        pj[e * omlp.STRIDE + omlp.OFF_B3] = 0.0
+    j_elem = s.J
+
+    def L_of(pc, pjj):
+        return omlp.charge_loss_through_qeq_chi_j(pc, pjj, X, s.species, s.pos, s.cell, s.sigma, j_elem, 0.2, 0.0,
+                                                  q_ref)[0]
+
+    L, gc, gj, q = omlp.charge_loss_through_qeq_chi_j(p, pj, X, s.species, s.pos, s.cell, s.sigma, j_elem, 0.2,
+                                                      0.0, q_ref)
+    h = 1e-5
+    for k in (omlp.OFF_W1 + 7, omlp.OFF_B2 + 2, omlp.OFF_W3 + 4, omlp.OFF_B3, omlp.STRIDE + omlp.OFF_W2 + 33):
+        pp, pm = pj.copy(), pj.copy()
+        pp[k] += h
+        pm[k] -= h
+        fd = (L_of(p, pp) - L_of(p, pm)) / (2 * h)
+        assert abs(fd - gj[k]) <= 1e-6 * max(abs(fd), 1e-6)
+    # the chi part agrees with the chi-only function when J is the element value
+    pz = np.zeros_like(pj)
+    L1, gc1, _, _ = omlp.charge_loss_through_qeq_chi_j(p, pz, X, s.species, s.pos, s.cell, s.sigma, j_elem, 0.2,
+                                                       0.0, q_ref)
+    L2, gc2, _, _ = omlp.charge_loss_through_qeq(p, X, s.species, s.pos, s.cell, s.sigma, s.J, 0.0, q_ref)
+    assert abs(L1 - L2) <= 1e-14 and np.abs(gc1 - gc2).max() <= 1e-12
