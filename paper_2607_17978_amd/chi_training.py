@@ -17,6 +17,10 @@ The last line reuses the network's own training kernel, whose loss is
 (y - t)/n is exactly dL/dchi, so mlp_train_step back-propagates the QEq
 gradient through the network and applies Adam.
 
+Hardness networks (the 4G J_i) are trained the same way: J_i = J_e exp(s y_i)
+with y the J network's output (positive for any output), and
+dL/dy_i = dL/dJ_i J_i s with dL/dJ from the same adjoint solve.
+
 The workload: a 4,096-atom subset of a simple-cubic lattice (density 0.01
 bohr^-3) moving as in the trajectory workload; reference charges are QEq
 charges of a hidden "teacher" electronegativity model (the fixed random
@@ -33,24 +37,37 @@ import numpy as np
 from . import qeq
 from .warmstart import CENTERS, RCUT_DESC, WIDTH
 
+J_SCALE = 0.2   # J_i = J_e exp(J_SCALE y_i): positive for any network output
+
 
 def charge_step(plan, net, G, species, pos, cell, sigma, J, q_ref, q_tot=0.0, lr=2e-3, update=True,
-                grad_out=None):
-    """One training step (or only the gradient with update=False, into
-    grad_out).  Returns (loss, q, dL/dchi, solve stats, adjoint stats)."""
+                grad_out=None, jnet=None, j_scale=J_SCALE, jgrad_out=None):
+    """One training step (or only the gradients with update=False, into
+    grad_out / jgrad_out).  J: the element hardnesses; with ``jnet`` the
+    hardness of atom i is J_i exp(j_scale y_i), y the J network's output, and
+    that network is trained through dL/dJ of the same adjoint solve.
+    Returns (loss, q, dL/dchi, solve stats, adjoint stats)."""
     n = int(G.shape[0])
     chi = net.predict(G, species)
-    q, _, _, st = plan.solve(pos, cell, sigma, J, chi, q_tot, forces=False)
+    if jnet is not None:
+        yj = jnet.predict(G, species)
+        Jv = J * (j_scale * yj).exp()
+    else:
+        Jv = J
+    q, _, _, st = plan.solve(pos, cell, sigma, Jv, chi, q_tot, forces=False)
     r = q - q_ref
     loss = float((r * r).mean())
-    dchi, _, _, st_b = plan.backward(2.0 * r / n, 0.0, 0.0)
+    dchi, dJ, _, st_b = plan.backward(2.0 * r / n, 0.0, 0.0)
     net.train_step(G, species, chi - n * dchi, lr=lr, update=update, grad_out=grad_out)
+    if jnet is not None:
+        jnet.train_step(G, species, yj - n * (dJ * Jv * j_scale), lr=lr, update=update, grad_out=jgrad_out)
     return loss, q, dchi, st, st_b
 
 
 def init_networks(n_species=2, seed=1011, chi_means=(0.1, -0.1)):
     """Xavier weights, output weights scaled by 0.1 and output biases at the
-    element means: an untrained network starts near the element-mean model."""
+    element means: an untrained network starts near the element-mean model
+    (chi_means = (0, 0) for the J networks: J starts at the element value)."""
     from inputs import gen
     nets = gen.warmstart_init(seed, n_species)
     for e, net in enumerate(nets):
@@ -60,11 +77,18 @@ def init_networks(n_species=2, seed=1011, chi_means=(0.1, -0.1)):
 
 
 def run_chi_training(n=4096, side=17, train_frames=8, test_frames=4, epochs=40, lr=2e-3, tol=1e-8,
-                     device=None, log=None):
+                     device=None, log=None, train_j=False, vary_j=None):
+    """Train the chi networks (and with train_j the J networks) on reference
+    charges of a teacher model.  With vary_j (default: train_j) the teacher's
+    hardness also varies with the environment, J_i = J_e exp(0.1 z_i), z a
+    second fixed random network on the descriptors (unit std on the first
+    frame)."""
     import torch
 
     from inputs import gen
 
+    if vary_j is None:
+        vary_j = train_j
     spacing = gen.MD_SPACING
     dev = device or torch.device("cuda", torch.cuda.current_device())
     T = lambda a, dt=torch.float64: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
@@ -75,13 +99,21 @@ def run_chi_training(n=4096, side=17, train_frames=8, test_frames=4, epochs=40, 
     sig_d, J_d, sp_d = T(sigma), T(J), T(species, torch.int32)
     frames = []
     scaling = y_std = None
+    j_w = gen.chi_network_weights(1014)
+    scaling_j = zj_std = None
     for t in range(train_frames + test_frames):
         if t > 0:
             pos = pos + gen.md_displacement(t - 1, n, seed=1010)
         posd = T(gen.wrap_positions(pos, cell))
         G = plan.descriptors(posd, cell, sig_d, CENTERS, WIDTH, RCUT_DESC)
         chi, scaling, y_std = gen.chi_from_descriptors(G.cpu().numpy(), species, chi_w, scaling, y_std)
-        q_ref, _, _, st = plan.solve(posd, cell, sig_d, J_d, T(chi), 0.0, forces=False)
+        Jt = J_d
+        if vary_j:
+            # chi_from_descriptors returns m_e + 0.05 z / z_std: recover z
+            zj, scaling_j, zj_std = gen.chi_from_descriptors(G.cpu().numpy(), species, j_w, scaling_j, zj_std)
+            z = (zj - np.asarray(gen.CHI_MEAN_2EL)[species]) / gen.CHI_SD
+            Jt = J_d * T(np.exp(0.1 * z))
+        q_ref, _, _, st = plan.solve(posd, cell, sig_d, Jt, T(chi), 0.0, forces=False)
         frames.append((posd, G, q_ref))
     train, test = frames[:train_frames], frames[train_frames:]
 
@@ -94,12 +126,19 @@ def run_chi_training(n=4096, side=17, train_frames=8, test_frames=4, epochs=40, 
     base = float(np.mean([rms(plan.solve(p, cell, sig_d, J_d, chi_base, 0.0, forces=False)[0], qr)
                           for p, _, qr in test]))
     net = qeq.WarmStartNet(init_networks(), device=dev)
-    net.fit_scaling(torch.cat([g for _, g, _ in train]), sp_d.repeat(train_frames))
+    Gall, spall = torch.cat([g for _, g, _ in train]), sp_d.repeat(train_frames)
+    net.fit_scaling(Gall, spall)
+    jnet = None
+    if train_j:
+        jnet = qeq.WarmStartNet(init_networks(seed=1015, chi_means=(0.0, 0.0)), device=dev)
+        jnet.fit_scaling(Gall, spall)
+    del Gall, spall
 
     def test_rms():
         errs = []
         for p, g, qr in test:
-            q, _, _, _ = plan.solve(p, cell, sig_d, J_d, net.predict(g, sp_d), 0.0, forces=False)
+            Jv = J_d if jnet is None else J_d * (J_SCALE * jnet.predict(g, sp_d)).exp()
+            q, _, _, _ = plan.solve(p, cell, sig_d, Jv, net.predict(g, sp_d), 0.0, forces=False)
             errs.append(rms(q, qr))
         return float(np.mean(errs))
 
@@ -112,7 +151,7 @@ def run_chi_training(n=4096, side=17, train_frames=8, test_frames=4, epochs=40, 
             p, g, qr = train[f]
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            loss, _, _, st, st_b = charge_step(plan, net, g, sp_d, p, cell, sig_d, J_d, qr, lr=lr)
+            loss, _, _, st, st_b = charge_step(plan, net, g, sp_d, p, cell, sig_d, J_d, qr, lr=lr, jnet=jnet)
             torch.cuda.synchronize()
             step_ms.append((time.perf_counter() - t0) * 1e3)
             losses.append(loss)
@@ -122,6 +161,7 @@ def run_chi_training(n=4096, side=17, train_frames=8, test_frames=4, epochs=40, 
     final = test_rms()
     plan.close()
     return {"n": n, "grid": [k, k, k], "train_frames": train_frames, "test_frames": test_frames,
+            "train_j": bool(train_j), "vary_j": bool(vary_j),
             "epochs": epochs, "rms_element_means": base, "rms_untrained": init, "rms_trained": final,
             "train_loss_first": hist[0], "train_loss_last": hist[-1],
             "ms_per_step": float(np.median(step_ms))}

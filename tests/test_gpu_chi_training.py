@@ -87,3 +87,50 @@ def test_training_beats_element_means(dev):
     assert out["train_loss_last"] < 0.1 * out["train_loss_first"]
     assert out["rms_trained"] < 0.3 * out["rms_element_means"]
     assert out["rms_trained"] < out["rms_untrained"]
+
+
+def test_hardness_gradient_matches_oracle(dev):
+    from paper_2607_17978_amd import chi_training, qeq
+    s = gen.system_64()
+    rng = np.random.default_rng(6)
+    G = rng.uniform(0.0, 2.0, (s.n, 16)).astype(np.float32)
+    q_ref = rng.normal(0.0, 0.2, s.n)
+    q_ref -= q_ref.mean()
+    nets = chi_training.init_networks(seed=1013)
+    jnets = chi_training.init_networks(seed=1016, chi_means=(0.0, 0.0))
+    for n in nets + jnets:
+        n["W3"] = 10.0 * np.asarray(n["W3"])
+    net, jnet = qeq.WarmStartNet(nets, device=dev), qeq.WarmStartNet(jnets, device=dev)
+    Gd, sd = T(G, dev, torch.float32), T(s.species, dev, torch.int32)
+    net.fit_scaling(Gd, sd)
+    jnet.fit_scaling(Gd, sd)
+    plan = qeq.Plan(s.n, eta=2.0, r_cut=11.0, grid=s.grid, tol=1e-10, max_iter=3000)
+    grad, jgrad = torch.zeros_like(net.params), torch.zeros_like(jnet.params)
+    loss, q, dchi, st, st_b = chi_training.charge_step(plan, net, Gd, sd, T(s.pos, dev), s.cell, T(s.sigma, dev),
+                                                       T(s.J, dev), T(q_ref, dev), update=False, grad_out=grad,
+                                                       jnet=jnet, jgrad_out=jgrad)
+    stats = omlp.feature_stats(f32(G), s.species, 2)
+    X = omlp.scale(f32(G), s.species, f32(stats))
+    ref_L, ref_gc, ref_gj, _ = omlp.charge_loss_through_qeq_chi_j(
+        oracle_params(nets), oracle_params(jnets), X, s.species, s.pos, s.cell, s.sigma, s.J,
+        chi_training.J_SCALE, 0.0, q_ref, use_bf16=True)
+    gc, gj = grad.cpu().numpy().astype(np.float64), jgrad.cpu().numpy().astype(np.float64)
+    rel_c = np.linalg.norm(gc - ref_gc) / np.linalg.norm(ref_gc)
+    rel_j = np.linalg.norm(gj - ref_gj) / np.linalg.norm(ref_gj)
+    print("loss", loss, ref_L, "chi grad rel", rel_c, "J grad rel", rel_j)
+    assert abs(loss - ref_L) <= 1e-4 * ref_L
+    assert rel_c <= 3e-3 and rel_j <= 3e-3
+    plan.close()
+
+
+def test_hardness_networks_gain(dev):
+    """Teacher with environment-dependent hardness: chi + J networks reach a
+    lower held-out charge error than chi networks alone."""
+    from paper_2607_17978_amd import chi_training
+    kw = dict(n=4096, side=17, train_frames=6, test_frames=2, epochs=30, device=dev, vary_j=True)
+    chi_only = chi_training.run_chi_training(train_j=False, **kw)
+    both = chi_training.run_chi_training(train_j=True, **kw)
+    print("chi only", chi_only)
+    print("chi + J", both)
+    assert both["rms_trained"] < 0.3 * both["rms_element_means"]
+    assert both["rms_trained"] < 0.8 * chi_only["rms_trained"]
