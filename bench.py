@@ -399,16 +399,40 @@ def batch_main(args, dev):
     seq_ms = (time.perf_counter() - t0) * 1e3
     for pl in plans.values():
         pl.close()
+    # autotuned discretisation and launch shape (untimed search, then timed)
+    from paper_2607_17978_amd import autotune
+    tune = autotune.tune_batched(a, r_cut=rc_cut, tol=args.tol, reps=2)
+    best = tune["best"]
+    tuned = None
+    if best is not None:
+        tplan = qeq.Plan(512, eta=2.0, r_cut=rc_cut, max_spacing=best["max_spacing"],
+                         spline_order=best["spline_order"], tol=args.tol, max_iter=2000)
+        tplan.batched_config(1024, best["wg_per_cu"])
+        for _ in range(max(1, args.warmup)):
+            tplan.solve_batched(**a)
+        tplan.batched_ms()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            _, _, _, tst, trc = tplan.solve_batched(**a)
+        torch.cuda.synchronize()
+        tuned = {"ms_per_step": round((time.perf_counter() - t0) * 1e3 / args.steps, 4),
+                 "kernel_ms": round(tplan.batched_ms() / args.steps, 4), "all_converged": bool(trc == 0),
+                 "cg_iters_mean": float(np.mean([x["iters"] for x in tst]))}
+        tuned.update({k: best[k] for k in ("spline_order", "max_spacing", "wg_per_cu", "max_dq", "max_rel_dE",
+                                           "max_rel_dF")})
+        tplan.close()
     flops = batch_flops(structs, st)
     achieved = flops / (kern_ms * 1e-3) / 1e12
+    value_ms = tuned["ms_per_step"] if tuned is not None else ms_step
     out = {
         "metric": METRIC,
-        "value": round(ms_step, 4),
+        "value": round(value_ms, 4),
         "unit": "ms",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4),
+        "ms_per_step": round(value_ms, 4),
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
@@ -416,16 +440,23 @@ def batch_main(args, dev):
         "data": "synthetic",
         "config": {"workload": "batched QEq, 1024 triclinic structures (N 32-512, 3 elements, Q in {-1,0,1}), "
                                "one persistent launch", "n_structures": len(structs), "n_atoms": int(offs[-1]),
-                   "r_cut_bohr": rc_cut, "tol": args.tol, "spline_order": 6,
-                   "grids": "per structure, spacing <= 0.8 bohr (24..60 per axis)"},
+                   "r_cut_bohr": rc_cut, "tol": args.tol,
+                   "spline_order": best["spline_order"] if best else 6,
+                   "grids": (f"per structure, spacing <= {best['max_spacing']} bohr, order and spacing chosen by "
+                             f"the autotuner" if best else "per structure, spacing <= 0.8 bohr")},
         "structures_per_s": round(len(structs) / (ms_step * 1e-3), 1),
         "per_structure_launches": {"ms": round(seq_ms, 2), "structures_per_s": round(len(structs) / (seq_ms * 1e-3), 1),
                                    "speedup_of_batched": round(seq_ms / ms_step, 2),
                                    "cg_iters_mean": float(np.mean(seq_iters))},
         "roofline": {"bound": "alu", "kernel": "k_batched", "achieved": round(achieved, 3),
                      "peak": 157.3, "unit": "TFLOP/s", "frac": round(achieved / 157.3, 5), "traffic": None,
-                     "flops_per_launch": flops, "us_per_launch": round(kern_ms * 1e3, 1)},
+                     "flops_per_launch": flops, "us_per_launch": round(kern_ms * 1e3, 1),
+                     "setting": "order 6, spacing 0.8 (the default run)"},
         "phase_us_per_structure": {k: round(v, 1) for k, v in zip(plan.BATCH_PHASES, phase)},
+        "autotuned": tuned,
+        "default_setting": {"spline_order": 6, "max_spacing": 0.8, "wg_per_cu": 1, "ms_per_step": round(ms_step, 4)},
+        "autotune_candidates": [{k: (float(f"{v:.4g}") if isinstance(v, float) else v) for k, v in r.items()}
+                                for r in tune["candidates"]],
         "cg_iters_mean": float(np.mean([x["iters"] for x in st])),
         "all_converged": bool(rc == 0),
     }
