@@ -261,7 +261,11 @@ int qeq_batched_phase_us(qeq_plan* plan, int32_t n_struct, double* us);
    weights is NULL.  Runs the plan's geometry set-up (which replaces the tape of
    the last solve), so r_cut must not exceed the plan's real-space cutoff.
    weights: device, n doubles, caller order, or NULL.  centers: host, n_feat
-   doubles.  G: device, n x n_feat floats, caller order. */
+   doubles.  G: device, n x n_feat floats, caller order.
+   pos == NULL reuses the geometry (sorted atoms, pair list) of the last
+   qeq_solve or qeq_descriptors call on this plan with the same n, skipping
+   the set-up and keeping the solve's tape; cell and sigma are then ignored
+   (QEQ_EINVAL if there is no such geometry). */
 int qeq_descriptors(qeq_plan* plan, int32_t n, const double* pos, const double* cell,
                     const double* sigma, const double* weights, int32_t n_feat,
                     const double* centers, double width, double r_cut, float* G);

@@ -673,8 +673,10 @@ int solve_impl(qeq_plan* pl, int n, const double* pos, const double* cell, const
     pl->tape_valid = false;
     pl->direct = false;
     pl->np_valid = false;
+    pl->geom_valid = false;
     QEQ_TRY(prepare(pl, n, cell, q_tot));
     QEQ_TRY(setup_geometry(pl, pos, sigma, J, chi));
+    pl->geom_valid = true;
     QEQ_TRY(spc_setup(pl));
     pl->fdst = pl->forces_s;
     bool conv = false;
@@ -843,6 +845,7 @@ int qeq_solve_nonperiodic(qeq_plan* plan, int32_t n, const double* pos, const do
     if (pos && sigma && J && chi && q) {
         pl->tape_valid = false;   // the adjoint and the virial follow periodic solves only
         pl->np_valid = false;
+        pl->geom_valid = false;
         pl->spc_active = false;
         rc = np_setup(pl, n, pos, sigma, J, chi, q_tot);
         if (rc == QEQ_OK) {
@@ -873,6 +876,7 @@ int qeq_matvec(qeq_plan* plan, int32_t n, const double* pos, const double* cell,
     qeq_plan* pl = plan;
     pl->tape_valid = false;
     pl->direct = false;
+    pl->geom_valid = false;   // the operator parts below differ from a solve's
     QEQ_TRY(prepare(pl, n, cell, 0.0));
     QEQ_TRY(setup_geometry(pl, pos, sigma, nullptr, nullptr));
     pl->kp.parts = parts;
@@ -967,11 +971,18 @@ int qeq_profile_read(qeq_plan* plan, double* total_ms, int64_t* launches, int32_
 int qeq_descriptors(qeq_plan* plan, int32_t n, const double* pos, const double* cell, const double* sigma,
                     const double* weights, int32_t n_feat, const double* centers, double width, double r_cut,
                     float* G) {
-    if (!plan || !pos || !sigma || !centers || !G) return QEQ_EINVAL;
+    if (!plan || !centers || !G) return QEQ_EINVAL;
     qeq_plan* pl = plan;
-    pl->tape_valid = false;   // the geometry set-up below replaces the solve's tape
-    QEQ_TRY(prepare(pl, n, cell, 0.0));
-    QEQ_TRY(setup_geometry(pl, pos, sigma, nullptr, nullptr));
+    if (pos) {
+        if (!sigma) return QEQ_EINVAL;
+        pl->tape_valid = false;   // the geometry set-up below replaces the solve's tape
+        pl->geom_valid = false;
+        QEQ_TRY(prepare(pl, n, cell, 0.0));
+        QEQ_TRY(setup_geometry(pl, pos, sigma, nullptr, nullptr));
+        pl->geom_valid = true;
+    } else if (!pl->geom_valid || n != pl->kp.n) {
+        return QEQ_EINVAL;   // no geometry of this size to reuse
+    }
     QEQ_TRY(launch_descriptors(pl, weights, n_feat, centers, width, r_cut, G));
     QEQ_HIP(hipStreamSynchronize(pl->stream));
     return QEQ_OK;

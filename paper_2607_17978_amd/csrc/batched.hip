@@ -1450,6 +1450,7 @@ int qeq_solve_batched(qeq_plan* plan, int32_t n_struct, const int32_t* atom_offs
     if (!plan) return QEQ_EINVAL;
     plan->tape_valid = false;
     plan->np_valid = false;
+    plan->geom_valid = false;
     return batched_impl(plan, n_struct, atom_offsets, pos, cells, sigma, J, chi, q_tot, q0, q, energies, forces,
                         stats);
 }

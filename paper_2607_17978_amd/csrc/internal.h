@@ -218,6 +218,7 @@ struct qeq_plan {
     // non-periodic solve (direct pair sum); direct = the last solve's mode
     bool direct = false;
     bool np_valid = false;        // q and the pair-sum buffers of the last isolated solve
+    bool geom_valid = false;      // sorted geometry and pair list of the last periodic set-up
     int np_cap = 0;               // atoms allocated
     int np_nsplit = 0;            // atom splits of the pair sum
     int np_tps = 0;               // tiles of 256 atoms per split

@@ -306,11 +306,15 @@ class Plan:
 
     def descriptors(self, pos, cell, sigma, centers, width, r_cut, weights=None):
         """Radial descriptors G (n x len(centers), float32, device), optionally
-        weighted per neighbour; see qeq_descriptors."""
+        weighted per neighbour; see qeq_descriptors.  pos=None reuses the
+        geometry of the last solve / descriptor call (n from sigma or weights)."""
         import torch
-        n = int(pos.shape[0])
-        _check_dev("pos", pos, n, 3, self.device)
-        _check_dev("sigma", sigma, n, None, self.device)
+        if pos is None:
+            n = int((sigma if sigma is not None else weights).shape[0])
+        else:
+            n = int(pos.shape[0])
+            _check_dev("pos", pos, n, 3, self.device)
+            _check_dev("sigma", sigma, n, None, self.device)
         if weights is not None:
             _check_dev("weights", weights, n, None, self.device)
         c = np.ascontiguousarray(np.asarray(centers, dtype=np.float64))
@@ -319,7 +323,8 @@ class Plan:
         rc = load_library().qeq_descriptors(self._h, n, _ptr(pos), cp, _ptr(sigma), _ptr(weights), len(c),
                                             c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                             float(width), float(r_cut), _ptr(G))
-        self._last_n = None       # the tape of the last solve is gone
+        if pos is not None:
+            self._last_n = None   # the tape of the last solve is gone
         if rc < 0:
             raise QEqError(rc, strerror(rc))
         return G

@@ -33,10 +33,13 @@ AUX_WIDTH = 1.0
 
 
 def chi_features(plan, posd, cell, sigma, chi):
-    """n x 16 float32 features: chi_i | sum_j chi_j g_mu(r_ij) (8) | sum_j g_nu(r_ij) (7)."""
+    """n x 16 float32 features: chi_i | sum_j chi_j g_mu(r_ij) (8) | sum_j g_nu(r_ij) (7).
+
+    posd=None reuses the plan's current geometry (the radial descriptors of
+    the same frame have just built it)."""
     import torch
     Gc = plan.descriptors(posd, cell, sigma, CHI_CENTERS, AUX_WIDTH, RCUT_DESC, weights=chi)
-    Gg = plan.descriptors(posd, cell, sigma, GEO_CENTERS, AUX_WIDTH, RCUT_DESC)
+    Gg = plan.descriptors(None, cell, sigma, GEO_CENTERS, AUX_WIDTH, RCUT_DESC)
     return torch.cat([chi.float()[:, None], Gc, Gg], 1).contiguous()
 
 
@@ -97,7 +100,7 @@ def run_trajectory(n=None, side=None, spacing=None, frames=200, epochs=30, lr=2e
         chid = T(chi)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        X = chi_features(plan, posd, cell, sig_d, chid)
+        X = chi_features(plan, None, cell, sig_d, chid)   # geometry of the descriptor call above
         torch.cuda.synchronize()
         t_feat.append((time.perf_counter() - t0) * 1e3)
         if t < n_train:

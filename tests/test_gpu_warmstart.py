@@ -157,3 +157,26 @@ def test_learned_warm_start_on_small_trajectory(dev):
     assert out["learned"]["iters"] < out["cold"]["iters"]
     assert out["prev"]["iters"] < out["cold"]["iters"]
     assert out["learned_chi"]["iters"] < out["prev"]["iters"]
+
+
+def test_descriptors_reuse_geometry(dev):
+    """pos=None reuses the geometry of the last solve / descriptor call: same
+    values as a fresh set-up, and the solve's tape stays valid."""
+    from paper_2607_17978_amd import qeq
+    s = gen.system_512()
+    plan = qeq.Plan(s.n, eta=2.0, r_cut=11.0, grid=s.grid, tol=1e-8)
+    pos, sig, chi = T(s.pos, dev), T(s.sigma, dev), T(s.chi, dev)
+    with pytest.raises(qeq.QEqError):
+        plan.descriptors(None, s.cell, sig, CENTERS, WIDTH, RCUT_DESC)   # nothing to reuse yet
+    G0 = plan.descriptors(pos, s.cell, sig, CENTERS, WIDTH, RCUT_DESC, weights=chi)
+    G1 = plan.descriptors(None, s.cell, sig, CENTERS, WIDTH, RCUT_DESC, weights=chi)
+    assert torch.equal(G0, G1)
+    plan.solve(pos, s.cell, sig, T(s.J, dev), chi, s.q_tot)
+    g = T(np.random.default_rng(2).normal(size=s.n), dev)
+    d0 = plan.backward(g, 0.0, 0.0)[0].cpu().numpy()
+    G2 = plan.descriptors(None, s.cell, sig, CENTERS, WIDTH, RCUT_DESC)
+    d1 = plan.backward(g, 0.0, 0.0)[0].cpu().numpy()   # tape kept
+    assert np.abs(d0 - d1).max() <= 1e-12 * np.abs(d0).max()
+    G3 = plan.descriptors(pos, s.cell, sig, CENTERS, WIDTH, RCUT_DESC)
+    assert torch.equal(G2, G3)
+    plan.close()
