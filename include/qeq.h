@@ -322,6 +322,24 @@ int qeq_use_graphs(qeq_plan* plan, int32_t enable);
    up to FP32 rounding.  Default on. */
 int qeq_use_fused_inverse(qeq_plan* plan, int32_t enable);
 
+/* Reciprocal-space method of later qeq_solve calls on this plan: enable = 0
+   (default) the particle mesh (B-spline spreading, FFT, Green's function,
+   interpolation); enable != 0 direct Ewald summation (SI "Ewald Summation";
+   the paper's O(N^3/2) solver for small cells): the explicit sum over the
+   reciprocal vectors 0 < |k| <= k_max of the half space with
+   exp(-eta^2 k^2 / 2) >= 1e-12, weights 2 (4 pi / V) exp(-eta^2 k^2 / 2) / k^2,
+   through structure factors, O(n M) per CG product for M such vectors
+   (M grows with the cell volume: about 2,800 at 64 atoms in an 18.6-bohr
+   cube with eta = 2, 22,000 at 512 atoms of the same density).  The real-space
+   pairs (plan r_cut), self and background terms, CG, energies and forces are
+   unchanged; there is no mesh and no mesh self-correction (the sums are
+   exact).  QEQ_EPLAN from qeq_solve when a cell needs more than 2^20
+   vectors.  The adjoint, the virial and the element potentials use the
+   mesh: after an Ewald solve qeq_backward, qeq_virial and
+   qeq_element_potentials return QEQ_EINVAL.  The batched and non-periodic
+   solves are not affected. */
+int qeq_use_ewald(qeq_plan* plan, int32_t enable);
+
 /* Preconditioner of the projected CG in qeq_solve / qeq_backward.
    k_cut <= 0 (default): Jacobi, D_i = J_i + 1/(sigma_i sqrt(pi)).
    k_cut > 0 (bohr^-1): spectral preconditioner for the long-wavelength

@@ -431,8 +431,10 @@ int prepare(qeq_plan* pl, int n, const double* cell, double q_tot) {
         QEQ_TRY(dalloc(&pl->cell_fill, ncell + 1));
         pl->ncell_alloc = ncell + 1;
     }
-    k.parts = QEQ_PART_RECIP | QEQ_PART_REAL | QEQ_PART_SELF | QEQ_PART_BG;
-    k.self_corr = pl->prm.self_correction;
+    // with direct Ewald sums the reciprocal part is added from outside the
+    // interpolation pass and is exact (no mesh self-correction)
+    k.parts = (pl->ew_active ? 0 : QEQ_PART_RECIP) | QEQ_PART_REAL | QEQ_PART_SELF | QEQ_PART_BG;
+    k.self_corr = pl->ew_active ? 0 : pl->prm.self_correction;
     k.eta = pl->prm.eta;
     k.rc = rc;
     k.rc2 = rc * rc;
@@ -483,7 +485,10 @@ void chunk_key(const qeq_plan* pl, std::vector<unsigned char>& key) {
                           pl->spc_atom, pl->spc_dpinv, pl->spc_tpart, pl->spc_s, pl->spc_scal,
                           pl->spc_sd, pl->spc_psi, (const void*)(size_t)pl->spc_nm,
                           (const void*)(size_t)pl->spc_npad, (const void*)(size_t)pl->direct, pl->np_pos,
-                          pl->np_ypart, (const void*)(size_t)pl->np_nsplit, (const void*)(size_t)pl->np_tps};
+                          pl->np_ypart, (const void*)(size_t)pl->np_nsplit, (const void*)(size_t)pl->np_tps,
+                          (const void*)(size_t)pl->ew_active, pl->ew_modes, pl->ew_w, pl->ew_sf, pl->ew_y,
+                          pl->ew_yrec, (const void*)(size_t)pl->ew_nm, (const void*)(size_t)pl->ew_fs,
+                          (const void*)(size_t)pl->ew_ms};
     key.resize(sizeof(KParams) + sizeof(ptrs) + sizeof(DeviceAxes));
     unsigned char* k = key.data();
     memcpy(k, &pl->kp, sizeof(KParams));
@@ -512,6 +517,10 @@ int next_direction(qeq_plan* pl, int parity, int init) {
 // direct pair sum of an isolated system.
 int cg_matvec(qeq_plan* pl, const double* src, int parity) {
     if (pl->direct) return launch_np_matvec(pl, src, pl->y, QEQ_MODE_CG);
+    if (pl->ew_active) {
+        QEQ_TRY(launch_ew_rec(pl, src, &pl->sc->done, false));
+        return launch_interp(pl, src, pl->y, QEQ_MODE_CG, parity);
+    }
     QEQ_TRY(launch_mesh_potential(pl, src, &pl->sc->done));
     return launch_interp(pl, src, pl->y, QEQ_MODE_CG, parity);
 }
@@ -628,6 +637,9 @@ int cg_run(qeq_plan* pl, const double* q0, double* q_out, double* energies, doub
         if (pl->direct) {
             QEQ_TRY(launch_np_matvec(pl, pl->q, pl->y, QEQ_MODE_FINAL));
             QEQ_TRY(launch_final_tail(pl, q_out, energies, forces_out));
+        } else if (pl->ew_active) {
+            QEQ_TRY(launch_ew_rec(pl, pl->q, nullptr, true));
+            QEQ_TRY(launch_final(pl, q_out, energies, forces_out));
         } else {
             QEQ_TRY(launch_mesh_potential(pl, pl->q, nullptr));
             QEQ_TRY(launch_final(pl, q_out, energies, forces_out));
@@ -674,15 +686,19 @@ int solve_impl(qeq_plan* pl, int n, const double* pos, const double* cell, const
     pl->direct = false;
     pl->np_valid = false;
     pl->geom_valid = false;
+    pl->ew_active = pl->ewald;
     QEQ_TRY(prepare(pl, n, cell, q_tot));
     QEQ_TRY(setup_geometry(pl, pos, sigma, J, chi));
     pl->geom_valid = true;
+    if (pl->ew_active) QEQ_TRY(ew_setup(pl));
     QEQ_TRY(spc_setup(pl));
     pl->fdst = pl->forces_s;
     bool conv = false;
     QEQ_TRY(cg_run(pl, q0, q, energies, forces, &conv));
     int status = cg_status(pl, conv, stats);
-    pl->tape_valid = status >= 0;
+    // the adjoint, the virial and the element potentials use the mesh: they
+    // follow mesh solves only
+    pl->tape_valid = status >= 0 && !pl->ew_active;
     return status;
 }
 
@@ -814,6 +830,7 @@ int qeq_plan_destroy(qeq_plan* pl) {
     dfree(pl->strain_tab); dfree(pl->vir_part);
     spc_free(pl);
     np_free(pl);
+    ew_free(pl);
     if (pl->elem_buf) (void)hipFree(pl->elem_buf);
     dfree(pl->sc); dfree(pl->final_dev); dfree(pl->scan_tmp);
     dfree(pl->cell_count); dfree(pl->cell_start); dfree(pl->cell_fill); dfree(pl->cell_atoms);
@@ -845,6 +862,7 @@ int qeq_solve_nonperiodic(qeq_plan* plan, int32_t n, const double* pos, const do
     if (pos && sigma && J && chi && q) {
         pl->tape_valid = false;   // the adjoint and the virial follow periodic solves only
         pl->np_valid = false;
+        pl->ew_active = false;
         pl->geom_valid = false;
         pl->spc_active = false;
         rc = np_setup(pl, n, pos, sigma, J, chi, q_tot);
@@ -876,6 +894,7 @@ int qeq_matvec(qeq_plan* plan, int32_t n, const double* pos, const double* cell,
     qeq_plan* pl = plan;
     pl->tape_valid = false;
     pl->direct = false;
+    pl->ew_active = false;
     pl->geom_valid = false;   // the operator parts below differ from a solve's
     QEQ_TRY(prepare(pl, n, cell, 0.0));
     QEQ_TRY(setup_geometry(pl, pos, sigma, nullptr, nullptr));
@@ -902,6 +921,15 @@ int qeq_use_spectral_preconditioner(qeq_plan* plan, double k_cut) {
     if (plan->stream) (void)hipStreamSynchronize(plan->stream);
     plan->spc_kc = k_cut > 0.0 ? k_cut : 0.0;
     plan->spc_active = false;
+    plan->tape_valid = false;
+    drop_graph(plan);
+    return QEQ_OK;
+}
+
+int qeq_use_ewald(qeq_plan* plan, int32_t enable) {
+    if (!plan) return QEQ_EINVAL;
+    if (plan->stream) (void)hipStreamSynchronize(plan->stream);
+    plan->ewald = enable != 0;
     plan->tape_valid = false;
     drop_graph(plan);
     return QEQ_OK;
@@ -977,6 +1005,7 @@ int qeq_descriptors(qeq_plan* plan, int32_t n, const double* pos, const double* 
         if (!sigma) return QEQ_EINVAL;
         pl->tape_valid = false;   // the geometry set-up below replaces the solve's tape
         pl->geom_valid = false;
+        pl->ew_active = false;
         QEQ_TRY(prepare(pl, n, cell, 0.0));
         QEQ_TRY(setup_geometry(pl, pos, sigma, nullptr, nullptr));
         pl->geom_valid = true;

@@ -226,6 +226,19 @@ struct qeq_plan {
     double* np_ypart = nullptr;   // [split][atom] partial products
     double* np_fpart = nullptr;   // [split][atom][3] partial force sums
     double* elem_buf = nullptr;   // 2 n_max: element source and product (caller order)
+
+    // reciprocal part by direct Ewald sums instead of the mesh (qeq_use_ewald)
+    bool ewald = false;           // requested for later periodic solves
+    bool ew_active = false;       // the current solve's operator uses it
+    int ew_nm = 0, ew_fs = 1, ew_fper = 0, ew_ms = 1, ew_mper = 0;   // modes, atom / mode splits
+    int ew_cap_m = 0, ew_cap_n = 0;
+    void* ew_modes = nullptr;     // int4 (m1, m2, m3, 0) per mode
+    double* ew_w = nullptr;       // weights 2 (4 pi / V) exp(-eta^2 k^2 / 2) / k^2
+    double* ew_sf = nullptr;      // [atom split][mode][2] structure-factor partials
+    double* ew_y = nullptr;       // [mode split][atom] potential partials
+    double* ew_f = nullptr;       // [mode split][atom][3] force partials
+    double* ew_yrec = nullptr;    // reciprocal product, sorted order
+    double* ew_frec = nullptr;    // reciprocal forces of the final product
     bool fused_inverse = true;    // fused inverse axis-2 + complex-to-real slab pass where it fits
 
     // the CG loop is replayed as a HIP graph of one chunk of iterations,
@@ -310,6 +323,11 @@ int np_setup(qeq_plan* pl, int n, const double* pos, const double* sigma, const 
 int launch_np_matvec(qeq_plan* pl, const double* src, double* dst, int mode);   // QEQ_MODE_CG / FINAL
 void np_free(qeq_plan* pl);
 int launch_final_tail(qeq_plan* pl, double* q_out, double* energies, double* forces_out);
+// direct Ewald reciprocal part (ewald.hip)
+int ew_setup(qeq_plan* pl);
+int launch_ew_rec(qeq_plan* pl, const double* src, const int* done, bool fin);
+int launch_ew_forces_add(qeq_plan* pl);
+void ew_free(qeq_plan* pl);
 // element-resolved potentials (embed.hip)
 int element_potentials_impl(qeq_plan* pl, const int32_t* species, int n_elem, double* out);
 int launch_scan(qeq_plan* pl, const int* in, int* out, int m);

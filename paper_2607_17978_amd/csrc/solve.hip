@@ -24,7 +24,8 @@ namespace {
 // dependent gathers each.)
 template <int MODE, int PC>
 __global__ __launch_bounds__(QEQ_BLOCK) void k_interp(
-    KParams k, const double* __restrict__ src, double* __restrict__ dst, const float* __restrict__ grid,
+    KParams k, const double* __restrict__ src, const double* __restrict__ yrec, double* __restrict__ dst,
+    const float* __restrict__ grid,
     const int* __restrict__ home, const float* __restrict__ wts, const float* __restrict__ dwts,
     const int* __restrict__ rowptr, const int* __restrict__ col, const float* __restrict__ kval,
     const float4* __restrict__ pdr, const double* __restrict__ dself, const double* __restrict__ Jv,
@@ -146,6 +147,7 @@ __global__ __launch_bounds__(QEQ_BLOCK) void k_interp(
     if (active && lane == 0) {
         const double vi = src[i];
         double y = v[0];
+        if (yrec) y += yrec[i];   // reciprocal part computed elsewhere (direct Ewald sums)
         if (k.parts & QEQ_PART_SELF) y += dself[i] * vi;
         if (MODE == QEQ_MODE_CG) {
             y += Jv[i] * vi;
@@ -424,7 +426,8 @@ static void interp_launch(qeq_plan* pl, const double* src, double* dst, double* 
                           hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
     const int nb = interp_blocks(pl->kp.n);   // one wave per atom
 #define QEQ_INTERP_ARGS                                                                              \
-    dim3(nb), dim3(QEQ_BLOCK), 0, pl->stream, ev0, ev1, 0, pl->kp, src, dst, pl->grid_r, pl->home, pl->wts, \
+    dim3(nb), dim3(QEQ_BLOCK), 0, pl->stream, ev0, ev1, 0, pl->kp, src,                                  \
+        (pl->ew_active ? (const double*)pl->ew_yrec : (const double*)nullptr), dst, pl->grid_r, pl->home, pl->wts, \
         pl->dwts, pl->rowptr, pl->col, pl->kval, pl->pdr, pl->dself, pl->Jv, pl->chi_raw, pl->chi,   \
         pl->sig, pl->selfgrad, pl->fdst, pl->gtmp, part, pl->sc, parity
     if (pl->kp.p == 6)
@@ -500,6 +503,7 @@ int launch_final(qeq_plan* pl, double* q_out, double* energies, double* forces_o
     double* part = part_buf(pl, 0);
     ProfScope ps(pl, PK_FINAL);
     interp_launch<QEQ_MODE_FINAL>(pl, pl->q, pl->y, part, 0, ps.start(), nullptr);
+    if (pl->ew_active) QEQ_TRY(launch_ew_forces_add(pl));   // reciprocal forces of the direct sums
     final_tail(pl, q_out, energies, forces_out, ps.stop());
     return qeq_check(hipGetLastError());
 }

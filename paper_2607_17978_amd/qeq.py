@@ -98,6 +98,8 @@ def load_library():
     L.qeq_matvec.restype = ctypes.c_int
     L.qeq_time_kernel.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_double)]
     L.qeq_time_kernel.restype = ctypes.c_int
+    L.qeq_use_ewald.argtypes = [vp, i32]
+    L.qeq_use_ewald.restype = ctypes.c_int
     L.qeq_use_spectral_preconditioner.argtypes = [vp, f64]
     L.qeq_use_spectral_preconditioner.restype = ctypes.c_int
     L.qeq_use_fused_inverse.argtypes = [vp, i32]
@@ -394,6 +396,13 @@ class Plan:
     def use_graphs(self, enable=True):
         """Replay the CG loop as a HIP graph (default) or launch kernels one by one."""
         load_library().qeq_use_graphs(self._h, 1 if enable else 0)
+
+    def use_ewald(self, enable=True):
+        """Reciprocal part by direct Ewald sums (True) or the particle mesh (False, default)."""
+        rc = load_library().qeq_use_ewald(self._h, 1 if enable else 0)
+        if rc != QEQ_OK:
+            raise QEqError(rc, strerror(rc))
+        self._last_n = None
 
     def use_spectral_preconditioner(self, k_cut=0.2):
         """Spectral (small-k Woodbury) preconditioner with cutoff k_cut in bohr^-1; 0 = Jacobi."""
