@@ -134,13 +134,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tol", type=float, default=1e-6)
-    ap.add_argument("--workload", choices=["cold32k", "warmstart", "batch", "nonperiodic", "adjoint"],
+    ap.add_argument("--workload", choices=["cold32k", "warmstart", "batch", "nonperiodic", "adjoint", "ewald"],
                     default="cold32k",
                     help="cold32k: the default cold-start solve; warmstart: the 131,072-atom "
                          "trajectory (learned vs cold vs previous-frame start); batch: 1,024 "
                          "structures in one persistent launch vs one launch sequence per structure; "
                          "nonperiodic: an isolated 16,384-atom cluster (direct pair sum); adjoint: "
-                         "the differentiated 32,768-atom workload (forward solve + adjoint backward)")
+                         "the differentiated 32,768-atom workload (forward solve + adjoint backward); ewald: "
+                         "direct Ewald sums vs the particle mesh over cell sizes")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="MB",
                     help="only run a plain device copy of this many MB (10 times) and exit: the "
                          "reference for scaling FETCH_SIZE / WRITE_SIZE counters")
@@ -179,6 +180,8 @@ def main():
         return nonperiodic_main(args, dev)
     if args.workload == "adjoint":
         return adjoint_main(args, dev)
+    if args.workload == "ewald":
+        return ewald_main(args, dev)
     s = gen.system_32k()
     T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
     pos, sig, J, chi = T(s.pos), T(s.sigma), T(s.J), T(s.chi)
@@ -544,6 +547,51 @@ def nonperiodic_main(args, dev):
         out["cpu_baseline"] = cpu_baseline_nonperiodic(n)
     print(json.dumps(out), flush=True)
     plan.close()
+
+
+def ewald_main(args, dev):
+    """Direct Ewald reciprocal sums vs the particle mesh on the lattice systems
+    of 64, 512, 4,096 and 32,768 atoms (same density, same CG); value = ms per
+    direct-Ewald solve of the 4,096-atom cell."""
+    import torch
+
+    from inputs import gen
+    from paper_2607_17978_amd import qeq
+
+    T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    systems = [gen.system_64(), gen.system_512(), gen.system_4096(), gen.system_32k()]
+    rows = []
+    for s in systems:
+        a = (T(s.pos), s.cell, T(s.sigma), T(s.J), T(s.chi), s.q_tot)
+        row = {"n_atoms": s.n, "grid": list(s.grid)}
+        for mode in ("mesh", "ewald"):
+            if mode == "ewald" and s.n > 4096:
+                continue   # the direct sums grow as N x M: minutes per solve at 32,768 atoms
+            plan = qeq.Plan(s.n, eta=2.0, r_cut=11.0, grid=s.grid, tol=args.tol, max_iter=3000,
+                            stream=torch.cuda.current_stream())
+            plan.use_ewald(mode == "ewald")
+            for _ in range(max(1, args.warmup)):
+                plan.solve(*a)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                _, _, _, st = plan.solve(*a)
+            torch.cuda.synchronize()
+            row[mode] = {"ms_per_step": round((time.perf_counter() - t0) * 1e3 / args.steps, 4),
+                         "cg_iters": st["iters"]}
+            plan.close()
+        rows.append(row)
+    ms = rows[2]["ewald"]["ms_per_step"]
+    out = {
+        "metric": METRIC, "value": ms, "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "cold QEq solve with direct Ewald reciprocal sums, 4096-atom lattice (value); "
+                               "mesh and Ewald over 64..32768 atoms", "tol": args.tol, "eta_bohr": 2.0,
+                   "r_cut_bohr": 11.0},
+        "sizes": rows,
+    }
+    print(json.dumps(out), flush=True)
 
 
 def adjoint_main(args, dev):
