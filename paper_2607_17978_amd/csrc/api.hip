@@ -2,6 +2,7 @@
 // the solve / matvec orchestration on the plan's stream, and the C ABI.
 #include <math.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -66,6 +67,10 @@ void prof_flush(qeq_plan* pl, int live_iters) {
     pl->prof_pending.clear();
 }
 
+void debug_poison(void* p, size_t bytes) {
+    if (p && bytes && getenv("QEQ_POISON_ALLOC") != nullptr) (void)hipMemset(p, 0xff, bytes);
+}
+
 namespace {
 
 const double PI = 3.14159265358979323846;
@@ -75,7 +80,9 @@ int dalloc(T** p, size_t count) {
     *p = nullptr;
     if (count == 0) count = 1;
     hipError_t e = hipMalloc((void**)p, count * sizeof(T));
-    return e == hipSuccess ? QEQ_OK : QEQ_ENOMEM;
+    if (e != hipSuccess) return QEQ_ENOMEM;
+    if (poisonable<T>) debug_poison(*p, count * sizeof(T));
+    return QEQ_OK;
 }
 
 template <typename T>

@@ -1110,6 +1110,7 @@ int grow(T** p, size_t* cap, size_t count) {
     *p = nullptr;
     *cap = 0;
     if (hipMalloc((void**)p, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) return QEQ_ENOMEM;
+    if (poisonable<T>) debug_poison(*p, count * sizeof(T));
     *cap = count;
     return QEQ_OK;
 }

@@ -178,7 +178,9 @@ __global__ void k_np_finish(int n, int nsplit, const double* __restrict__ src, c
 
 int np_alloc(double** p, size_t count) {
     *p = nullptr;
-    return hipMalloc((void**)p, sizeof(double) * (count ? count : 1)) == hipSuccess ? QEQ_OK : QEQ_ENOMEM;
+    if (hipMalloc((void**)p, sizeof(double) * (count ? count : 1)) != hipSuccess) return QEQ_ENOMEM;
+    debug_poison(*p, sizeof(double) * count);
+    return QEQ_OK;
 }
 
 }  // namespace

@@ -50,6 +50,7 @@ int element_potentials_impl(qeq_plan* pl, const int32_t* species, int n_elem, do
             pl->elem_buf = nullptr;
             return QEQ_ENOMEM;
         }
+        debug_poison(pl->elem_buf, sizeof(double) * 2 * (size_t)pl->n_max);
     }
     const int n = pl->kp.n;
     const int nb = nblocks(n);

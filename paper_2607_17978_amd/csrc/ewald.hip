@@ -164,7 +164,9 @@ template <typename T>
 int ew_alloc(T** p, size_t count) {
     if (*p) (void)hipFree(*p);
     *p = nullptr;
-    return hipMalloc((void**)p, sizeof(T) * (count ? count : 1)) == hipSuccess ? QEQ_OK : QEQ_ENOMEM;
+    if (hipMalloc((void**)p, sizeof(T) * (count ? count : 1)) != hipSuccess) return QEQ_ENOMEM;
+    if (poisonable<T>) debug_poison(*p, sizeof(T) * count);
+    return QEQ_OK;
 }
 
 }  // namespace

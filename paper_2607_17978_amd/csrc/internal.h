@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
 #include <vector>
 
 #include "common.h"
@@ -275,6 +276,14 @@ void prof_flush(qeq_plan* pl, int live_iters);
 
 // ------------------------------------------------------------------ helpers
 int qeq_check(hipError_t e);
+// With QEQ_POISON_ALLOC set in the environment, fresh floating-point device
+// buffers are filled with NaN bytes: a result that reads memory no kernel
+// wrote then turns into NaN instead of depending on what the allocator
+// handed back (a check for the tests; off by default).
+void debug_poison(void* p, size_t bytes);
+template <typename T>
+constexpr bool poisonable = std::is_floating_point<T>::value || std::is_same<T, float2>::value ||
+                            std::is_same<T, float4>::value || std::is_same<T, double2>::value;
 #define QEQ_TRY(x)                                   \
     do {                                             \
         int _rc = (x);                               \

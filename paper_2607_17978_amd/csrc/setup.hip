@@ -523,6 +523,8 @@ int launch_cells_and_pairs(qeq_plan* pl) {
             hipMalloc(&pl->kval, cap * sizeof(float)) != hipSuccess ||
             hipMalloc(&pl->pdr, cap * sizeof(float4)) != hipSuccess)
             return QEQ_ENOMEM;
+        debug_poison(pl->kval, cap * sizeof(float));
+        debug_poison(pl->pdr, cap * sizeof(float4));
         pl->nnz_cap = cap;
     }
     hipLaunchKernelGGL(k_pairs<true>, dim3(pair_blocks), dim3(QEQ_BLOCK), 0, pl->stream, k,

@@ -323,7 +323,8 @@ __global__ void k_cg_dir(KParams k, const double* __restrict__ r, const double* 
     const double beta = init ? 0.0 : rz / sc->rz[parity];
     const double res = sc->chi_norm > 0.0 ? sqrt(tot[2]) / sc->chi_norm : sqrt(tot[2]);
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < k.n) p[i] = dinv[i] * (r[i] - c) + beta * p[i];
+    // the first direction does not read p: its memory may hold anything (0 * NaN = NaN)
+    if (i < k.n) p[i] = dinv[i] * (r[i] - c) + (init ? 0.0 : beta * p[i]);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         sc->rz[parity ^ 1] = rz;
         sc->res = res;

@@ -469,7 +469,7 @@ __global__ void k_spc_dir(KParams k, const double* __restrict__ w, const double*
     const double beta = init ? 0.0 : rz / sc->rz[parity];
     const double res = sc->chi_norm > 0.0 ? sqrt(tot[2]) / sc->chi_norm : sqrt(tot[2]);
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < k.n) p[i] = w[i] - c * m1[i] + beta * p[i];
+    if (i < k.n) p[i] = w[i] - c * m1[i] + (init ? 0.0 : beta * p[i]);   // first direction: p not read
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         sc->rz[parity ^ 1] = rz;
         sc->res = res;
@@ -486,7 +486,9 @@ template <typename T>
 int spc_alloc(T** p, size_t count) {
     if (*p) (void)hipFree(*p);
     *p = nullptr;
-    return hipMalloc((void**)p, sizeof(T) * (count ? count : 1)) == hipSuccess ? QEQ_OK : QEQ_ENOMEM;
+    if (hipMalloc((void**)p, sizeof(T) * (count ? count : 1)) != hipSuccess) return QEQ_ENOMEM;
+    if (poisonable<T>) debug_poison(*p, sizeof(T) * count);
+    return QEQ_OK;
 }
 
 double* part2(qeq_plan* pl) { return pl->part + (size_t)pl->nblk_max * QEQ_NPART; }

@@ -27,7 +27,9 @@ constexpr double PI = 3.14159265358979323846;
 int alloc_doubles(double** p, size_t count) {
     if (*p) (void)hipFree(*p);
     *p = nullptr;
-    return hipMalloc((void**)p, sizeof(double) * count) == hipSuccess ? QEQ_OK : QEQ_ENOMEM;
+    if (hipMalloc((void**)p, sizeof(double) * count) != hipSuccess) return QEQ_ENOMEM;
+    debug_poison(*p, sizeof(double) * count);
+    return QEQ_OK;
 }
 
 // Real-space pair virial: one wave per atom over its CSR row (pairs are

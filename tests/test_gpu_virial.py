@@ -42,6 +42,7 @@ def gpu_virial(dev, s, rc, self_correction=True, tol=1e-8):
     from paper_2607_17978_amd import qeq
     plan = qeq.Plan(s.n, eta=ETA, r_cut=rc, grid=s.grid, tol=tol, self_correction=self_correction)
     q, en, f, st = plan.solve(T(s.pos, dev), s.cell, T(s.sigma, dev), T(s.J, dev), T(s.chi, dev), s.q_tot)
+    print(s.name, st, flush=True)
     assert st["rc"] == 0
     W = plan.virial().cpu().numpy()
     plan.close()
