@@ -134,7 +134,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tol", type=float, default=1e-6)
-    ap.add_argument("--workload", choices=["cold32k", "warmstart", "batch", "nonperiodic", "adjoint", "ewald"],
+    ap.add_argument("--workload", choices=["cold32k", "warmstart", "batch", "nonperiodic", "adjoint", "ewald", "planewave"],
                     default="cold32k",
                     help="cold32k: the default cold-start solve; warmstart: the 131,072-atom "
                          "trajectory (learned vs cold vs previous-frame start); batch: 1,024 "
@@ -182,6 +182,8 @@ def main():
         return adjoint_main(args, dev)
     if args.workload == "ewald":
         return ewald_main(args, dev)
+    if args.workload == "planewave":
+        return planewave_main(args, dev)
     s = gen.system_32k()
     T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
     pos, sig, J, chi = T(s.pos), T(s.sigma), T(s.J), T(s.chi)
@@ -589,6 +591,49 @@ def ewald_main(args, dev):
         "config": {"workload": "cold QEq solve with direct Ewald reciprocal sums, 4096-atom lattice (value); "
                                "mesh and Ewald over 64..32768 atoms", "tol": args.tol, "eta_bohr": 2.0,
                    "r_cut_bohr": 11.0},
+        "sizes": rows,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def planewave_main(args, dev):
+    """Gaussian-on-grid (plane-wave, no Ewald split) operator vs the split
+    particle mesh on the lattice systems of 4,096 and 32,768 atoms (same
+    grid, same CG, Jacobi); value = ms per plane-wave solve at 32,768 atoms."""
+    import torch
+
+    from inputs import gen
+    from paper_2607_17978_amd import qeq
+
+    T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    rows = []
+    for s in (gen.system_4096(), gen.system_32k()):
+        a = (T(s.pos), s.cell, T(s.sigma), T(s.J), T(s.chi), s.q_tot)
+        row = {"n_atoms": s.n, "grid": list(s.grid)}
+        for mode in ("mesh", "planewave"):
+            plan = qeq.Plan(s.n, eta=2.0, r_cut=11.0, grid=s.grid, tol=args.tol, max_iter=3000,
+                            stream=torch.cuda.current_stream())
+            plan.use_planewave(mode == "planewave")
+            for _ in range(max(1, args.warmup)):
+                plan.solve(*a)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                _, _, _, st = plan.solve(*a)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / args.steps
+            row[mode] = {"ms_per_step": round(ms, 4), "cg_iters": st["iters"],
+                         "ms_per_iteration": round(ms / (st["iters"] + 2), 4), "e_elec": st["e_elec"]}
+            plan.close()
+        rows.append(row)
+    ms = rows[-1]["planewave"]["ms_per_step"]
+    out = {
+        "metric": METRIC, "value": ms, "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "cold QEq solve with the Gaussian-on-grid operator (6-sigma support, no Ewald "
+                               "split), 32768-atom lattice, 192^3 (value); split mesh beside it", "tol": args.tol,
+                   "support_sigma": 6.0},
         "sizes": rows,
     }
     print(json.dumps(out), flush=True)

@@ -440,13 +440,19 @@ int prepare(qeq_plan* pl, int n, const double* cell, double q_tot) {
     }
     // with direct Ewald sums the reciprocal part is added from outside the
     // interpolation pass and is exact (no mesh self-correction)
-    k.parts = (pl->ew_active ? 0 : QEQ_PART_RECIP) | QEQ_PART_REAL | QEQ_PART_SELF | QEQ_PART_BG;
-    k.self_corr = pl->ew_active ? 0 : pl->prm.self_correction;
+    // The Gaussian-on-grid operator is the whole Coulomb operator of the
+    // periodic densities (no split: no real-space pairs, no self or
+    // background terms, no screening in the Green's function).
+    const bool ext_rec = pl->ew_active || pl->pw_active;
+    k.parts = (ext_rec ? 0 : QEQ_PART_RECIP) |
+              (pl->pw_active ? 0 : (QEQ_PART_REAL | QEQ_PART_SELF | QEQ_PART_BG));
+    k.self_corr = ext_rec ? 0 : pl->prm.self_correction;
     k.eta = pl->prm.eta;
+    k.eta_green = pl->pw_active ? 0.0 : pl->prm.eta;
     k.rc = rc;
     k.rc2 = rc * rc;
     k.green_pref = 4.0 * PI / det;
-    k.bg_pref = 2.0 * PI / det;
+    k.bg_pref = pl->pw_active ? 0.0 : 2.0 * PI / det;
     k.q_tot = q_tot;
     k.tol = pl->prm.tol;
     bool same_cell = true;
@@ -495,12 +501,14 @@ void chunk_key(const qeq_plan* pl, std::vector<unsigned char>& key) {
                           pl->np_ypart, (const void*)(size_t)pl->np_nsplit, (const void*)(size_t)pl->np_tps,
                           (const void*)(size_t)pl->ew_active, pl->ew_modes, pl->ew_w, pl->ew_sf, pl->ew_y,
                           pl->ew_yrec, (const void*)(size_t)pl->ew_nm, (const void*)(size_t)pl->ew_fs,
-                          (const void*)(size_t)pl->ew_ms};
-    key.resize(sizeof(KParams) + sizeof(ptrs) + sizeof(DeviceAxes));
+                          (const void*)(size_t)pl->ew_ms, (const void*)(size_t)pl->pw_active, pl->pw_ones,
+                          pl->pw_y, pl->pw_f};
+    key.resize(sizeof(KParams) + sizeof(ptrs) + sizeof(DeviceAxes) + sizeof(PwGeom));
     unsigned char* k = key.data();
     memcpy(k, &pl->kp, sizeof(KParams));
     memcpy(k + sizeof(KParams), ptrs, sizeof(ptrs));
     memcpy(k + sizeof(KParams) + sizeof(ptrs), &pl->axes, sizeof(DeviceAxes));
+    memcpy(k + sizeof(KParams) + sizeof(ptrs) + sizeof(DeviceAxes), &pl->pw_geom, sizeof(PwGeom));
 }
 
 void drop_graph(qeq_plan* pl) {
@@ -526,6 +534,10 @@ int cg_matvec(qeq_plan* pl, const double* src, int parity) {
     if (pl->direct) return launch_np_matvec(pl, src, pl->y, QEQ_MODE_CG);
     if (pl->ew_active) {
         QEQ_TRY(launch_ew_rec(pl, src, &pl->sc->done, false));
+        return launch_interp(pl, src, pl->y, QEQ_MODE_CG, parity);
+    }
+    if (pl->pw_active) {
+        QEQ_TRY(launch_pw_rec(pl, src, &pl->sc->done, false));
         return launch_interp(pl, src, pl->y, QEQ_MODE_CG, parity);
     }
     QEQ_TRY(launch_mesh_potential(pl, src, &pl->sc->done));
@@ -647,6 +659,9 @@ int cg_run(qeq_plan* pl, const double* q0, double* q_out, double* energies, doub
         } else if (pl->ew_active) {
             QEQ_TRY(launch_ew_rec(pl, pl->q, nullptr, true));
             QEQ_TRY(launch_final(pl, q_out, energies, forces_out));
+        } else if (pl->pw_active) {
+            QEQ_TRY(launch_pw_rec(pl, pl->q, nullptr, true));
+            QEQ_TRY(launch_final(pl, q_out, energies, forces_out));
         } else {
             QEQ_TRY(launch_mesh_potential(pl, pl->q, nullptr));
             QEQ_TRY(launch_final(pl, q_out, energies, forces_out));
@@ -694,18 +709,20 @@ int solve_impl(qeq_plan* pl, int n, const double* pos, const double* cell, const
     pl->np_valid = false;
     pl->geom_valid = false;
     pl->ew_active = pl->ewald;
+    pl->pw_active = pl->planewave;
     QEQ_TRY(prepare(pl, n, cell, q_tot));
     QEQ_TRY(setup_geometry(pl, pos, sigma, J, chi));
     pl->geom_valid = true;
     if (pl->ew_active) QEQ_TRY(ew_setup(pl));
+    if (pl->pw_active) QEQ_TRY(pw_setup(pl));
     QEQ_TRY(spc_setup(pl));
     pl->fdst = pl->forces_s;
     bool conv = false;
     QEQ_TRY(cg_run(pl, q0, q, energies, forces, &conv));
     int status = cg_status(pl, conv, stats);
-    // the adjoint, the virial and the element potentials use the mesh: they
-    // follow mesh solves only
-    pl->tape_valid = status >= 0 && !pl->ew_active;
+    // the adjoint, the virial and the element potentials use the split
+    // mesh operator: they follow its solves only
+    pl->tape_valid = status >= 0 && !pl->ew_active && !pl->pw_active;
     return status;
 }
 
@@ -838,6 +855,7 @@ int qeq_plan_destroy(qeq_plan* pl) {
     spc_free(pl);
     np_free(pl);
     ew_free(pl);
+    pw_free(pl);
     if (pl->elem_buf) (void)hipFree(pl->elem_buf);
     dfree(pl->sc); dfree(pl->final_dev); dfree(pl->scan_tmp);
     dfree(pl->cell_count); dfree(pl->cell_start); dfree(pl->cell_fill); dfree(pl->cell_atoms);
@@ -870,6 +888,7 @@ int qeq_solve_nonperiodic(qeq_plan* plan, int32_t n, const double* pos, const do
         pl->tape_valid = false;   // the adjoint and the virial follow periodic solves only
         pl->np_valid = false;
         pl->ew_active = false;
+        pl->pw_active = false;
         pl->geom_valid = false;
         pl->spc_active = false;
         rc = np_setup(pl, n, pos, sigma, J, chi, q_tot);
@@ -902,6 +921,7 @@ int qeq_matvec(qeq_plan* plan, int32_t n, const double* pos, const double* cell,
     pl->tape_valid = false;
     pl->direct = false;
     pl->ew_active = false;
+    pl->pw_active = false;
     pl->geom_valid = false;   // the operator parts below differ from a solve's
     QEQ_TRY(prepare(pl, n, cell, 0.0));
     QEQ_TRY(setup_geometry(pl, pos, sigma, nullptr, nullptr));
@@ -937,6 +957,22 @@ int qeq_use_ewald(qeq_plan* plan, int32_t enable) {
     if (!plan) return QEQ_EINVAL;
     if (plan->stream) (void)hipStreamSynchronize(plan->stream);
     plan->ewald = enable != 0;
+    if (plan->ewald) plan->planewave = false;
+    plan->tape_valid = false;
+    drop_graph(plan);
+    return QEQ_OK;
+}
+
+int qeq_use_planewave(qeq_plan* plan, int32_t enable, double support) {
+    if (!plan) return QEQ_EINVAL;
+    if (support == 0.0) support = 6.0;
+    if (enable && !(support >= 3.0 && support <= 12.0)) return QEQ_EINVAL;
+    if (plan->stream) (void)hipStreamSynchronize(plan->stream);
+    plan->planewave = enable != 0;
+    if (plan->planewave) {
+        plan->ewald = false;
+        plan->pw_support = support;
+    }
     plan->tape_valid = false;
     drop_graph(plan);
     return QEQ_OK;
@@ -1013,6 +1049,7 @@ int qeq_descriptors(qeq_plan* plan, int32_t n, const double* pos, const double* 
         pl->tape_valid = false;   // the geometry set-up below replaces the solve's tape
         pl->geom_valid = false;
         pl->ew_active = false;
+        pl->pw_active = false;
         QEQ_TRY(prepare(pl, n, cell, 0.0));
         QEQ_TRY(setup_geometry(pl, pos, sigma, nullptr, nullptr));
         pl->geom_valid = true;

@@ -1453,6 +1453,7 @@ int qeq_solve_batched(qeq_plan* plan, int32_t n_struct, const int32_t* atom_offs
     plan->np_valid = false;
     plan->geom_valid = false;
     plan->ew_active = false;
+    plan->pw_active = false;
     return batched_impl(plan, n_struct, atom_offsets, pos, cells, sigma, J, chi, q_tot, q0, q, energies, forces,
                         stats);
 }

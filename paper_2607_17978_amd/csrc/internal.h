@@ -49,12 +49,24 @@ struct KParams {
     double M[6];              // (H H^T)^-1: 11 22 33 12 13 23
     double vol;
     double eta;
+    double eta_green;         // screening width in the mesh Green's function (0: plain 4 pi / k^2)
     double rc, rc2;
     double green_pref;        // 4 pi / V
     double bg_pref;           // 2 pi / V
     double q_tot;
     double c_eta;             // (4 pi / V) sum_{k != 0} exp(-eta^2 k^2 / 2) / k^2
     double tol;
+};
+
+// Geometry of the Gaussian-on-grid (plane-wave) operator, in grid steps:
+// a grid point at integer offsets t from the atom's cell, d = t - frac(u),
+// lies at squared distance d^T G d from the atom.
+struct PwGeom {
+    float G[6];       // (a_a . a_b) / (K_a K_b): 11 22 33 12 13 23 (a_a = cell rows)
+    float Ginv[6];    // G^-1 in the same order (diagonal: squared extents per unit radius)
+    float HK[9];      // H[a][c] / K_a: Cartesian offset of one grid step along axis a
+    float c2;         // (support radius / sigma)^2
+    float wpref;      // dV / (2 pi)^{3/2}: theta = wpref / sigma^3 exp(-d^T G d / (2 sigma^2))
 };
 
 // Scalars that live on the device between CG kernels.
@@ -240,6 +252,16 @@ struct qeq_plan {
     double* ew_f = nullptr;       // [mode split][atom][3] force partials
     double* ew_yrec = nullptr;    // reciprocal product, sorted order
     double* ew_frec = nullptr;    // reciprocal forces of the final product
+    // Gaussian-on-grid (plane-wave) operator instead of the split (qeq_use_planewave)
+    bool planewave = false;       // requested for later periodic solves
+    bool pw_active = false;       // the current solve's operator uses it
+    double pw_support = 6.0;      // support radius in units of sigma_i
+    PwGeom pw_geom{};
+    int pw_cap_n = 0, pw_cap_k = 0;
+    float* pw_ones = nullptr;     // unit moduli for the Green's function pass
+    double* pw_y = nullptr;       // operator product, sorted order
+    double* pw_f = nullptr;       // forces of the final product, sorted order
+    double* pw_smax = nullptr;    // per-block maxima of sigma (host read once per set-up)
     bool fused_inverse = true;    // fused inverse axis-2 + complex-to-real slab pass where it fits
 
     // the CG loop is replayed as a HIP graph of one chunk of iterations,
@@ -337,6 +359,11 @@ int ew_setup(qeq_plan* pl);
 int launch_ew_rec(qeq_plan* pl, const double* src, const int* done, bool fin);
 int launch_ew_forces_add(qeq_plan* pl);
 void ew_free(qeq_plan* pl);
+// Gaussian-on-grid operator (planewave.hip)
+int pw_setup(qeq_plan* pl);
+int launch_pw_rec(qeq_plan* pl, const double* src, const int* done, bool fin);
+int launch_pw_forces_add(qeq_plan* pl);
+void pw_free(qeq_plan* pl);
 // element-resolved potentials (embed.hip)
 int element_potentials_impl(qeq_plan* pl, const int32_t* species, int n_elem, double* out);
 int launch_scan(qeq_plan* pl, const int* in, int* out, int m);
@@ -348,6 +375,9 @@ int launch_mesh_potential(qeq_plan* pl, const double* src, const int* done);
 size_t qeq_mesh_max_smem(const KParams& k);
 // Inverse transforms only (grid_c already holds a spectrum) -> grid_r.
 int launch_mesh_inverse(qeq_plan* pl);
+// Passes 2-5 (axis-2 FFT, axis-1 FFT + Green's function + inverse, inverse
+// axes 2 and 3) on a half spectrum that another pass 1 wrote into grid_c.
+int launch_mesh_from_spectrum(qeq_plan* pl, const int* done);
 // One launch of a single mesh pass (PK_SPREAD_R2C from src, or PK_C2R).
 int launch_mesh_stage(qeq_plan* pl, int kind, const double* src);
 int launch_write_green(qeq_plan* pl);

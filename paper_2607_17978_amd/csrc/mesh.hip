@@ -296,7 +296,7 @@ __device__ __forceinline__ float green_value(const KParams& k, int m1, int m2, i
     const float q = (float)k.M[0] * x1 * x1 + (float)k.M[1] * x2 * x2 + (float)k.M[2] * x3 * x3 +
                     2.0f * ((float)k.M[3] * x1 * x2 + (float)k.M[4] * x1 * x3 + (float)k.M[5] * x2 * x3);
     const float k2 = 39.478417604357434475f * q;   // (2 pi)^2
-    const float eta = (float)k.eta;
+    const float eta = (float)k.eta_green;
     const float g = (float)k.green_pref * expf(-0.5f * eta * eta * k2) / k2;
     return g * b1[m1] * b2[m2] * b3[m3];
 }
@@ -663,17 +663,20 @@ int cols_pass(qeq_plan* pl, int mode, double* epart, const int* done) {
     dim3 g(k.K3h * k.ntile), b(NT);
     const size_t sh = smem_cols(k);
     ProfScope ps(pl, PK_COLS_GREEN);
+    // Gaussian-on-grid densities carry no B-spline moduli
+    const float* b1 = pl->pw_active ? pl->pw_ones : pl->bmod[0];
+    const float* b2 = pl->pw_active ? pl->pw_ones : pl->bmod[1];
+    const float* b3 = pl->pw_active ? pl->pw_ones : pl->bmod[2];
 #define X(KK, TT)                                                                                  \
     if (k.K1 == KK && k.TW == TT) {                                                                \
         hipExtLaunchKernelGGL((k_fft_cols<KK, TT>), g, b, sh, pl->stream, ps.start(), ps.stop(), 0, k,   \
-                              pl->axes.ax[0], pl->grid_c, pl->bmod[0], pl->bmod[1], pl->bmod[2], mode, \
-                              epart, done);                                                          \
+                              pl->axes.ax[0], pl->grid_c, b1, b2, b3, mode, epart, done);           \
         return qeq_check(hipGetLastError());                                                       \
     }
     QEQ_FOR_EACH_SIZE(X)
 #undef X
     hipExtLaunchKernelGGL((k_fft_cols<0, 0>), g, b, sh, pl->stream, ps.start(), ps.stop(), 0, k, pl->axes.ax[0],
-                          pl->grid_c, pl->bmod[0], pl->bmod[1], pl->bmod[2], mode, epart, done);
+                          pl->grid_c, b1, b2, b3, mode, epart, done);
     return qeq_check(hipGetLastError());
 }
 
@@ -764,6 +767,12 @@ size_t qeq_mesh_max_smem(const KParams& k) {
 
 int launch_mesh_potential(qeq_plan* pl, const double* src, const int* done) {
     QEQ_TRY(spread_pass(pl, src, done));
+    QEQ_TRY(rows_pass(pl, 0, done));
+    QEQ_TRY(cols_pass(pl, MESH_FWD | MESH_GREEN | MESH_INV, nullptr, done));
+    return inverse_tail(pl, done);
+}
+
+int launch_mesh_from_spectrum(qeq_plan* pl, const int* done) {
     QEQ_TRY(rows_pass(pl, 0, done));
     QEQ_TRY(cols_pass(pl, MESH_FWD | MESH_GREEN | MESH_INV, nullptr, done));
     return inverse_tail(pl, done);

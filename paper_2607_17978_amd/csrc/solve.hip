@@ -428,7 +428,7 @@ static void interp_launch(qeq_plan* pl, const double* src, double* dst, double* 
     const int nb = interp_blocks(pl->kp.n);   // one wave per atom
 #define QEQ_INTERP_ARGS                                                                              \
     dim3(nb), dim3(QEQ_BLOCK), 0, pl->stream, ev0, ev1, 0, pl->kp, src,                                  \
-        (pl->ew_active ? (const double*)pl->ew_yrec : (const double*)nullptr), dst, pl->grid_r, pl->home, pl->wts, \
+        (pl->ew_active ? (const double*)pl->ew_yrec : pl->pw_active ? (const double*)pl->pw_y : nullptr), dst, pl->grid_r, pl->home, pl->wts, \
         pl->dwts, pl->rowptr, pl->col, pl->kval, pl->pdr, pl->dself, pl->Jv, pl->chi_raw, pl->chi,   \
         pl->sig, pl->selfgrad, pl->fdst, pl->gtmp, part, pl->sc, parity
     if (pl->kp.p == 6)
@@ -505,6 +505,7 @@ int launch_final(qeq_plan* pl, double* q_out, double* energies, double* forces_o
     ProfScope ps(pl, PK_FINAL);
     interp_launch<QEQ_MODE_FINAL>(pl, pl->q, pl->y, part, 0, ps.start(), nullptr);
     if (pl->ew_active) QEQ_TRY(launch_ew_forces_add(pl));   // reciprocal forces of the direct sums
+    if (pl->pw_active) QEQ_TRY(launch_pw_forces_add(pl));   // forces of the Gaussian-on-grid operator
     final_tail(pl, q_out, energies, forces_out, ps.stop());
     return qeq_check(hipGetLastError());
 }

@@ -100,6 +100,8 @@ def load_library():
     L.qeq_time_kernel.restype = ctypes.c_int
     L.qeq_use_ewald.argtypes = [vp, i32]
     L.qeq_use_ewald.restype = ctypes.c_int
+    L.qeq_use_planewave.argtypes = [vp, i32, ctypes.c_double]
+    L.qeq_use_planewave.restype = ctypes.c_int
     L.qeq_use_spectral_preconditioner.argtypes = [vp, f64]
     L.qeq_use_spectral_preconditioner.restype = ctypes.c_int
     L.qeq_use_fused_inverse.argtypes = [vp, i32]
@@ -400,6 +402,14 @@ class Plan:
     def use_ewald(self, enable=True):
         """Reciprocal part by direct Ewald sums (True) or the particle mesh (False, default)."""
         rc = load_library().qeq_use_ewald(self._h, 1 if enable else 0)
+        if rc != QEQ_OK:
+            raise QEqError(rc, strerror(rc))
+        self._last_n = None
+
+    def use_planewave(self, enable=True, support=6.0):
+        """Gaussian-on-grid operator without the Ewald split (True) or the
+        particle mesh (False, default); support: cut radius in sigma_i."""
+        rc = load_library().qeq_use_planewave(self._h, 1 if enable else 0, float(support))
         if rc != QEQ_OK:
             raise QEqError(rc, strerror(rc))
         self._last_n = None
