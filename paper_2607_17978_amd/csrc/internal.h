@@ -63,7 +63,9 @@ struct KParams {
 // lies at squared distance d^T G d from the atom.
 struct PwGeom {
     float G[6];       // (a_a . a_b) / (K_a K_b): 11 22 33 12 13 23 (a_a = cell rows)
-    float Ginv[6];    // G^-1 in the same order (diagonal: squared extents per unit radius)
+    float ext1;       // sqrt((G^-1)_11): axis-1 extent of d^T G d <= 1
+    float inv_det23;  // 1 / (G22 G33 - G23^2)
+    float ext2, ext3; // sqrt(G33 / det23), sqrt(G22 / det23): in-plane extents per unit radius
     float HK[9];      // H[a][c] / K_a: Cartesian offset of one grid step along axis a
     float c2;         // (support radius / sigma)^2
     float wpref;      // dV / (2 pi)^{3/2}: theta = wpref / sigma^3 exp(-d^T G d / (2 sigma^2))

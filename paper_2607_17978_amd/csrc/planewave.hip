@@ -49,19 +49,18 @@ __device__ __forceinline__ int pw_wrap(int g, int K) {
 
 // Cross-section of the ellipsoid d^T G d <= R2 with the grid plane at offset
 // d1 along axis 1: centre (x2, x3) and half-extents (e2, e3) of its bounding
-// box; false when the plane misses it.
+// box; false when the plane misses it.  (The 2x2 block of G and the extent
+// factors are constants of the cell, precomputed on the host.)
 __device__ __forceinline__ bool pw_section(const PwGeom& g, float d1, float R2, float& x2, float& x3, float& e2,
                                            float& e3) {
-    const float G22 = g.G[1], G33 = g.G[2], G23 = g.G[5];
-    const float det = G22 * G33 - G23 * G23;
     const float b2 = g.G[3] * d1, b3 = g.G[4] * d1;
-    x2 = -(G33 * b2 - G23 * b3) / det;
-    x3 = -(G22 * b3 - G23 * b2) / det;
+    x2 = -(g.G[2] * b2 - g.G[5] * b3) * g.inv_det23;
+    x3 = -(g.G[1] * b3 - g.G[5] * b2) * g.inv_det23;
     const float rho2 = R2 - (g.G[0] * d1 * d1 + b2 * x2 + b3 * x3);
     if (!(rho2 >= 0.f)) return false;
     const float rho = sqrtf(rho2);
-    e2 = rho * sqrtf(G33 / det);
-    e3 = rho * sqrtf(G22 / det);
+    e2 = rho * g.ext2;
+    e3 = rho * g.ext3;
     return true;
 }
 
@@ -101,7 +100,7 @@ __device__ __forceinline__ PwAtom pw_atom(const KParams& k, const PwGeom& g, con
 template <typename Body>
 __device__ __forceinline__ void pw_walk(const KParams& k, const PwGeom& g, const PwAtom& a, int lane, Body body) {
     if (!(a.R2 > 0.f)) return;
-    const float e1 = sqrtf(a.R2 * g.Ginv[0]);
+    const float e1 = sqrtf(a.R2) * g.ext1;
     const int t1lo = (int)ceilf(a.du[0] - e1), t1hi = (int)floorf(a.du[0] + e1);
     for (int t1 = t1lo; t1 <= t1hi; ++t1) {
         const float d1 = (float)t1 - a.du[0];
@@ -115,7 +114,10 @@ __device__ __forceinline__ void pw_walk(const KParams& k, const PwGeom& g, const
         const float c1 = g.G[0] * d1 * d1, l2 = 2.f * g.G[3] * d1, l3 = 2.f * g.G[4] * d1;
         const int nbox = n2 * n3;
         const int dq = 64 / n3, dr = 64 - dq * n3;
-        int qq = lane / n3, rr = lane - (lane / n3) * n3;
+        // lane / n3 through the reciprocal: exact for lane < 64 (the quotient
+        // is at least 0.5 / n3 away from an integer)
+        int qq = (int)(((float)lane + 0.5f) * (1.0f / (float)n3));
+        int rr = lane - qq * n3;
         for (int j = lane; j < nbox; j += 64) {
             const int t2 = t2lo + qq, t3 = t3lo + rr;
             const float d2 = (float)t2 - a.du[1], d3 = (float)t3 - a.du[2];
@@ -155,32 +157,17 @@ __global__ __launch_bounds__(PW_NT) void k_pw_spread(KParams k, PwGeom g, const 
         const PwAtom a = pw_atom(k, g, frac, s, i);
         const float amp = (float)(q * (double)g.wpref / (s * s * s));
         pw_walk(k, g, a, lane, [&](size_t idx, float Q, float, float, float) {
-            unsafeAtomicAdd(grid + idx, amp * exp2f(-Q * a.lsc));
+            unsafeAtomicAdd(grid + idx, amp * __builtin_amdgcn_exp2f(-Q * a.lsc));
         });
     }
 }
 
-// Real-to-complex transform along axis 3 of the real grid, block = (g1, tile
-// of TW rows g2), two real rows packed into one complex column; the half
-// spectra are written transposed (C[m3][g1][g2]) as by the spline spread.
-__global__ __launch_bounds__(PW_NT) void k_pw_r2c(KParams k, FftAxis ax3, const float* __restrict__ R,
-                                                float2* __restrict__ C, const int* __restrict__ done) {
-    if (done && *done) return;
-    extern __shared__ float2 sm[];
+// Axis-3 FFT of the tile in LDS (two real rows packed per complex column,
+// acc[g3][row] viewed as buf[g3][row pair]) and the half spectra written
+// transposed, C[m3][g1][g2] (m2 contiguous).
+__device__ __forceinline__ void pw_tile_r2c(const KParams& k, const FftAxis& ax3, float2* buf, const float2* tw,
+                                            int g1, int g20, float2* __restrict__ C, int tid) {
     const int K1 = k.K1, K2 = k.K2, K3 = k.K3, TW = k.TWS, ncol = TW >> 1;
-    float2* tw = sm;
-    float2* buf = sm + K3;
-    float* acc = reinterpret_cast<float*>(buf);
-    const int tid = threadIdx.x;
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int g1 = blk / k.ntile_s;
-    const int g20 = (blk - g1 * k.ntile_s) * TW;
-    for (int t = tid; t < K3; t += PW_NT) tw[t] = ax3.tw[t];
-    for (int e = tid; e < TW * K3; e += PW_NT) {
-        const int r = e / K3, g3 = e - r * K3;
-        acc[g3 * TW + r] = R[((size_t)g1 * K2 + g20 + r) * K3 + g3];
-    }
-    __syncthreads();
     int twl = 0;
     while ((1 << twl) < TW) ++twl;
     fft_lds(buf, ax3, twl - 1, tw, false, tid, PW_NT);
@@ -204,6 +191,37 @@ __global__ __launch_bounds__(PW_NT) void k_pw_r2c(KParams k, FftAxis ax3, const 
     }
 }
 
+// Real-to-complex transform along axis 3 of the real grid, block = (g1, tile
+// of TW rows g2), two real rows packed into one complex column; the half
+// spectra are written transposed (C[m3][g1][g2]) as by the spline spread.
+__global__ __launch_bounds__(PW_NT) void k_pw_r2c(KParams k, FftAxis ax3, const float* __restrict__ R,
+                                                float2* __restrict__ C, const int* __restrict__ done) {
+    if (done && *done) return;
+    extern __shared__ float2 sm[];
+    const int K2 = k.K2, K3 = k.K3, TW = k.TWS;
+    float2* tw = sm;
+    float2* buf = sm + K3;
+    float* acc = reinterpret_cast<float*>(buf);
+    const int tid = threadIdx.x;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int g1 = blk / k.ntile_s;
+    const int g20 = (blk - g1 * k.ntile_s) * TW;
+    for (int t = tid; t < K3; t += PW_NT) tw[t] = ax3.tw[t];
+    // row index fastest: consecutive lanes write consecutive LDS words (the
+    // transposed [g3][row] layout the FFT needs); each lane loads 4 values
+    // of its row (K3 % 4 == 0)
+    for (int e = tid; e < TW * (K3 >> 2); e += PW_NT) {
+        const int r = e & (TW - 1), c4 = e / TW;
+        const float4 x = *reinterpret_cast<const float4*>(R + ((size_t)g1 * K2 + g20 + r) * K3 + 4 * c4);
+        acc[(4 * c4) * TW + r] = x.x;
+        acc[(4 * c4 + 1) * TW + r] = x.y;
+        acc[(4 * c4 + 2) * TW + r] = x.z;
+        acc[(4 * c4 + 3) * TW + r] = x.w;
+    }
+    __syncthreads();
+    pw_tile_r2c(k, ax3, buf, tw, g1, g20, C, tid);
+}
+
 // y_i = sum_g theta_i(g) phi(g); with FIN the forces of that product for the
 // charges src (both sorted order), one wave per atom.
 template <bool FIN>
@@ -224,7 +242,7 @@ __global__ __launch_bounds__(PW_NT) void k_pw_interp(KParams k, PwGeom g, const 
             s = sig[i];
             const PwAtom a = pw_atom(k, g, frac, s, i);
             pw_walk(k, g, a, lane, [&](size_t idx, float Q, float d1, float d2, float d3) {
-                const float t = exp2f(-Q * a.lsc) * grid[idx];
+                const float t = __builtin_amdgcn_exp2f(-Q * a.lsc) * grid[idx];
                 v[0] += t;
                 if (FIN) {
                     v[1] += t * d1;
@@ -342,10 +360,14 @@ int pw_setup(qeq_plan* pl) {
     if (!invert3(G, Gi)) return QEQ_EINVAL;
     PwGeom& g = pl->pw_geom;
     const int o[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
-    for (int t = 0; t < 6; ++t) {
-        g.G[t] = (float)G[o[t][0] * 3 + o[t][1]];
-        g.Ginv[t] = (float)Gi[o[t][0] * 3 + o[t][1]];
-    }
+    for (int t = 0; t < 6; ++t) g.G[t] = (float)G[o[t][0] * 3 + o[t][1]];
+    // extent of d^T G d <= 1 along axis a: sqrt((G^-1)_aa); plane sections
+    // use the inverse of the (2, 3) block of G
+    const double det23 = G[4] * G[8] - G[5] * G[7];
+    g.ext1 = (float)sqrt(Gi[0]);
+    g.inv_det23 = (float)(1.0 / det23);
+    g.ext2 = (float)sqrt(G[8] / det23);
+    g.ext3 = (float)sqrt(G[4] / det23);
     for (int a = 0; a < 3; ++a)
         for (int c = 0; c < 3; ++c) g.HK[a * 3 + c] = (float)(k.H[a * 3 + c] / Kd[a]);
     g.c2 = (float)(pl->pw_support * pl->pw_support);
@@ -367,22 +389,8 @@ int pw_setup(qeq_plan* pl) {
     return QEQ_OK;
 }
 
-// y = A src into pw_y (sorted order); with fin also the forces into pw_f.
-int launch_pw_rec(qeq_plan* pl, const double* src, const int* done, bool fin) {
+static int pw_interp_launch(qeq_plan* pl, const double* src, const int* done, bool fin, int nb) {
     const KParams& k = pl->kp;
-    const size_t nreal = (size_t)k.K1 * k.K2 * k.K3;   // a multiple of 4 (K_a % 4 == 0)
-    hipLaunchKernelGGL(k_pw_zero, dim3((unsigned)((nreal / 4 + PW_NT - 1) / PW_NT)), dim3(PW_NT), 0, pl->stream,
-                       (float4*)pl->grid_r, nreal / 4, done);
-    const int nb = pw_blocks(k.n);
-    hipLaunchKernelGGL(k_pw_spread, dim3(nb), dim3(PW_NT), 0, pl->stream, k, pl->pw_geom, src, pl->frac, pl->sig,
-                       pl->grid_r, done);
-    const size_t sh = sizeof(float2) * ((size_t)k.K3 + (size_t)k.K3 * (k.TWS / 2));
-    if (sh > 65536)
-        QEQ_HIP(hipFuncSetAttribute((const void*)k_pw_r2c, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
-    hipLaunchKernelGGL(k_pw_r2c, dim3(k.K1 * k.ntile_s), dim3(PW_NT), sh, pl->stream, k, pl->axes.ax[2],
-                       pl->grid_r, pl->grid_c, done);
-    QEQ_TRY(qeq_check(hipGetLastError()));
-    QEQ_TRY(launch_mesh_from_spectrum(pl, done));
     if (fin)
         hipLaunchKernelGGL(k_pw_interp<true>, dim3(nb), dim3(PW_NT), 0, pl->stream, k, pl->pw_geom, src, pl->frac,
                            pl->sig, pl->grid_r, pl->pw_y, pl->pw_f, done);
@@ -390,6 +398,25 @@ int launch_pw_rec(qeq_plan* pl, const double* src, const int* done, bool fin) {
         hipLaunchKernelGGL(k_pw_interp<false>, dim3(nb), dim3(PW_NT), 0, pl->stream, k, pl->pw_geom, src, pl->frac,
                            pl->sig, pl->grid_r, pl->pw_y, pl->pw_f, done);
     return qeq_check(hipGetLastError());
+}
+
+// y = A src into pw_y (sorted order); with fin also the forces into pw_f.
+int launch_pw_rec(qeq_plan* pl, const double* src, const int* done, bool fin) {
+    const KParams& k = pl->kp;
+    const size_t sh = sizeof(float2) * ((size_t)k.K3 + (size_t)k.K3 * (k.TWS / 2));
+    const int nb = pw_blocks(k.n);
+    const size_t nreal = (size_t)k.K1 * k.K2 * k.K3;   // a multiple of 4 (K_a % 4 == 0)
+    hipLaunchKernelGGL(k_pw_zero, dim3((unsigned)((nreal / 4 + PW_NT - 1) / PW_NT)), dim3(PW_NT), 0, pl->stream,
+                       (float4*)pl->grid_r, nreal / 4, done);
+    hipLaunchKernelGGL(k_pw_spread, dim3(nb), dim3(PW_NT), 0, pl->stream, k, pl->pw_geom, src, pl->frac, pl->sig,
+                       pl->grid_r, done);
+    if (sh > 65536)
+        QEQ_HIP(hipFuncSetAttribute((const void*)k_pw_r2c, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
+    hipLaunchKernelGGL(k_pw_r2c, dim3(k.K1 * k.ntile_s), dim3(PW_NT), sh, pl->stream, k, pl->axes.ax[2],
+                       pl->grid_r, pl->grid_c, done);
+    QEQ_TRY(qeq_check(hipGetLastError()));
+    QEQ_TRY(launch_mesh_from_spectrum(pl, done));
+    return pw_interp_launch(pl, src, done, fin, nb);
 }
 
 int launch_pw_forces_add(qeq_plan* pl) {

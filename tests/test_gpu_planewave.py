@@ -130,3 +130,4 @@ def test_planewave_support_and_refusals(dev):
     plan.backward(T(np.ones(s.n), dev))
     assert np.abs(qm.cpu().numpy() - qa.cpu().numpy()).max() <= 1e-5
     plan.close()
+
