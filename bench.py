@@ -134,7 +134,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tol", type=float, default=1e-6)
-    ap.add_argument("--workload", choices=["cold32k", "warmstart", "batch", "nonperiodic", "adjoint", "ewald", "planewave"],
+    ap.add_argument("--workload", choices=["cold32k", "warmstart", "batch", "nonperiodic", "adjoint", "ewald", "planewave", "sqnm"],
                     default="cold32k",
                     help="cold32k: the default cold-start solve; warmstart: the 131,072-atom "
                          "trajectory (learned vs cold vs previous-frame start); batch: 1,024 "
@@ -184,6 +184,8 @@ def main():
         return ewald_main(args, dev)
     if args.workload == "planewave":
         return planewave_main(args, dev)
+    if args.workload == "sqnm":
+        return sqnm_main(args, dev)
     s = gen.system_32k()
     T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
     pos, sig, J, chi = T(s.pos), T(s.sigma), T(s.J), T(s.chi)
@@ -634,6 +636,48 @@ def planewave_main(args, dev):
         "config": {"workload": "cold QEq solve with the Gaussian-on-grid operator (6-sigma support, no Ewald "
                                "split), 32768-atom lattice, 192^3 (value); split mesh beside it", "tol": args.tol,
                    "support_sigma": 6.0},
+        "sizes": rows,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def sqnm_main(args, dev):
+    """SQNM (stabilised quasi-Newton minimisation) vs projected CG on the
+    4,096- and 32,768-atom lattice systems (same mesh operator, Jacobi
+    metric / preconditioner); value = ms per SQNM solve at 32,768 atoms."""
+    import torch
+
+    from inputs import gen
+    from paper_2607_17978_amd import qeq
+
+    T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    rows = []
+    for s in (gen.system_4096(), gen.system_32k()):
+        a = (T(s.pos), s.cell, T(s.sigma), T(s.J), T(s.chi), s.q_tot)
+        row = {"n_atoms": s.n, "grid": list(s.grid)}
+        for solver in ("cg", "sqnm"):
+            plan = qeq.Plan(s.n, eta=2.0, r_cut=11.0, grid=s.grid, tol=args.tol, max_iter=3000,
+                            stream=torch.cuda.current_stream())
+            plan.use_sqnm(solver == "sqnm")
+            for _ in range(max(1, args.warmup)):
+                plan.solve(*a)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                _, _, _, st = plan.solve(*a)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / args.steps
+            row[solver] = {"ms_per_step": round(ms, 4), "iters": st["iters"],
+                           "true_rel_resid": st["true_rel_resid"], "e_qeq": st["e_qeq"]}
+            plan.close()
+        rows.append(row)
+    ms = rows[-1]["sqnm"]["ms_per_step"]
+    out = {
+        "metric": METRIC, "value": ms, "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "cold QEq solve by SQNM (history 10, Jacobi metric), 32768-atom lattice, 192^3 "
+                               "(value); projected CG beside it", "tol": args.tol},
         "sizes": rows,
     }
     print(json.dumps(out), flush=True)

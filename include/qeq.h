@@ -363,6 +363,30 @@ int qeq_use_ewald(qeq_plan* plan, int32_t enable);
    rounding, not bit for bit. */
 int qeq_use_planewave(qeq_plan* plan, int32_t enable, double support);
 
+/* Solver of later qeq_solve calls on this plan: enable != 0 stabilised
+   quasi-Newton minimisation (SQNM; the paper's alternative to conjugate
+   gradients in its solver comparison) of E_QEq on the plane
+   sum(q) = Q_tot instead of projected CG; enable = 0 (default) CG.  The
+   minimiser works in the Jacobi metric (D_i = J_i + 1/(sigma_i sqrt(pi))),
+   keeps the last `history` displacement / gradient-difference pairs
+   (0 selects 10; 1 .. 16 accepted, else QEQ_EINVAL), builds the Hessian in
+   their well-conditioned span (overlap eigenvalues above 1e-4 of the
+   largest), takes quasi-Newton steps there and scaled steepest-descent steps
+   in the complement, undoes a step that raises the energy (halving the
+   step scale and clearing the history; energy changes below 1e-6 of the
+   energy's terms count as rounding) and stops at the relative residual
+   max(tol, 1e-7): its gradient is the FP32 operator's, whose residual floor
+   is near 1e-7 (the CG path's true-residual check allows 2 max(tol, 1e-7)
+   for the same reason).  One host synchronisation per iteration (the m x m
+   eigenproblems run on the host); no graph replay.  The charges, energies,
+   forces, mu and true residual come from the same final pass as after CG;
+   stats->iters counts SQNM iterations, undone ones included.  Works with
+   the mesh, Ewald and Gaussian-on-grid operators; the spectral
+   preconditioner is not used by it; the tape for qeq_backward / qeq_virial
+   / qeq_element_potentials is kept (the adjoint solve itself stays CG).
+   qeq_solve_nonperiodic and qeq_solve_batched keep CG. */
+int qeq_use_sqnm(qeq_plan* plan, int32_t enable, int32_t history);
+
 /* Preconditioner of the projected CG in qeq_solve / qeq_backward.
    k_cut <= 0 (default): Jacobi, D_i = J_i + 1/(sigma_i sqrt(pi)).
    k_cut > 0 (bohr^-1): spectral preconditioner for the long-wavelength

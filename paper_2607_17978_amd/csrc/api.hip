@@ -585,6 +585,44 @@ int ensure_chunk_graph(qeq_plan* pl, int chunk) {
 }
 
 
+}  // namespace
+
+// Final product on q: energies, mu, true residual, forces; scatter to caller
+// order; host copies of the results and of the CG scalars.
+int final_pass(qeq_plan* pl, double* q_out, double* energies, double* forces_out) {
+    if (pl->direct) {
+        QEQ_TRY(launch_np_matvec(pl, pl->q, pl->y, QEQ_MODE_FINAL));
+        QEQ_TRY(launch_final_tail(pl, q_out, energies, forces_out));
+    } else if (pl->ew_active) {
+        QEQ_TRY(launch_ew_rec(pl, pl->q, nullptr, true));
+        QEQ_TRY(launch_final(pl, q_out, energies, forces_out));
+    } else if (pl->pw_active) {
+        QEQ_TRY(launch_pw_rec(pl, pl->q, nullptr, true));
+        QEQ_TRY(launch_final(pl, q_out, energies, forces_out));
+    } else {
+        QEQ_TRY(launch_mesh_potential(pl, pl->q, nullptr));
+        QEQ_TRY(launch_final(pl, q_out, energies, forces_out));
+    }
+    QEQ_HIP(hipMemcpyAsync(pl->out_host, pl->final_dev, 4 * sizeof(double), hipMemcpyDeviceToHost, pl->stream));
+    QEQ_HIP(hipMemcpyAsync(pl->sc_host, pl->sc, sizeof(CgScalars), hipMemcpyDeviceToHost, pl->stream));
+    QEQ_HIP(hipStreamSynchronize(pl->stream));
+    return QEQ_OK;
+}
+
+// dst = E src (sorted order, no J, no partial sums) with the solve's operator.
+int operator_product(qeq_plan* pl, const double* src, double* dst) {
+    if (pl->ew_active) {
+        QEQ_TRY(launch_ew_rec(pl, src, nullptr, false));
+    } else if (pl->pw_active) {
+        QEQ_TRY(launch_pw_rec(pl, src, nullptr, false));
+    } else {
+        QEQ_TRY(launch_mesh_potential(pl, src, nullptr));
+    }
+    return launch_interp(pl, src, dst, QEQ_MODE_MATVEC, 0);
+}
+
+namespace {
+
 // Projected CG from q0 (or Q/N) to the tolerance, with the true-residual
 // restart, then the final matvec: energies, mu, true residual and forces are
 // computed; q_out / energies / forces_out (caller order) may be NULL.
@@ -652,24 +690,7 @@ int cg_run(qeq_plan* pl, const double* q0, double* q_out, double* energies, doub
         QEQ_HIP(hipMemcpyAsync(pl->sc_host, pl->sc, sizeof(CgScalars), hipMemcpyDeviceToHost, pl->stream));
         QEQ_HIP(hipStreamSynchronize(pl->stream));
         conv = pl->sc_host->done != 0;
-        // final matvec on q: energies, mu, true residual, forces; scatter to caller order
-        if (pl->direct) {
-            QEQ_TRY(launch_np_matvec(pl, pl->q, pl->y, QEQ_MODE_FINAL));
-            QEQ_TRY(launch_final_tail(pl, q_out, energies, forces_out));
-        } else if (pl->ew_active) {
-            QEQ_TRY(launch_ew_rec(pl, pl->q, nullptr, true));
-            QEQ_TRY(launch_final(pl, q_out, energies, forces_out));
-        } else if (pl->pw_active) {
-            QEQ_TRY(launch_pw_rec(pl, pl->q, nullptr, true));
-            QEQ_TRY(launch_final(pl, q_out, energies, forces_out));
-        } else {
-            QEQ_TRY(launch_mesh_potential(pl, pl->q, nullptr));
-            QEQ_TRY(launch_final(pl, q_out, energies, forces_out));
-        }
-        QEQ_HIP(hipMemcpyAsync(pl->out_host, pl->final_dev, 4 * sizeof(double), hipMemcpyDeviceToHost,
-                               pl->stream));
-        QEQ_HIP(hipMemcpyAsync(pl->sc_host, pl->sc, sizeof(CgScalars), hipMemcpyDeviceToHost, pl->stream));
-        QEQ_HIP(hipStreamSynchronize(pl->stream));
+        QEQ_TRY(final_pass(pl, q_out, energies, forces_out));
         bool gap = !(pl->out_host[3] <= restart_thr);
         if (!conv || !gap || restart >= 4 || it >= pl->prm.max_iter) {
             if (conv && gap) conv = false;
@@ -718,7 +739,10 @@ int solve_impl(qeq_plan* pl, int n, const double* pos, const double* cell, const
     QEQ_TRY(spc_setup(pl));
     pl->fdst = pl->forces_s;
     bool conv = false;
-    QEQ_TRY(cg_run(pl, q0, q, energies, forces, &conv));
+    if (pl->sqnm)
+        QEQ_TRY(sqnm_run(pl, q0, q, energies, forces, &conv));
+    else
+        QEQ_TRY(cg_run(pl, q0, q, energies, forces, &conv));
     int status = cg_status(pl, conv, stats);
     // the adjoint, the virial and the element potentials use the split
     // mesh operator: they follow its solves only
@@ -856,6 +880,7 @@ int qeq_plan_destroy(qeq_plan* pl) {
     np_free(pl);
     ew_free(pl);
     pw_free(pl);
+    sqnm_free(pl);
     if (pl->elem_buf) (void)hipFree(pl->elem_buf);
     dfree(pl->sc); dfree(pl->final_dev); dfree(pl->scan_tmp);
     dfree(pl->cell_count); dfree(pl->cell_start); dfree(pl->cell_fill); dfree(pl->cell_atoms);
@@ -960,6 +985,19 @@ int qeq_use_ewald(qeq_plan* plan, int32_t enable) {
     if (plan->ewald) plan->planewave = false;
     plan->tape_valid = false;
     drop_graph(plan);
+    return QEQ_OK;
+}
+
+int qeq_use_sqnm(qeq_plan* plan, int32_t enable, int32_t history) {
+    if (!plan) return QEQ_EINVAL;
+    if (history == 0) history = 10;
+    if (enable && (history < 1 || history > 16)) return QEQ_EINVAL;
+    if (plan->stream) (void)hipStreamSynchronize(plan->stream);
+    plan->sqnm = enable != 0;
+    if (plan->sqnm && history != plan->sq_m) {
+        sqnm_free(plan);
+        plan->sq_m = history;
+    }
     return QEQ_OK;
 }
 

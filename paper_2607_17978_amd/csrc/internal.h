@@ -254,6 +254,20 @@ struct qeq_plan {
     double* ew_f = nullptr;       // [mode split][atom][3] force partials
     double* ew_yrec = nullptr;    // reciprocal product, sorted order
     double* ew_frec = nullptr;    // reciprocal forces of the final product
+    // SQNM instead of CG for qeq_solve (qeq_use_sqnm)
+    bool sqnm = false;
+    int sq_m = 10;                // history length
+    int sq_cap_n = 0, sq_cap_m = 0;
+    double* sq_S = nullptr;       // [m + 1][n_max] displacement ring
+    double* sq_Y = nullptr;       // [m + 1][n_max] gradient-difference ring
+    double* sq_g = nullptr;       // [2][n_max] gradients (current, trial)
+    double* sq_part = nullptr;    // [blocks][SQ_NS_MAX] partial sums
+    double* sq_sums = nullptr;    // [SQ_NS_MAX] reduced sums
+    int* sq_desc = nullptr;       // [SQ_NS_MAX] sum descriptors (kind, i, j packed)
+    double* sq_host = nullptr;    // pinned host copy of the sums
+    int sq_iters = 0;             // iterations of the last SQNM solve (accepted + rejected)
+    int sq_rejected = 0;          // steps undone after an energy rise
+
     // Gaussian-on-grid (plane-wave) operator instead of the split (qeq_use_planewave)
     bool planewave = false;       // requested for later periodic solves
     bool pw_active = false;       // the current solve's operator uses it
@@ -361,6 +375,13 @@ int ew_setup(qeq_plan* pl);
 int launch_ew_rec(qeq_plan* pl, const double* src, const int* done, bool fin);
 int launch_ew_forces_add(qeq_plan* pl);
 void ew_free(qeq_plan* pl);
+// final product and host copies after a solve (api.hip); E src with the
+// solve's operator, sorted order (api.hip)
+int final_pass(qeq_plan* pl, double* q_out, double* energies, double* forces_out);
+int operator_product(qeq_plan* pl, const double* src, double* dst);
+// stabilised quasi-Newton minimisation instead of CG (sqnm.hip)
+int sqnm_run(qeq_plan* pl, const double* q0, double* q_out, double* energies, double* forces_out, bool* conv);
+void sqnm_free(qeq_plan* pl);
 // Gaussian-on-grid operator (planewave.hip)
 int pw_setup(qeq_plan* pl);
 int launch_pw_rec(qeq_plan* pl, const double* src, const int* done, bool fin);

@@ -102,6 +102,8 @@ def load_library():
     L.qeq_use_ewald.restype = ctypes.c_int
     L.qeq_use_planewave.argtypes = [vp, i32, ctypes.c_double]
     L.qeq_use_planewave.restype = ctypes.c_int
+    L.qeq_use_sqnm.argtypes = [vp, i32, i32]
+    L.qeq_use_sqnm.restype = ctypes.c_int
     L.qeq_use_spectral_preconditioner.argtypes = [vp, f64]
     L.qeq_use_spectral_preconditioner.restype = ctypes.c_int
     L.qeq_use_fused_inverse.argtypes = [vp, i32]
@@ -405,6 +407,12 @@ class Plan:
         if rc != QEQ_OK:
             raise QEqError(rc, strerror(rc))
         self._last_n = None
+
+    def use_sqnm(self, enable=True, history=10):
+        """SQNM (True) or projected CG (False, default) for later solves."""
+        rc = load_library().qeq_use_sqnm(self._h, 1 if enable else 0, int(history))
+        if rc != QEQ_OK:
+            raise QEqError(rc, strerror(rc))
 
     def use_planewave(self, enable=True, support=6.0):
         """Gaussian-on-grid operator without the Ewald split (True) or the
