@@ -42,11 +42,24 @@ __global__ __launch_bounds__(QEQ_BLOCK) void k_interp(
     for (int t = 0; t < QEQ_NPART; ++t) acc[t] = 0.0;
     // waves stride over atoms; the loop trip count is uniform across the block
     const int rounds = (k.n + nwaves - 1) / nwaves;
+    const int wave = (xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) >> 6;
+    // the row bounds and home indices of the next round's atom are loaded
+    // one round ahead, so that each round starts with its first load level
+    // already in flight
+    int nx_e0 = 0, nx_e1 = 0, nx_h1 = 0, nx_h2 = 0, nx_h3 = 0;
+    if (wave < k.n) {
+        nx_e0 = rowptr[wave];
+        nx_e1 = rowptr[wave + 1];
+        nx_h1 = home[4 * wave];
+        nx_h2 = home[4 * wave + 1];
+        nx_h3 = home[4 * wave + 2];
+    }
     for (int rnd = 0; rnd < rounds; ++rnd) {
-    const int i = rnd * nwaves + ((xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) >> 6);
+    const int i = rnd * nwaves + wave;
     // per-lane partials: y, du[3] (reciprocal gradient / q), fr[3] (pair gradient / q)
     double v[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     const bool active = i < k.n;
+    const int cur_e0 = nx_e0, cur_e1 = nx_e1, cur_h1 = nx_h1, cur_h2 = nx_h2, cur_h3 = nx_h3;
     if (active) {
         // Loads are issued in three dependent levels so that their latencies
         // overlap (the memory counter retires loads in issue order): the row
@@ -56,8 +69,8 @@ __global__ __launch_bounds__(QEQ_BLOCK) void k_interp(
         constexpr int PM = PC ? PC : QEQ_MAXP;
         const bool do_recip = (k.parts & QEQ_PART_RECIP) && lane < p * p;
         const bool do_real = (k.parts & QEQ_PART_REAL) != 0;
-        const int e0 = rowptr[i], e1 = rowptr[i + 1];
-        const int h1 = home[4 * i], h2 = home[4 * i + 1], h3 = home[4 * i + 2];
+        const int e0 = cur_e0, e1 = cur_e1;
+        const int h1 = cur_h1, h2 = cur_h2, h3 = cur_h3;
         const int ef = e0 + lane;
         const bool has_pair = do_real && ef < e1;
         int cj = 0;
@@ -98,6 +111,15 @@ __global__ __launch_bounds__(QEQ_BLOCK) void k_interp(
                 dw2 = dw[QEQ_MAXP + k2];
                 dw3 = dw[2 * QEQ_MAXP + k3];
             }
+        }
+        // next round's first load level, behind this round's second
+        const int in = i + nwaves;
+        if (in < k.n) {
+            nx_e0 = rowptr[in];
+            nx_e1 = rowptr[in + 1];
+            nx_h1 = home[4 * in];
+            nx_h2 = home[4 * in + 1];
+            nx_h3 = home[4 * in + 2];
         }
         const double vj = has_pair ? src[cj] : 0.0;
         if (do_recip) {
