@@ -394,23 +394,30 @@ int prepare(qeq_plan* pl, int n, const double* cell, double q_tot) {
     k.K2 = K[1];
     k.K3 = K[2];
     k.K3h = K[2] / 2 + 1;
-    // axis-2 tile: 16, 8 or 4 rows, with LDS per block within 48 KB
-    int tw = 16;
-    while (tw > 4 && (K[1] % tw != 0 || (size_t)K[0] * tw * 8 > 49152 ||
-                      (size_t)K[2] * (tw / 2) * 8 + (size_t)(K[2] / 2 + 1) * tw * 8 > 49152))
-        tw >>= 1;
+    // Axis-2 tile of the spread pass: 16, 8 or 4 rows within 48 KB of LDS
+    // (wider tiles mean fewer blocks re-staging the same atoms; 32 and 8
+    // rows both measured slower than 16 at 192^3).  The axis-1 and C2R
+    // passes and the axis-2 rows pass keep their blocks within 32 KB: at
+    // 320^3 (the HBM-bound size) 8-row tiles let more blocks overlap their
+    // loads and stores (axis-1 pass 110 -> 88 us, C2R 94 -> 71 us, rows
+    // 79 / 70 -> 58 / 54 us), while at 192^3 the 16-row blocks stay faster.
+    auto tile_fits = [&](int t, size_t lds) {
+        return K[1] % t == 0 && (size_t)K[0] * t * 8 <= lds &&
+               (size_t)K[2] * (t / 2) * 8 + (size_t)(K[2] / 2 + 1) * t * 8 <= lds;
+    };
+    int tws = 16;
+    while (tws > 4 && !tile_fits(tws, 49152)) tws >>= 1;
+    if (K[1] % tws != 0 || K[1] < tws + p - 1) return QEQ_EPLAN;
+    int tw = tws;
+    while (tw > 4 && !tile_fits(tw, 32768)) tw >>= 1;
     if (K[1] % tw != 0 || K[1] < tw + p - 1) return QEQ_EPLAN;
     k.TW = tw;
     k.TWlog2 = ilog2(tw);
     k.ntile = K[1] / tw;
-    // the spread pass takes wider tiles when they fit: fewer blocks re-stage
-    // the same atoms (halo p - 1 rows per tile)
-    int tws = tw;
-    (void)tws;   // wider spread tiles (32 rows) measured slower on gfx950; keep the C2R tile
     k.TWS = tws;
     k.ntile_s = K[1] / tws;
     int nr = 16;
-    while (nr > 1 && (size_t)K[1] * nr * 8 > 49152) nr >>= 1;
+    while (nr > 1 && (size_t)K[1] * nr * 8 > 32768) nr >>= 1;
     k.NR = nr;
     k.NRlog2 = ilog2(nr);
     // every FFT stage must fit the per-thread register budget

@@ -606,7 +606,7 @@ size_t smem_c2r(const KParams& k) {
 }
 
 // Specialised (length, tile) pairs; anything else runs the runtime-sized kernels.
-#define QEQ_FOR_EACH_SIZE(X) X(24, 8) X(48, 16) X(96, 16) X(192, 16) X(320, 16)
+#define QEQ_FOR_EACH_SIZE(X) X(24, 8) X(48, 16) X(96, 16) X(192, 16) X(320, 16) X(320, 8)
 #define QEQ_FOR_EACH_SPREAD(X) X(24, 8) X(48, 16) X(96, 16) X(192, 16) X(320, 16)
 
 int spread_pass(qeq_plan* pl, const double* src, const int* done) {
@@ -648,6 +648,14 @@ int rows_pass_t(qeq_plan* pl, const int* done) {
         return qeq_check(hipGetLastError());                                                       \
     }
     QEQ_FOR_EACH_SIZE(X)
+#undef X
+#define X(KK)                                                                                      \
+    if (k.K2 == KK && k.NR == 8) {                                                                 \
+        hipExtLaunchKernelGGL((k_fft_rows<KK, 8, INV>), g, b, sh, pl->stream, ps.start(), ps.stop(), 0, \
+                              k, pl->axes.ax[1], pl->grid_c, nrows, done);                          \
+        return qeq_check(hipGetLastError());                                                       \
+    }
+    X(320)
 #undef X
     hipExtLaunchKernelGGL((k_fft_rows<0, 0, INV>), g, b, sh, pl->stream, ps.start(), ps.stop(), 0, k,
                           pl->axes.ax[1], pl->grid_c, nrows, done);

@@ -270,3 +270,31 @@ def test_n4096_matches_matfree_oracle(dev):
     assert st["rc"] == 0
     assert dq <= 1e-5 and de_q <= 1e-6 and de_e <= 1e-6 and df <= 1e-4
     plan.close()
+
+
+def test_grid320_matches_oracle(dev):
+    """The 320^3 grid of the trajectory workload (8-row tiles in the axis-1,
+    axis-2 and C2R passes, no fused slab): 64 atoms in its 235.7-bohr cube
+    against dense Ewald + Gaussian elimination
+    (tests/golden/make_grid320_reference.py): solve and one operator product."""
+    import os
+    from paper_2607_17978_amd import qeq
+    path = os.path.join(os.path.dirname(__file__), "golden", "grid320_reference.npz")
+    if not os.path.exists(path):
+        pytest.skip("reference not generated")
+    ref = np.load(path)
+    s = gen.lattice_system(4, 235.7, 1009, grid=(320, 320, 320), name="n64_L235.7")
+    plan = qeq.Plan(s.n, eta=ETA, r_cut=RC, grid=s.grid, tol=1e-9)
+    q, en, f, st = plan.solve(T(s.pos, dev), s.cell, T(s.sigma, dev), T(s.J, dev), T(s.chi, dev), s.q_tot)
+    assert st["rc"] == 0, st
+    q, en, f = q.cpu().numpy(), en.cpu().numpy(), f.cpu().numpy()
+    dq = np.abs(q - ref["q"]).max()
+    de_q = abs(en[0] - float(ref["e_qeq"])) / abs(float(ref["e_qeq"]))
+    de_e = abs(en[1] - float(ref["e_elec"])) / abs(float(ref["e_elec"]))
+    df = np.sqrt(np.mean((f - ref["forces"]) ** 2)) / np.sqrt(np.mean(ref["forces"] ** 2))
+    Ev = plan.matvec(T(s.pos, dev), s.cell, T(s.sigma, dev), T(ref["v"], dev)).cpu().numpy()
+    dEv = np.abs(Ev - ref["Ev"]).max() / np.abs(ref["Ev"]).max()
+    print("grid320", st["iters"], "dq", dq, "dEqeq", de_q, "dEelec", de_e, "dF", df, "dEv", dEv)
+    assert dq <= 1e-5 and de_q <= 1e-6 and de_e <= 1e-6 and df <= 1e-4
+    assert dEv <= 1e-5
+    plan.close()
