@@ -394,22 +394,21 @@ int prepare(qeq_plan* pl, int n, const double* cell, double q_tot) {
     k.K2 = K[1];
     k.K3 = K[2];
     k.K3h = K[2] / 2 + 1;
-    // Axis-2 tile of the spread pass: 16, 8 or 4 rows within 48 KB of LDS
-    // (wider tiles mean fewer blocks re-staging the same atoms; 32 and 8
-    // rows both measured slower than 16 at 192^3).  The axis-1 and C2R
-    // passes and the axis-2 rows pass keep their blocks within 32 KB: at
-    // 320^3 (the HBM-bound size) 8-row tiles let more blocks overlap their
-    // loads and stores (axis-1 pass 110 -> 88 us, C2R 94 -> 71 us, rows
-    // 79 / 70 -> 58 / 54 us), while at 192^3 the 16-row blocks stay faster.
-    auto tile_fits = [&](int t, size_t lds) {
-        return K[1] % t == 0 && (size_t)K[0] * t * 8 <= lds &&
-               (size_t)K[2] * (t / 2) * 8 + (size_t)(K[2] / 2 + 1) * t * 8 <= lds;
+    // Axis-2 tiles of 16, 8 or 4 rows, every pass's block within 32 KB of
+    // LDS.  At 320^3 (the HBM-bound size) 8-row tiles let more blocks
+    // overlap their loads and stores (spread 106 -> 90 us, axis-1 pass
+    // 110 -> 88 us, C2R 94 -> 71 us, axis-2 rows 79 / 70 -> 58 / 54 us);
+    // at 192^3 the 16-row blocks (about 25 KB) are faster, and 32 rows were
+    // slower everywhere.
+    auto tile_fits = [&](int t) {
+        return K[1] % t == 0 && (size_t)K[0] * t * 8 <= 32768 &&
+               (size_t)K[2] * (t / 2) * 8 + (size_t)(K[2] / 2 + 1) * t * 8 <= 32768;
     };
-    int tws = 16;
-    while (tws > 4 && !tile_fits(tws, 49152)) tws >>= 1;
+    int tws = 16;   // spread: twiddles + int64 accumulator of the tile
+    while (tws > 4 && (K[1] % tws != 0 || (size_t)K[2] * 8 + (size_t)K[2] * tws * 8 > 32768)) tws >>= 1;
     if (K[1] % tws != 0 || K[1] < tws + p - 1) return QEQ_EPLAN;
-    int tw = tws;
-    while (tw > 4 && !tile_fits(tw, 32768)) tw >>= 1;
+    int tw = 16;
+    while (tw > 4 && !tile_fits(tw)) tw >>= 1;
     if (K[1] % tw != 0 || K[1] < tw + p - 1) return QEQ_EPLAN;
     k.TW = tw;
     k.TWlog2 = ilog2(tw);

@@ -607,7 +607,7 @@ size_t smem_c2r(const KParams& k) {
 
 // Specialised (length, tile) pairs; anything else runs the runtime-sized kernels.
 #define QEQ_FOR_EACH_SIZE(X) X(24, 8) X(48, 16) X(96, 16) X(192, 16) X(320, 16) X(320, 8)
-#define QEQ_FOR_EACH_SPREAD(X) X(24, 8) X(48, 16) X(96, 16) X(192, 16) X(320, 16)
+#define QEQ_FOR_EACH_SPREAD(X) X(24, 8) X(48, 16) X(96, 16) X(192, 16) X(320, 8)
 
 int spread_pass(qeq_plan* pl, const double* src, const int* done) {
     const KParams& k = pl->kp;
