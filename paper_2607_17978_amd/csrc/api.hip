@@ -417,6 +417,11 @@ int prepare(qeq_plan* pl, int n, const double* cell, double q_tot) {
     k.ntile_s = K[1] / tws;
     int nr = 16;
     while (nr > 1 && (size_t)K[1] * nr * 8 > 32768) nr >>= 1;
+    // grids beyond the ~256 MB Infinity Cache stream from HBM: there 4 rows
+    // per block of the axis-2 pass overlap better (320^3: 58 / 54 -> 53 /
+    // 46 us); cache-resident grids keep the larger blocks
+    const size_t grid_bytes = (size_t)K[0] * K[1] * K[2] * 4 + (size_t)K[0] * K[1] * (K[2] / 2 + 1) * 8;
+    if (grid_bytes > ((size_t)192 << 20) && nr > 4) nr = 4;
     k.NR = nr;
     k.NRlog2 = ilog2(nr);
     // every FFT stage must fit the per-thread register budget

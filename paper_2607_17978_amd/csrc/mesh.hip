@@ -650,8 +650,8 @@ int rows_pass_t(qeq_plan* pl, const int* done) {
     QEQ_FOR_EACH_SIZE(X)
 #undef X
 #define X(KK)                                                                                      \
-    if (k.K2 == KK && k.NR == 8) {                                                                 \
-        hipExtLaunchKernelGGL((k_fft_rows<KK, 8, INV>), g, b, sh, pl->stream, ps.start(), ps.stop(), 0, \
+    if (k.K2 == KK && k.NR == 4) {                                                                 \
+        hipExtLaunchKernelGGL((k_fft_rows<KK, 4, INV>), g, b, sh, pl->stream, ps.start(), ps.stop(), 0, \
                               k, pl->axes.ax[1], pl->grid_c, nrows, done);                          \
         return qeq_check(hipGetLastError());                                                       \
     }
