@@ -72,3 +72,26 @@ def test_struct_layouts_match_header(tmp_path):
     want = [ctypes.sizeof(P), P.grid.offset, P.tol.offset, P.self_correction.offset,
             ctypes.sizeof(S), S.rel_resid.offset, S.mu.offset, S.e_elec.offset]
     assert got == want
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py runs on one GPU; --gpus above 1 exits with a message before
+    touching a device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_bench_traffic_record_matches_the_spread_source():
+    """The HBM traffic in the bench line comes from rocprofv3 counters taken on
+    one version of the spread kernel; the stored source hash must still match
+    (bench.py reports traffic as null otherwise)."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    rec = bench.MEASURED_TRAFFIC["spread_r2c"]
+    assert bench.kernel_source_hash(rec["file"], rec["kernel"]) == rec["source_sha256_16"]
