@@ -131,3 +131,21 @@ def test_planewave_support_and_refusals(dev):
     assert np.abs(qm.cpu().numpy() - qa.cpu().numpy()).max() <= 1e-5
     plan.close()
 
+
+
+def test_planewave_grid320_matches_oracle(dev):
+    """The 320^3 grid (8-row tiles in the axis-3 pass of the plane-wave path
+    too): 64 atoms in the 235.7-bohr cube against dense Ewald
+    (tests/golden/make_grid320_reference.py)."""
+    path = os.path.join(os.path.dirname(__file__), "golden", "grid320_reference.npz")
+    if not os.path.exists(path):
+        pytest.skip("reference not generated")
+    ref = np.load(path)
+    s = gen.lattice_system(4, 235.7, 1009, grid=(320, 320, 320), name="n64_L235.7")
+    q, en, f, st = solve(dev, s, "planewave")
+    dq = np.abs(q - ref["q"]).max()
+    de_q = abs(en[0] - float(ref["e_qeq"])) / abs(float(ref["e_qeq"]))
+    de_e = abs(en[1] - float(ref["e_elec"])) / abs(float(ref["e_elec"]))
+    df = np.sqrt(np.mean((f - ref["forces"]) ** 2)) / np.sqrt(np.mean(ref["forces"] ** 2))
+    print("grid320 planewave", st["iters"], "dq", dq, "dEqeq", de_q, "dEelec", de_e, "dF", df)
+    assert dq <= 1e-5 and de_q <= 1e-6 and de_e <= 1e-6 and df <= 1e-4
