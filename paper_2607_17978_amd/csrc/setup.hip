@@ -271,9 +271,19 @@ __global__ __launch_bounds__(QEQ_BLOCK) void k_pairs(KParams k, const double* __
                                                     const int* __restrict__ cell_atoms, int* __restrict__ rowcnt,
                                                     const int* __restrict__ rowptr, int* __restrict__ col,
                                                     float* __restrict__ kval, float4* __restrict__ pdr) {
+    // FILL stages a row of up to PBUF pairs in this wave's LDS slice and
+    // evaluates the FP64 kernel values afterwards with one pair per lane
+    // (inside the stencil loop the divergent lanes would run the erf pair
+    // once per step); longer rows evaluate them in place
+    constexpr int PBUF = 128;
+    __shared__ float4 st_d[FILL ? (QEQ_BLOCK / 64) * PBUF : 1];
+    __shared__ int st_j[FILL ? (QEQ_BLOCK / 64) * PBUF : 1];
     const int lane = threadIdx.x & 63;
     const int i = (xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) >> 6;
     if (i >= k.n) return;   // uniform across the wave
+    const int sbase = (threadIdx.x >> 6) * PBUF;
+    const bool staged = FILL && rowptr[i + 1] - rowptr[i] <= PBUF;
+    int loff = 0;
     const double si[3] = {frac[3 * i], frac[3 * i + 1], frac[3 * i + 2]};
     const int ck = home[4 * i + 3];
     const int c3 = ck % k.nc[2];
@@ -306,14 +316,21 @@ __global__ __launch_bounds__(QEQ_BLOCK) void k_pairs(KParams k, const double* __
                 const double r2v = dx * dx + dy * dy + dz * dz;
                 if (r2v >= k.rc2) continue;
                 if (FILL && pass == 1) {
-                    const double sj = sig[j];
-                    double K, dKr;
-                    pair_kernel(sqrt(r2v), sqrt(sgi * sgi + sj * sj), k.eta, &K, &dKr);
-                    col[off] = j;
-                    kval[off] = (float)K;
-                    // store r_i - r_j(image) for the force
-                    pdr[off] = make_float4((float)(-dx), (float)(-dy), (float)(-dz), (float)dKr);
-                    ++off;
+                    if (staged) {
+                        // r_i - r_j(image) for the force; the distance waits in .w
+                        st_j[sbase + loff] = j;
+                        st_d[sbase + loff] =
+                            make_float4((float)(-dx), (float)(-dy), (float)(-dz), (float)sqrt(r2v));
+                        ++loff;
+                    } else {
+                        const double sj = sig[j];
+                        double K, dKr;
+                        pair_kernel(sqrt(r2v), sqrt(sgi * sgi + sj * sj), k.eta, &K, &dKr);
+                        col[off] = j;
+                        kval[off] = (float)K;
+                        pdr[off] = make_float4((float)(-dx), (float)(-dy), (float)(-dz), (float)dKr);
+                        ++off;
+                    }
                 }
                 ++cnt;
             }
@@ -326,8 +343,23 @@ __global__ __launch_bounds__(QEQ_BLOCK) void k_pairs(KParams k, const double* __
         }
         if (FILL) {
             off = rowptr[i] + incl - cnt;
+            loff = incl - cnt;
         } else if (lane == 63) {
             rowcnt[i] = incl;
+        }
+    }
+    if (staged) {
+        __threadfence_block();   // the other lanes' LDS writes before the reads below
+        const int e0 = rowptr[i], rl = rowptr[i + 1] - e0;
+        for (int e = lane; e < rl; e += 64) {
+            const int j = st_j[sbase + e];
+            const float4 d = st_d[sbase + e];
+            const double sj = sig[j];
+            double K, dKr;
+            pair_kernel((double)d.w, sqrt(sgi * sgi + sj * sj), k.eta, &K, &dKr);
+            col[e0 + e] = j;
+            kval[e0 + e] = (float)K;
+            pdr[e0 + e] = make_float4(d.x, d.y, d.z, (float)dKr);
         }
     }
 }
