@@ -706,7 +706,7 @@ def adjoint_main(args, dev):
 
         def step():
             q, en, f, st = plan.solve(pos, s.cell, sig, J, chi, s.q_tot)
-            out = plan.backward(2.0 * wd * (q - qrd), 0.0, 1.0)
+            out = plan.backward(2.0 * wd * (q - qrd), dL_dEelec=1.0)
             return st, out[3]
 
         for _ in range(max(1, args.warmup)):

@@ -71,6 +71,11 @@ typedef struct qeq_params {
     int32_t max_iter;        /* CG iteration cap */
     int32_t self_correction; /* 1: replace each atom's mesh self-interaction by the exact
                                 reciprocal self term (energy and force), 0: plain SPME */
+    int32_t precond;         /* preconditioner of the projected CG: 0 Jacobi
+                                (D_i = J_i + 1/(sigma_i sqrt(pi))), 1 spectral (the
+                                long-wavelength Coulomb modes up to spectral_kcut on top of
+                                Jacobi; see qeq_use_spectral_preconditioner) */
+    double  spectral_kcut;   /* bohr^-1, used when precond == 1; <= 0 selects 0.2 */
 } qeq_params;
 
 typedef struct qeq_stats {   /* host memory */
@@ -86,12 +91,15 @@ typedef struct qeq_stats {   /* host memory */
 } qeq_stats;
 
 /* Default parameters: eta 2.0, r_cut 11.0, max_spacing 0.8, grid derived,
-   p = 6, tol 1e-6, max_iter 1000, self_correction 1. */
+   p = 6, tol 1e-6, max_iter 1000, self_correction 1, precond 0 (Jacobi),
+   spectral_kcut 0.2. */
 void qeq_params_default(qeq_params* p);
 
 /* Create a plan for up to n_atoms_max atoms on the current HIP device.
    hip_stream: a hipStream_t (NULL = the default stream).  Returns QEQ_EPLAN
-   for an unsupported grid or spline order, QEQ_EINVAL for bad parameters. */
+   for an unsupported grid or spline order, QEQ_EINVAL for bad parameters
+   (including precond outside {0, 1} or a NaN spectral_kcut).  precond == 1
+   has the effect of qeq_use_spectral_preconditioner(plan, spectral_kcut). */
 int qeq_plan_create(qeq_plan** out, const qeq_params* params, int32_t n_atoms_max,
                     void* hip_stream);
 int qeq_plan_destroy(qeq_plan* plan);
@@ -156,8 +164,8 @@ int qeq_element_potentials(qeq_plan* plan, const int32_t* species, int32_t n_ele
 /* Gradient of a loss L(q, E_QEq, E_elec) through the last solve on this plan
    (SI eq. 4g_force_trick: Lagrange / adjoint route, one extra linear solve
    with the same operator instead of 3N charge derivatives).
-   dL_dq (n, device, caller order) or NULL for zero; dL_dEqeq, dL_dEelec:
-   scalar weights of the two energies.
+   dL_dq (n, device, caller order) or NULL for zero; dL_dEelec, dL_dEqeq:
+   scalar weights of the two energies, in that order (E_elec first).
    Outputs (device, caller order, each may be NULL):
      dL_dchi (n) = -a + dL_dEqeq q,
      dL_dJ   (n) = -a q + dL_dEqeq q^2 / 2,
@@ -166,7 +174,7 @@ int qeq_element_potentials(qeq_plan* plan, const int32_t* species, int32_t n_ele
    stats (host) report the adjoint CG.  Needs a preceding successful
    qeq_solve on the same plan (QEQ_EINVAL otherwise); gradients with respect to
    sigma and the cell are not provided. */
-int qeq_backward(qeq_plan* plan, const double* dL_dq, double dL_dEqeq, double dL_dEelec,
+int qeq_backward(qeq_plan* plan, const double* dL_dq, double dL_dEelec, double dL_dEqeq,
                  double* dL_dchi, double* dL_dJ, double* dL_dpos, qeq_stats* stats);
 
 /* Virial of the last solve on this plan (SI "Stress Tensor": the stress is
@@ -400,7 +408,7 @@ int qeq_use_sqnm(qeq_plan* plan, int32_t enable, int32_t history);
    and applied by the Woodbury identity with the small inverse built once per
    geometry.  The converged charges are the same as with Jacobi (the solve
    tolerance applies unchanged); k_cut ~ 0.2 bohr^-1 cuts the cold-start
-   iterations of a 32,768-atom cell from 57 to about 20.  If the geometry
+   iterations of a 32,768-atom cell from 57 to 17.  If the geometry
    falls outside the range where the construction is safe (D' <= 0.1 D or a
    weakly dominant small matrix) the solve uses Jacobi.  QEQ_EINVAL for NaN. */
 int qeq_use_spectral_preconditioner(qeq_plan* plan, double k_cut);

@@ -57,7 +57,7 @@ def charge_step(plan, net, G, species, pos, cell, sigma, J, q_ref, q_tot=0.0, lr
     q, _, _, st = plan.solve(pos, cell, sigma, Jv, chi, q_tot, forces=False)
     r = q - q_ref
     loss = float((r * r).mean())
-    dchi, dJ, _, st_b = plan.backward(2.0 * r / n, 0.0, 0.0)
+    dchi, dJ, _, st_b = plan.backward(2.0 * r / n)
     net.train_step(G, species, chi - n * dchi, lr=lr, update=update, grad_out=grad_out)
     if jnet is not None:
         jnet.train_step(G, species, yj - n * (dJ * Jv * j_scale), lr=lr, update=update, grad_out=jgrad_out)

@@ -764,7 +764,7 @@ int solve_impl(qeq_plan* pl, int n, const double* pos, const double* cell, const
 // Adjoint of the solve (SI eq. 4g_force_trick, Lagrange route): one more
 // projected CG with the same operator and right-hand side g, then the
 // bilinear position derivative of a^T E q from two mesh potentials.
-int backward_impl(qeq_plan* pl, const double* dL_dq, double dL_dEqeq, double dL_dEelec, double* dL_dchi,
+int backward_impl(qeq_plan* pl, const double* dL_dq, double dL_dEelec, double dL_dEqeq, double* dL_dchi,
                   double* dL_dJ, double* dL_dpos, qeq_stats* stats) {
     if (!pl->tape_valid) return QEQ_EINVAL;
     if (!isfinite(dL_dEqeq) || !isfinite(dL_dEelec)) return QEQ_EINVAL;
@@ -806,6 +806,8 @@ void qeq_params_default(qeq_params* p) {
     p->tol = 1e-6;
     p->max_iter = 1000;
     p->self_correction = 1;
+    p->precond = 0;
+    p->spectral_kcut = 0.2;
 }
 
 int qeq_plan_create(qeq_plan** out, const qeq_params* params, int32_t n_atoms_max, void* hip_stream) {
@@ -815,6 +817,8 @@ int qeq_plan_create(qeq_plan** out, const qeq_params* params, int32_t n_atoms_ma
     if (!(p.eta > 0.0) || !(p.r_cut > 0.0) || !(p.tol > 0.0) || p.max_iter < 0) return QEQ_EINVAL;
     if (p.grid[0] <= 0 && !(p.max_spacing > 0.0)) return QEQ_EINVAL;
     if (p.spline_order < 4 || p.spline_order > QEQ_MAXP || (p.spline_order & 1)) return QEQ_EPLAN;
+    if (p.precond != 0 && p.precond != 1) return QEQ_EINVAL;
+    if (!(p.spectral_kcut == p.spectral_kcut)) return QEQ_EINVAL;
     qeq_plan* pl = new (std::nothrow) qeq_plan();
     if (!pl) return QEQ_ENOMEM;
     pl->prm = p;
@@ -864,6 +868,7 @@ int qeq_plan_create(qeq_plan** out, const qeq_params* params, int32_t n_atoms_ma
     if (rc == QEQ_OK && hipHostMalloc((void**)&pl->out_host, 16 * sizeof(double)) != hipSuccess)
         rc = QEQ_ENOMEM;
     if (rc == QEQ_OK && p.grid[0] > 0) rc = ensure_grid(pl, p.grid);
+    if (p.precond == 1) pl->spc_kc = p.spectral_kcut > 0.0 ? p.spectral_kcut : 0.2;
     if (rc != QEQ_OK) {
         qeq_plan_destroy(pl);
         return rc;
@@ -1110,10 +1115,10 @@ int qeq_descriptors(qeq_plan* plan, int32_t n, const double* pos, const double* 
     return QEQ_OK;
 }
 
-int qeq_backward(qeq_plan* plan, const double* dL_dq, double dL_dEqeq, double dL_dEelec,
+int qeq_backward(qeq_plan* plan, const double* dL_dq, double dL_dEelec, double dL_dEqeq,
                  double* dL_dchi, double* dL_dJ, double* dL_dpos, qeq_stats* stats) {
     if (!plan) return QEQ_EINVAL;
-    int rc = backward_impl(plan, dL_dq, dL_dEqeq, dL_dEelec, dL_dchi, dL_dJ, dL_dpos, stats);
+    int rc = backward_impl(plan, dL_dq, dL_dEelec, dL_dEqeq, dL_dchi, dL_dJ, dL_dpos, stats);
     if (rc < 0 && stats) {
         memset(stats, 0, sizeof(*stats));
         stats->status = rc;

@@ -39,6 +39,8 @@ class Params(ctypes.Structure):
         ("tol", ctypes.c_double),
         ("max_iter", ctypes.c_int32),
         ("self_correction", ctypes.c_int32),
+        ("precond", ctypes.c_int32),
+        ("spectral_kcut", ctypes.c_double),
     ]
 
 
@@ -188,7 +190,7 @@ class Plan:
     """A solver plan bound to one device and stream (see qeq_plan_create)."""
 
     def __init__(self, n_max, eta=2.0, r_cut=11.0, grid=None, max_spacing=0.8, spline_order=6,
-                 tol=1e-6, max_iter=1000, self_correction=True, stream=None):
+                 tol=1e-6, max_iter=1000, self_correction=True, stream=None, spectral_kcut=0.0):
         import torch
         L = load_library()
         p = default_params()
@@ -198,6 +200,8 @@ class Plan:
             p.grid[a] = int(g[a])
         p.spline_order, p.tol, p.max_iter = spline_order, tol, max_iter
         p.self_correction = 1 if self_correction else 0
+        if spectral_kcut > 0.0:
+            p.precond, p.spectral_kcut = 1, float(spectral_kcut)
         self.params = p
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.stream = stream if stream is not None else torch.cuda.current_stream()
@@ -280,8 +284,9 @@ class Plan:
             raise QEqError(rc, strerror(rc))
         return out
 
-    def backward(self, dL_dq=None, dL_dEqeq=0.0, dL_dEelec=0.0, check=True):
-        """Adjoint gradients (dL/dchi, dL/dJ, dL/dpos, stats) through the last solve."""
+    def backward(self, dL_dq=None, dL_dEelec=0.0, dL_dEqeq=0.0, check=True):
+        """Adjoint gradients (dL/dchi, dL/dJ, dL/dpos, stats) through the last solve;
+        the energy weights come in the C ABI's order, E_elec first."""
         import torch
         n = self._last_n
         if n is None:
@@ -292,7 +297,7 @@ class Plan:
         dJ = torch.empty(n, dtype=torch.float64, device=self.device)
         dpos = torch.empty((n, 3), dtype=torch.float64, device=self.device)
         st = Stats()
-        rc = load_library().qeq_backward(self._h, _ptr(dL_dq), float(dL_dEqeq), float(dL_dEelec),
+        rc = load_library().qeq_backward(self._h, _ptr(dL_dq), float(dL_dEelec), float(dL_dEqeq),
                                          _ptr(dchi), _ptr(dJ), _ptr(dpos), ctypes.byref(st))
         if check and rc < 0:
             raise QEqError(rc, strerror(rc))
@@ -490,7 +495,7 @@ def _autograd_function():
             dq = gq.contiguous() if gq is not None else None
             e_qeq = float(gen[0]) if gen is not None else 0.0
             e_elec = float(gen[1]) if gen is not None else 0.0
-            dchi, dJ, dpos, _ = plan.backward(dq, e_qeq, e_elec)
+            dchi, dJ, dpos, _ = plan.backward(dq, dL_dEelec=e_elec, dL_dEqeq=e_qeq)
             return dpos, dchi, dJ, None, None, None, None
 
     return QEqFunction

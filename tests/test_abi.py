@@ -34,6 +34,7 @@ def test_default_params_and_strerror():
     p = qeq.default_params()
     assert p.eta == 2.0 and p.r_cut == 11.0 and p.spline_order == 6 and p.self_correction == 1
     assert p.tol == 1e-6 and tuple(p.grid) == (0, 0, 0)
+    assert p.precond == 0 and p.spectral_kcut == 0.2
     for code in (0, 1, -1, -2, -3, -4, -5):
         assert qeq.strerror(code) != "unknown status code"
     assert qeq.strerror(42) == "unknown status code"
@@ -50,6 +51,10 @@ def test_plan_create_rejects_bad_params_before_touching_the_device():
     assert L.qeq_plan_create(ctypes.byref(h), ctypes.byref(p), 10, None) == qeq.QEQ_EINVAL
     p.eta = 2.0
     assert L.qeq_plan_create(ctypes.byref(h), ctypes.byref(p), 0, None) == qeq.QEQ_EINVAL
+    p.precond = 2
+    assert L.qeq_plan_create(ctypes.byref(h), ctypes.byref(p), 10, None) == qeq.QEQ_EINVAL
+    p.precond, p.spectral_kcut = 1, float("nan")
+    assert L.qeq_plan_create(ctypes.byref(h), ctypes.byref(p), 10, None) == qeq.QEQ_EINVAL
 
 
 def test_struct_layouts_match_header(tmp_path):
@@ -61,16 +66,17 @@ def test_struct_layouts_match_header(tmp_path):
     src = tmp_path / "layout.c"
     src.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "qeq.h"\n'
-        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu\\n\","
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\","
         "sizeof(qeq_params), offsetof(qeq_params, grid), offsetof(qeq_params, tol),"
-        "offsetof(qeq_params, self_correction), sizeof(qeq_stats), offsetof(qeq_stats, rel_resid),"
-        "offsetof(qeq_stats, mu), offsetof(qeq_stats, e_elec));return 0;}\n")
+        "offsetof(qeq_params, precond), sizeof(qeq_stats), offsetof(qeq_stats, rel_resid),"
+        "offsetof(qeq_stats, mu), offsetof(qeq_stats, e_elec), offsetof(qeq_params, spectral_kcut));"
+        "return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
     P, S = qeq.Params, qeq.Stats
-    want = [ctypes.sizeof(P), P.grid.offset, P.tol.offset, P.self_correction.offset,
-            ctypes.sizeof(S), S.rel_resid.offset, S.mu.offset, S.e_elec.offset]
+    want = [ctypes.sizeof(P), P.grid.offset, P.tol.offset, P.precond.offset,
+            ctypes.sizeof(S), S.rel_resid.offset, S.mu.offset, S.e_elec.offset, P.spectral_kcut.offset]
     assert got == want
 
 

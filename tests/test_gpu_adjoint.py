@@ -47,7 +47,7 @@ def test_adjoint_matches_oracle(dev, which):
     plan = qeq.Plan(s.n, eta=ETA, r_cut=rc, grid=s.grid, tol=1e-9)
     q, en, f, st = plan.solve(T(s.pos, dev), s.cell, T(s.sigma, dev), T(s.J, dev), T(s.chi, dev), s.q_tot)
     dldq = 2 * T(w, dev) * (q - T(q_ref, dev))
-    g_chi, g_J, g_pos, ast = plan.backward(dldq, 0.0, 1.0)
+    g_chi, g_J, g_pos, ast = plan.backward(dldq, dL_dEelec=1.0)
     g_chi, g_J, g_pos = g_chi.cpu().numpy(), g_J.cpu().numpy(), g_pos.cpu().numpy()
     print(which, ast, "dchi", np.abs(g_chi - dchi).max(), "dJ", np.abs(g_J - dJ).max(),
           "dpos", rel_rms(g_pos, dpos))
@@ -70,11 +70,40 @@ def test_adjoint_energy_weights_and_repeat(dev):
     plan = qeq.Plan(s.n, eta=ETA, r_cut=RC, grid=s.grid, tol=1e-9)
     plan.solve(T(s.pos, dev), s.cell, T(s.sigma, dev), T(s.J, dev), T(s.chi, dev), 0.0)
     for _ in range(2):
-        g_chi, g_J, g_pos, st = plan.backward(None, -1.3, 0.7)
+        g_chi, g_J, g_pos, st = plan.backward(None, dL_dEelec=0.7, dL_dEqeq=-1.3)
         assert st["rc"] == 0
         assert np.abs(g_chi.cpu().numpy() - dchi).max() <= 1e-5
         assert np.abs(g_J.cpu().numpy() - dJ).max() <= 1e-5
         assert rel_rms(g_pos.cpu().numpy(), dpos) <= 1e-4
+    plan.close()
+
+
+@pytest.mark.parametrize("weights", [(1.0, 0.0), (0.0, 1.0)])
+def test_backward_scalar_order_through_the_c_abi(dev, weights):
+    """qeq_backward(plan, dL_dq, dL_dEelec, dL_dEqeq, ...) called positionally
+    through the raw C ABI with one energy weight nonzero at a time, checked
+    against the oracle adjoint with that weight: a swap of the two scalars
+    anywhere between the header and the kernels fails one of the two cases."""
+    import ctypes
+    from paper_2607_17978_amd import qeq
+    w_elec, w_qeq = weights
+    s = gen.system_64()
+    _, dchi, dpos, dJ = ewald.qeq_adjoint(s.pos, s.cell, s.sigma, s.J, s.chi, 0.0, np.zeros(s.n),
+                                          dL_dEelec=w_elec, dL_dEqeq=w_qeq)
+    plan = qeq.Plan(s.n, eta=ETA, r_cut=RC, grid=s.grid, tol=1e-9)
+    plan.solve(T(s.pos, dev), s.cell, T(s.sigma, dev), T(s.J, dev), T(s.chi, dev), 0.0)
+    g_chi = torch.empty(s.n, dtype=torch.float64, device=dev)
+    g_J = torch.empty_like(g_chi)
+    g_pos = torch.empty((s.n, 3), dtype=torch.float64, device=dev)
+    st = qeq.Stats()
+    P = lambda t: ctypes.c_void_p(t.data_ptr())
+    rc = qeq.load_library().qeq_backward(plan._h, None, w_elec, w_qeq, P(g_chi), P(g_J), P(g_pos),
+                                         ctypes.byref(st))
+    torch.cuda.synchronize()
+    assert rc == 0 and st.status == 0
+    assert np.abs(g_chi.cpu().numpy() - dchi).max() <= 1e-5
+    assert np.abs(g_J.cpu().numpy() - dJ).max() <= 1e-5
+    assert rel_rms(g_pos.cpu().numpy(), dpos) <= 1e-4
     plan.close()
 
 
@@ -90,7 +119,7 @@ def test_adjoint_against_oracle_finite_differences(dev):
 
     plan = qeq.Plan(s.n, eta=ETA, r_cut=RC, grid=s.grid, tol=1e-9)
     q, _, _, _ = plan.solve(T(s.pos, dev), s.cell, T(s.sigma, dev), T(s.J, dev), T(s.chi, dev), 0.0)
-    g_chi, _, g_pos, _ = plan.backward(2 * T(w, dev) * (q - T(q_ref, dev)), 0.0, 1.0)
+    g_chi, _, g_pos, _ = plan.backward(2 * T(w, dev) * (q - T(q_ref, dev)), dL_dEelec=1.0)
     g_chi, g_pos = g_chi.cpu().numpy(), g_pos.cpu().numpy()
     h = 1e-5
     scale = np.abs(g_pos).max()
@@ -145,7 +174,7 @@ def test_full_size_directional_derivatives(dev):
         return float((wd * (q - qrd) ** 2).sum()) + float(en[1]), q
 
     L0, q = loss(s.pos, s.chi)
-    dchi, dJ, dpos, st = plan.backward(2.0 * wd * (q - qrd), 0.0, 1.0)
+    dchi, dJ, dpos, st = plan.backward(2.0 * wd * (q - qrd), dL_dEelec=1.0)
     assert st["rc"] == 0
     dchi, dpos = dchi.cpu().numpy(), dpos.cpu().numpy()
     rng = np.random.default_rng(11)

@@ -94,10 +94,10 @@ def test_tape_kept_and_refusals(dev):
         plan.element_potentials(sp, 2)   # no solve yet
     plan.solve(T(s.pos, dev), s.cell, T(s.sigma, dev), T(s.J, dev), T(s.chi, dev), s.q_tot)
     g = T(np.random.default_rng(1).normal(size=s.n), dev)
-    d1 = [t.cpu().numpy() for t in plan.backward(g, 0.3, 0.7)[:3]]
+    d1 = [t.cpu().numpy() for t in plan.backward(g, dL_dEelec=0.7, dL_dEqeq=0.3)[:3]]
     w1 = plan.virial().cpu().numpy()
     G1 = plan.element_potentials(sp, 2)
-    d2 = [t.cpu().numpy() for t in plan.backward(g, 0.3, 0.7)[:3]]
+    d2 = [t.cpu().numpy() for t in plan.backward(g, dL_dEelec=0.7, dL_dEqeq=0.3)[:3]]
     w2 = plan.virial().cpu().numpy()
     G2 = plan.element_potentials(sp, 2)
     for a, b in zip(d1, d2):

@@ -116,10 +116,28 @@ def test_spectral_adjoint_matches_jacobi(dev):
         plan = qeq.Plan(s.n, eta=ETA, r_cut=12.0, grid=s.grid, tol=1e-9)
         plan.use_spectral_preconditioner(kc)
         plan.solve(T(s.pos, dev), s.cell, T(s.sigma, dev), T(s.J, dev), T(s.chi, dev), s.q_tot)
-        dchi, dJ, dpos, st = plan.backward(g, 0.3, 0.7)
+        dchi, dJ, dpos, st = plan.backward(g, dL_dEelec=0.7, dL_dEqeq=0.3)
         out.append((dchi.cpu().numpy(), dpos.cpu().numpy(), st["iters"]))
         plan.close()
     (c0, p0, i0), (c1, p1, i1) = out
     print("adjoint iters Jacobi", i0, "spectral", i1)
     assert np.abs(c1 - c0).max() <= 1e-6 * np.abs(c0).max()
     assert np.abs(p1 - p0).max() <= 1e-5 * np.abs(p0).max()
+
+
+def test_precond_field_of_the_plan_parameters(dev):
+    """qeq_params.precond = 1 with spectral_kcut selects the same preconditioner
+    as qeq_use_spectral_preconditioner: identical iteration count and charges
+    (same kernels, same modes), and the oracle's bars."""
+    from paper_2607_17978_amd import qeq
+    s = gen.system_4096()
+    ref = matfree.qeq_matfree(s.pos, s.cell, s.sigma, s.J, s.chi, s.q_tot, tol=1e-10)
+    q1, en1, f1, st1 = solve(dev, s, 11.0, 0.25)
+    plan = qeq.Plan(s.n, eta=ETA, r_cut=11.0, grid=s.grid, tol=1e-7, spectral_kcut=0.25)
+    assert plan.params.precond == 1
+    q2, en2, f2, st2 = plan.solve(T(s.pos, dev), s.cell, T(s.sigma, dev), T(s.J, dev), T(s.chi, dev), s.q_tot)
+    q2 = q2.cpu().numpy()
+    plan.close()
+    assert st2["iters"] == st1["iters"] and st1["iters"] < 40, (st1["iters"], st2["iters"])
+    assert np.abs(q2 - q1).max() <= 1e-9
+    check(q2, en2.cpu().numpy(), f2.cpu().numpy(), ref)

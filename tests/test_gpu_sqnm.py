@@ -122,10 +122,10 @@ def test_sqnm_history_backward_and_errors(dev):
     w = T(np.random.default_rng(4).uniform(size=s.n), dev)
     plan.use_sqnm(True)
     q1, _, _, _ = plan.solve(*args)
-    g1 = plan.backward(w * q1, 0.0, 1.0)
+    g1 = plan.backward(w * q1, dL_dEelec=1.0)
     plan.use_sqnm(False)
     q2, _, _, _ = plan.solve(*args)
-    g2 = plan.backward(w * q2, 0.0, 1.0)
+    g2 = plan.backward(w * q2, dL_dEelec=1.0)
     for a, b in zip(g1[:3], g2[:3]):
         a, b = a.cpu().numpy(), b.cpu().numpy()
         assert np.abs(a - b).max() <= 1e-5 * max(1.0, np.abs(b).max())

@@ -65,7 +65,7 @@ def periodic_run(dev, s, rc, spectral=0.0, ewald=False, extras=True, planewave=F
         if extras and not ewald and not planewave:
             out["virial"] = plan.virial().cpu().numpy()
             w = np.random.default_rng(3).uniform(size=s.n)
-            dchi, dJ, dpos, st_b = plan.backward(T(w * (q.cpu().numpy() - 0.1), dev), 0.0, 1.0)
+            dchi, dJ, dpos, st_b = plan.backward(T(w * (q.cpu().numpy() - 0.1), dev), dL_dEelec=1.0)
             out.update(dchi=dchi.cpu().numpy(), dJ=dJ.cpu().numpy(), dpos=dpos.cpu().numpy())
             out["gamma"] = plan.element_potentials(T(s.species, dev, torch.int32), 2).cpu().numpy()
         plan.close()
