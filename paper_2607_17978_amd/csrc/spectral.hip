@@ -68,6 +68,7 @@ typedef double spc_d4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ unsigned short spc_bf16(float x) {   // round to nearest even
     unsigned u = __float_as_uint(x);
+    if ((u & 0x7FFFFFFFu) > 0x7F800000u) return (unsigned short)((u >> 16) | 0x40u);   // NaN stays a (quiet) NaN
     u += 0x7FFFu + ((u >> 16) & 1u);
     return (unsigned short)(u >> 16);
 }
