@@ -43,8 +43,24 @@ def chi_features(plan, posd, cell, sigma, chi):
     return torch.cat([chi.float()[:, None], Gc, Gg], 1).contiguous()
 
 
+PROFILE_KINDS_MESH = 9   # kinds 0..8 of qeq_profile: the mesh passes, interpolation, CG, final pass
+
+
 def run_trajectory(n=None, side=None, spacing=None, frames=200, epochs=30, lr=2e-3, tol=1e-6,
-                   grid=None, log=None, device=None, spectral_kc=0.0):
+                   grid=None, log=None, device=None, spectral_kc=0.0, train_frames=None,
+                   chi_override=None, keep_frame=None, profile_matvec=False):
+    """Run the trajectory workflow and return its record.
+
+    train_frames: frames solved cold for training (default frames // 2).
+    chi_override: {frame: chi (numpy, n)} replaces the workload's
+    electronegativities of those frames (e.g. values computed elsewhere for a
+    parity check); the network inputs still come from the frame's geometry.
+    keep_frame: an evaluation frame whose charges, energies and forces of
+    every start are returned (numpy) under "kept".
+    profile_matvec: after the last frame, one more cold solve of it with every
+    launch kind bracketed by HIP events (kernels launched one by one); the
+    per-launch microseconds are returned under "stage_us".
+    """
     import torch
 
     from inputs import gen
@@ -70,7 +86,7 @@ def run_trajectory(n=None, side=None, spacing=None, frames=200, epochs=30, lr=2e
     net_x = qeq.WarmStartNet(gen.warmstart_init(1005, 2), device=dev)
     chi_w = gen.chi_network_weights(1004)
     sig_d, J_d, sp_d = T(sigma), T(J), T(species, torch.int32)
-    n_train = frames // 2
+    n_train = frames // 2 if train_frames is None else int(train_frames)
     scaling = y_std = None
     train_G, train_X, train_q = [], [], []
     variants = ["cold", "prev", "learned", "learned_chi"]
@@ -79,12 +95,18 @@ def run_trajectory(n=None, side=None, spacing=None, frames=200, epochs=30, lr=2e
     rec = {k: [] for k in variants}
     q_prev = None
 
-    def solve(posd, chid, q0=None, pl=None):
+    kept = {}
+
+    def solve(posd, chid, q0=None, pl=None, keep=None):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        q, en, _, st = (pl or plan).solve(posd, cell, sig_d, J_d, chid, 0.0, q0=q0, forces=False)
+        q, en, f, st = (pl or plan).solve(posd, cell, sig_d, J_d, chid, 0.0, q0=q0, forces=keep is not None)
         torch.cuda.synchronize()
-        return q, st, (time.perf_counter() - t0) * 1e3
+        ms = (time.perf_counter() - t0) * 1e3
+        if keep is not None:
+            kept[keep] = {"q": q.cpu().numpy(), "energies": en.cpu().numpy(), "forces": f.cpu().numpy(),
+                          "iters": st["iters"], "rc": st["rc"], "q0_rejected": st["q0_rejected"]}
+        return q, st, ms
 
     t_desc, t_feat, t_pred, t_pred_x, max_dq = [], [], [], [], 0.0
     for t in range(frames):
@@ -97,6 +119,8 @@ def run_trajectory(n=None, side=None, spacing=None, frames=200, epochs=30, lr=2e
         torch.cuda.synchronize()
         t_desc.append((time.perf_counter() - t0) * 1e3)
         chi, scaling, y_std = gen.chi_from_descriptors(G.cpu().numpy(), species, chi_w, scaling, y_std)
+        if chi_override is not None and t in chi_override:
+            chi = np.asarray(chi_override[t], dtype=np.float64)
         chid = T(chi)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -132,20 +156,21 @@ def run_trajectory(n=None, side=None, spacing=None, frames=200, epochs=30, lr=2e
                 if log:
                     log(f"trained {epochs} epochs in {rec['train_s']:.1f} s, loss {rec['train_loss']:.3e}")
             continue
-        q_c, st_c, ms_c = solve(posd, chid)
-        q_p, st_p, ms_p = solve(posd, chid, q0=q_prev)
+        kf = (lambda name: name) if t == keep_frame else (lambda name: None)
+        q_c, st_c, ms_c = solve(posd, chid, keep=kf("cold"))
+        q_p, st_p, ms_p = solve(posd, chid, q0=q_prev, keep=kf("prev"))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         q0 = net.predict(G, sp_d)
         torch.cuda.synchronize()
         t_pred.append((time.perf_counter() - t0) * 1e3)
-        q_l, st_l, ms_l = solve(posd, chid, q0=q0)
+        q_l, st_l, ms_l = solve(posd, chid, q0=q0, keep=kf("learned"))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         q0x = net_x.predict(X, sp_d)
         torch.cuda.synchronize()
         t_pred_x.append((time.perf_counter() - t0) * 1e3)
-        q_x, st_x, ms_x = solve(posd, chid, q0=q0x)
+        q_x, st_x, ms_x = solve(posd, chid, q0=q0x, keep=kf("learned_chi"))
         dq_p, dq_l = float((q_p - q_c).abs().max()), float((q_l - q_c).abs().max())
         dq_x = float((q_x - q_c).abs().max())
         max_dq = max(max_dq, dq_p, dq_l, dq_x)
@@ -153,7 +178,7 @@ def run_trajectory(n=None, side=None, spacing=None, frames=200, epochs=30, lr=2e
                 ("learned_chi", st_x, ms_x)]
         if plan_s is not None:
             for k, q0s in (("cold_spectral", None), ("prev_spectral", q_prev), ("learned_chi_spectral", q0x)):
-                q_s, st_s, ms_s = solve(posd, chid, q0=q0s, pl=plan_s)
+                q_s, st_s, ms_s = solve(posd, chid, q0=q0s, pl=plan_s, keep=kf(k))
                 max_dq = max(max_dq, float((q_s - q_c).abs().max()))
                 runs.append((k, st_s, ms_s))
         for k, st, ms in runs:
@@ -165,6 +190,15 @@ def run_trajectory(n=None, side=None, spacing=None, frames=200, epochs=30, lr=2e
                 f"max|dq| {max_dq:.1e}; rms |q0 - q| learned "
                 f"{float((q0 - q_c).pow(2).mean().sqrt()):.2e} learned_chi "
                 f"{float((q0x - q_c).pow(2).mean().sqrt()):.2e}")
+    stage = None
+    if profile_matvec:
+        plan.profile((1 << PROFILE_KINDS_MESH) - 1)
+        plan.profile_read(reset=True)
+        for _ in range(2):
+            plan.solve(posd, cell, sig_d, J_d, chid, 0.0, forces=False)
+        d = plan.profile_read(reset=True)
+        plan.profile(0)
+        stage = {k: (ms * 1e3 / c if c else 0.0, int(c)) for k, (ms, c) in d.items()}
     plan.close()
     if plan_s is not None:
         plan_s.close()
@@ -178,6 +212,11 @@ def run_trajectory(n=None, side=None, spacing=None, frames=200, epochs=30, lr=2e
            "train_steps": rec.get("train_steps")}
     if plan_s is not None:
         out["spectral_kc"] = spectral_kc
+    if stage is not None:
+        out["stage_us"] = stage
+    if kept:
+        out["kept"] = kept
+        out["kept_frame"] = keep_frame
     for k in variants:
         a = np.array(rec[k], dtype=float)
         out[k] = {"iters": float(a[:, 0].mean()), "ms": float(a[:, 1].mean()),
