@@ -199,6 +199,7 @@ int qeq_virial(qeq_plan* plan, double* virial);
    matrix-vector product of eq. matvec on its own.  parts is a bit mask:
    1 reciprocal (mesh) part, 2 real-space pair part, 4 self terms (Gaussian
    self energy and mesh self-correction), 8 background term; 15 = all of E.
+   The mesh part takes the path of the CG products (see qeq_use_fused_interp).
    v, y: n doubles on the device. */
 int qeq_matvec(qeq_plan* plan, int32_t n, const double* pos, const double* cell,
                const double* sigma, const double* v, double* y, int32_t parts);
@@ -329,6 +330,18 @@ int qeq_use_graphs(qeq_plan* plan, int32_t enable);
    trip); enable = 0 runs them as two passes.  Both give the same potential
    up to FP32 rounding.  Default on. */
 int qeq_use_fused_inverse(qeq_plan* plan, int32_t enable);
+
+/* The CG products of qeq_solve / qeq_backward: enable != 0 (default) runs the
+   axis-3 complex-to-real transform of each (g1, row-tile) block and the
+   back-interpolation of eq. matvec (sum_g theta_i(g) phi(g)) over that tile in
+   one pass, so the real potential grid is neither written nor read again;
+   each atom's 2p tile partials are summed in a fixed order with its
+   real-space pair product.  enable = 0 writes the potential grid and
+   interpolates from it (the path the final energies and forces always use).
+   Both give the same product up to FP32 rounding order.  Applies where the
+   axis-2 tile is at least p - 1 rows wide (every supported grid with p <= 8
+   at 8- or 16-row tiles). */
+int qeq_use_fused_interp(qeq_plan* plan, int32_t enable);
 
 /* Reciprocal-space method of later qeq_solve calls on this plan: enable = 0
    (default) the particle mesh (B-spline spreading, FFT, Green's function,

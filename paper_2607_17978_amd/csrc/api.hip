@@ -551,8 +551,9 @@ int cg_matvec(qeq_plan* pl, const double* src, int parity) {
         QEQ_TRY(launch_pw_rec(pl, src, &pl->sc->done, false));
         return launch_interp(pl, src, pl->y, QEQ_MODE_CG, parity);
     }
-    QEQ_TRY(launch_mesh_potential(pl, src, &pl->sc->done));
-    return launch_interp(pl, src, pl->y, QEQ_MODE_CG, parity);
+    bool partials = false;
+    QEQ_TRY(launch_mesh_cg(pl, src, &pl->sc->done, &partials));
+    return launch_interp(pl, src, pl->y, QEQ_MODE_CG, parity, partials ? pl->mpart : nullptr);
 }
 
 int cg_iteration(qeq_plan* pl, int parity) {
@@ -854,6 +855,7 @@ int qeq_plan_create(qeq_plan** out, const qeq_params* params, int32_t n_atoms_ma
     A(dalloc(&pl->chi_adj, n));
     A(dalloc(&pl->adj_scratch, 3 * n));
     A(dalloc(&pl->tq, 3 * n));
+    A(dalloc(&pl->mpart, 2 * QEQ_MAXP * n));
     pl->fdst = pl->forces_s;
     A(dalloc(&pl->rowptr, n + 1));
     A(dalloc(&pl->cell_atoms, n));
@@ -891,7 +893,7 @@ int qeq_plan_destroy(qeq_plan* pl) {
     dfree(pl->sig); dfree(pl->Jv); dfree(pl->chi); dfree(pl->chi_raw); dfree(pl->dself); dfree(pl->dinv);
     dfree(pl->selfgrad); dfree(pl->q); dfree(pl->r); dfree(pl->pvec); dfree(pl->y); dfree(pl->forces_s);
     dfree(pl->gtmp); dfree(pl->q_adj); dfree(pl->y_adj); dfree(pl->chi_adj); dfree(pl->adj_scratch); dfree(pl->tq); dfree(pl->rowptr); dfree(pl->rowcnt); dfree(pl->theta_tab); dfree(pl->part);
-    dfree(pl->strain_tab); dfree(pl->vir_part);
+    dfree(pl->strain_tab); dfree(pl->vir_part); dfree(pl->mpart);
     spc_free(pl);
     np_free(pl);
     ew_free(pl);
@@ -968,8 +970,10 @@ int qeq_matvec(qeq_plan* plan, int32_t n, const double* pos, const double* cell,
     QEQ_TRY(setup_geometry(pl, pos, sigma, nullptr, nullptr));
     pl->kp.parts = parts;
     QEQ_TRY(launch_matvec_io(pl, v, nullptr, 0));
-    if (parts & QEQ_PART_RECIP) QEQ_TRY(launch_mesh_potential(pl, pl->pvec, nullptr));
-    QEQ_TRY(launch_interp(pl, pl->pvec, pl->y, QEQ_MODE_MATVEC, 0));
+    // the CG product's mesh path (fused interpolation where it applies)
+    bool partials = false;
+    if (parts & QEQ_PART_RECIP) QEQ_TRY(launch_mesh_cg(pl, pl->pvec, nullptr, &partials));
+    QEQ_TRY(launch_interp(pl, pl->pvec, pl->y, QEQ_MODE_MATVEC, 0, partials ? pl->mpart : nullptr));
     QEQ_TRY(launch_matvec_io(pl, nullptr, y, 1));
     QEQ_HIP(hipStreamSynchronize(pl->stream));
     pl->kp.parts = 15;
@@ -1036,6 +1040,14 @@ int qeq_use_fused_inverse(qeq_plan* plan, int32_t enable) {
     if (!plan) return QEQ_EINVAL;
     if (plan->stream) (void)hipStreamSynchronize(plan->stream);
     plan->fused_inverse = enable != 0;
+    drop_graph(plan);
+    return QEQ_OK;
+}
+
+int qeq_use_fused_interp(qeq_plan* plan, int32_t enable) {
+    if (!plan) return QEQ_EINVAL;
+    if (plan->stream) (void)hipStreamSynchronize(plan->stream);
+    plan->fused_interp = enable != 0;
     drop_graph(plan);
     return QEQ_OK;
 }

@@ -279,6 +279,8 @@ struct qeq_plan {
     double* pw_f = nullptr;       // forces of the final product, sorted order
     double* pw_smax = nullptr;    // per-block maxima of sigma (host read once per set-up)
     bool fused_inverse = true;    // fused inverse axis-2 + complex-to-real slab pass where it fits
+    bool fused_interp = true;     // CG products: complex-to-real pass fused with the interpolation
+    float* mpart = nullptr;       // [2 MAXP][n_max] interpolation partials of the fused pass
 
     // the CG loop is replayed as a HIP graph of one chunk of iterations,
     // captured on a private stream and re-captured when its arguments change
@@ -395,6 +397,10 @@ int launch_rhs_norm(qeq_plan* pl, const double* b);
 // ------------------------------------------------------------------ mesh kernels (mesh.hip)
 // Reciprocal potential of the charges src (sorted, FP64): real grid phi in grid_r.
 int launch_mesh_potential(qeq_plan* pl, const double* src, const int* done);
+// The CG product's mesh part: as launch_mesh_potential, or, where the fused
+// complex-to-real + interpolation pass applies, the per-atom interpolation
+// partials in pl->mpart instead of the real grid (*partials = true).
+int launch_mesh_cg(qeq_plan* pl, const double* src, const int* done, bool* partials);
 size_t qeq_mesh_max_smem(const KParams& k);
 // Inverse transforms only (grid_c already holds a spectrum) -> grid_r.
 int launch_mesh_inverse(qeq_plan* pl);
@@ -412,7 +418,8 @@ int launch_mesh_virial(qeq_plan* pl, const double* src, double* part);
 int mesh_virial_blocks(const KParams& k);
 
 // ------------------------------------------------------------------ solver kernels (solve.hip)
-int launch_interp(qeq_plan* pl, const double* src, double* dst, int mode, int parity);
+int launch_interp(qeq_plan* pl, const double* src, double* dst, int mode, int parity,
+                  const float* mpart = nullptr);
 int launch_cg_init_q(qeq_plan* pl, const double* q0);
 int launch_cg_init_r(qeq_plan* pl);
 int launch_start_energy(qeq_plan* pl);

@@ -413,6 +413,168 @@ __global__ __launch_bounds__(NT) void k_c2r(KParams k, FftAxis ax3, const float2
     }
 }
 
+// ------------------------------------------------------------------ pass 5 fused with interpolation
+// The complex-to-real pass of a (g1, TW-row) tile followed, while the tile's
+// potential is still in LDS, by the part of every atom's back-interpolation
+// (eq. matvec: the integral of the potential over the atom's charge
+// distribution, here sum_g theta_i(g) phi(g)) that falls on this tile, so the
+// real grid is never written or read again:
+//   partial = w1(k1) sum_{k2: row in tile} w2(k2) sum_k3 w3(k3) phi(g1, h2 - k2, h3 - k3)
+// for every atom with h1 = g1 + k1 (k1 < p) whose rows h2 - p + 1 .. h2 meet
+// the tile (TW >= p - 1, so at most two tiles).  Each partial goes to its own
+// slot, mpart[(2 k1 + t) n + atom] with t = 0 for the tile holding row h2 and
+// t = 1 for the tile before it (written as 0 by the first when the atom's rows
+// all lie in one tile): 2p FP32 partials per atom, summed in a fixed order by
+// the pair-product kernel, so the result does not depend on block timing.
+template <int KC, int TWC, int PC>
+__global__ __launch_bounds__(NT) void k_c2r_interp(KParams k, FftAxis ax3, const float2* __restrict__ C,
+                                                  const int* __restrict__ bin_start,
+                                                  const int* __restrict__ home,
+                                                  const float* __restrict__ wts, float* __restrict__ mpart,
+                                                  const int* __restrict__ done) {
+    if (done && *done) return;
+    extern __shared__ float2 sm[];
+    constexpr bool CT = KC > 0 && TWC > 0;
+    const int K3 = KC ? KC : k.K3;
+    const int TW = TWC ? TWC : k.TW;
+    const int p = PC ? PC : k.p;
+    const int K3h = K3 / 2 + 1;
+    const int K1 = k.K1, K2 = k.K2;
+    const int ncol = TW >> 1;
+    const int twl = ilog2_dev(TW);
+    const int ncl = twl - 1;
+    float2* tw = sm;
+    float2* X = sm + K3;
+    // compile-time sizes: the packed rows Z (K3 x TW/2) replace X (K3/2 + 1
+    // rows of TW) in place through registers, halving the block's LDS
+    float2* Z = CT ? X : X + K3h * TW;
+    __shared__ int seg_lo[2 * QEQ_MAXP], seg_len[2 * QEQ_MAXP], seg_off[2 * QEQ_MAXP + 1];
+    const int tid = threadIdx.x;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int g1 = blk / k.ntile;
+    const int g20 = (blk - g1 * k.ntile) * TW;
+    // candidate segments (as in the spread pass): homes h1 = g1 + k1,
+    // h2 in [g20, g20 + TW + p - 1), two pieces when the range wraps
+    if (tid < p) {
+        const int k1 = tid;
+        int h1 = g1 + k1;
+        if (h1 >= K1) h1 -= K1;
+        const int b0 = h1 * K2;
+        const int hi = g20 + TW + p - 1;
+        const int e1 = hi < K2 ? hi : K2;
+        const int lo0 = bin_start[b0 + g20];
+        seg_lo[2 * k1] = lo0;
+        seg_len[2 * k1] = bin_start[b0 + e1] - lo0;
+        if (hi > K2) {
+            const int lo1 = bin_start[b0];
+            seg_lo[2 * k1 + 1] = lo1;
+            seg_len[2 * k1 + 1] = bin_start[b0 + (hi - K2)] - lo1;
+        } else {
+            seg_lo[2 * k1 + 1] = 0;
+            seg_len[2 * k1 + 1] = 0;
+        }
+    }
+    for (int t = tid; t < K3; t += NT) tw[t] = ax3.tw[t];
+    for (int t = tid; t < K3h * TW; t += NT) {
+        const int r = t & (TW - 1), m = t >> twl;
+        X[t] = C[((size_t)m * K1 + g1) * K2 + g20 + r];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int off = 0;
+        for (int sg = 0; sg < 2 * p; ++sg) {
+            seg_off[sg] = off;
+            off += seg_len[sg];
+        }
+        seg_off[2 * p] = off;
+    }
+    // Z = X_even + i X_odd over the full axis (Hermitian extension)
+    auto zval = [&](int t) {
+        const int pr = t & (ncol - 1), m = t >> ncl;
+        float2 xa, xb;
+        if (2 * m <= K3) {
+            xa = X[m * TW + 2 * pr];
+            xb = X[m * TW + 2 * pr + 1];
+        } else {
+            xa = X[(K3 - m) * TW + 2 * pr];
+            xb = X[(K3 - m) * TW + 2 * pr + 1];
+            xa.y = -xa.y;
+            xb.y = -xb.y;
+        }
+        return make_float2(xa.x - xb.y, xa.y + xb.x);
+    };
+    if constexpr (CT) {
+        constexpr int NZ = KC * (TWC / 2);
+        constexpr int PER = (NZ + NT - 1) / NT;
+        float2 zr[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u)
+            if (tid + u * NT < NZ) zr[u] = zval(tid + u * NT);
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < PER; ++u)
+            if (tid + u * NT < NZ) Z[tid + u * NT] = zr[u];
+    } else {
+        for (int t = tid; t < K3 * ncol; t += NT) Z[t] = zval(t);
+    }
+    __syncthreads();
+    // the first round's candidate is fetched before the transform so that its
+    // loads overlap it
+    const int ncand = seg_off[2 * p];
+    const int n = k.n;
+    constexpr int PM = PC ? PC : QEQ_MAXP;
+    float w1 = 0.f, w2[PM], w3[PM];
+    int a = 0, k1 = 0, h2 = 0, h3 = 0;
+    auto load_cand = [&](int cidx) {
+        int sg = 0;
+        while (cidx >= seg_off[sg + 1]) ++sg;
+        k1 = sg >> 1;
+        a = seg_lo[sg] + (cidx - seg_off[sg]);
+        const float* w = wts + (size_t)a * 3 * QEQ_MAXP;
+        w1 = w[k1];
+#pragma unroll
+        for (int kk = 0; kk < PM; ++kk) {
+            if (!PC && kk >= p) break;
+            w2[kk] = w[QEQ_MAXP + kk];
+            w3[kk] = w[2 * QEQ_MAXP + kk];
+        }
+        h2 = home[4 * a + 1];
+        h3 = home[4 * a + 2];
+    };
+    if (tid < ncand) load_cand(tid);
+    if constexpr (CT)
+        fft_ct<KC, TWC / 2, TWC / 2, NT, true>(Z, tw, tid);
+    else
+        fft_lds(Z, ax3, ncl, tw, true, tid, NT);
+    // phi(g1, g20 + r, g3) = zf[(g3 ncol + r / 2) 2 + r % 2]
+    const float* zf = reinterpret_cast<const float*>(Z);
+    for (int cidx = tid; cidx < ncand; cidx += NT) {
+        if (cidx != tid) load_cand(cidx);
+        int d = h2 - g20;
+        if (d < 0) d += K2;
+        float s = 0.f;
+#pragma unroll
+        for (int k2 = 0; k2 < PM; ++k2) {
+            if (!PC && k2 >= p) break;
+            const int r = d - k2;
+            if (r < 0 || r >= TW) continue;
+            const float* zr = zf + (r >> 1) * 2 + (r & 1);
+            float t = 0.f;
+#pragma unroll
+            for (int k3 = 0; k3 < PM; ++k3) {
+                if (!PC && k3 >= p) break;
+                int g3 = h3 - k3;
+                if (g3 < 0) g3 += K3;
+                t += w3[k3] * zr[g3 * ncol * 2];
+            }
+            s += w2[k2] * t;
+        }
+        const int slot = 2 * k1 + (d < TW ? 0 : 1);
+        mpart[(size_t)slot * n + a] = w1 * s;
+        if (d < TW && d >= p - 1) mpart[(size_t)(slot + 1) * n + a] = 0.f;
+    }
+}
+
 // ------------------------------------------------------------------ passes 4 + 5 fused
 // Inverse axis-2 and axis-3 complex-to-real transforms of one g1 slab in LDS,
 // for grids whose slab half spectrum K2 (K3/2 + 1) fits (one block per CU):
@@ -425,12 +587,21 @@ __global__ __launch_bounds__(NT) void k_c2r(KParams k, FftAxis ax3, const float2
 //   (both IFFT(E) and IFFT(O) are real because the line is),
 //   store R[g1][g2][g3] as pairs.  Saves the grid round trip between the two
 //   separate passes.
+//   INTERP: instead of storing the slab, every atom whose spline support meets
+//   plane g1 (h1 = g1 + k1, k1 < p) takes its partial back-interpolation
+//   w1(k1) sum_k2 w2(k2) sum_k3 w3(k3) phi(g1, h2 - k2, h3 - k3) from the slab
+//   in LDS into slot 2 k1 of mpart (slot 2 k1 + 1 = 0: the whole plane is
+//   here), as the fused tile pass does.
 constexpr int SLAB_NT = 1024;
 
-template <int K2C, int K3C>
+template <int K2C, int K3C, bool INTERP = false>
 __global__ __launch_bounds__(SLAB_NT) void k_slab_inv(KParams k, FftAxis ax2, FftAxis ax3,
                                                      const float2* __restrict__ C, float* __restrict__ R,
-                                                     const int* __restrict__ done) {
+                                                     const int* __restrict__ done,
+                                                     const int* __restrict__ bin_start = nullptr,
+                                                     const int* __restrict__ home = nullptr,
+                                                     const float* __restrict__ wts = nullptr,
+                                                     float* __restrict__ mpart = nullptr) {
     if (done && *done) return;
     constexpr int K3H = K3C / 2 + 1;
     constexpr int KS = K3H;
@@ -476,10 +647,44 @@ __global__ __launch_bounds__(SLAB_NT) void k_slab_inv(KParams k, FftAxis ax2, Ff
     }
     __syncthreads();
     fft_ct<NH, K2C, 1, SLAB_NT, true, 0, 1, KS>(X, twh, tid);
-    float2* R2 = reinterpret_cast<float2*>(R) + (size_t)g1 * K2C * NH;
-    for (int t = tid; t < K2C * NH; t += SLAB_NT) {
-        const int g2 = t / NH, n = t - g2 * NH;
-        R2[t] = X[g2 * KS + n];
+    if constexpr (!INTERP) {
+        float2* R2 = reinterpret_cast<float2*>(R) + (size_t)g1 * K2C * NH;
+        for (int t = tid; t < K2C * NH; t += SLAB_NT) {
+            const int g2 = t / NH, n = t - g2 * NH;
+            R2[t] = X[g2 * KS + n];
+        }
+    } else {
+        // phi(g1, g2, g3) = xf[2 KS g2 + g3]
+        const float* xf = reinterpret_cast<const float*>(X);
+        constexpr int P = 6;
+        const int n = k.n;
+        for (int k1 = 0; k1 < P; ++k1) {
+            int h1 = g1 + k1;
+            if (h1 >= K1) h1 -= K1;
+            const int lo = bin_start[h1 * K2C], hi = bin_start[(h1 + 1) * K2C];
+            for (int a = lo + tid; a < hi; a += SLAB_NT) {
+                const float* w = wts + (size_t)a * 3 * QEQ_MAXP;
+                const int h2 = home[4 * a + 1];
+                const int h3 = home[4 * a + 2];
+                float s = 0.f;
+#pragma unroll
+                for (int k2 = 0; k2 < P; ++k2) {
+                    int g2 = h2 - k2;
+                    if (g2 < 0) g2 += K2C;
+                    const float* row = xf + 2 * KS * g2;
+                    float t = 0.f;
+#pragma unroll
+                    for (int k3 = 0; k3 < P; ++k3) {
+                        int g3 = h3 - k3;
+                        if (g3 < 0) g3 += K3C;
+                        t += w[2 * QEQ_MAXP + k3] * row[g3];
+                    }
+                    s += w[QEQ_MAXP + k2] * t;
+                }
+                mpart[(size_t)(2 * k1) * n + a] = w[k1] * s;
+                mpart[(size_t)(2 * k1 + 1) * n + a] = 0.f;
+            }
+        }
     }
 }
 
@@ -723,6 +928,32 @@ int c2r_pass(qeq_plan* pl, const int* done) {
     return qeq_check(hipGetLastError());
 }
 
+// The complex-to-real pass fused with the back-interpolation (2p partials per
+// atom in pl->mpart); needs TW >= p - 1 (at most two tiles per atom).
+bool c2r_interp_available(const qeq_plan* pl) {
+    const KParams& k = pl->kp;
+    return pl->fused_interp && k.TW >= k.p - 1 && k.K2 >= k.TW + k.p - 1 && pl->mpart != nullptr;
+}
+
+int c2r_interp_pass(qeq_plan* pl, const int* done) {
+    const KParams& k = pl->kp;
+    dim3 g(k.K1 * k.ntile), b(NT);
+    const size_t sh = smem_c2r(k);
+    const size_t sh_ct = sizeof(float2) * ((size_t)k.K3 + (size_t)k.K3h * k.TW);   // Z in place of X
+    ProfScope ps(pl, PK_C2R);
+#define X(KK, TT)                                                                                  \
+    if (k.K3 == KK && k.TW == TT && k.p == 6) {                                                     \
+        hipExtLaunchKernelGGL((k_c2r_interp<KK, TT, 6>), g, b, sh_ct, pl->stream, ps.start(), ps.stop(), 0, k, \
+                              pl->axes.ax[2], pl->grid_c, pl->bin_start, pl->home, pl->wts, pl->mpart, done); \
+        return qeq_check(hipGetLastError());                                                       \
+    }
+    QEQ_FOR_EACH_SIZE(X)
+#undef X
+    hipExtLaunchKernelGGL((k_c2r_interp<0, 0, 0>), g, b, sh, pl->stream, ps.start(), ps.stop(), 0, k, pl->axes.ax[2],
+                          pl->grid_c, pl->bin_start, pl->home, pl->wts, pl->mpart, done);
+    return qeq_check(hipGetLastError());
+}
+
 size_t smem_slab(int K2, int K3) {
     return sizeof(float2) * ((size_t)K2 + K3 + K3 / 2 + (size_t)K2 * (K3 / 2 + 1));
 }
@@ -739,6 +970,28 @@ bool slab_available(const qeq_plan* pl) {
     return false;
 }
 
+int slab_interp_pass(qeq_plan* pl, const int* done) {
+    const KParams& k = pl->kp;
+    ProfScope ps(pl, PK_C2R);
+#define X(A, B)                                                                                    \
+    if (k.K2 == A && k.K3 == B && k.p == 6) {                                                      \
+        const size_t sh = smem_slab(A, B);                                                         \
+        QEQ_HIP(hipFuncSetAttribute((const void*)k_slab_inv<A, B, true>,                           \
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));         \
+        hipExtLaunchKernelGGL((k_slab_inv<A, B, true>), dim3(k.K1), dim3(SLAB_NT), sh, pl->stream, ps.start(), \
+                              ps.stop(), 0, k, pl->axes.ax[1], pl->axes.ax[2], pl->grid_c, pl->grid_r, done, \
+                              pl->bin_start, pl->home, pl->wts, pl->mpart);                         \
+        return qeq_check(hipGetLastError());                                                       \
+    }
+    QEQ_FOR_EACH_SLAB(X)
+#undef X
+    return QEQ_EPLAN;
+}
+
+bool slab_interp_available(const qeq_plan* pl) {
+    return slab_available(pl) && pl->fused_interp && pl->kp.p == 6 && pl->mpart != nullptr;
+}
+
 int slab_inv_pass(qeq_plan* pl, const int* done) {
     const KParams& k = pl->kp;
     ProfScope ps(pl, PK_C2R);
@@ -748,7 +1001,8 @@ int slab_inv_pass(qeq_plan* pl, const int* done) {
         QEQ_HIP(hipFuncSetAttribute((const void*)k_slab_inv<A, B>,                                 \
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));         \
         hipExtLaunchKernelGGL((k_slab_inv<A, B>), dim3(k.K1), dim3(SLAB_NT), sh, pl->stream, ps.start(), \
-                              ps.stop(), 0, k, pl->axes.ax[1], pl->axes.ax[2], pl->grid_c, pl->grid_r, done); \
+                              ps.stop(), 0, k, pl->axes.ax[1], pl->axes.ax[2], pl->grid_c, pl->grid_r, done, \
+                              nullptr, nullptr, nullptr, nullptr);                                  \
         return qeq_check(hipGetLastError());                                                       \
     }
     QEQ_FOR_EACH_SLAB(X)
@@ -778,6 +1032,19 @@ int launch_mesh_potential(qeq_plan* pl, const double* src, const int* done) {
     QEQ_TRY(rows_pass(pl, 0, done));
     QEQ_TRY(cols_pass(pl, MESH_FWD | MESH_GREEN | MESH_INV, nullptr, done));
     return inverse_tail(pl, done);
+}
+
+int launch_mesh_cg(qeq_plan* pl, const double* src, const int* done, bool* partials) {
+    *partials = false;
+    const bool slab = slab_interp_available(pl);
+    if (!slab && !c2r_interp_available(pl)) return launch_mesh_potential(pl, src, done);
+    QEQ_TRY(spread_pass(pl, src, done));
+    QEQ_TRY(rows_pass(pl, 0, done));
+    QEQ_TRY(cols_pass(pl, MESH_FWD | MESH_GREEN | MESH_INV, nullptr, done));
+    *partials = true;
+    if (slab) return slab_interp_pass(pl, done);
+    QEQ_TRY(rows_pass(pl, 1, done));
+    return c2r_interp_pass(pl, done);
 }
 
 int launch_mesh_from_spectrum(qeq_plan* pl, const int* done) {

@@ -31,7 +31,7 @@ __global__ __launch_bounds__(QEQ_BLOCK) void k_interp(
     const float4* __restrict__ pdr, const double* __restrict__ dself, const double* __restrict__ Jv,
     const double* __restrict__ chi_raw, const double* __restrict__ chi_eff, const double* __restrict__ sig,
     const double* __restrict__ selfgrad, double* __restrict__ forces, double* __restrict__ gvec,
-    double* __restrict__ part, CgScalars* __restrict__ sc, int parity) {
+    double* __restrict__ part, CgScalars* __restrict__ sc, int parity, const float* __restrict__ mpart) {
     if (MODE == QEQ_MODE_CG && sc->done) return;
     constexpr bool FIN = MODE == QEQ_MODE_FINAL;
     const int lane = threadIdx.x & 63;
@@ -67,7 +67,9 @@ __global__ __launch_bounds__(QEQ_BLOCK) void k_interp(
         // kernel values, the lane's grid line and weights; then the source
         // values of those columns.  Arithmetic follows.
         constexpr int PM = PC ? PC : QEQ_MAXP;
-        const bool do_recip = (k.parts & QEQ_PART_RECIP) && lane < p * p;
+        // mesh part already interpolated by the fused complex-to-real pass:
+        // lanes < 2p hold its per-atom partials
+        const bool do_recip = (k.parts & QEQ_PART_RECIP) && lane < p * p && !mpart;
         const bool do_real = (k.parts & QEQ_PART_REAL) != 0;
         const int e0 = cur_e0, e1 = cur_e1;
         const int h1 = cur_h1, h2 = cur_h2, h3 = cur_h3;
@@ -122,6 +124,7 @@ __global__ __launch_bounds__(QEQ_BLOCK) void k_interp(
             nx_h3 = home[4 * in + 2];
         }
         const double vj = has_pair ? src[cj] : 0.0;
+        if (mpart && (k.parts & QEQ_PART_RECIP) && lane < 2 * p) v[0] = (double)mpart[(size_t)lane * k.n + i];
         if (do_recip) {
             float s = 0.f, s1 = 0.f;
 #pragma unroll
@@ -446,13 +449,13 @@ static double* part_buf(qeq_plan* pl, int which) { return pl->part + (size_t)whi
 
 template <int MODE>
 static void interp_launch(qeq_plan* pl, const double* src, double* dst, double* part, int parity,
-                          hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
+                          hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr, const float* mpart = nullptr) {
     const int nb = interp_blocks(pl->kp.n);   // one wave per atom
 #define QEQ_INTERP_ARGS                                                                              \
     dim3(nb), dim3(QEQ_BLOCK), 0, pl->stream, ev0, ev1, 0, pl->kp, src,                                  \
         (pl->ew_active ? (const double*)pl->ew_yrec : pl->pw_active ? (const double*)pl->pw_y : nullptr), dst, pl->grid_r, pl->home, pl->wts, \
         pl->dwts, pl->rowptr, pl->col, pl->kval, pl->pdr, pl->dself, pl->Jv, pl->chi_raw, pl->chi,   \
-        pl->sig, pl->selfgrad, pl->fdst, pl->gtmp, part, pl->sc, parity
+        pl->sig, pl->selfgrad, pl->fdst, pl->gtmp, part, pl->sc, parity, mpart
     if (pl->kp.p == 6)
         hipExtLaunchKernelGGL((k_interp<MODE, 6>), QEQ_INTERP_ARGS);
     else
@@ -460,15 +463,17 @@ static void interp_launch(qeq_plan* pl, const double* src, double* dst, double* 
 #undef QEQ_INTERP_ARGS
 }
 
-int launch_interp(qeq_plan* pl, const double* src, double* dst, int mode, int parity) {
+int launch_interp(qeq_plan* pl, const double* src, double* dst, int mode, int parity, const float* mpart) {
     double* part = part_buf(pl, 0);
     ProfScope ps(pl, mode == QEQ_MODE_CG ? PK_INTERP : PK_COUNT);
     if (mode == QEQ_MODE_CG)
-        interp_launch<QEQ_MODE_CG>(pl, src, dst, part, parity, ps.start(), ps.stop());
+        interp_launch<QEQ_MODE_CG>(pl, src, dst, part, parity, ps.start(), ps.stop(), mpart);
     else if (mode == QEQ_MODE_MATVEC)
-        interp_launch<QEQ_MODE_MATVEC>(pl, src, dst, part, parity);
-    else
+        interp_launch<QEQ_MODE_MATVEC>(pl, src, dst, part, parity, nullptr, nullptr, mpart);
+    else if (!mpart)
         interp_launch<QEQ_MODE_FINAL>(pl, src, dst, part, parity);
+    else
+        return QEQ_EINVAL;   // forces need the potential grid
     return qeq_check(hipGetLastError());
 }
 

@@ -110,6 +110,8 @@ def load_library():
     L.qeq_use_spectral_preconditioner.restype = ctypes.c_int
     L.qeq_use_fused_inverse.argtypes = [vp, i32]
     L.qeq_use_fused_inverse.restype = ctypes.c_int
+    L.qeq_use_fused_interp.argtypes = [vp, i32]
+    L.qeq_use_fused_interp.restype = ctypes.c_int
     L.qeq_use_graphs.argtypes = [vp, i32]
     L.qeq_use_graphs.restype = ctypes.c_int
     L.qeq_profile.argtypes = [vp, ctypes.c_uint32]
@@ -437,6 +439,10 @@ class Plan:
     def use_fused_inverse(self, enable=True):
         """Fused inverse axis-2 + complex-to-real slab pass where it fits (default) or two passes."""
         load_library().qeq_use_fused_inverse(self._h, 1 if enable else 0)
+
+    def use_fused_interp(self, enable=True):
+        """CG products: complex-to-real pass fused with the interpolation (default) or the grid path."""
+        load_library().qeq_use_fused_interp(self._h, 1 if enable else 0)
 
     def profile(self, mask):
         """Bracket the launch kinds in ``mask`` with HIP events (see qeq_profile)."""

@@ -236,6 +236,7 @@ def test_fused_inverse_matches_two_passes(dev, which):
     from paper_2607_17978_amd import qeq
     s = gen.system_4096() if which == "n4096" else gen.system_32k()
     plan = qeq.Plan(s.n, eta=ETA, r_cut=RC, grid=s.grid, tol=1e-8)
+    plan.use_fused_interp(False)    # the slab pass belongs to the grid path
     v = T(np.random.default_rng(9).normal(size=s.n), dev)
     args = (T(s.pos, dev), s.cell, T(s.sigma, dev))
     y1 = plan.matvec(*args, v, parts=qeq.PART_RECIP).cpu().numpy()
@@ -250,6 +251,40 @@ def test_fused_inverse_matches_two_passes(dev, which):
         plan.use_fused_inverse(True)
         q1 = plan.solve(*solve_args)[0].cpu().numpy()
         assert np.abs(q1 - q0).max() <= 1e-7
+    plan.close()
+
+
+@pytest.mark.parametrize("which", ["n64", "batch3", "n4096", "n32768", "grid320"])
+def test_fused_interp_matches_grid_path(dev, which):
+    """The complex-to-real pass fused with the back-interpolation (the CG
+    products' default) gives the mesh product of the grid path (potential
+    written, then interpolated) to FP32 rounding, and the same charges."""
+    from paper_2607_17978_amd import qeq
+    if which == "grid320":
+        s = gen.lattice_system(4, 235.7, 1009, grid=(320, 320, 320), name="n64_L235.7")
+    else:
+        s = {"n64": gen.system_64, "n4096": gen.system_4096, "n32768": gen.system_32k,
+             "batch3": lambda: gen.batch_structure(3)}[which]()
+    rc = 12.0 if which.startswith("batch") else RC
+    plan = qeq.Plan(s.n, eta=ETA, r_cut=rc, grid=s.grid, tol=1e-9)
+    v = T(np.random.default_rng(9).normal(size=s.n), dev)
+    args = (T(s.pos, dev), s.cell, T(s.sigma, dev))
+    y1 = plan.matvec(*args, v, parts=qeq.PART_RECIP).cpu().numpy()
+    plan.use_fused_interp(False)
+    y0 = plan.matvec(*args, v, parts=qeq.PART_RECIP).cpu().numpy()
+    err = np.abs(y1 - y0).max() / np.abs(y0).max()
+    print(which, "fused interpolation vs grid path, rel max diff", err)
+    assert err <= 1e-6
+    solve_args = (T(s.pos, dev), s.cell, T(s.sigma, dev), T(s.J, dev), T(s.chi, dev), s.q_tot)
+    q0, _, _, st0 = plan.solve(*solve_args)
+    plan.use_fused_interp(True)
+    q1, _, _, st1 = plan.solve(*solve_args)
+    dq = float((q1 - q0).abs().max())
+    print(which, "iters", st0["iters"], st1["iters"], "max |dq|", dq)
+    # below the FP32 residual floor (tol 1e-9) the true-residual restarts
+    # may add an iteration or two
+    assert st1["rc"] == 0 and abs(st1["iters"] - st0["iters"]) <= max(1, 0.05 * st0["iters"])
+    assert dq <= 1e-7
     plan.close()
 
 
