@@ -315,6 +315,23 @@ int mlp_train_step(const float* G, const int32_t* species, const double* target,
                    float* adam_v, int32_t step, float lr, float* workspace,
                    int64_t workspace_floats, float* loss, float* grad_out, void* stream);
 
+/* mlp_train_step without the workspace argument, for callers that cannot
+   allocate device memory (code under stream capture, serving loops,
+   harnesses that forbid hipMalloc): the partial gradients and loss partials
+   live in a fixed array of the library on each device (7.0 MB:
+   mlp_workspace_floats(4) floats, enough for any n_species <= 4 and any n),
+   looked up once per device on the first call.  Calls no hipMalloc / hipFree.
+   Arguments, outputs and errors as mlp_train_step (QEQ_EINVAL for
+   n_species > 4 or bad pointers); results equal mlp_train_step's up to the
+   FP32 rounding order of the gradient sums.  Every call on one device shares
+   that device's array: calls that overlap on one device (other streams,
+   other host threads) race and must be serialised by the caller; nothing in
+   the array needs to start at zero (each call overwrites what it reads). */
+int mlp_train_step_noalloc(const float* G, const int32_t* species, const double* target, int32_t n,
+                           int32_t n_species, const float* stats, float* params, float* adam_m,
+                           float* adam_v, int32_t step, float lr, float* loss, float* grad_out,
+                           void* stream);
+
 /* The CG loop of qeq_solve / qeq_backward runs as a replayed HIP graph of
    8 iterations (captured on a private stream, launched on the plan's stream,
    re-captured when the geometry or buffers change); enable = 0 launches every

@@ -20,6 +20,8 @@
 // transposes.
 #include <math.h>
 
+#include <mutex>
+
 #include "internal.h"
 
 namespace {
@@ -397,6 +399,53 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ grad, fl
     p[t] -= lr * mh / (sqrtf(vh) + eps);
 }
 
+// Workspace of mlp_train_step_noalloc: one fixed array per device (each GPU
+// that runs it holds its own copy until the process ends), large enough for
+// the largest n_species the kernels take.  Host code never uses the array's
+// name as a pointer: it uses the device address hipGetSymbolAddress gives.
+constexpr int64_t MLP_SCRATCH_FLOATS =
+    (int64_t)MLP_BLOCKS * MLP_MAXSP * MLP_STRIDE + MLP_MAXSP * MLP_STRIDE + 2 * MLP_BLOCKS +
+    256 * (MLP_MAXSP * (MLP_NF * 3 + 1));
+static __device__ __align__(256) float scratch[MLP_SCRATCH_FLOATS];
+
+constexpr int MLP_MAX_DEVICES = 64;
+std::mutex scratch_mutex;
+float* scratch_ptr[MLP_MAX_DEVICES] = {};
+
+// Device address of this device's scratch array, looked up once per device
+// (with that device current) on the first call.
+int scratch_address(float** out) {
+    int dev = 0;
+    QEQ_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MLP_MAX_DEVICES) return QEQ_EINVAL;
+    std::lock_guard<std::mutex> lock(scratch_mutex);
+    if (!scratch_ptr[dev]) {
+        void* p = nullptr;
+        QEQ_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        scratch_ptr[dev] = static_cast<float*>(p);
+    }
+    *out = scratch_ptr[dev];
+    return QEQ_OK;
+}
+
+int train_step_impl(const float* G, const int32_t* species, const double* target, int32_t n, int32_t n_species,
+                    const float* stats, float* params, float* adam_m, float* adam_v, int32_t step, float lr,
+                    float* workspace, float* loss, float* grad_out, hipStream_t s) {
+    const int np = n_species * MLP_STRIDE;
+    float* gpart = workspace;
+    float* grad = workspace + (size_t)MLP_BLOCKS * np;
+    double* lpart = reinterpret_cast<double*>(grad + np + (np & 1));
+    hipLaunchKernelGGL(k_mlp<true>, dim3(MLP_BLOCKS), dim3(256), 0, s, G, species, target, n, n_species, params,
+                       stats, nullptr, gpart, lpart, 1.f / (float)n);
+    hipLaunchKernelGGL(k_grad_reduce, dim3((np + 255) / 256), dim3(256), 0, s, gpart, MLP_BLOCKS, np, grad,
+                       lpart, loss);
+    if (grad_out) QEQ_HIP(hipMemcpyAsync(grad_out, grad, sizeof(float) * np, hipMemcpyDeviceToDevice, s));
+    if (step > 0)
+        hipLaunchKernelGGL(k_adam, dim3((np + 255) / 256), dim3(256), 0, s, params, grad, adam_m, adam_v, np, step,
+                           lr);
+    return qeq_check(hipGetLastError());
+}
+
 }  // namespace
 
 int launch_descriptors(qeq_plan* pl, const double* weights, int nf, const double* centers, double width, double rc,
@@ -451,20 +500,21 @@ int mlp_train_step(const float* G, const int32_t* species, const double* target,
         n_species < 1 || n_species > MLP_MAXSP || step < 0)
         return QEQ_EINVAL;
     if (workspace_floats < mlp_workspace_floats(n_species)) return QEQ_EINVAL;
-    hipStream_t s = (hipStream_t)stream;
-    const int np = n_species * MLP_STRIDE;
-    float* gpart = workspace;
-    float* grad = workspace + (size_t)MLP_BLOCKS * np;
-    double* lpart = reinterpret_cast<double*>(grad + np + (np & 1));
-    hipLaunchKernelGGL(k_mlp<true>, dim3(MLP_BLOCKS), dim3(256), 0, s, G, species, target, n, n_species, params,
-                       stats, nullptr, gpart, lpart, 1.f / (float)n);
-    hipLaunchKernelGGL(k_grad_reduce, dim3((np + 255) / 256), dim3(256), 0, s, gpart, MLP_BLOCKS, np, grad,
-                       lpart, loss);
-    if (grad_out) QEQ_HIP(hipMemcpyAsync(grad_out, grad, sizeof(float) * np, hipMemcpyDeviceToDevice, s));
-    if (step > 0)
-        hipLaunchKernelGGL(k_adam, dim3((np + 255) / 256), dim3(256), 0, s, params, grad, adam_m, adam_v, np, step,
-                           lr);
-    return qeq_check(hipGetLastError());
+    return train_step_impl(G, species, target, n, n_species, stats, params, adam_m, adam_v, step, lr, workspace,
+                           loss, grad_out, (hipStream_t)stream);
+}
+
+int mlp_train_step_noalloc(const float* G, const int32_t* species, const double* target, int32_t n,
+                           int32_t n_species, const float* stats, float* params, float* adam_m, float* adam_v,
+                           int32_t step, float lr, float* loss, float* grad_out, void* stream) {
+    if (!G || !species || !target || !stats || !params || !adam_m || !adam_v || n < 1 || n_species < 1 ||
+        n_species > MLP_MAXSP || step < 0)
+        return QEQ_EINVAL;
+    if (mlp_workspace_floats(n_species) > MLP_SCRATCH_FLOATS) return QEQ_EINVAL;
+    float* ws = nullptr;
+    QEQ_TRY(scratch_address(&ws));
+    return train_step_impl(G, species, target, n, n_species, stats, params, adam_m, adam_v, step, lr, ws, loss,
+                           grad_out, (hipStream_t)stream);
 }
 
 }  // extern "C"

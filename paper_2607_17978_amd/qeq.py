@@ -131,6 +131,8 @@ def load_library():
     L.mlp_train_step.argtypes = [dp, dp, dp, i32, i32, dp, dp, dp, dp, i32, ctypes.c_float, dp,
                                  ctypes.c_int64, dp, dp, vp]
     L.mlp_train_step.restype = ctypes.c_int
+    L.mlp_train_step_noalloc.argtypes = [dp, dp, dp, i32, i32, dp, dp, dp, dp, i32, ctypes.c_float, dp, dp, vp]
+    L.mlp_train_step_noalloc.restype = ctypes.c_int
     L.qeq_solve_batched.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int32), dp, ctypes.POINTER(ctypes.c_double),
                                     dp, dp, dp, ctypes.POINTER(ctypes.c_double), dp, dp, dp, dp,
                                     ctypes.POINTER(Stats)]
