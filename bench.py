@@ -171,7 +171,7 @@ def trajectory_record(args, dev):
 
     def log(msg):   # progress on stderr: every 25th frame and the training summary
         w = msg.split()
-        if w[0] != "frame" or int(w[1]) % 25 == 0:
+        if w[0] != "frame" or int(w[1].rstrip(":")) % 25 == 0:
             print("trajectory: " + msg, file=sys.stderr, flush=True)
 
     t0 = time.perf_counter()

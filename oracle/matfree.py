@@ -33,12 +33,30 @@ def _is_orthorhombic(H):
     return np.allclose(H - np.diag(np.diag(H)), 0.0)
 
 
-def real_space_pairs(pos, cell, r_max, chunk=256):
-    """All (i, j, d = r_i - r_j + n.H) with |d| < r_max, excluding i = j, n = 0."""
+def real_space_pairs(pos, cell, r_max, chunk=256, tree=True):
+    """All (i, j, d = r_i - r_j + n.H) with |d| < r_max, excluding i = j, n = 0.
+
+    Orthorhombic cells with r_max below half the shortest edge have at most
+    one image per pair (the minimum image); there the candidate pairs come
+    from scipy's periodic k-d tree (a library search, same pair set as the
+    all-pairs loop below, which ``tree=False`` selects and a test compares),
+    else every pair and image shift is tested directly."""
     pos = np.asarray(pos, dtype=np.float64)
     H = np.asarray(cell, dtype=np.float64)
     n = pos.shape[0]
     rows, cols, ds = [], [], []
+    if tree and _is_orthorhombic(H) and r_max < 0.5 * np.diag(H).min():
+        from scipy.spatial import cKDTree
+        L = np.diag(H)
+        wrapped = pos - L * np.floor(pos / L)
+        wrapped[wrapped >= L] -= L[np.nonzero(wrapped >= L)[1]]
+        ij = cKDTree(wrapped, boxsize=L).query_pairs(r_max, output_type="ndarray")
+        i, j = ij[:, 0], ij[:, 1]
+        d = pos[i] - pos[j]
+        d -= L * np.round(d / L)
+        keep = np.einsum("ij,ij->i", d, d) < r_max * r_max
+        i, j, d = i[keep], j[keep], d[keep]
+        return np.concatenate([i, j]), np.concatenate([j, i]), np.concatenate([d, -d])
     if _is_orthorhombic(H) and r_max < 0.5 * np.diag(H).min():
         # each pair has at most one image inside r_max: minimum image
         L = np.diag(H)

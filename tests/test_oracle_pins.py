@@ -501,3 +501,18 @@ def test_virial_pins_catch_planted_mistakes(monkeypatch):
     monkeypatch.setattr(ewald, "background_energy", lambda *a: 0.0)
     assert err() > 1e-3
     monkeypatch.setattr(ewald, "background_energy", orig_bg)
+
+
+def test_real_space_pairs_tree_equals_all_pairs():
+    """The k-d tree search of the oracle's real-space pair table returns the
+    same pairs and displacements as the all-pairs minimum-image loop."""
+    from oracle import matfree
+    s = gen.system_512()
+    for r in (9.0, 11.0, 15.0):
+        a = matfree.real_space_pairs(s.pos, s.cell, r, tree=True)
+        b = matfree.real_space_pairs(s.pos, s.cell, r, tree=False)
+        ka = np.lexsort((a[1], a[0]))
+        kb = np.lexsort((b[1], b[0]))
+        assert len(ka) == len(kb) > 0
+        assert np.array_equal(a[0][ka], b[0][kb]) and np.array_equal(a[1][ka], b[1][kb])
+        assert np.abs(a[2][ka] - b[2][kb]).max() == 0.0
