@@ -150,7 +150,7 @@ class EwaldOperator:
         S = np.zeros(self.W.shape, dtype=np.complex128)
         for a in self.active:
             X = v * self.T1[:, a]
-            S[a] = (self.T2 * X[:, None]).T @ self.T3
+            S[a] = self.T2.T @ (X[:, None] * self.T3)
         return S
 
     def _back(self, U):
