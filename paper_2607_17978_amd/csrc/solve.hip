@@ -213,6 +213,79 @@ __global__ __launch_bounds__(QEQ_BLOCK) void k_interp(
     (void)parity;
 }
 
+// The CG product when the mesh part arrives as interpolation partials (the
+// fused complex-to-real pass): y_i = sum of the atom's 2p partials +
+// sum_j K_ij v_j + d_i v_i (+ J_i v_i).  Sixteen lanes per atom (four atoms
+// per wave); each lane takes every sixteenth pair of the row, with the loads
+// of four pairs issued before their sums so that the column, kernel-value and
+// source gathers of a row overlap; the sixteen partial sums are combined in a
+// fixed butterfly order.  Same partial-sum layout as k_interp (the next CG
+// kernel reduces them): 16 atoms per block and round.
+template <int MODE>
+__global__ __launch_bounds__(QEQ_BLOCK) void k_pairs_fused(
+    KParams k, const double* __restrict__ src, double* __restrict__ dst, const int* __restrict__ rowptr,
+    const int* __restrict__ col, const float* __restrict__ kval, const double* __restrict__ dself,
+    const double* __restrict__ Jv, const float* __restrict__ mpart, double* __restrict__ part,
+    CgScalars* __restrict__ sc) {
+    if (MODE == QEQ_MODE_CG && sc->done) return;
+    constexpr int G = 16;
+    const int lane = threadIdx.x & (G - 1);
+    const int grp = (xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) / G;
+    const int ngrp = gridDim.x * (blockDim.x / G);
+    const int n = k.n;
+    const bool do_real = (k.parts & QEQ_PART_REAL) != 0;
+    const bool do_recip = (k.parts & QEQ_PART_RECIP) != 0 && lane < 2 * k.p;
+    double acc[2] = {0.0, 0.0};
+    const int rounds = (n + ngrp - 1) / ngrp;
+    for (int rnd = 0; rnd < rounds; ++rnd) {
+        const int i = rnd * ngrp + grp;
+        double v = 0.0;
+        if (i < n) {
+            const int e0 = rowptr[i], e1 = rowptr[i + 1];
+            const float mp = do_recip ? mpart[(size_t)lane * n + i] : 0.f;
+            if (do_real) {
+                for (int base = e0 + lane; base < e1; base += 4 * G) {
+                    int cj[4];
+                    float kv[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int e = base + u * G;
+                        cj[u] = e < e1 ? col[e] : -1;
+                        kv[u] = e < e1 ? kval[e] : 0.f;
+                    }
+                    double vj[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) vj[u] = cj[u] >= 0 ? src[cj[u]] : 0.0;
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) v += (double)kv[u] * vj[u];
+                }
+            }
+            v += (double)mp;
+        }
+#pragma unroll
+        for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, G);
+        if (i < n && lane == 0) {
+            const double vi = src[i];
+            double y = v;
+            if (k.parts & QEQ_PART_SELF) y += dself[i] * vi;
+            if (MODE == QEQ_MODE_CG) {
+                y += Jv[i] * vi;
+                acc[0] += vi * y;
+                acc[1] += y;
+            }
+            dst[i] = y;
+        }
+    }
+    if (MODE == QEQ_MODE_CG) {
+        block_sum<2>(acc);
+        if (threadIdx.x == 0) {
+            part[blockIdx.x * QEQ_NPART] = acc[0];
+            part[blockIdx.x * QEQ_NPART + 1] = acc[1];
+            for (int t = 2; t < 5; ++t) part[blockIdx.x * QEQ_NPART + t] = 0.0;
+        }
+    }
+}
+
 // q <- q0 (original order, gathered to sorted) or Q/N; partial sum(q).
 __global__ void k_cg_init_q(KParams k, const double* __restrict__ q0, const int* __restrict__ perm,
                             double* __restrict__ q, double* __restrict__ part, CgScalars* sc) {
@@ -466,6 +539,18 @@ static void interp_launch(qeq_plan* pl, const double* src, double* dst, double* 
 int launch_interp(qeq_plan* pl, const double* src, double* dst, int mode, int parity, const float* mpart) {
     double* part = part_buf(pl, 0);
     ProfScope ps(pl, mode == QEQ_MODE_CG ? PK_INTERP : PK_COUNT);
+    if (mpart && (mode == QEQ_MODE_CG || mode == QEQ_MODE_MATVEC) && !pl->ew_active && !pl->pw_active) {
+        const int nb = interp_blocks(pl->kp.n);   // the partial-sum count the CG kernels expect
+        if (mode == QEQ_MODE_CG)
+            hipExtLaunchKernelGGL(k_pairs_fused<QEQ_MODE_CG>, dim3(nb), dim3(QEQ_BLOCK), 0, pl->stream, ps.start(),
+                                  ps.stop(), 0, pl->kp, src, dst, pl->rowptr, pl->col, pl->kval, pl->dself,
+                                  pl->Jv, mpart, part, pl->sc);
+        else
+            hipExtLaunchKernelGGL(k_pairs_fused<QEQ_MODE_MATVEC>, dim3(nb), dim3(QEQ_BLOCK), 0, pl->stream,
+                                  nullptr, nullptr, 0, pl->kp, src, dst, pl->rowptr, pl->col, pl->kval, pl->dself,
+                                  pl->Jv, mpart, part, pl->sc);
+        return qeq_check(hipGetLastError());
+    }
     if (mode == QEQ_MODE_CG)
         interp_launch<QEQ_MODE_CG>(pl, src, dst, part, parity, ps.start(), ps.stop(), mpart);
     else if (mode == QEQ_MODE_MATVEC)
