@@ -40,7 +40,7 @@ KIND_NAMES = ["spread_r2c", "fft_rows_fwd", "fft_cols_green", "fft_rows_inv", "c
 MEASURED_TRAFFIC = {
     "spread_r2c": {"kernel": "k_spread_r2c", "file": "paper_2607_17978_amd/csrc/mesh.hip",
                    "source_sha256_16": "74cfb27206d190dd",
-                   "fetch_kib": 2447.875, "fetch_scale": 2.0, "write_kib": 27936.0, "write_scale": 1.0},
+                   "fetch_kib": 2577.0625, "fetch_scale": 2.0, "write_kib": 27936.0, "write_scale": 1.0},
 }
 
 
@@ -63,20 +63,28 @@ def measured_traffic(name):
     return 1024.0 * (m["fetch_kib"] * m["fetch_scale"] + m["write_kib"] * m["write_scale"])
 
 
-def algorithmic_bytes(K, n, nnz):
-    """Minimal HBM bytes each kernel kind must move once per launch."""
+def algorithmic_bytes(K, n, nnz, fused=True):
+    """Minimal HBM bytes each kernel kind must move once per launch.
+
+    fused: the CG products' default path, where the complex-to-real pass
+    interpolates from LDS (kind "c2r": half spectrum read, per-atom spline
+    data read and 2p = 12 FP32 partials written) and the pair kernel reads
+    those partials instead of the real grid (kind "interp_pairs")."""
     K1, K2, K3 = K
     wc = 8.0 * K1 * K2 * (K3 // 2 + 1)      # half-complex grid, complex64
     wr = 4.0 * K1 * K2 * K3                 # real grid, float32
     atom_in = 16 + 3 * 6 * 4 + 8            # home index, 3 x 6 spline weights, source value
+    parts = 12 * 4.0                        # interpolation partials per atom
     return {
         "spread_r2c": wc + atom_in * n,
         "fft_rows_fwd": 2 * wc,
         "fft_cols_green": 2 * wc,
         "fft_rows_inv": 2 * wc,
-        "c2r": wc + wr,
-        # grid read once, per-atom data, CSR (col + value), y and diagonal terms
-        "interp_pairs": wr + atom_in * n + 8.0 * nnz + 4 * (n + 1) + 3 * 8 * n,
+        "c2r": wc + (atom_in - 8 + parts) * n if fused else wc + wr,
+        # fused: CSR (col + value), row pointers, partials, source and diagonal terms, y
+        # grid path: real grid read once, per-atom data, CSR, y and diagonal terms
+        "interp_pairs": (8.0 * nnz + 4 * (n + 1) + parts * n + 4 * 8 * n if fused else
+                         wr + atom_in * n + 8.0 * nnz + 4 * (n + 1) + 3 * 8 * n),
         "cg_update": 8.0 * n * 6,
         "cg_dir": 8.0 * n * 4,
     }
@@ -163,6 +171,25 @@ def matvec_record(stage_us, grid, n, nnz):
     }
 
 
+def trajectory_frame0(dev):
+    """The 131,072-atom trajectory's first frame on its 320^3 grid, with the
+    workload's electronegativities (fixed network on the frame's radial
+    descriptors, computed on the GPU as the trajectory workflow does)."""
+    import torch
+
+    from inputs import gen
+    from paper_2607_17978_amd import qeq, warmstart
+    pos, cell, species, sigma, J = gen.md_initial()
+    posw = gen.wrap_positions(pos, cell)
+    T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    plan = qeq.Plan(len(pos), eta=2.0, r_cut=11.0, grid=(320, 320, 320))
+    G = plan.descriptors(T(posw), cell, T(sigma), warmstart.CENTERS, warmstart.WIDTH, warmstart.RCUT_DESC)
+    chi, _, _ = gen.chi_from_descriptors(G.cpu().numpy(), species, gen.chi_network_weights(1004))
+    plan.close()
+    return gen.System(name="md131k_frame0", pos=posw, cell=cell, species=species, sigma=sigma, J=J, chi=chi,
+                      q_tot=0.0, grid=(320, 320, 320))
+
+
 def trajectory_record(args, dev):
     """The 131,072-atom trajectory (320^3 grid): cold vs previous-frame vs
     learned starts over the evaluation frames, and the 320^3 product's
@@ -199,7 +226,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tol", type=float, default=1e-6)
-    ap.add_argument("--workload", choices=["cold32k", "warmstart", "batch", "nonperiodic", "adjoint", "ewald", "planewave", "sqnm"],
+    ap.add_argument("--workload", choices=["cold32k", "cold131k", "warmstart", "batch", "nonperiodic", "adjoint", "ewald",
+                                           "planewave", "sqnm"],
                     default="cold32k",
                     help="cold32k: the default cold-start solve; warmstart: the 131,072-atom "
                          "trajectory (learned vs cold vs previous-frame start); batch: 1,024 "
@@ -253,7 +281,7 @@ def main():
         return planewave_main(args, dev)
     if args.workload == "sqnm":
         return sqnm_main(args, dev)
-    s = gen.system_32k()
+    s = gen.system_32k() if args.workload == "cold32k" else trajectory_frame0(dev)
     T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
     pos, sig, J, chi = T(s.pos), T(s.sigma), T(s.J), T(s.chi)
     stream = torch.cuda.current_stream()
@@ -361,7 +389,9 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": "cold-start QEq solve, 32768-atom jittered cubic lattice, L=148.6 bohr",
+            "workload": ("cold-start QEq solve, 32768-atom jittered cubic lattice, L=148.6 bohr"
+                         if args.workload == "cold32k" else
+                         "cold-start QEq solve, first frame of the 131072-atom trajectory, L=235.7 bohr, 320^3"),
             "n_atoms": s.n, "grid": list(s.grid), "spline_order": 6, "eta_bohr": 2.0,
             "r_cut_bohr": 11.0, "tol": args.tol, "cg_iters": int(np.median(iters)),
             "precision": "f32 grids/FFT/pair values, f64 CG vectors and reductions",
