@@ -39,6 +39,7 @@ KIND_NAMES = ["spread_r2c", "fft_rows_fwd", "fft_cols_green", "fft_rows_inv", "c
 # that source the traffic is reported as null until it is measured again.
 MEASURED_TRAFFIC = {
     "spread_r2c": {"kernel": "k_spread_r2c", "file": "paper_2607_17978_amd/csrc/mesh.hip",
+                   "grid": (192, 192, 192), "spread_rows": 16,
                    "source_sha256_16": "74cfb27206d190dd",
                    "fetch_kib": 2577.0625, "fetch_scale": 2.0, "write_kib": 27936.0, "write_scale": 1.0},
 }
@@ -56,9 +57,13 @@ def kernel_source_hash(path, kernel):
     return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
 
 
-def measured_traffic(name):
+def measured_traffic(name, tiles=(0, 0, 0), grid=(192, 192, 192)):
+    """Counter-measured bytes per launch, while the kernel source, the grid and
+    the spread tile width are those the counters were taken with."""
     m = MEASURED_TRAFFIC.get(name)
     if not m or kernel_source_hash(m["file"], m["kernel"]) != m["source_sha256_16"]:
+        return None
+    if tuple(grid) != tuple(m["grid"]) or tiles[0] not in (0, m["spread_rows"]):
         return None
     return 1024.0 * (m["fetch_kib"] * m["fetch_scale"] + m["write_kib"] * m["write_scale"])
 
@@ -171,6 +176,36 @@ def matvec_record(stage_us, grid, n, nnz):
     }
 
 
+def literal_settings_record(s, dev):
+    """Errors of the 32,768-atom solve against the stored FP64 oracle solution
+    (tests/golden/n32768_reference.npz, written by the oracle alone) at the
+    configs' literal discretisation (real-space cutoff 9 bohr, order-6
+    splines, with and without the mesh self-correction) beside the parity
+    settings the benchmark uses (cutoff 11 bohr, self-correction)."""
+    import torch
+
+    from paper_2607_17978_amd import qeq
+    path = os.path.join(ROOT, "tests", "golden", "n32768_reference.npz")
+    if not os.path.exists(path):
+        return None
+    ref = np.load(path)
+    T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    out = {"reference": "FP64 matrix-free oracle, relative residual 1e-10", "solve_tol": 1e-6}
+    for name, rc, corr in (("literal_rc9_selfcorr", 9.0, True), ("literal_rc9_plain_spme", 9.0, False),
+                           ("parity_rc11_selfcorr", 11.0, True)):
+        plan = qeq.Plan(s.n, eta=2.0, r_cut=rc, grid=s.grid, tol=1e-6, self_correction=corr)
+        q, en, f, st = plan.solve(T(s.pos), s.cell, T(s.sigma), T(s.J), T(s.chi), s.q_tot)
+        plan.close()
+        q, en, f = q.cpu().numpy(), en.cpu().numpy(), f.cpu().numpy()
+        F = ref["forces"]
+        out[name] = {"max_abs_dq": float(np.abs(q - ref["q"]).max()),
+                     "rel_E_qeq": float(abs(en[0] - ref["e_qeq"]) / abs(ref["e_qeq"])),
+                     "rel_E_elec": float(abs(en[1] - ref["e_elec"]) / abs(ref["e_elec"])),
+                     "rel_force_rms": float(np.sqrt(np.mean((f - F) ** 2)) / np.sqrt(np.mean(F ** 2))),
+                     "cg_iters": st["iters"]}
+    return out
+
+
 def trajectory_frame0(dev):
     """The 131,072-atom trajectory's first frame on its 320^3 grid, with the
     workload's electronegativities (fixed network on the frame's radial
@@ -241,6 +276,9 @@ def main():
     ap.add_argument("--spectral-kc", type=float, default=0.2, metavar="BOHR^-1",
                     help="also time the solve with the spectral preconditioner at this cutoff "
                          "(0 = skip); the headline value stays the Jacobi solve of the workload")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the built-in mesh tile rule instead of the autotuner's choice")
+    ap.add_argument("--retune", action="store_true", help="ignore the autotuner's cache")
     ap.add_argument("--no-trajectory", action="store_true",
                     help="skip the 131,072-atom trajectory record (warm vs cold, 320^3 product)")
     ap.add_argument("--frames", type=int, default=200)
@@ -285,8 +323,22 @@ def main():
     T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
     pos, sig, J, chi = T(s.pos), T(s.sigma), T(s.J), T(s.chi)
     stream = torch.cuda.current_stream()
+    # mesh tile widths from the autotuner (untimed search, or its cache): every
+    # candidate must reproduce the rule's charges and, where the stored FP64
+    # oracle solution of the workload exists, meet the parity bars against it
+    tiles = None
+    if not args.no_autotune:
+        from paper_2607_17978_amd import autotune
+        ref = None
+        gold = os.path.join(ROOT, "tests", "golden", "n32768_reference.npz")
+        if args.workload == "cold32k" and os.path.exists(gold):
+            ref = dict(np.load(gold))
+        tiles = autotune.tune_tiles(s, dev, tol=args.tol, reference=ref, use_cache=not args.retune)
+        tiles.pop("rows", None)
     plan = qeq.Plan(s.n, eta=2.0, r_cut=11.0, grid=s.grid, spline_order=6, tol=args.tol,
                     max_iter=2000, self_correction=True, stream=stream)
+    if tiles is not None:
+        plan.set_tiles(*tiles["tiles"])
     def prof_read():
         d = plan.profile_read(reset=True)
         return [d[k][0] for k in KIND_NAMES], [d[k][1] for k in KIND_NAMES]
@@ -395,10 +447,12 @@ def main():
             "n_atoms": s.n, "grid": list(s.grid), "spline_order": 6, "eta_bohr": 2.0,
             "r_cut_bohr": 11.0, "tol": args.tol, "cg_iters": int(np.median(iters)),
             "precision": "f32 grids/FFT/pair values, f64 CG vectors and reductions",
+            "mesh_tiles": (tiles or {}).get("tiles", [0, 0, 0]),
         },
         "roofline": {
             "bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": measured_traffic(name),
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+            "traffic": measured_traffic(name, (tiles or {}).get("tiles", [0, 0, 0]), s.grid),
             "bytes_per_launch": by[name], "us_per_launch": round(dur_s * 1e6, 3),
         },
         "matvec": {
@@ -413,6 +467,10 @@ def main():
         "spectral_preconditioner": spectral,
     }
     plan.close()
+    if tiles is not None:
+        out["autotune_tiles"] = tiles
+    if args.workload == "cold32k":
+        out["literal_settings"] = literal_settings_record(s, dev)
     if not args.no_trajectory:
         torch.cuda.empty_cache()
         out["warmstart_131k"], out["matvec_320"] = trajectory_record(args, dev)

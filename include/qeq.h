@@ -360,6 +360,18 @@ int qeq_use_fused_inverse(qeq_plan* plan, int32_t enable);
    at 8- or 16-row tiles). */
 int qeq_use_fused_interp(qeq_plan* plan, int32_t enable);
 
+/* Tile widths of the mesh passes for later solves on this plan, replacing the
+   built-in rule (which keeps every block within 32 KB of LDS and picks narrower
+   tiles for grids beyond the Infinity Cache): spread_rows = axis-2 rows per
+   block of the spread + axis-3 real-to-complex pass, tile_rows = axis-2 rows
+   of the axis-1 and complex-to-real passes, fft_rows = rows per block of the
+   axis-2 pass; 0 keeps the rule for that one.  Powers of two, 4..32 rows (1..32
+   for fft_rows), else QEQ_EINVAL.  A choice that does not divide the grid, is
+   narrower than p - 1 rows or needs more than 60 KB of LDS makes the next
+   solve return QEQ_EPLAN.  The widths change the blocking only: results agree
+   to FP32 rounding order.  paper_2607_17978_amd.autotune measures them. */
+int qeq_set_tiles(qeq_plan* plan, int32_t spread_rows, int32_t tile_rows, int32_t fft_rows);
+
 /* Reciprocal-space method of later qeq_solve calls on this plan: enable = 0
    (default) the particle mesh (B-spline spreading, FFT, Green's function,
    interpolation); enable != 0 direct Ewald summation (SI "Ewald Summation";

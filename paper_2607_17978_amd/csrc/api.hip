@@ -406,10 +406,16 @@ int prepare(qeq_plan* pl, int n, const double* cell, double q_tot) {
     };
     int tws = 16;   // spread: twiddles + int64 accumulator of the tile
     while (tws > 4 && (K[1] % tws != 0 || (size_t)K[2] * 8 + (size_t)K[2] * tws * 8 > 32768)) tws >>= 1;
-    if (K[1] % tws != 0 || K[1] < tws + p - 1) return QEQ_EPLAN;
     int tw = 16;
     while (tw > 4 && !tile_fits(tw)) tw >>= 1;
+    // tile widths set with qeq_set_tiles (e.g. by the autotuner) replace the rule
+    if (pl->tile_set[0] > 0) tws = pl->tile_set[0];
+    if (pl->tile_set[1] > 0) tw = pl->tile_set[1];
+    if (K[1] % tws != 0 || K[1] < tws + p - 1) return QEQ_EPLAN;
     if (K[1] % tw != 0 || K[1] < tw + p - 1) return QEQ_EPLAN;
+    if ((size_t)K[2] * 8 + (size_t)K[2] * tws * 8 > 61440 || (size_t)K[0] * tw * 8 + K[0] * 8 > 61440 ||
+        (size_t)K[2] * (tw / 2) * 8 + (size_t)(K[2] / 2 + 1) * tw * 8 + K[2] * 8 > 61440)
+        return QEQ_EPLAN;
     k.TW = tw;
     k.TWlog2 = ilog2(tw);
     k.ntile = K[1] / tw;
@@ -422,6 +428,8 @@ int prepare(qeq_plan* pl, int n, const double* cell, double q_tot) {
     // 46 us); cache-resident grids keep the larger blocks
     const size_t grid_bytes = (size_t)K[0] * K[1] * K[2] * 4 + (size_t)K[0] * K[1] * (K[2] / 2 + 1) * 8;
     if (grid_bytes > ((size_t)192 << 20) && nr > 4) nr = 4;
+    if (pl->tile_set[2] > 0) nr = pl->tile_set[2];
+    if ((size_t)K[1] * (nr + 2) * 8 > 61440) return QEQ_EPLAN;
     k.NR = nr;
     k.NRlog2 = ilog2(nr);
     // every FFT stage must fit the per-thread register budget
@@ -1040,6 +1048,22 @@ int qeq_use_fused_inverse(qeq_plan* plan, int32_t enable) {
     if (!plan) return QEQ_EINVAL;
     if (plan->stream) (void)hipStreamSynchronize(plan->stream);
     plan->fused_inverse = enable != 0;
+    drop_graph(plan);
+    return QEQ_OK;
+}
+
+int qeq_set_tiles(qeq_plan* plan, int32_t spread_rows, int32_t tile_rows, int32_t fft_rows) {
+    if (!plan) return QEQ_EINVAL;
+    const int v[3] = {spread_rows, tile_rows, fft_rows};
+    for (int a = 0; a < 3; ++a) {
+        const int t = v[a];
+        const bool pow2 = t > 0 && (t & (t - 1)) == 0;
+        if (t != 0 && !(pow2 && t >= (a == 2 ? 1 : 4) && t <= (a == 2 ? 32 : 32))) return QEQ_EINVAL;
+    }
+    if (plan->stream) (void)hipStreamSynchronize(plan->stream);
+    for (int a = 0; a < 3; ++a) plan->tile_set[a] = v[a];
+    plan->geom_valid = false;
+    plan->tape_valid = false;
     drop_graph(plan);
     return QEQ_OK;
 }

@@ -280,6 +280,7 @@ struct qeq_plan {
     double* pw_smax = nullptr;    // per-block maxima of sigma (host read once per set-up)
     bool fused_inverse = true;    // fused inverse axis-2 + complex-to-real slab pass where it fits
     bool fused_interp = true;     // CG products: complex-to-real pass fused with the interpolation
+    int tile_set[3] = {0, 0, 0};  // qeq_set_tiles: spread rows, tile rows, axis-2 rows (0 = rule)
     float* mpart = nullptr;       // [2 MAXP][n_max] interpolation partials of the fused pass
 
     // the CG loop is replayed as a HIP graph of one chunk of iterations,

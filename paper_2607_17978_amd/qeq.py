@@ -112,6 +112,8 @@ def load_library():
     L.qeq_use_fused_inverse.restype = ctypes.c_int
     L.qeq_use_fused_interp.argtypes = [vp, i32]
     L.qeq_use_fused_interp.restype = ctypes.c_int
+    L.qeq_set_tiles.argtypes = [vp, i32, i32, i32]
+    L.qeq_set_tiles.restype = ctypes.c_int
     L.qeq_use_graphs.argtypes = [vp, i32]
     L.qeq_use_graphs.restype = ctypes.c_int
     L.qeq_profile.argtypes = [vp, ctypes.c_uint32]
@@ -441,6 +443,12 @@ class Plan:
     def use_fused_inverse(self, enable=True):
         """Fused inverse axis-2 + complex-to-real slab pass where it fits (default) or two passes."""
         load_library().qeq_use_fused_inverse(self._h, 1 if enable else 0)
+
+    def set_tiles(self, spread_rows=0, tile_rows=0, fft_rows=0):
+        """Tile widths of the mesh passes (0 = the built-in rule); see qeq_set_tiles."""
+        rc = load_library().qeq_set_tiles(self._h, int(spread_rows), int(tile_rows), int(fft_rows))
+        if rc != QEQ_OK:
+            raise QEqError(rc, strerror(rc))
 
     def use_fused_interp(self, enable=True):
         """CG products: complex-to-real pass fused with the interpolation (default) or the grid path."""
