@@ -100,10 +100,13 @@ def test_batched_equals_single_and_split(dev):
 @pytest.mark.parametrize("shape", [
     pytest.param((256, 2), marks=pytest.mark.skip(
         reason="256-thread workgroups are disabled: a run of this shape ended in a GPU fault whose cause "
-               "has not been found; qeq_batched_config rejects 256")),
+               "has not been found (the host replay of every thread-count-dependent index, "
+               "tests/test_batched_index_replay.py, and a reading of the barriers after early exits found "
+               "none); qeq_batched_config rejects 256")),
     pytest.param((512, 1), marks=pytest.mark.skip(
         reason="512-thread workgroups are disabled: with the fixed-point spread they returned "
-               "NOT_CONVERGED on structures the 1024-thread shape solves; cause not found")),
+               "NOT_CONVERGED on structures the 1024-thread shape solves; cause not found (index replay "
+               "and barrier reading clean); qeq_batched_config rejects 512")),
     (1024, 1), (1024, 2)])
 def test_batched_launch_shapes_agree(dev, shape):
     from paper_2607_17978_amd import qeq
