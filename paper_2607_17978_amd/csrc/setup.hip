@@ -274,9 +274,12 @@ __global__ __launch_bounds__(QEQ_BLOCK) void k_pairs(KParams k, const double* __
     // FILL stages a row of up to PBUF pairs in this wave's LDS slice and
     // evaluates the FP64 kernel values afterwards with one pair per lane
     // (inside the stencil loop the divergent lanes would run the erf pair
-    // once per step); longer rows evaluate them in place
+    // once per step); longer rows evaluate them in place.  The staged
+    // distance is kept in FP64, so staged and in-place rows evaluate the
+    // kernel at the same argument.
     constexpr int PBUF = 128;
     __shared__ float4 st_d[FILL ? (QEQ_BLOCK / 64) * PBUF : 1];
+    __shared__ double st_r[FILL ? (QEQ_BLOCK / 64) * PBUF : 1];
     __shared__ int st_j[FILL ? (QEQ_BLOCK / 64) * PBUF : 1];
     const int lane = threadIdx.x & 63;
     const int i = (xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) >> 6;
@@ -317,10 +320,10 @@ __global__ __launch_bounds__(QEQ_BLOCK) void k_pairs(KParams k, const double* __
                 if (r2v >= k.rc2) continue;
                 if (FILL && pass == 1) {
                     if (staged) {
-                        // r_i - r_j(image) for the force; the distance waits in .w
+                        // r_i - r_j(image) for the force, the FP64 distance beside it
                         st_j[sbase + loff] = j;
-                        st_d[sbase + loff] =
-                            make_float4((float)(-dx), (float)(-dy), (float)(-dz), (float)sqrt(r2v));
+                        st_d[sbase + loff] = make_float4((float)(-dx), (float)(-dy), (float)(-dz), 0.f);
+                        st_r[sbase + loff] = sqrt(r2v);
                         ++loff;
                     } else {
                         const double sj = sig[j];
@@ -349,14 +352,16 @@ __global__ __launch_bounds__(QEQ_BLOCK) void k_pairs(KParams k, const double* __
         }
     }
     if (staged) {
-        __threadfence_block();   // the other lanes' LDS writes before the reads below
+        // the other lanes' LDS writes before the reads below (one wave)
+        __threadfence_block();
+        __builtin_amdgcn_wave_barrier();
         const int e0 = rowptr[i], rl = rowptr[i + 1] - e0;
         for (int e = lane; e < rl; e += 64) {
             const int j = st_j[sbase + e];
             const float4 d = st_d[sbase + e];
             const double sj = sig[j];
             double K, dKr;
-            pair_kernel((double)d.w, sqrt(sgi * sgi + sj * sj), k.eta, &K, &dKr);
+            pair_kernel(st_r[sbase + e], sqrt(sgi * sgi + sj * sj), k.eta, &K, &dKr);
             col[e0 + e] = j;
             kval[e0 + e] = (float)K;
             pdr[e0 + e] = make_float4(d.x, d.y, d.z, (float)dKr);

@@ -202,6 +202,32 @@ def test_full_size_32768_matches_oracle(dev):
     plan.close()
 
 
+@pytest.mark.parametrize("rc", [14.0, 15.0, 17.0])
+def test_long_pair_rows_match_oracle(dev, rc):
+    """Cutoffs whose rows straddle (14, 15 bohr: about 115 and 141 pairs per
+    atom on average) or exceed (17 bohr: about 206) the 128 pairs the pair-list
+    fill stages in LDS: the real-space product matches the oracle's
+    real-space matrix at the same cutoff, and the solve meets the bars."""
+    from paper_2607_17978_amd import qeq
+    s = gen.system_512()
+    E, real, self_, bg, recip = oracle_parts(s, ETA, rc)
+    v = np.random.default_rng(8).normal(size=s.n)
+    plan = qeq.Plan(s.n, eta=ETA, r_cut=rc, grid=s.grid, tol=1e-8)
+    args = (T(s.pos, dev), s.cell, T(s.sigma, dev))
+    y_real = plan.matvec(*args, T(v, dev), parts=qeq.PART_REAL).cpu().numpy()
+    err = np.abs(y_real - real @ v).max() / np.abs(E @ v).max()
+    ref = ewald.qeq_dense(s.pos, s.cell, s.sigma, s.J, s.chi, s.q_tot)
+    q, en, f, st = plan.solve(*args, T(s.J, dev), T(s.chi, dev), s.q_tot)
+    q, en, f = q.cpu().numpy(), en.cpu().numpy(), f.cpu().numpy()
+    dq = np.abs(q - ref.q).max()
+    de = abs(en[0] - ref.e_qeq) / abs(ref.e_qeq)
+    df = np.sqrt(np.mean((f - ref.forces) ** 2)) / np.sqrt(np.mean(ref.forces ** 2))
+    print("rc", rc, "real rel", err, "dq", dq, "dE", de, "dF", df)
+    assert err < 1e-6
+    assert st["rc"] == 0 and dq <= 1e-5 and de <= 1e-6 and df <= 1e-4
+    plan.close()
+
+
 @pytest.mark.parametrize("which", ["n64", "n32768"])
 def test_literal_settings_errors(dev, which):
     """The configs' literal discretisation (real-space cutoff 9 bohr, order-6
