@@ -497,10 +497,16 @@ int setup_geometry(qeq_plan* pl, const double* pos, const double* sigma, const d
     QEQ_TRY(launch_stage(pl, pos, sigma, J, chi));
     QEQ_TRY(launch_sort_bins(pl));
     QEQ_TRY(launch_gather(pl, pos, sigma, J, chi));
-    QEQ_TRY(launch_cells_and_pairs(pl));   // synchronises for the pair count
+    QEQ_TRY(launch_cells_and_pairs(pl));
+    // one read-back for the input check and the pair count
     QEQ_HIP(hipMemcpyAsync(pl->sc_host, pl->sc, sizeof(CgScalars), hipMemcpyDeviceToHost, pl->stream));
     QEQ_HIP(hipStreamSynchronize(pl->stream));
     if (pl->sc_host->err & QEQ_ERRBIT_INPUT) return QEQ_EINVAL;
+    pl->nnz = *pl->nnz_host;
+    if ((size_t)pl->nnz > pl->nnz_cap) {   // rows past the capacity were skipped: grow and fill again
+        QEQ_TRY(grow_pairs(pl, (size_t)(pl->nnz * 1.25) + 1024));
+        QEQ_TRY(launch_pair_fill(pl));
+    }
     if (pl->kp.self_corr) QEQ_TRY(launch_selfcorr(pl));
     return QEQ_OK;
 }
@@ -686,7 +692,22 @@ int cg_run(qeq_plan* pl, const double* q0, double* q_out, double* energies, doub
         }
         conv = false;
         int local = 0;
-        while (it < pl->prm.max_iter) {
+        // Each chunk's scalars are copied to a pinned ring slot behind it.
+        // While the last residual seen is far above the tolerance (more than
+        // two chunks of CG reduction away), the next chunk is launched before
+        // the host waits for the copy, so the GPU does not idle during the
+        // read-back; near convergence the host waits after every chunk, so
+        // at most one chunk of early-returning kernels is ever launched in
+        // vain.
+        if (!pl->ring_ev[0]) {
+            for (int e = 0; e < 2; ++e)
+                QEQ_HIP(hipEventCreateWithFlags(&pl->ring_ev[e], hipEventDisableTiming));
+        }
+        int slot = 0, prev = -1;
+        double res_seen = 1e300;
+        const double ahead_thr = 20.0 * pl->prm.tol;
+        bool stop = false;
+        while (it < pl->prm.max_iter && !stop) {
             int m = std::min(chunk, pl->prm.max_iter - it);
             // per-stage timers need eager launches (events recorded inside a
             // graph cannot be read back with hipEventElapsedTime)
@@ -702,10 +723,23 @@ int cg_run(qeq_plan* pl, const double* q0, double* q_out, double* energies, doub
                 }
             }
             pl->cur_it = -1;
-            QEQ_HIP(hipMemcpyAsync(pl->sc_host, pl->sc, sizeof(CgScalars), hipMemcpyDeviceToHost,
+            QEQ_HIP(hipMemcpyAsync(&pl->sc_ring[slot], pl->sc, sizeof(CgScalars), hipMemcpyDeviceToHost,
                                    pl->stream));
-            QEQ_HIP(hipStreamSynchronize(pl->stream));
-            if (pl->sc_host->done) break;
+            QEQ_HIP(hipEventRecord(pl->ring_ev[slot], pl->stream));
+            if (prev >= 0) {   // the chunk before this one
+                QEQ_HIP(hipEventSynchronize(pl->ring_ev[prev]));
+                if (pl->sc_ring[prev].done) break;
+                res_seen = pl->sc_ring[prev].res;
+                prev = -1;
+            }
+            if (res_seen > ahead_thr && pl->prof_mask == 0) {
+                prev = slot;   // go on without waiting for this chunk
+            } else {
+                QEQ_HIP(hipEventSynchronize(pl->ring_ev[slot]));
+                stop = pl->sc_ring[slot].done != 0;
+                res_seen = pl->sc_ring[slot].res;
+            }
+            slot ^= 1;
         }
         QEQ_HIP(hipMemcpyAsync(pl->sc_host, pl->sc, sizeof(CgScalars), hipMemcpyDeviceToHost, pl->stream));
         QEQ_HIP(hipStreamSynchronize(pl->stream));
@@ -877,6 +911,9 @@ int qeq_plan_create(qeq_plan** out, const qeq_params* params, int32_t n_atoms_ma
     if (rc == QEQ_OK && hipHostMalloc((void**)&pl->sc_host, sizeof(CgScalars)) != hipSuccess) rc = QEQ_ENOMEM;
     if (rc == QEQ_OK && hipHostMalloc((void**)&pl->out_host, 16 * sizeof(double)) != hipSuccess)
         rc = QEQ_ENOMEM;
+    if (rc == QEQ_OK && hipHostMalloc((void**)&pl->nnz_host, sizeof(int)) != hipSuccess) rc = QEQ_ENOMEM;
+    if (rc == QEQ_OK && hipHostMalloc((void**)&pl->sc_ring, 2 * sizeof(CgScalars)) != hipSuccess)
+        rc = QEQ_ENOMEM;
     if (rc == QEQ_OK && p.grid[0] > 0) rc = ensure_grid(pl, p.grid);
     if (p.precond == 1) pl->spc_kc = p.spectral_kcut > 0.0 ? p.spectral_kcut : 0.2;
     if (rc != QEQ_OK) {
@@ -913,6 +950,10 @@ int qeq_plan_destroy(qeq_plan* pl) {
     dfree(pl->col); dfree(pl->kval); dfree(pl->pdr);
     if (pl->sc_host) (void)hipHostFree(pl->sc_host);
     if (pl->out_host) (void)hipHostFree(pl->out_host);
+    if (pl->nnz_host) (void)hipHostFree(pl->nnz_host);
+    for (int e = 0; e < 2; ++e)
+        if (pl->ring_ev[e]) (void)hipEventDestroy(pl->ring_ev[e]);
+    if (pl->sc_ring) (void)hipHostFree(pl->sc_ring);
     delete pl;
     return QEQ_OK;
 }

@@ -194,6 +194,9 @@ struct qeq_plan {
     CgScalars* sc = nullptr;
     CgScalars* sc_host = nullptr; // pinned
     double* out_host = nullptr;   // pinned, 16 doubles
+    int* nnz_host = nullptr;      // pinned: pair count of the last set-up
+    CgScalars* sc_ring = nullptr; // pinned, 2: scalars of the CG chunks in flight
+    hipEvent_t ring_ev[2] = {nullptr, nullptr};
     double* final_dev = nullptr;  // 16 doubles on device
 
     KParams kp;
@@ -350,7 +353,12 @@ int launch_stage(qeq_plan* pl, const double* pos, const double* sigma, const dou
 int launch_sort_bins(qeq_plan* pl);
 int launch_gather(qeq_plan* pl, const double* pos, const double* sigma, const double* J,
                   const double* chi);
+// cell list, pair count and pair fill; the count goes to pl->nnz_host
+// (pinned) without a synchronisation: after reading it the caller must call
+// grow_pairs + launch_pair_fill again if it exceeds the capacity the fill saw
 int launch_cells_and_pairs(qeq_plan* pl);
+int launch_pair_fill(qeq_plan* pl);
+int grow_pairs(qeq_plan* pl, size_t cap);
 int launch_theta(qeq_plan* pl);          // mesh kernel table for the self-correction
 int launch_selfcorr(qeq_plan* pl);
 // the six d Theta / d eps_ab tables (6 x (2p-1)^3) for the virial

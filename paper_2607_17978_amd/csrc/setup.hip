@@ -270,7 +270,8 @@ __global__ __launch_bounds__(QEQ_BLOCK) void k_pairs(KParams k, const double* __
                                                     const int* __restrict__ cell_start,
                                                     const int* __restrict__ cell_atoms, int* __restrict__ rowcnt,
                                                     const int* __restrict__ rowptr, int* __restrict__ col,
-                                                    float* __restrict__ kval, float4* __restrict__ pdr) {
+                                                    float* __restrict__ kval, float4* __restrict__ pdr,
+                                                    long long cap) {
     // FILL stages a row of up to PBUF pairs in this wave's LDS slice and
     // evaluates the FP64 kernel values afterwards with one pair per lane
     // (inside the stencil loop the divergent lanes would run the erf pair
@@ -284,6 +285,10 @@ __global__ __launch_bounds__(QEQ_BLOCK) void k_pairs(KParams k, const double* __
     const int lane = threadIdx.x & 63;
     const int i = (xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) >> 6;
     if (i >= k.n) return;   // uniform across the wave
+    // the host sized the pair arrays before the count was known: a row that
+    // would run past the capacity is left out (the host reads the count,
+    // grows the arrays and fills again)
+    if (FILL && rowptr[i + 1] > cap) return;
     const int sbase = (threadIdx.x >> 6) * PBUF;
     const bool staged = FILL && rowptr[i + 1] - rowptr[i] <= PBUF;
     int loff = 0;
@@ -541,33 +546,44 @@ int launch_cells_and_pairs(qeq_plan* pl) {
     const int pair_blocks = nblocks(k.n * 64);   // one wave per atom
     hipLaunchKernelGGL(k_pairs<false>, dim3(pair_blocks), dim3(QEQ_BLOCK), 0, pl->stream, k,
                        pl->frac, pl->home, pl->sig, pl->cell_start, pl->cell_atoms, pl->rowcnt,
-                       pl->rowptr, pl->col, pl->kval, pl->pdr);
+                       pl->rowptr, pl->col, pl->kval, pl->pdr, (long long)0);
     QEQ_TRY(launch_scan(pl, pl->rowcnt, pl->rowptr, k.n));
-    int nnz = 0;
-    QEQ_HIP(hipMemcpyAsync(&nnz, pl->rowptr + k.n, sizeof(int), hipMemcpyDeviceToHost, pl->stream));
-    QEQ_HIP(hipStreamSynchronize(pl->stream));
-    pl->nnz = nnz;
-    if ((size_t)nnz > pl->nnz_cap) {
-        size_t cap = (size_t)(nnz * 1.25) + 1024;
-        if (pl->col) (void)hipFree(pl->col);
-        if (pl->kval) (void)hipFree(pl->kval);
-        if (pl->pdr) (void)hipFree(pl->pdr);
-        pl->col = nullptr;
-        pl->kval = nullptr;
-        pl->pdr = nullptr;
-        pl->nnz_cap = 0;
-        if (hipMalloc(&pl->col, cap * sizeof(int)) != hipSuccess ||
-            hipMalloc(&pl->kval, cap * sizeof(float)) != hipSuccess ||
-            hipMalloc(&pl->pdr, cap * sizeof(float4)) != hipSuccess)
-            return QEQ_ENOMEM;
-        debug_poison(pl->kval, cap * sizeof(float));
-        debug_poison(pl->pdr, cap * sizeof(float4));
-        pl->nnz_cap = cap;
+    // the total goes to the host with the set-up's error flag (one read-back
+    // for both, in setup_geometry); until then the arrays keep their size, or
+    // on a plan's first set-up the size a uniform density predicts
+    if (pl->nnz_cap == 0) {
+        const double vol = fabs(k.vol);
+        const double mean = (double)k.n / vol * 4.0 / 3.0 * 3.14159265358979 * k.rc * k.rc * k.rc;
+        QEQ_TRY(grow_pairs(pl, (size_t)((double)k.n * (mean * 1.15 + 8.0)) + 1024));
     }
-    hipLaunchKernelGGL(k_pairs<true>, dim3(pair_blocks), dim3(QEQ_BLOCK), 0, pl->stream, k,
+    QEQ_HIP(hipMemcpyAsync(pl->nnz_host, pl->rowptr + k.n, sizeof(int), hipMemcpyDeviceToHost, pl->stream));
+    return launch_pair_fill(pl);
+}
+
+int launch_pair_fill(qeq_plan* pl) {
+    const KParams& k = pl->kp;
+    hipLaunchKernelGGL(k_pairs<true>, dim3(nblocks(k.n * 64)), dim3(QEQ_BLOCK), 0, pl->stream, k,
                        pl->frac, pl->home, pl->sig, pl->cell_start, pl->cell_atoms, pl->rowcnt,
-                       pl->rowptr, pl->col, pl->kval, pl->pdr);
+                       pl->rowptr, pl->col, pl->kval, pl->pdr, (long long)pl->nnz_cap);
     return qeq_check(hipGetLastError());
+}
+
+int grow_pairs(qeq_plan* pl, size_t cap) {
+    if (cap <= pl->nnz_cap) return QEQ_OK;
+    if (pl->col) (void)hipFree(pl->col);
+    if (pl->kval) (void)hipFree(pl->kval);
+    if (pl->pdr) (void)hipFree(pl->pdr);
+    pl->col = nullptr;
+    pl->kval = nullptr;
+    pl->pdr = nullptr;
+    pl->nnz_cap = 0;
+    if (hipMalloc(&pl->col, cap * sizeof(int)) != hipSuccess || hipMalloc(&pl->kval, cap * sizeof(float)) != hipSuccess ||
+        hipMalloc(&pl->pdr, cap * sizeof(float4)) != hipSuccess)
+        return QEQ_ENOMEM;
+    debug_poison(pl->kval, cap * sizeof(float));
+    debug_poison(pl->pdr, cap * sizeof(float4));
+    pl->nnz_cap = cap;
+    return QEQ_OK;
 }
 
 int launch_theta(qeq_plan* pl) {
