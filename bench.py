@@ -40,8 +40,8 @@ KIND_NAMES = ["spread_r2c", "fft_rows_fwd", "fft_cols_green", "fft_rows_inv", "c
 MEASURED_TRAFFIC = {
     "spread_r2c": {"kernel": "k_spread_r2c", "file": "paper_2607_17978_amd/csrc/mesh.hip",
                    "grid": (192, 192, 192), "spread_rows": 16,
-                   "source_sha256_16": "74cfb27206d190dd",
-                   "fetch_kib": 2577.0625, "fetch_scale": 2.0, "write_kib": 27936.0, "write_scale": 1.0},
+                   "source_sha256_16": "5b8acc7b3de70b64",
+                   "fetch_kib": 2567.5625, "fetch_scale": 2.0, "write_kib": 27936.0, "write_scale": 1.0},
 }
 
 

@@ -281,6 +281,74 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 }
 
 // ---------------------------------------------------------------------------
+// Global -> LDS staging.  A strided copy loop waits for each load before its
+// LDS store, so a thread's loads run one memory round trip apart; these
+// helpers issue all of a thread's loads into registers first and store them
+// afterwards, so the whole copy costs one round trip.  ld(t) returns element
+// t, st(t, v) stores it; COUNT known at compile time (every load in flight at
+// once) or at run time (CH loads in flight per step).
+// ---------------------------------------------------------------------------
+template <int COUNT, int NTH, typename T, typename Ld, typename St>
+__device__ __forceinline__ void stage_ct(int tid, Ld ld, St st) {
+    constexpr int PER = (COUNT + NTH - 1) / NTH;
+    T v[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int t = tid + u * NTH;
+        if (COUNT % NTH == 0 || t < COUNT) v[u] = ld(t);
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int t = tid + u * NTH;
+        if (COUNT % NTH == 0 || t < COUNT) st(t, v[u]);
+    }
+}
+
+// Two arrays in one round trip (e.g. a twiddle table and a data tile).
+template <int C1, int C2, int NTH, typename T, typename Ld1, typename St1, typename Ld2, typename St2>
+__device__ __forceinline__ void stage2_ct(int tid, Ld1 ld1, St1 st1, Ld2 ld2, St2 st2) {
+    constexpr int P1 = (C1 + NTH - 1) / NTH, P2 = (C2 + NTH - 1) / NTH;
+    T a[P1], b[P2];
+#pragma unroll
+    for (int u = 0; u < P1; ++u) {
+        const int t = tid + u * NTH;
+        if (C1 % NTH == 0 || t < C1) a[u] = ld1(t);
+    }
+#pragma unroll
+    for (int u = 0; u < P2; ++u) {
+        const int t = tid + u * NTH;
+        if (C2 % NTH == 0 || t < C2) b[u] = ld2(t);
+    }
+#pragma unroll
+    for (int u = 0; u < P1; ++u) {
+        const int t = tid + u * NTH;
+        if (C1 % NTH == 0 || t < C1) st1(t, a[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < P2; ++u) {
+        const int t = tid + u * NTH;
+        if (C2 % NTH == 0 || t < C2) st2(t, b[u]);
+    }
+}
+
+template <int CH, typename T, typename Ld, typename St>
+__device__ __forceinline__ void stage_rt(int count, int tid, int nth, Ld ld, St st) {
+    for (int t0 = tid; t0 < count; t0 += CH * nth) {
+        T v[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const int t = t0 + u * nth;
+            if (t < count) v[u] = ld(t);
+        }
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const int t = t0 + u * nth;
+            if (t < count) st(t, v[u]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // FP64 block reductions (wave64 shuffles, then LDS across waves)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double wave_sum(double v) {

@@ -45,7 +45,6 @@ __global__ __launch_bounds__(NT) void k_spread_r2c(KParams k, FftAxis ax3, const
                                                   const int* __restrict__ home,
                                                   const float* __restrict__ wts, float2* __restrict__ C,
                                                   const int* __restrict__ done) {
-    if (done && *done) return;
     extern __shared__ float2 sm[];
     const int K3 = KC ? KC : k.K3;
     const int TW = TWC ? TWC : k.TWS;
@@ -57,7 +56,7 @@ __global__ __launch_bounds__(NT) void k_spread_r2c(KParams k, FftAxis ax3, const
     long long* acc = reinterpret_cast<long long*>(sm + K3);
     float2* buf = sm + K3;
     __shared__ int seg_lo[2 * QEQ_MAXP], seg_off[2 * QEQ_MAXP + 1], seg_k1[2 * QEQ_MAXP];
-    __shared__ int nseg;
+    __shared__ int seg_len[2 * QEQ_MAXP];
     __shared__ float sh_scale;
     const int tid = threadIdx.x;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
@@ -65,31 +64,47 @@ __global__ __launch_bounds__(NT) void k_spread_r2c(KParams k, FftAxis ax3, const
     const int g20 = (blk - g1 * k.ntile_s) * TW;
     const int K1 = k.K1, K2 = k.K2;
 
-    for (int t = tid; t < K3; t += NT) tw[t] = ax3.tw[t];
-    for (int t = tid; t < K3 * TW; t += NT) acc[t] = 0;
-    // candidate segments: for each k1, homes h1 = g1 + k1 and h2 in [g20, g20 + TW + p - 1)
-    // (two pieces when the h2 range wraps); lanes k1 < p fetch their bounds in parallel
-    __shared__ int seg_len[2 * QEQ_MAXP];
+    // The twiddles and the candidate bin bounds are requested before the
+    // converged flag is examined, so the three loads share one round trip.
+    // Candidate segments: for each k1, homes h1 = g1 + k1 and h2 in
+    // [g20, g20 + TW + p - 1) (two pieces when the h2 range wraps); lanes
+    // k1 < p fetch their bounds.
+    constexpr bool TW1 = KC > 0;
+    constexpr int PT = KC > 0 ? (KC + NT - 1) / NT : 1;
+    float2 twv[PT];
+#pragma unroll
+    for (int u = 0; u < PT; ++u)
+        if (TW1 && tid + u * NT < K3) twv[u] = ax3.tw[tid + u * NT];
+    int lo0 = 0, len0 = 0, lo1 = 0, len1 = 0;
     if (tid < p) {
-        const int k1 = tid;
-        int h1 = g1 + k1;
+        int h1 = g1 + tid;
         if (h1 >= K1) h1 -= K1;
         const int b0 = h1 * K2;
         const int hi = g20 + TW + p - 1;
         const int e1 = hi < K2 ? hi : K2;
-        const int lo0 = bin_start[b0 + g20];
-        seg_lo[2 * k1] = lo0;
-        seg_len[2 * k1] = bin_start[b0 + e1] - lo0;
-        seg_k1[2 * k1] = k1;
-        seg_k1[2 * k1 + 1] = k1;
+        lo0 = bin_start[b0 + g20];
+        len0 = bin_start[b0 + e1];
         if (hi > K2) {
-            const int lo1 = bin_start[b0];
-            seg_lo[2 * k1 + 1] = lo1;
-            seg_len[2 * k1 + 1] = bin_start[b0 + (hi - K2)] - lo1;
-        } else {
-            seg_lo[2 * k1 + 1] = 0;
-            seg_len[2 * k1 + 1] = 0;
+            lo1 = bin_start[b0];
+            len1 = bin_start[b0 + (hi - K2)];
         }
+    }
+    if (done && *done) return;
+    if (TW1) {
+#pragma unroll
+        for (int u = 0; u < PT; ++u)
+            if (tid + u * NT < K3) tw[tid + u * NT] = twv[u];
+    } else {
+        for (int t = tid; t < K3; t += NT) tw[t] = ax3.tw[t];
+    }
+    for (int t = tid; t < K3 * TW; t += NT) acc[t] = 0;
+    if (tid < p) {
+        seg_lo[2 * tid] = lo0;
+        seg_len[2 * tid] = len0 - lo0;
+        seg_lo[2 * tid + 1] = lo1;
+        seg_len[2 * tid + 1] = len1 - lo1;
+        seg_k1[2 * tid] = tid;
+        seg_k1[2 * tid + 1] = tid;
     }
     __syncthreads();
     if (tid == 0) {
@@ -99,20 +114,29 @@ __global__ __launch_bounds__(NT) void k_spread_r2c(KParams k, FftAxis ax3, const
             off += seg_len[sg];
         }
         seg_off[2 * p] = off;
-        nseg = 2 * p;
     }
     __syncthreads();
-    const int ncand = seg_off[nseg];
-    // Candidate c of a round is held by thread c in registers: its source
-    // value times the axis-1 weight, the axis-2 and axis-3 weights and its home
-    // indices (no LDS staging, so more blocks fit per CU).
+    const int ncand = seg_off[2 * p];
+    // Candidate c of a round is held by thread c in registers: its
+    // source value times the axis-1 weight, the axis-2 and axis-3 weights and
+    // its home indices (no LDS staging, so more blocks fit per CU).
     constexpr int PM = PC ? PC : QEQ_MAXP;
     float a0 = 0.f, w2[PM], w3[PM];
     int h2 = 0, h3 = 0;
     double asrc = 0.0;
-    auto load_cand = [&](int cidx) {
+    auto seg_of = [&](int cidx) {
+        // last segment starting at or before cidx (empty segments share their
+        // start with the next one and are passed over); independent LDS reads
         int sg = 0;
-        while (cidx >= seg_off[sg + 1]) ++sg;
+#pragma unroll
+        for (int s2 = 1; s2 < 2 * PM; ++s2) {
+            if (!PC && s2 >= 2 * p) break;
+            sg += cidx >= seg_off[s2] ? 1 : 0;
+        }
+        return sg;
+    };
+    auto load_cand = [&](int cidx) {
+        const int sg = seg_of(cidx);
         const int a = seg_lo[sg] + (cidx - seg_off[sg]);
         const float* w = wts + (size_t)a * 3 * QEQ_MAXP;
         const double sv = src[a];
@@ -129,9 +153,10 @@ __global__ __launch_bounds__(NT) void k_spread_r2c(KParams k, FftAxis ax3, const
     };
     // Fixed-point scale: every grid value of the tile is a sum over the
     // candidates of src times a weight product <= 1, taken at most once per
-    // candidate, so |value| <= S = sum |src|; with scale = 2^(60 - e),
-    // S < 2^e, every partial sum stays below 2^60 in magnitude.  One round:
-    // S from the registers; more rounds: a pass over the sources first.
+    // candidate, so |value| <= S = sum |src|; with scale = 2^(50 - e),
+    // S < 2^e, every term and every partial sum stays below 2^50 in
+    // magnitude.  One round: S from the registers; more rounds: a pass over
+    // the sources first.
     const bool one_round = ncand <= NT;
     {
         double v[1] = {0.0};
@@ -142,8 +167,7 @@ __global__ __launch_bounds__(NT) void k_spread_r2c(KParams k, FftAxis ax3, const
             }
         } else {
             for (int cidx = tid; cidx < ncand; cidx += NT) {
-                int sg = 0;
-                while (cidx >= seg_off[sg + 1]) ++sg;
+                const int sg = seg_of(cidx);
                 v[0] += fabs(src[seg_lo[sg] + (cidx - seg_off[sg])]);
             }
         }
@@ -151,17 +175,33 @@ __global__ __launch_bounds__(NT) void k_spread_r2c(KParams k, FftAxis ax3, const
         if (tid == 0) {
             int e = 0;
             (void)frexp(v[0] > 0.0 ? v[0] : 1.0, &e);   // v < 2^e
-            sh_scale = ldexpf(1.0f, max(-126, min(126, 60 - e)));
+            sh_scale = ldexpf(1.0f, max(-126, min(126, 50 - e)));
         }
         __syncthreads();
     }
     const float scale = sh_scale;
+    // A term t (|t| < 2^51) becomes an integer by one FP64 fused multiply-add
+    // with 1.5 * 2^52: the sum lies in [2^52, 2^53), where the spacing of
+    // doubles is 1, so it is t rounded to the nearest integer plus 2^52 + 2^51,
+    // and its bit pattern minus that of 1.5 * 2^52 (low word zero) is the
+    // two's-complement integer.
+    constexpr double RND = 6755399441055744.0;   // 1.5 * 2^52
     unsigned long long* acc_u = reinterpret_cast<unsigned long long*>(acc);
     for (int base = 0; base < ncand; base += NT) {
         const int cidx = base + tid;
         if (cidx < ncand) {
             if (!one_round) load_cand(cidx);
-            const float as = a0 * scale;
+            const double as = (double)(a0 * scale);
+            double w3d[PM];
+            int col[PM];
+#pragma unroll
+            for (int k3 = 0; k3 < PM; ++k3) {
+                if (!PC && k3 >= p) break;
+                w3d[k3] = (double)w3[k3];
+                int g3 = h3 - k3;
+                if (g3 < 0) g3 += K3;
+                col[k3] = g3 * TW;
+            }
 #pragma unroll
             for (int k2 = 0; k2 < PM; ++k2) {
                 if (!PC && k2 >= p) break;
@@ -170,13 +210,14 @@ __global__ __launch_bounds__(NT) void k_spread_r2c(KParams k, FftAxis ax3, const
                 int r = h2 - k2 - g20;
                 if (r < 0) r += K2;
                 if (r < 0 || r >= TW) continue;
-                const float a1 = as * w2[k2];
+                const double a1 = as * (double)w2[k2];   // exact: two 24-bit significands
 #pragma unroll
                 for (int k3 = 0; k3 < PM; ++k3) {
                     if (!PC && k3 >= p) break;
-                    int g3 = h3 - k3;
-                    if (g3 < 0) g3 += K3;
-                    atomicAdd(acc_u + g3 * TW + r, (unsigned long long)__float2ll_rn(a1 * w3[k3]));
+                    const long long b = __double_as_longlong(fma(a1, w3d[k3], RND));
+                    const unsigned hi = (unsigned)(b >> 32) - 0x43380000u;
+                    const unsigned long long t = ((unsigned long long)hi << 32) | (unsigned)b;
+                    atomicAdd(acc_u + col[k3] + r, t);
                 }
             }
         }
@@ -258,12 +299,21 @@ __global__ __launch_bounds__(NT) void k_fft_rows(KParams k, FftAxis ax2, float2*
     float2* buf = sm + K2;
     const int tid = threadIdx.x;
     const int row0 = blockIdx.x * NR;
-    for (int t = tid; t < K2; t += NT) tw[t] = ax2.tw[t];
-    for (int t = tid; t < NR * K2; t += NT) {
-        const int row = t / K2;
-        const int kk = t - row * K2;
-        buf[kk * KS + row] =
-            (row0 + row < nrows) ? C[(size_t)(row0 + row) * K2 + kk] : make_float2(0.f, 0.f);
+    auto ld_tw = [&](int t) { return ax2.tw[t]; };
+    auto st_tw = [&](int t, float2 v) { tw[t] = v; };
+    auto ld = [&](int t) {
+        const int row = t / K2, kk = t - row * K2;
+        return (row0 + row < nrows) ? C[(size_t)(row0 + row) * K2 + kk] : make_float2(0.f, 0.f);
+    };
+    auto st = [&](int t, float2 v) {
+        const int row = t / K2, kk = t - row * K2;
+        buf[kk * KS + row] = v;
+    };
+    if constexpr (KC > 0 && NRC > 0) {
+        stage2_ct<KC, NRC * KC, NT, float2>(tid, ld_tw, st_tw, ld, st);
+    } else {
+        stage_rt<4, float2>(K2, tid, NT, ld_tw, st_tw);
+        stage_rt<4, float2>(NR * K2, tid, NT, ld, st);
     }
     __syncthreads();
     if constexpr (KC > 0 && NRC > 0)
@@ -285,9 +335,7 @@ __global__ __launch_bounds__(NT) void k_fft_rows(KParams k, FftAxis ax2, float2*
 // is below 1e-14 for grids at the supported spacings).  Evaluated in FP32: it
 // multiplies an FP32 spectrum, and FP32 exp / divide keep its relative error
 // at a few ulp.
-__device__ __forceinline__ float green_value(const KParams& k, int m1, int m2, int m3,
-                                             const float* __restrict__ b1, const float* __restrict__ b2,
-                                             const float* __restrict__ b3) {
+__device__ __forceinline__ float green_core(const KParams& k, int m1, int m2, int m3) {
     if ((m1 | m2 | m3) == 0) return 0.f;
     if (2 * m1 == k.K1 || 2 * m2 == k.K2 || 2 * m3 == k.K3) return 0.f;
     const float x1 = (float)(m1 <= k.K1 / 2 ? m1 : m1 - k.K1);
@@ -297,7 +345,13 @@ __device__ __forceinline__ float green_value(const KParams& k, int m1, int m2, i
                     2.0f * ((float)k.M[3] * x1 * x2 + (float)k.M[4] * x1 * x3 + (float)k.M[5] * x2 * x3);
     const float k2 = 39.478417604357434475f * q;   // (2 pi)^2
     const float eta = (float)k.eta_green;
-    const float g = (float)k.green_pref * expf(-0.5f * eta * eta * k2) / k2;
+    return (float)k.green_pref * expf(-0.5f * eta * eta * k2) / k2;
+}
+
+__device__ __forceinline__ float green_value(const KParams& k, int m1, int m2, int m3,
+                                             const float* __restrict__ b1, const float* __restrict__ b2,
+                                             const float* __restrict__ b3) {
+    const float g = green_core(k, m1, m2, m3);
     return g * b1[m1] * b2[m2] * b3[m3];
 }
 
@@ -318,11 +372,34 @@ __global__ __launch_bounds__(NT) void k_fft_cols(KParams k, FftAxis ax1, float2*
     const int K2 = k.K2;
     const int m3 = blockIdx.x / k.ntile;
     const int g20 = (blockIdx.x - m3 * k.ntile) * TW;
-    for (int t = tid; t < K1; t += NT) tw[t] = ax1.tw[t];
     float2* base = C + (size_t)m3 * K1 * K2 + g20;
-    for (int t = tid; t < K1 * TW; t += NT) {
+    constexpr bool CT = KC > 0 && TWC > 0;
+    // compile-time tiles: the B-spline moduli of the Green's function are
+    // loaded with the tile (a thread's column c = t mod TW is the same for all
+    // its elements, since NT is a multiple of TW)
+    constexpr int PER = CT ? (KC * TWC + NT - 1) / NT : 1;
+    float bm1[PER];
+    float bm23 = 0.f;
+    if (CT && (mode & MESH_GREEN)) {
+        bm23 = b2[g20 + (tid & (TW - 1))] * b3[m3];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int t = tid + u * NT;
+            bm1[u] = (t < K1 * TW) ? b1[t >> twl] : 0.f;
+        }
+    }
+    auto ld_tw = [&](int t) { return ax1.tw[t]; };
+    auto st_tw = [&](int t, float2 v) { tw[t] = v; };
+    auto ld = [&](int t) {
         const int c = t & (TW - 1), g1 = t >> twl;
-        buf[t] = base[(size_t)g1 * K2 + c];
+        return base[(size_t)g1 * K2 + c];
+    };
+    auto st = [&](int t, float2 v) { buf[t] = v; };
+    if constexpr (CT) {
+        stage2_ct<KC, KC * TWC, NT, float2>(tid, ld_tw, st_tw, ld, st);
+    } else {
+        stage_rt<4, float2>(K1, tid, NT, ld_tw, st_tw);
+        stage_rt<4, float2>(K1 * TW, tid, NT, ld, st);
     }
     __syncthreads();
     if (mode & MESH_FWD) {
@@ -334,12 +411,25 @@ __global__ __launch_bounds__(NT) void k_fft_cols(KParams k, FftAxis ax1, float2*
     if (mode & MESH_GREEN) {
         double e = 0.0;
         const float mult = (m3 == 0) ? 1.f : 2.f;
-        for (int t = tid; t < K1 * TW; t += NT) {
-            const int c = t & (TW - 1), m1 = t >> twl;
-            const float g = green_value(k, m1, g20 + c, m3, b1, b2, b3);
-            const float2 x = buf[t];
-            if (mode & MESH_ENERGY) e += (double)(g * mult * (x.x * x.x + x.y * x.y));
-            buf[t] = make_float2(x.x * g, x.y * g);
+        if constexpr (CT) {
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const int t = tid + u * NT;
+                if (t >= K1 * TW) break;
+                const int c = t & (TW - 1), m1 = t >> twl;
+                const float g = green_core(k, m1, g20 + c, m3) * (bm1[u] * bm23);
+                const float2 x = buf[t];
+                if (mode & MESH_ENERGY) e += (double)(g * mult * (x.x * x.x + x.y * x.y));
+                buf[t] = make_float2(x.x * g, x.y * g);
+            }
+        } else {
+            for (int t = tid; t < K1 * TW; t += NT) {
+                const int c = t & (TW - 1), m1 = t >> twl;
+                const float g = green_value(k, m1, g20 + c, m3, b1, b2, b3);
+                const float2 x = buf[t];
+                if (mode & MESH_ENERGY) e += (double)(g * mult * (x.x * x.x + x.y * x.y));
+                buf[t] = make_float2(x.x * g, x.y * g);
+            }
         }
         if (mode & MESH_ENERGY) {
             double v[1] = {e};
@@ -379,10 +469,20 @@ __global__ __launch_bounds__(NT) void k_c2r(KParams k, FftAxis ax3, const float2
     const int tid = threadIdx.x;
     const int g1 = blockIdx.x / k.ntile;
     const int g20 = (blockIdx.x - g1 * k.ntile) * TW;
-    for (int t = tid; t < K3; t += NT) tw[t] = ax3.tw[t];
-    for (int t = tid; t < K3h * TW; t += NT) {
-        const int r = t & (TW - 1), m = t >> twl;
-        X[t] = C[((size_t)m * K1 + g1) * K2 + g20 + r];
+    {
+        auto ld_tw = [&](int t) { return ax3.tw[t]; };
+        auto st_tw = [&](int t, float2 v) { tw[t] = v; };
+        auto ld = [&](int t) {
+            const int r = t & (TW - 1), m = t >> twl;
+            return C[((size_t)m * K1 + g1) * K2 + g20 + r];
+        };
+        auto st = [&](int t, float2 v) { X[t] = v; };
+        if constexpr (KC > 0 && TWC > 0) {
+            stage2_ct<KC, (KC / 2 + 1) * TWC, NT, float2>(tid, ld_tw, st_tw, ld, st);
+        } else {
+            stage_rt<4, float2>(K3, tid, NT, ld_tw, st_tw);
+            stage_rt<4, float2>(K3h * TW, tid, NT, ld, st);
+        }
     }
     __syncthreads();
     // Z = X_even + i X_odd over the full axis (Hermitian extension)
@@ -474,10 +574,20 @@ __global__ __launch_bounds__(NT) void k_c2r_interp(KParams k, FftAxis ax3, const
             seg_len[2 * k1 + 1] = 0;
         }
     }
-    for (int t = tid; t < K3; t += NT) tw[t] = ax3.tw[t];
-    for (int t = tid; t < K3h * TW; t += NT) {
-        const int r = t & (TW - 1), m = t >> twl;
-        X[t] = C[((size_t)m * K1 + g1) * K2 + g20 + r];
+    {
+        auto ld_tw = [&](int t) { return ax3.tw[t]; };
+        auto st_tw = [&](int t, float2 v) { tw[t] = v; };
+        auto ld = [&](int t) {
+            const int r = t & (TW - 1), m = t >> twl;
+            return C[((size_t)m * K1 + g1) * K2 + g20 + r];
+        };
+        auto st = [&](int t, float2 v) { X[t] = v; };
+        if constexpr (CT) {
+            stage2_ct<KC, (KC / 2 + 1) * TWC, NT, float2>(tid, ld_tw, st_tw, ld, st);
+        } else {
+            stage_rt<4, float2>(K3, tid, NT, ld_tw, st_tw);
+            stage_rt<4, float2>(K3h * TW, tid, NT, ld, st);
+        }
     }
     __syncthreads();
     if (tid == 0) {
@@ -526,8 +636,13 @@ __global__ __launch_bounds__(NT) void k_c2r_interp(KParams k, FftAxis ax3, const
     float w1 = 0.f, w2[PM], w3[PM];
     int a = 0, k1 = 0, h2 = 0, h3 = 0;
     auto load_cand = [&](int cidx) {
+        // last segment starting at or before cidx (empty segments are passed over)
         int sg = 0;
-        while (cidx >= seg_off[sg + 1]) ++sg;
+#pragma unroll
+        for (int s2 = 1; s2 < 2 * PM; ++s2) {
+            if (!PC && s2 >= 2 * p) break;
+            sg += cidx >= seg_off[s2] ? 1 : 0;
+        }
         k1 = sg >> 1;
         a = seg_lo[sg] + (cidx - seg_off[sg]);
         const float* w = wts + (size_t)a * 3 * QEQ_MAXP;
@@ -615,12 +730,21 @@ __global__ __launch_bounds__(SLAB_NT) void k_slab_inv(KParams k, FftAxis ax2, Ff
     const int tid = threadIdx.x;
     const int g1 = blockIdx.x;
     const int K1 = k.K1;
-    for (int t = tid; t < K2C; t += SLAB_NT) tw2[t] = ax2.tw[t];
-    for (int t = tid; t < K3C; t += SLAB_NT) tw3[t] = ax3.tw[t];
-    for (int t = tid; t < NH; t += SLAB_NT) twh[t] = ax3.tw[2 * t];
-    for (int t = tid; t < K3H * K2C; t += SLAB_NT) {
-        const int m3 = t / K2C, m2 = t - m3 * K2C;
-        X[m2 * KS + m3] = C[((size_t)m3 * K1 + g1) * K2C + m2];
+    // the three twiddle tables (K2C + K3C + NH entries) and the plane
+    {
+        auto ld_tw = [&](int t) {
+            return t < K2C ? ax2.tw[t] : (t < K2C + K3C ? ax3.tw[t - K2C] : ax3.tw[2 * (t - K2C - K3C)]);
+        };
+        auto st_tw = [&](int t, float2 v) { tw2[t] = v; };   // tw2 | tw3 | twh are contiguous
+        auto ld = [&](int t) {
+            const int m3 = t / K2C, m2 = t - m3 * K2C;
+            return C[((size_t)m3 * K1 + g1) * K2C + m2];
+        };
+        auto st = [&](int t, float2 v) {
+            const int m3 = t / K2C, m2 = t - m3 * K2C;
+            X[m2 * KS + m3] = v;
+        };
+        stage2_ct<K2C + K3C + NH, K3H * K2C, SLAB_NT, float2>(tid, ld_tw, st_tw, ld, st);
     }
     __syncthreads();
     fft_ct<K2C, K3H, KS, SLAB_NT, true>(X, tw2, tid);
