@@ -42,6 +42,13 @@ MEASURED_TRAFFIC = {
                    "grid": (192, 192, 192), "spread_rows": 16,
                    "source_sha256_16": "5b8acc7b3de70b64",
                    "fetch_kib": 2567.5625, "fetch_scale": 2.0, "write_kib": 27936.0, "write_scale": 1.0},
+    # the complex-to-real pass of the CG products at 192^3: the plane kernel
+    # (inverse axis-2 and axis-3 transforms, then the back-interpolation
+    # partials), whose blocks hold whole planes (no tile width)
+    "c2r": {"kernel": "k_slab_inv", "file": "paper_2607_17978_amd/csrc/mesh.hip",
+            "grid": (192, 192, 192), "spread_rows": None,
+            "source_sha256_16": "895067507116dec8",
+            "fetch_kib": 16358.5625, "fetch_scale": 2.0, "write_kib": 1536.5, "write_scale": 1.0},
 }
 
 
@@ -69,7 +76,9 @@ def measured_traffic(name, tiles=(0, 0, 0), grid=(192, 192, 192)):
     m = MEASURED_TRAFFIC.get(name)
     if not m or kernel_source_hash(m["file"], m["kernel"]) != m["source_sha256_16"]:
         return None
-    if tuple(grid) != tuple(m["grid"]) or tiles[0] not in (0, m["spread_rows"]):
+    if tuple(grid) != tuple(m["grid"]):
+        return None
+    if m["spread_rows"] is not None and tiles[0] not in (0, m["spread_rows"]):
         return None
     return 1024.0 * (m["fetch_kib"] * m["fetch_scale"] + m["write_kib"] * m["write_scale"])
 

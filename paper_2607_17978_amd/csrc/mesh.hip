@@ -728,7 +728,9 @@ __global__ __launch_bounds__(SLAB_NT) void k_slab_inv(KParams k, FftAxis ax2, Ff
     float2* twh = tw3 + K3C;     // NH:  e^{-2 pi i j / NH}
     float2* X = twh + NH;        // K2C x KS
     const int tid = threadIdx.x;
-    const int g1 = blockIdx.x;
+    // XCD-aware plane order: the p planes that read one atom's weights run
+    // on the same XCD and share its L2
+    const int g1 = xcd_remap(blockIdx.x, gridDim.x);
     const int K1 = k.K1;
     // the three twiddle tables (K2C + K3C + NH entries) and the plane
     {

@@ -91,13 +91,14 @@ def test_bench_refuses_more_than_one_gpu():
     assert "one GPU" in (r.stdout + r.stderr)
 
 
-def test_bench_traffic_record_matches_the_spread_source():
+def test_bench_traffic_records_match_the_kernel_sources():
     """The HBM traffic in the bench line comes from rocprofv3 counters taken on
-    one version of the spread kernel; the stored source hash must still match
-    (bench.py reports traffic as null otherwise)."""
+    one version of each kernel that can be the dominant one; the stored source
+    hashes must still match (bench.py reports traffic as null otherwise)."""
     import importlib.util
     spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
     bench = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(bench)
-    rec = bench.MEASURED_TRAFFIC["spread_r2c"]
-    assert bench.kernel_source_hash(rec["file"], rec["kernel"]) == rec["source_sha256_16"]
+    assert set(bench.MEASURED_TRAFFIC) >= {"spread_r2c", "c2r"}
+    for name, rec in bench.MEASURED_TRAFFIC.items():
+        assert bench.kernel_source_hash(rec["file"], rec["kernel"]) == rec["source_sha256_16"], name
