@@ -240,10 +240,17 @@ def trajectory_frame0(dev):
                       q_tot=0.0, grid=(320, 320, 320))
 
 
-def trajectory_record(args, dev):
+# CG tolerance at which every start of the 131,072-atom trajectory frame meets
+# the charge bar (max |dq| <= 1e-5 e) against the FP64 oracle; at 1e-6 the
+# starts are 3e-5 to 5e-5 e off (tests/test_gpu_trajectory_parity.py)
+TRAJ_PARITY_TOL = 2e-7
+
+
+def trajectory_record(args, dev, tol=None, profile=True):
     """The 131,072-atom trajectory (320^3 grid): cold vs previous-frame vs
-    learned starts over the evaluation frames, and the 320^3 product's
-    per-pass timing on the last frame."""
+    learned starts over the evaluation frames at CG tolerance tol, and (with
+    profile) the 320^3 product's per-pass timing on the last frame."""
+    tol = args.tol if tol is None else tol
     from paper_2607_17978_amd import warmstart
 
     def log(msg):   # progress on stderr: every 25th frame and the training summary
@@ -252,16 +259,16 @@ def trajectory_record(args, dev):
             print("trajectory: " + msg, file=sys.stderr, flush=True)
 
     t0 = time.perf_counter()
-    out = warmstart.run_trajectory(frames=args.frames, epochs=args.epochs, tol=args.tol, device=dev,
-                                   spectral_kc=args.spectral_kc, profile_matvec=True, log=log)
+    out = warmstart.run_trajectory(frames=args.frames, epochs=args.epochs, tol=tol, device=dev,
+                                   spectral_kc=args.spectral_kc, profile_matvec=profile, log=log)
     wall = time.perf_counter() - t0
     nnz = int(round(out["n"] * 0.01 * 4.0 / 3.0 * np.pi * 11.0 ** 3))
-    mv = matvec_record(out.pop("stage_us"), tuple(out["grid"]), out["n"], nnz)
+    mv = matvec_record(out.pop("stage_us"), tuple(out["grid"]), out["n"], nnz) if profile else None
     keep = ("iters", "ms", "ms_with_inference", "all_converged", "q0_rejected")
     starts = {k: {f: (round(v[f], 3) if isinstance(v[f], float) else v[f]) for f in keep if f in v}
               for k, v in out.items() if isinstance(v, dict) and "iters" in v}
     rec = {"workload": f"131072-atom trajectory, 320^3 grid, frames {out['train_frames']}..{out['frames'] - 1} "
-                       f"evaluated (trained on the frames before), tol {args.tol:g}",
+                       f"evaluated (trained on the frames before), tol {tol:g}",
            "starts": starts, "max_dq_vs_cold": out["max_dq_vs_cold"],
            "descriptor_ms": round(out["descriptor_ms"], 3), "chi_feature_ms": round(out["chi_feature_ms"], 3),
            "predict_ms": out["predict_ms"], "predict_chi_ms": out["predict_chi_ms"],
@@ -489,6 +496,9 @@ def main():
     if not args.no_trajectory:
         torch.cuda.empty_cache()
         out["warmstart_131k"], out["matvec_320"] = trajectory_record(args, dev)
+        # the same study at the tolerance where every start meets the charge bar
+        torch.cuda.empty_cache()
+        out["warmstart_131k_parity_tol"], _ = trajectory_record(args, dev, TRAJ_PARITY_TOL, profile=False)
     if not args.no_cpu_baseline:
         print("cpu baseline: FP64 oracle on the 32768-atom system", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()
