@@ -53,9 +53,9 @@ MEASURED_TRAFFIC = {
 
 
 # HBM traffic of one k_batched launch (1,024 structures, order 6, spacing 0.8,
-# 1,024-thread workgroups, one per CU): FETCH_SIZE 4.89e7 KiB x 2.0 +
-# WRITE_SIZE 6.37e7 KiB x 1.0 (profiles/batched_1024_structures_counters.md)
-BATCH_TRAFFIC = 1024.0 * (4.89e7 * 2.0 + 6.37e7)
+# 1,024-thread workgroups, one per CU): FETCH_SIZE 5.067e7 KiB x 2.0 +
+# WRITE_SIZE 6.425e7 KiB x 1.0 (profiles/batched_1024_structures_counters.md)
+BATCH_TRAFFIC = 1024.0 * (5.067e7 * 2.0 + 6.425e7)
 
 
 def kernel_source_hash(path, kernel):
@@ -669,7 +669,7 @@ def batch_main(args, dev):
                                    "cg_iters_mean": float(np.mean(seq_iters))},
         # bound from counters (profiles/batched_1024_structures_counters.md): the
         # slots' grids (256 slots of ~3 MB) exceed the Infinity Cache and stream
-        # through HBM, ~165 GB per launch
+        # through HBM, ~170 GB per launch
         "roofline": {"bound": "hbm", "kernel": "k_batched", "achieved": round(bbytes / (kern_ms * 1e-3) / 1e9, 1),
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(bbytes / (kern_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),

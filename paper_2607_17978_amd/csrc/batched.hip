@@ -203,7 +203,9 @@ __device__ __forceinline__ void bq_lines_fft(float2* buf, const BAxis& ax, const
 // order-independent; FP32 LDS atomics are several times slower on gfx950),
 // scaled per batch so that no sum can overflow: a grid value is a sum over the
 // batch's candidate atoms of src times a weight product <= 1, each candidate at
-// most once, so |value| <= sum |src| < 2^e and the scale is 2^(60 - e).
+// most once, so |value| <= sum |src| < 2^e and the scale is 2^(50 - e); each
+// term is rounded to an integer by one FP64 fused multiply-add with 1.5 * 2^52
+// (its bit pattern minus the constant's is the integer, exact below 2^51).
 template <int K3C, int NT>
 __device__ void bq_passA(const BStruct& S, const Slot& sl, const double* src, int p, float2* buf,
                          const float2* tw, const int* hstart, const int* order, int tid) {
@@ -230,10 +232,11 @@ __device__ void bq_passA(const BStruct& S, const Slot& sl, const double* src, in
         if (tid == 0) {
             int e = 0;
             (void)frexp(v[0] > 0.0 ? v[0] : 1.0, &e);
-            sh_scale = ldexpf(1.0f, max(-126, min(126, 60 - e)));
+            sh_scale = ldexpf(1.0f, max(-126, min(126, 50 - e)));
         }
         __syncthreads();
         const float scale = sh_scale;
+        constexpr double RND = 6755399441055744.0;   // 1.5 * 2^52
         for (int t = tid; t < ncand * Dp; t += NT) {
             const int c = t / Dp;
             const int rem = t - c * Dp;
@@ -252,7 +255,9 @@ __device__ void bq_passA(const BStruct& S, const Slot& sl, const double* src, in
             for (int k3 = 0; k3 < p; ++k3) {
                 int g3 = h3 - k3;
                 if (g3 < 0) g3 += K3;
-                atomicAdd(acc_u + g3 * RW + r, (unsigned long long)__float2ll_rn(a0 * w[2 * QEQ_MAXP + k3]));
+                const long long b = __double_as_longlong(fma((double)a0, (double)w[2 * QEQ_MAXP + k3], RND));
+                const unsigned hi = (unsigned)(b >> 32) - 0x43380000u;
+                atomicAdd(acc_u + g3 * RW + r, ((unsigned long long)hi << 32) | (unsigned)b);
             }
         }
         __syncthreads();
@@ -346,13 +351,35 @@ __device__ void bq_pass_lines(const BStruct& S, const Slot& sl, int mode, float2
             const int g1 = L / K3h;
             base = (size_t)g1 * K2 * K3h + (L - g1 * K3h);
         }
-        for (int k = k0; k < K; k += KSTEP)
-            buf[k * KS + c] = live ? sl.C[base + k * kstride] : make_float2(0.f, 0.f);
+        // the line's elements (and its Green's function values) are all
+        // requested before the first LDS store, so the batch costs one memory
+        // round trip instead of one per element
+        constexpr int MAXIT = (BQ_KAX + KSTEP - 1) / KSTEP;
+        float gv[MAXIT];
+        {
+            float2 v[MAXIT];
+#pragma unroll
+            for (int u = 0; u < MAXIT; ++u) {
+                const int k = k0 + u * KSTEP;
+                if (k < K) v[u] = live ? sl.C[base + k * kstride] : make_float2(0.f, 0.f);
+                if (k < K && live && (mode & BQ_GREEN)) gv[u] = sl.G[base + k * kstride];
+            }
+#pragma unroll
+            for (int u = 0; u < MAXIT; ++u) {
+                const int k = k0 + u * KSTEP;
+                if (k < K) buf[k * KS + c] = v[u];
+            }
+        }
         __syncthreads();
         if (mode & BQ_FWD) bq_lines_fft<KC, NT, false>(buf, S.ax[AX], tw, tid);
         if (mode & BQ_GREEN) {
-            if (live)
-                for (int k = k0; k < K; k += KSTEP) buf[k * KS + c] = cscale(buf[k * KS + c], sl.G[base + k * kstride]);
+            if (live) {
+#pragma unroll
+                for (int u = 0; u < MAXIT; ++u) {
+                    const int k = k0 + u * KSTEP;
+                    if (k < K) buf[k * KS + c] = cscale(buf[k * KS + c], gv[u]);
+                }
+            }
             __syncthreads();
         }
         if (mode & BQ_INV) bq_lines_fft<KC, NT, true>(buf, S.ax[AX], tw, tid);
@@ -372,12 +399,30 @@ __device__ void bq_passE(const BStruct& S, const Slot& sl, float2* buf, const fl
     const int K3h = K3 / 2 + 1;
     const int nrows = S.ax[0].K * S.ax[1].K;
     const float* bf = reinterpret_cast<const float*>(buf);
+    // both halves' rows are requested before the first LDS store (one memory
+    // round trip per batch of rows)
+    constexpr int EIT = (NC * (BQ_KAX / 2 + 1) + NT - 1) / NT;
     for (int r0 = 0; r0 < nrows; r0 += 2 * NC) {
+        float2 xv[2][EIT];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int u = 0; u < EIT; ++u) {
+                const int t = tid + u * NT;
+                if (t < NC * K3h) {
+                    const int pr = t / K3h, m = t - pr * K3h;
+                    const int row = r0 + 2 * pr + h;
+                    xv[h][u] = row < nrows ? sl.C[(size_t)row * K3h + m] : make_float2(0.f, 0.f);
+                }
+            }
+#pragma unroll
         for (int half = 0; half < 2; ++half) {
-            for (int t = tid; t < NC * K3h; t += NT) {
+#pragma unroll
+            for (int u = 0; u < EIT; ++u) {
+                const int t = tid + u * NT;
+                if (t >= NC * K3h) continue;
                 const int pr = t / K3h, m = t - pr * K3h;
-                const int row = r0 + 2 * pr + half;
-                float2 X = row < nrows ? sl.C[(size_t)row * K3h + m] : make_float2(0.f, 0.f);
+                float2 X = xv[half][u];
                 float2 Xm = make_float2(X.x, -X.y);     // conj, for K3 - m
                 if (half) {
                     X = make_float2(-X.y, X.x);          // i X
