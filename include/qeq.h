@@ -366,9 +366,10 @@ int qeq_use_fused_interp(qeq_plan* plan, int32_t enable);
    block of the spread + axis-3 real-to-complex pass, tile_rows = axis-2 rows
    of the axis-1 and complex-to-real passes, fft_rows = rows per block of the
    axis-2 pass; 0 keeps the rule for that one.  Powers of two, 4..32 rows (1..32
-   for fft_rows), else QEQ_EINVAL.  A choice that does not divide the grid, is
-   narrower than p - 1 rows or needs more than 60 KB of LDS makes the next
-   solve return QEQ_EPLAN.  The widths change the blocking only: results agree
+   for fft_rows; spread_rows also 12 or 24), else QEQ_EINVAL.  A choice that
+   does not divide the grid, is narrower than p - 1 rows or needs more than
+   60 KB of LDS, or a spread width of 12 or 24 rows on a grid length without
+   a compiled kernel for it, makes the next solve return QEQ_EPLAN.  The widths change the blocking only: results agree
    to FP32 rounding order.  paper_2607_17978_amd.autotune measures them. */
 int qeq_set_tiles(qeq_plan* plan, int32_t spread_rows, int32_t tile_rows, int32_t fft_rows);
 

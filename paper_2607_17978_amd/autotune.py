@@ -147,6 +147,7 @@ def tune_batched(args, n_max=512, eta=2.0, r_cut=12.0, tol=1e-6, tol_q=1e-5, tol
 # ------------------------------------------------------------------ single-structure tiles
 # (spread rows, axis-1 / complex-to-real tile rows, axis-2 rows); 0 = the built-in rule
 TILE_ROWS = (8, 16, 32)
+SPREAD_ROWS = (8, 12, 16, 32)
 FFT_ROWS = (4, 8, 16)
 
 
@@ -209,7 +210,7 @@ def tune_tiles(system, dev, eta=2.0, r_cut=11.0, spline_order=6, tol=1e-6, reps=
     T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
     args = (T(system.pos), system.cell, T(system.sigma), T(system.J), T(system.chi), system.q_tot)
     n = len(system.pos)
-    cands = [(0, 0, 0)] + [(a, b, c) for a in TILE_ROWS for b in TILE_ROWS for c in FFT_ROWS]
+    cands = [(0, 0, 0)] + [(a, b, c) for a in SPREAD_ROWS for b in TILE_ROWS for c in FFT_ROWS]
     rows, base_q = [], None
     for tiles in cands:
         row = {"tiles": list(tiles)}

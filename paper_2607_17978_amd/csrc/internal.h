@@ -410,6 +410,8 @@ int launch_mesh_potential(qeq_plan* pl, const double* src, const int* done);
 // complex-to-real + interpolation pass applies, the per-atom interpolation
 // partials in pl->mpart instead of the real grid (*partials = true).
 int launch_mesh_cg(qeq_plan* pl, const double* src, const int* done, bool* partials);
+// whether the spread pass has a compile-time kernel for this length and tile width
+bool spread_tile_compiled(int K3, int tws, int p);
 size_t qeq_mesh_max_smem(const KParams& k);
 // Inverse transforms only (grid_c already holds a spectrum) -> grid_r.
 int launch_mesh_inverse(qeq_plan* pl);

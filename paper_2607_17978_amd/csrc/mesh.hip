@@ -267,8 +267,9 @@ __global__ __launch_bounds__(NT) void k_spread_r2c(KParams k, FftAxis ax3, const
     const int K3h = K3 / 2 + 1;
     const int twl = ilog2_dev(TW);
     for (int t = tid; t < K3h * TW; t += NT) {
-        const int r = t & (TW - 1);
-        const int m = t >> twl;
+        // compile-time tiles may have any even width (division by a constant)
+        const int m = TWC ? t / TWC : t >> twl;
+        const int r = t - m * TW;
         const int pr = r >> 1;
         const float2 Z = buf[m * ncol + pr];
         float2 Zc = buf[(m == 0 ? 0 : K3 - m) * ncol + pr];
@@ -938,7 +939,7 @@ size_t smem_c2r(const KParams& k) {
 
 // Specialised (length, tile) pairs; anything else runs the runtime-sized kernels.
 #define QEQ_FOR_EACH_SIZE(X) X(24, 8) X(48, 16) X(96, 16) X(192, 16) X(320, 16) X(320, 8)
-#define QEQ_FOR_EACH_SPREAD(X) X(24, 8) X(48, 16) X(96, 16) X(192, 16) X(320, 8)
+#define QEQ_FOR_EACH_SPREAD(X) X(24, 8) X(48, 16) X(96, 16) X(192, 12) X(192, 16) X(320, 8)
 
 int spread_pass(qeq_plan* pl, const double* src, const int* done) {
     const KParams& k = pl->kp;
@@ -957,6 +958,8 @@ int spread_pass(qeq_plan* pl, const double* src, const int* done) {
     }
     QEQ_FOR_EACH_SPREAD(X)
 #undef X
+    // the runtime-sized kernel indexes the tile by shifts: power-of-two widths only
+    if (k.TWS & (k.TWS - 1)) return QEQ_EPLAN;
     if (sh > 65536)
         QEQ_HIP(hipFuncSetAttribute((const void*)k_spread_r2c<0, 0, 0>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)sh));
@@ -1145,6 +1148,13 @@ int inverse_tail(qeq_plan* pl, const int* done) {
 }
 
 }  // namespace
+
+bool spread_tile_compiled(int K3, int tws, int p) {
+#define X(KK, TT) if (K3 == KK && tws == TT && p == 6) return true;
+    QEQ_FOR_EACH_SPREAD(X)
+#undef X
+    return false;
+}
 
 size_t qeq_mesh_max_smem(const KParams& k) {
     size_t a = smem_spread(k), b = smem_rows(k), c = smem_cols(k), d = smem_c2r(k);

@@ -167,7 +167,7 @@ __global__ __launch_bounds__(PW_NT) void k_pw_spread(KParams k, PwGeom g, const 
 // transposed, C[m3][g1][g2] (m2 contiguous).
 __device__ __forceinline__ void pw_tile_r2c(const KParams& k, const FftAxis& ax3, float2* buf, const float2* tw,
                                             int g1, int g20, float2* __restrict__ C, int tid) {
-    const int K1 = k.K1, K2 = k.K2, K3 = k.K3, TW = k.TWS, ncol = TW >> 1;
+    const int K1 = k.K1, K2 = k.K2, K3 = k.K3, TW = k.TW, ncol = TW >> 1;
     int twl = 0;
     while ((1 << twl) < TW) ++twl;
     fft_lds(buf, ax3, twl - 1, tw, false, tid, PW_NT);
@@ -192,20 +192,21 @@ __device__ __forceinline__ void pw_tile_r2c(const KParams& k, const FftAxis& ax3
 }
 
 // Real-to-complex transform along axis 3 of the real grid, block = (g1, tile
-// of TW rows g2), two real rows packed into one complex column; the half
+// of TW rows g2: the axis-1 / complex-to-real tile, a power of two), two
+// real rows packed into one complex column; the half
 // spectra are written transposed (C[m3][g1][g2]) as by the spline spread.
 __global__ __launch_bounds__(PW_NT) void k_pw_r2c(KParams k, FftAxis ax3, const float* __restrict__ R,
                                                 float2* __restrict__ C, const int* __restrict__ done) {
     if (done && *done) return;
     extern __shared__ float2 sm[];
-    const int K2 = k.K2, K3 = k.K3, TW = k.TWS;
+    const int K2 = k.K2, K3 = k.K3, TW = k.TW;
     float2* tw = sm;
     float2* buf = sm + K3;
     float* acc = reinterpret_cast<float*>(buf);
     const int tid = threadIdx.x;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int g1 = blk / k.ntile_s;
-    const int g20 = (blk - g1 * k.ntile_s) * TW;
+    const int g1 = blk / k.ntile;
+    const int g20 = (blk - g1 * k.ntile) * TW;
     for (int t = tid; t < K3; t += PW_NT) tw[t] = ax3.tw[t];
     // row index fastest: consecutive lanes write consecutive LDS words (the
     // transposed [g3][row] layout the FFT needs); each lane loads 4 values
@@ -403,7 +404,7 @@ static int pw_interp_launch(qeq_plan* pl, const double* src, const int* done, bo
 // y = A src into pw_y (sorted order); with fin also the forces into pw_f.
 int launch_pw_rec(qeq_plan* pl, const double* src, const int* done, bool fin) {
     const KParams& k = pl->kp;
-    const size_t sh = sizeof(float2) * ((size_t)k.K3 + (size_t)k.K3 * (k.TWS / 2));
+    const size_t sh = sizeof(float2) * ((size_t)k.K3 + (size_t)k.K3 * (k.TW / 2));
     const int nb = pw_blocks(k.n);
     const size_t nreal = (size_t)k.K1 * k.K2 * k.K3;   // a multiple of 4 (K_a % 4 == 0)
     hipLaunchKernelGGL(k_pw_zero, dim3((unsigned)((nreal / 4 + PW_NT - 1) / PW_NT)), dim3(PW_NT), 0, pl->stream,
@@ -412,7 +413,7 @@ int launch_pw_rec(qeq_plan* pl, const double* src, const int* done, bool fin) {
                        pl->grid_r, done);
     if (sh > 65536)
         QEQ_HIP(hipFuncSetAttribute((const void*)k_pw_r2c, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
-    hipLaunchKernelGGL(k_pw_r2c, dim3(k.K1 * k.ntile_s), dim3(PW_NT), sh, pl->stream, k, pl->axes.ax[2],
+    hipLaunchKernelGGL(k_pw_r2c, dim3(k.K1 * k.ntile), dim3(PW_NT), sh, pl->stream, k, pl->axes.ax[2],
                        pl->grid_r, pl->grid_c, done);
     QEQ_TRY(qeq_check(hipGetLastError()));
     QEQ_TRY(launch_mesh_from_spectrum(pl, done));

@@ -98,9 +98,12 @@ def test_tile_tuner_meets_oracle_and_caches(dev, tmp_path):
     plan = qeq.Plan(s.n, eta=2.0, r_cut=11.0, grid=s.grid)
     plan.set_tiles(32, 0, 0)                          # 32 spread rows: fits 96 rows, allowed
     with pytest.raises(qeq.QEqError):
-        plan.set_tiles(12, 0, 0)                          # not a power of two
+        plan.set_tiles(10, 0, 0)                          # neither a power of two nor 12 / 24
+    solve_args = (T(s.pos, dev), s.cell, T(s.sigma, dev), T(s.J, dev), T(s.chi, dev), s.q_tot)
+    plan.set_tiles(12, 0, 0)                          # accepted, but 96 has no compiled 12-row spread
+    q, _, _, st = plan.solve(*solve_args, check=False)
+    assert st["rc"] == qeq.QEQ_EPLAN
     plan.set_tiles(0, 0, 32)
-    q, _, _, st = plan.solve(T(s.pos, dev), s.cell, T(s.sigma, dev), T(s.J, dev), T(s.chi, dev), s.q_tot,
-                             check=False)
+    q, _, _, st = plan.solve(*solve_args, check=False)
     assert st["rc"] == 0
     plan.close()
