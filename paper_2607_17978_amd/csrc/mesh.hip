@@ -413,12 +413,30 @@ __global__ __launch_bounds__(NT) void k_fft_cols(KParams k, FftAxis ax1, float2*
         double e = 0.0;
         const float mult = (m3 == 0) ? 1.f : 2.f;
         if constexpr (CT) {
+            // a thread's elements share m2 (its column) and m3 (the block's):
+            // the quadratic form k^2 / (2 pi)^2 = M11 x1^2 + l1 x1 + q23 is two
+            // FMAs per element, and the screened kernel uses the hardware
+            // exponential and reciprocal (a few ulp, far below the FP32
+            // spectrum's own rounding where G is not already negligible)
+            const int m2 = g20 + (tid & (TW - 1));
+            const float x2 = (float)(m2 <= k.K2 / 2 ? m2 : m2 - k.K2), x3 = (float)m3;
+            const float M11 = (float)k.M[0];
+            const float l1 = 2.0f * ((float)k.M[3] * x2 + (float)k.M[4] * x3);
+            const float q23 = (float)k.M[1] * x2 * x2 + (float)k.M[2] * x3 * x3 + 2.0f * (float)k.M[5] * x2 * x3;
+            const float eta = (float)k.eta_green;
+            // exp(-eta^2 k^2 / 2) = 2^(ce q): ce = -eta^2 (2 pi)^2 log2(e) / 2
+            const float ce = -0.5f * eta * eta * 39.478417604357434475f * 1.4426950408889634f;
+            const float pref = (float)k.green_pref / 39.478417604357434475f;
+            const bool nyq23 = 2 * m2 == k.K2 || 2 * m3 == k.K3;
 #pragma unroll
             for (int u = 0; u < PER; ++u) {
                 const int t = tid + u * NT;
                 if (t >= K1 * TW) break;
-                const int c = t & (TW - 1), m1 = t >> twl;
-                const float g = green_core(k, m1, g20 + c, m3) * (bm1[u] * bm23);
+                const int m1 = t >> twl;
+                const float x1 = (float)(m1 <= K1 / 2 ? m1 : m1 - K1);
+                const float q = fmaf(fmaf(M11, x1, l1), x1, q23);
+                float g = pref * __builtin_amdgcn_exp2f(ce * q) * __builtin_amdgcn_rcpf(q) * (bm1[u] * bm23);
+                if (nyq23 || 2 * m1 == K1 || (m1 | m2 | m3) == 0) g = 0.f;
                 const float2 x = buf[t];
                 if (mode & MESH_ENERGY) e += (double)(g * mult * (x.x * x.x + x.y * x.y));
                 buf[t] = make_float2(x.x * g, x.y * g);
