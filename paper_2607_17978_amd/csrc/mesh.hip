@@ -740,7 +740,6 @@ __global__ __launch_bounds__(SLAB_NT) void k_slab_inv(KParams k, FftAxis ax2, Ff
     constexpr int K3H = K3C / 2 + 1;
     constexpr int KS = K3H;
     constexpr int NH = K3C / 2;
-    constexpr int NQ = NH / 2 + 1;
     extern __shared__ float2 sm[];
     float2* tw2 = sm;            // K2C: e^{-2 pi i j / K2}
     float2* tw3 = tw2 + K2C;     // K3C: e^{-2 pi i j / K3}
@@ -769,29 +768,51 @@ __global__ __launch_bounds__(SLAB_NT) void k_slab_inv(KParams k, FftAxis ax2, Ff
     }
     __syncthreads();
     fft_ct<K2C, K3H, KS, SLAB_NT, true>(X, tw2, tid);
-    // pairs (k, N/2 - k), k <= N/4: one thread reads both and writes both
-    for (int t = tid; t < K2C * NQ; t += SLAB_NT) {
-        const int g2 = t / NQ, kk = t - g2 * NQ;
-        float2* row = X + g2 * KS;
-        const int kp = NH - kk;
-        const float2 a = row[kk], b = row[kp];
-        float2 z[2];
+    // Length-NH inverse transform along each row g2 of the packed sequence
+    // z(n) = (X(n) + conj X(NH - n)) + i (X(n) - conj X(NH - n)) e^{2 pi i n / K3}
+    // (two real outputs per complex one).  Its first radix stage builds z
+    // while loading: each item reads its R0 elements and their mirrors, so the
+    // pairing costs no pass of its own over the plane.
+    {
+        constexpr int R0 = ct_radix_at(NH, 0);
+        constexpr int PER0 = NH / R0;
+        constexpr int ITEMS = PER0 * K2C;
+        constexpr int IT0 = (ITEMS + SLAB_NT - 1) / SLAB_NT;
+        float2 v[IT0][R0];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const float2 xk = h ? b : a, xq = h ? a : b;   // X[idx], X[N/2 - idx]
-            const int idx = h ? kp : kk;
-            const float2 cq = make_float2(xq.x, -xq.y);
-            const float2 e = cadd(xk, cq);
-            float2 w = tw3[idx];
-            w.y = -w.y;
-            const float2 o = cmul(csub(xk, cq), w);
-            z[h] = make_float2(e.x - o.y, e.y + o.x);
+        for (int it = 0; it < IT0; ++it) {
+            const int item = tid + it * SLAB_NT;
+            if (ITEMS % SLAB_NT == 0 || item < ITEMS) {
+                const int c = item % K2C, j = item / K2C;
+                const float2* row = X + c * KS;
+#pragma unroll
+                for (int r = 0; r < R0; ++r) {
+                    const int idx = j + r * PER0;
+                    const float2 xk = row[idx], xq = row[NH - idx];
+                    const float2 cq = make_float2(xq.x, -xq.y);
+                    const float2 e = cadd(xk, cq);
+                    float2 w = tw3[idx];
+                    w.y = -w.y;
+                    const float2 o = cmul(csub(xk, cq), w);
+                    v[it][r] = make_float2(e.x - o.y, e.y + o.x);
+                }
+            }
         }
-        row[kk] = z[0];
-        if (kp < NH && kp != kk) row[kp] = z[1];
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < IT0; ++it) {
+            const int item = tid + it * SLAB_NT;
+            if (ITEMS % SLAB_NT == 0 || item < ITEMS) {
+                const int c = item % K2C, j = item / K2C;
+                dft<R0>(v[it], true);
+                float2* row = X + c * KS;
+#pragma unroll
+                for (int r = 0; r < R0; ++r) row[j * R0 + r] = v[it][r];
+            }
+        }
+        __syncthreads();
+        fft_ct<NH, K2C, 1, SLAB_NT, true, 1, R0, KS>(X, twh, tid);
     }
-    __syncthreads();
-    fft_ct<NH, K2C, 1, SLAB_NT, true, 0, 1, KS>(X, twh, tid);
     if constexpr (!INTERP) {
         float2* R2 = reinterpret_cast<float2*>(R) + (size_t)g1 * K2C * NH;
         for (int t = tid; t < K2C * NH; t += SLAB_NT) {
