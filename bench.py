@@ -47,8 +47,8 @@ MEASURED_TRAFFIC = {
     # partials), whose blocks hold whole planes (no tile width)
     "c2r": {"kernel": "k_slab_inv", "file": "paper_2607_17978_amd/csrc/mesh.hip",
             "grid": (192, 192, 192), "spread_rows": None,
-            "source_sha256_16": "e31375062465aa4b",
-            "fetch_kib": 16358.5625, "fetch_scale": 2.0, "write_kib": 1536.5, "write_scale": 1.0},
+            "source_sha256_16": "c47e40ee927f63c0",
+            "fetch_kib": 16367.0625, "fetch_scale": 2.0, "write_kib": 1536.5, "write_scale": 1.0},
 }
 
 
