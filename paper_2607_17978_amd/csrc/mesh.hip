@@ -632,17 +632,25 @@ __global__ __launch_bounds__(NT) void k_c2r_interp(KParams k, FftAxis ax3, const
         }
         return make_float2(xa.x - xb.y, xa.y + xb.x);
     };
+    // compile-time sizes: the packed values are built inside the first radix
+    // stage of the transform (each item reads the X elements of its R0 inputs
+    // into registers; after the barrier the stage's outputs overwrite X in
+    // place), so the packing costs no LDS pass of its own
+    constexpr int NCZ = CT ? TWC / 2 : 1;
+    constexpr int R0 = CT ? ct_radix_at(KC, 0) : 1;
+    constexpr int PER0 = CT ? KC / R0 : 1;
+    constexpr int IT0 = CT ? (PER0 * NCZ + NT - 1) / NT : 1;
+    float2 v0[IT0][R0];
     if constexpr (CT) {
-        constexpr int NZ = KC * (TWC / 2);
-        constexpr int PER = (NZ + NT - 1) / NT;
-        float2 zr[PER];
 #pragma unroll
-        for (int u = 0; u < PER; ++u)
-            if (tid + u * NT < NZ) zr[u] = zval(tid + u * NT);
-        __syncthreads();
+        for (int it = 0; it < IT0; ++it) {
+            const int item = tid + it * NT;
+            if ((PER0 * NCZ) % NT == 0 || item < PER0 * NCZ) {
+                const int c = item % NCZ, j = item / NCZ;
 #pragma unroll
-        for (int u = 0; u < PER; ++u)
-            if (tid + u * NT < NZ) Z[tid + u * NT] = zr[u];
+                for (int r = 0; r < R0; ++r) v0[it][r] = zval((j + r * PER0) * NCZ + c);
+            }
+        }
     } else {
         for (int t = tid; t < K3 * ncol; t += NT) Z[t] = zval(t);
     }
@@ -676,10 +684,22 @@ __global__ __launch_bounds__(NT) void k_c2r_interp(KParams k, FftAxis ax3, const
         h3 = home[4 * a + 2];
     };
     if (tid < ncand) load_cand(tid);
-    if constexpr (CT)
-        fft_ct<KC, TWC / 2, TWC / 2, NT, true>(Z, tw, tid);
-    else
+    if constexpr (CT) {
+#pragma unroll
+        for (int it = 0; it < IT0; ++it) {
+            const int item = tid + it * NT;
+            if ((PER0 * NCZ) % NT == 0 || item < PER0 * NCZ) {
+                const int c = item % NCZ, j = item / NCZ;
+                dft<R0>(v0[it], true);
+#pragma unroll
+                for (int r = 0; r < R0; ++r) Z[(j * R0 + r) * NCZ + c] = v0[it][r];
+            }
+        }
+        __syncthreads();
+        fft_ct<KC, TWC / 2, TWC / 2, NT, true, 1, R0>(Z, tw, tid);
+    } else {
         fft_lds(Z, ax3, ncl, tw, true, tid, NT);
+    }
     // phi(g1, g20 + r, g3) = zf[(g3 ncol + r / 2) 2 + r % 2]
     const float* zf = reinterpret_cast<const float*>(Z);
     for (int cidx = tid; cidx < ncand; cidx += NT) {
