@@ -40,15 +40,15 @@ KIND_NAMES = ["spread_r2c", "fft_rows_fwd", "fft_cols_green", "fft_rows_inv", "c
 MEASURED_TRAFFIC = {
     "spread_r2c": {"kernel": "k_spread_r2c", "file": "paper_2607_17978_amd/csrc/mesh.hip",
                    "grid": (192, 192, 192), "spread_rows": 12,
-                   "source_sha256_16": "8aa8bda28dd6c394",
-                   "fetch_kib": 2568.0625, "fetch_scale": 2.0, "write_kib": 27936.0, "write_scale": 1.0},
+                   "source_sha256_16": "cbf6698befb443eb",
+                   "fetch_kib": 2564.5625, "fetch_scale": 2.0, "write_kib": 27936.0, "write_scale": 1.0},
     # the complex-to-real pass of the CG products at 192^3: the plane kernel
     # (inverse axis-2 and axis-3 transforms, then the back-interpolation
     # partials), whose blocks hold whole planes (no tile width)
     "c2r": {"kernel": "k_slab_inv", "file": "paper_2607_17978_amd/csrc/mesh.hip",
             "grid": (192, 192, 192), "spread_rows": None,
             "source_sha256_16": "c47e40ee927f63c0",
-            "fetch_kib": 16367.0625, "fetch_scale": 2.0, "write_kib": 1536.5, "write_scale": 1.0},
+            "fetch_kib": 16359.5625, "fetch_scale": 2.0, "write_kib": 1536.5, "write_scale": 1.0},
 }
 
 

@@ -223,46 +223,58 @@ __global__ __launch_bounds__(NT) void k_spread_r2c(KParams k, FftAxis ax3, const
         }
     }
     __syncthreads();
-    // fixed point -> FP32, packed two real rows per complex column
-    {
-        const float inv = 1.0f / scale;
-        constexpr int PER = KC > 0 && TWC > 0 ? (KC * (TWC / 2) + NT - 1) / NT : 1;
-        if constexpr (KC > 0 && TWC > 0) {
-            float2 v[PER];
+    // fixed point -> FP32, packed two real rows per complex column, then the
+    // axis-3 transform
+    const float inv = 1.0f / scale;
+    if constexpr (KC > 0 && TWC > 0) {
+        // the conversion happens inside the first radix stage: each item
+        // reads the fixed-point values of its R0 inputs into registers, and
+        // after the barrier the stage's outputs overwrite the accumulator
+        constexpr int NCS = TWC / 2;
+        constexpr int R0 = ct_radix_at(KC, 0), PER0 = KC / R0;
+        constexpr int ITEMS = PER0 * NCS, IT0 = (ITEMS + NT - 1) / NT;
+        float2 v[IT0][R0];
 #pragma unroll
-            for (int u = 0; u < PER; ++u) {
-                const int e = tid + u * NT;
-                if (e < KC * (TWC / 2)) {
-                    const int g3 = e / (TWC / 2), pr = e - g3 * (TWC / 2);
-                    v[u] = make_float2((float)acc[g3 * TWC + 2 * pr] * inv, (float)acc[g3 * TWC + 2 * pr + 1] * inv);
-                }
-            }
-            __syncthreads();
+        for (int it = 0; it < IT0; ++it) {
+            const int item = tid + it * NT;
+            if (ITEMS % NT == 0 || item < ITEMS) {
+                const int c = item % NCS, j = item / NCS;
 #pragma unroll
-            for (int u = 0; u < PER; ++u) {
-                const int e = tid + u * NT;
-                if (e < KC * (TWC / 2)) buf[e] = v[u];
-            }
-        } else {
-            // runtime sizes: convert through registers one chunk of NT at a time
-            for (int e0 = 0; e0 < K3 * ncol; e0 += NT) {
-                const int e = e0 + tid;
-                float2 v = make_float2(0.f, 0.f);
-                if (e < K3 * ncol) {
-                    const int g3 = e / ncol, pr = e - g3 * ncol;
-                    v = make_float2((float)acc[g3 * TW + 2 * pr] * inv, (float)acc[g3 * TW + 2 * pr + 1] * inv);
+                for (int r = 0; r < R0; ++r) {
+                    const int g3 = j + r * PER0;
+                    v[it][r] = make_float2((float)acc[g3 * TWC + 2 * c] * inv, (float)acc[g3 * TWC + 2 * c + 1] * inv);
                 }
-                __syncthreads();
-                if (e < K3 * ncol) buf[e] = v;
-                __syncthreads();
             }
         }
         __syncthreads();
-    }
-    if constexpr (KC > 0 && TWC > 0)
-        fft_ct<KC, TWC / 2, TWC / 2, NT, false>(buf, tw, tid);
-    else
+#pragma unroll
+        for (int it = 0; it < IT0; ++it) {
+            const int item = tid + it * NT;
+            if (ITEMS % NT == 0 || item < ITEMS) {
+                const int c = item % NCS, j = item / NCS;
+                dft<R0>(v[it], false);
+#pragma unroll
+                for (int r = 0; r < R0; ++r) buf[(j * R0 + r) * NCS + c] = v[it][r];
+            }
+        }
+        __syncthreads();
+        fft_ct<KC, NCS, NCS, NT, false, 1, R0>(buf, tw, tid);
+    } else {
+        // runtime sizes: convert through registers one chunk of NT at a time
+        for (int e0 = 0; e0 < K3 * ncol; e0 += NT) {
+            const int e = e0 + tid;
+            float2 v = make_float2(0.f, 0.f);
+            if (e < K3 * ncol) {
+                const int g3 = e / ncol, pr = e - g3 * ncol;
+                v = make_float2((float)acc[g3 * TW + 2 * pr] * inv, (float)acc[g3 * TW + 2 * pr + 1] * inv);
+            }
+            __syncthreads();
+            if (e < K3 * ncol) buf[e] = v;
+            __syncthreads();
+        }
+        __syncthreads();
         fft_lds(buf, ax3, ilog2_dev(ncol), tw, false, tid, NT);
+    }
     // unpack the two real rows of each complex column and write the half spectra
     const int K3h = K3 / 2 + 1;
     const int twl = ilog2_dev(TW);
