@@ -258,13 +258,28 @@ __device__ __forceinline__ void fft_stage_ct(float2* buf, const float2* tw, int 
 
 // CS: stride between columns (1 = interleaved columns; a transposed layout
 // has KS = 1 and CS = the row length).
-template <int K, int NCOL, int KS, int NTHR, bool INV, int S = 0, int NS = 1, int CS = 1>
+// SEND: the stage to stop before (the transform's remaining stages can then
+// be done by the caller, e.g. one that stores straight to global memory).
+template <int K, int NCOL, int KS, int NTHR, bool INV, int S = 0, int NS = 1, int CS = 1, int SEND = 64>
 __device__ __forceinline__ void fft_ct(float2* buf, const float2* tw, int tid) {
     constexpr int R = ct_radix_at(K, S);
-    if constexpr (R != 0) {
+    if constexpr (R != 0 && S < SEND) {
         fft_stage_ct<K, R, NS, NCOL, KS, NTHR, INV, CS>(buf, tw, tid);
-        fft_ct<K, NCOL, KS, NTHR, INV, S + 1, NS * R, CS>(buf, tw, tid);
+        fft_ct<K, NCOL, KS, NTHR, INV, S + 1, NS * R, CS, SEND>(buf, tw, tid);
     }
+}
+
+// Number of radix stages of the compile-time transform of length K, and the
+// product of the radices of the stages before stage s.
+constexpr int ct_nstages(int K) {
+    int s = 0;
+    while (ct_radix_at(K, s) != 0) ++s;
+    return s;
+}
+constexpr int ct_span(int K, int s) {
+    int ns = 1;
+    for (int t = 0; t < s; ++t) ns *= ct_radix_at(K, t);
+    return ns;
 }
 
 // ---------------------------------------------------------------------------

@@ -387,6 +387,137 @@ __global__ __launch_bounds__(NT) void k_fft_cols(KParams k, FftAxis ax1, float2*
     const int g20 = (blockIdx.x - m3 * k.ntile) * TW;
     float2* base = C + (size_t)m3 * K1 * K2 + g20;
     constexpr bool CT = KC > 0 && TWC > 0;
+    if constexpr (CT) {
+        if ((mode & (MESH_FWD | MESH_GREEN | MESH_INV)) == (MESH_FWD | MESH_GREEN | MESH_INV)) {
+            // The full product pass with the global-memory traffic folded into
+            // the transforms: the forward transform's first radix stage reads
+            // its inputs from HBM, the Green's function multiplies the inverse
+            // transform's first-stage inputs as they are read, and the
+            // inverse transform's last stage stores straight to HBM; each
+            // saves an LDS pass and a barrier.  Every item of every stage
+            // keeps the thread's column c = tid mod TW (NT is a multiple of
+            // TW), so the Green's function's m2 is fixed per thread.
+            constexpr int R0 = ct_radix_at(KC, 0), PER0 = KC / R0;
+            constexpr int IT0 = (PER0 * TWC + NT - 1) / NT;
+            constexpr int NST = ct_nstages(KC);
+            constexpr int RL = ct_radix_at(KC, NST - 1), NSL = ct_span(KC, NST - 1), PERL = KC / RL;
+            constexpr int ITL = (PERL * TWC + NT - 1) / NT;
+            constexpr int PT = (KC + NT - 1) / NT;
+            const int c = tid & (TWC - 1);
+            const int m2 = g20 + c;
+            float2 twv[PT], v[IT0][R0];
+            float bmv[IT0][R0];
+            // twiddles, the tile and the moduli of the thread's elements, all
+            // requested before any is used
+#pragma unroll
+            for (int u = 0; u < PT; ++u)
+                if (tid + u * NT < KC) twv[u] = ax1.tw[tid + u * NT];
+#pragma unroll
+            for (int it = 0; it < IT0; ++it) {
+                const int item = tid + it * NT;
+                if ((PER0 * TWC) % NT == 0 || item < PER0 * TWC) {
+                    const int j = item / TWC;
+#pragma unroll
+                    for (int r = 0; r < R0; ++r) {
+                        const int g1 = j + r * PER0;
+                        v[it][r] = base[(size_t)g1 * K2 + c];
+                        bmv[it][r] = b1[g1];   // index of the same element after the transform
+                    }
+                }
+            }
+            const float bm23v = b2[m2] * b3[m3];
+#pragma unroll
+            for (int u = 0; u < PT; ++u)
+                if (tid + u * NT < KC) tw[tid + u * NT] = twv[u];
+            // forward transform: first stage from registers (no twiddles), the rest in LDS
+#pragma unroll
+            for (int it = 0; it < IT0; ++it) {
+                const int item = tid + it * NT;
+                if ((PER0 * TWC) % NT == 0 || item < PER0 * TWC) {
+                    const int j = item / TWC;
+                    dft<R0>(v[it], false);
+#pragma unroll
+                    for (int r = 0; r < R0; ++r) buf[(j * R0 + r) * TWC + c] = v[it][r];
+                }
+            }
+            __syncthreads();
+            fft_ct<KC, TWC, TWC, NT, false, 1, R0>(buf, tw, tid);
+            // Green's function on the inverse transform's first-stage inputs
+            // (the quadratic form k^2 / (2 pi)^2 = M11 x1^2 + l1 x1 + q23,
+            // hardware exp2 and reciprocal)
+            const float x2 = (float)(m2 <= k.K2 / 2 ? m2 : m2 - k.K2), x3 = (float)m3;
+            const float M11 = (float)k.M[0];
+            const float l1 = 2.0f * ((float)k.M[3] * x2 + (float)k.M[4] * x3);
+            const float q23 = (float)k.M[1] * x2 * x2 + (float)k.M[2] * x3 * x3 + 2.0f * (float)k.M[5] * x2 * x3;
+            const float eta = (float)k.eta_green;
+            const float ce = -0.5f * eta * eta * 39.478417604357434475f * 1.4426950408889634f;
+            const float pref = (float)k.green_pref / 39.478417604357434475f;
+            const bool nyq23 = 2 * m2 == k.K2 || 2 * m3 == k.K3;
+            const float mult = (m3 == 0) ? 1.f : 2.f;
+            double e = 0.0;
+#pragma unroll
+            for (int it = 0; it < IT0; ++it) {
+                const int item = tid + it * NT;
+                if ((PER0 * TWC) % NT == 0 || item < PER0 * TWC) {
+                    const int j = item / TWC;
+#pragma unroll
+                    for (int r = 0; r < R0; ++r) {
+                        const int m1 = j + r * PER0;
+                        const float x1 = (float)(m1 <= KC / 2 ? m1 : m1 - KC);
+                        const float q = fmaf(fmaf(M11, x1, l1), x1, q23);
+                        float g = pref * __builtin_amdgcn_exp2f(ce * q) * __builtin_amdgcn_rcpf(q) *
+                                  (bmv[it][r] * bm23v);
+                        if (nyq23 || 2 * m1 == KC || (m1 | m2 | m3) == 0) g = 0.f;
+                        const float2 x = buf[m1 * TWC + c];
+                        if (mode & MESH_ENERGY) e += (double)(g * mult * (x.x * x.x + x.y * x.y));
+                        v[it][r] = make_float2(x.x * g, x.y * g);
+                    }
+                }
+            }
+            if (mode & MESH_ENERGY) {
+                double ev[1] = {e};
+                block_sum<1>(ev);
+                if (tid == 0) epart[blockIdx.x] = ev[0];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int it = 0; it < IT0; ++it) {
+                const int item = tid + it * NT;
+                if ((PER0 * TWC) % NT == 0 || item < PER0 * TWC) {
+                    const int j = item / TWC;
+                    dft<R0>(v[it], true);
+#pragma unroll
+                    for (int r = 0; r < R0; ++r) buf[(j * R0 + r) * TWC + c] = v[it][r];
+                }
+            }
+            __syncthreads();
+            fft_ct<KC, TWC, TWC, NT, true, 1, R0, 1, NST - 1>(buf, tw, tid);
+            // last inverse stage: LDS to registers, twiddles, DFT, stores to HBM
+            constexpr int STEPL = KC / (NSL * RL);
+#pragma unroll
+            for (int it = 0; it < ITL; ++it) {
+                const int item = tid + it * NT;
+                if ((PERL * TWC) % NT == 0 || item < PERL * TWC) {
+                    const int j = item / TWC;
+                    float2 u[RL];
+#pragma unroll
+                    for (int r = 0; r < RL; ++r) u[r] = buf[(j + r * PERL) * TWC + c];
+                    const int kk = j % NSL;
+#pragma unroll
+                    for (int r = 1; r < RL; ++r) {
+                        float2 w = tw[kk * r * STEPL];
+                        w.y = -w.y;
+                        u[r] = cmul(u[r], w);
+                    }
+                    dft<RL>(u, true);
+                    const int bk = (j - kk) * RL + kk;
+#pragma unroll
+                    for (int r = 0; r < RL; ++r) base[(size_t)(bk + r * NSL) * K2 + c] = u[r];
+                }
+            }
+            return;
+        }
+    }
     // compile-time tiles: the B-spline moduli of the Green's function are
     // loaded with the tile (a thread's column c = t mod TW is the same for all
     // its elements, since NT is a multiple of TW)
