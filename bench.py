@@ -39,16 +39,16 @@ KIND_NAMES = ["spread_r2c", "fft_rows_fwd", "fft_cols_green", "fft_rows_inv", "c
 # that source the traffic is reported as null until it is measured again.
 MEASURED_TRAFFIC = {
     "spread_r2c": {"kernel": "k_spread_r2c", "file": "paper_2607_17978_amd/csrc/mesh.hip",
-                   "grid": (192, 192, 192), "spread_rows": 12,
-                   "source_sha256_16": "cbf6698befb443eb",
-                   "fetch_kib": 2564.5625, "fetch_scale": 2.0, "write_kib": 27936.0, "write_scale": 1.0},
+                   "grid": (192, 192, 192), "spread_rows": 24,
+                   "source_sha256_16": "3d07f9713b40cbf8",
+                   "fetch_kib": 2574.5625, "fetch_scale": 2.0, "write_kib": 27936.0, "write_scale": 1.0},
     # the complex-to-real pass of the CG products at 192^3: the plane kernel
     # (inverse axis-2 and axis-3 transforms, then the back-interpolation
     # partials), whose blocks hold whole planes (no tile width)
     "c2r": {"kernel": "k_slab_inv", "file": "paper_2607_17978_amd/csrc/mesh.hip",
             "grid": (192, 192, 192), "spread_rows": None,
-            "source_sha256_16": "c47e40ee927f63c0",
-            "fetch_kib": 16359.5625, "fetch_scale": 2.0, "write_kib": 1536.5, "write_scale": 1.0},
+            "source_sha256_16": "6a5d23ab03dda841",
+            "fetch_kib": 16365.5625, "fetch_scale": 2.0, "write_kib": 1536.5, "write_scale": 1.0},
 }
 
 
@@ -59,14 +59,15 @@ BATCH_TRAFFIC = 1024.0 * (5.067e7 * 2.0 + 6.425e7)
 
 
 def kernel_source_hash(path, kernel):
-    """sha256 (16 hex digits) of a kernel's source text, from its template line to the next pass."""
+    """sha256 (16 hex digits) of a kernel's source text, from its template line
+    to the closing brace of its body (the first line that is a lone "}")."""
     import hashlib
     src = open(os.path.join(ROOT, path)).read()
     i = src.find("void " + kernel + "(")
     if i < 0:
         return None
     a = src.rfind("template <", 0, i)
-    b = src.find("// ------------------------------------------------------------------", i)
+    b = src.find("\n}\n", i) + 3
     return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
 
 

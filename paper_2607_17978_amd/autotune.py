@@ -147,7 +147,7 @@ def tune_batched(args, n_max=512, eta=2.0, r_cut=12.0, tol=1e-6, tol_q=1e-5, tol
 # ------------------------------------------------------------------ single-structure tiles
 # (spread rows, axis-1 / complex-to-real tile rows, axis-2 rows); 0 = the built-in rule
 TILE_ROWS = (8, 16, 32)
-SPREAD_ROWS = (8, 12, 16, 32)
+SPREAD_ROWS = (8, 12, 16, 24, 32)
 FFT_ROWS = (4, 8, 16)
 
 

@@ -404,15 +404,28 @@ int prepare(qeq_plan* pl, int n, const double* cell, double q_tot) {
         return K[1] % t == 0 && (size_t)K[0] * t * 8 <= 32768 &&
                (size_t)K[2] * (t / 2) * 8 + (size_t)(K[2] / 2 + 1) * t * 8 <= 32768;
     };
-    int tws = 16;   // spread: twiddles + int64 accumulator of the tile
-    while (tws > 4 && (K[1] % tws != 0 || (size_t)K[2] * 8 + (size_t)K[2] * tws * 8 > 32768)) tws >>= 1;
-    // A compiled spread tile of 12 rows keeps the block within 20 KB of LDS,
-    // so eight blocks (the wave limit) share a CU instead of six; at 192^3
-    // the spread's 3,072 blocks then start in 1.5 rounds instead of 2,304
-    // in two (24.1 -> 22.9 us per launch, 6.60 -> 6.50 ms per solve).
-    if (tws == 16 && K[1] % 12 == 0 && spread_tile_compiled(K[2], 12, p) &&
-        (size_t)K[2] * 8 + (size_t)K[2] * 12 * 8 <= 20480)
-        tws = 12;
+    // Spread tiles (block LDS: twiddles + int32 accumulator of the tile):
+    // the widest compiled width whose block stays within 26 KB (six blocks
+    // fit a CU) and that still gives at least two blocks per CU; failing
+    // that the widest compiled one within 26 KB; failing that the runtime
+    // kernel's power-of-two widths within 32 KB.  The spread's blocks wait
+    // mostly on their own chain of loads, atomics and barriers, so few,
+    // wide tiles that start together beat many narrow ones: 192^3, 24 rows
+    // (1,536 blocks, one round): 17.6 us per launch against 19.1 for 12
+    // rows; 320^3, 16 rows: 52.9 us against 55.7 for 8.
+    auto spread_fits = [&](int w) {
+        return K[1] % w == 0 && K[1] >= w + p - 1 && spread_tile_compiled(K[2], w, p) &&
+               (size_t)K[2] * 8 + (size_t)K[2] * w * 4 <= 26624;
+    };
+    int tws = 0;
+    for (int w : {32, 24, 16, 12, 8})
+        if (!tws && spread_fits(w) && (size_t)K[0] * (K[1] / w) >= 512) tws = w;
+    for (int w : {32, 24, 16, 12, 8})
+        if (!tws && spread_fits(w)) tws = w;
+    if (!tws) {
+        tws = 16;
+        while (tws > 4 && (K[1] % tws != 0 || (size_t)K[2] * 8 + (size_t)K[2] * tws * 4 > 32768)) tws >>= 1;
+    }
     int tw = 16;
     while (tw > 4 && !tile_fits(tw)) tw >>= 1;
     // tile widths set with qeq_set_tiles (e.g. by the autotuner) replace the rule
@@ -420,7 +433,7 @@ int prepare(qeq_plan* pl, int n, const double* cell, double q_tot) {
     if (pl->tile_set[1] > 0) tw = pl->tile_set[1];
     if (K[1] % tws != 0 || K[1] < tws + p - 1) return QEQ_EPLAN;
     if (K[1] % tw != 0 || K[1] < tw + p - 1) return QEQ_EPLAN;
-    if ((size_t)K[2] * 8 + (size_t)K[2] * tws * 8 > 61440 || (size_t)K[0] * tw * 8 + K[0] * 8 > 61440 ||
+    if ((size_t)K[2] * 8 + (size_t)K[2] * tws * 4 > 61440 || (size_t)K[0] * tw * 8 + K[0] * 8 > 61440 ||
         (size_t)K[2] * (tw / 2) * 8 + (size_t)(K[2] / 2 + 1) * tw * 8 + K[2] * 8 > 61440)
         return QEQ_EPLAN;
     k.TW = tw;

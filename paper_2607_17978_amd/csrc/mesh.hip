@@ -8,12 +8,11 @@
 // Passes (each one read and one write of the grid, transforms in LDS):
 //   1. spread + R2C along axis 3  : block = (g1, tile of TW rows g2).  The
 //      atoms whose spline support reaches the tile are held in registers (one
-//      per thread), their weights accumulated into the tile in 64-bit fixed
-//      point with integer
-//      LDS atomics (exact, order-independent sums; FP32 LDS atomics run at a
-//      fraction of the integer rate on gfx950), converted to FP32, two real
-//      rows packed into one complex FFT and the half spectra written
-//      transposed so that m2 becomes contiguous.
+//      per thread), their weights accumulated into the tile in 32-bit fixed
+//      point with integer LDS atomics (order-independent sums; FP32 LDS
+//      atomics run at a fraction of the integer rate on gfx950), converted
+//      to FP32, two real rows packed into one complex FFT and the half
+//      spectra written transposed so that m2 becomes contiguous.
 //   2. C2C along axis 2 (rows contiguous), NR rows per block.
 //   3. C2C along axis 1 (stride K2) on tiles of TW columns: forward FFT,
 //      multiplication by G(m) computed on the fly, inverse FFT, in one pass.
@@ -50,10 +49,11 @@ __global__ __launch_bounds__(NT) void k_spread_r2c(KParams k, FftAxis ax3, const
     const int TW = TWC ? TWC : k.TWS;
     const int p = PC ? PC : k.p;
     const int ncol = TW >> 1;
-    // LDS: twiddles | accumulator acc[g3][row] (int64; the FFT buffer
-    // buf[g3][pr] (complex) aliases its first half once converted)
+    // LDS: twiddles | accumulator acc[g3][row] (int32; the FFT buffer
+    // buf[g3][pr] (complex, two rows per element) takes its place once
+    // converted)
     float2* tw = sm;
-    long long* acc = reinterpret_cast<long long*>(sm + K3);
+    int* acc = reinterpret_cast<int*>(sm + K3);
     float2* buf = sm + K3;
     __shared__ int seg_lo[2 * QEQ_MAXP], seg_off[2 * QEQ_MAXP + 1], seg_k1[2 * QEQ_MAXP];
     __shared__ int seg_len[2 * QEQ_MAXP];
@@ -123,7 +123,7 @@ __global__ __launch_bounds__(NT) void k_spread_r2c(KParams k, FftAxis ax3, const
     constexpr int PM = PC ? PC : QEQ_MAXP;
     float a0 = 0.f, w2[PM], w3[PM];
     int h2 = 0, h3 = 0;
-    double asrc = 0.0;
+    double abound = 0.0;
     auto seg_of = [&](int cidx) {
         // last segment starting at or before cidx (empty segments share their
         // start with the next one and are passed over); independent LDS reads
@@ -140,53 +140,58 @@ __global__ __launch_bounds__(NT) void k_spread_r2c(KParams k, FftAxis ax3, const
         const int a = seg_lo[sg] + (cidx - seg_off[sg]);
         const float* w = wts + (size_t)a * 3 * QEQ_MAXP;
         const double sv = src[a];
-        asrc = fabs(sv);
-        a0 = (float)sv * w[seg_k1[sg]];
+        const float w1 = w[seg_k1[sg]];
+        a0 = (float)sv * w1;
+        float m2 = 0.f, m3 = 0.f;
 #pragma unroll
         for (int kk = 0; kk < PM; ++kk) {
             if (!PC && kk >= p) break;
             w2[kk] = w[QEQ_MAXP + kk];
             w3[kk] = w[2 * QEQ_MAXP + kk];
+            m2 = fmaxf(m2, w2[kk]);
+            m3 = fmaxf(m3, w3[kk]);
         }
+        abound = fabs(sv) * (double)w1 * (double)m2 * (double)m3;
         h2 = home[4 * a + 1];
         h3 = home[4 * a + 2];
     };
     // Fixed-point scale: every grid value of the tile is a sum over the
-    // candidates of src times a weight product <= 1, taken at most once per
-    // candidate, so |value| <= S = sum |src|; with scale = 2^(50 - e),
-    // S < 2^e, every term and every partial sum stays below 2^50 in
-    // magnitude.  One round: S from the registers; more rounds: a pass over
-    // the sources first.
+    // candidates of one term each, src w1(k1) w2(k2) w3(k3), so |value| <=
+    // S = sum over candidates of |src| w1 max(w2) max(w3); with scale =
+    // 2^(30 - e), S < 2^e, every scaled term and partial sum (rounding of
+    // each term included) stays below 2^31 in magnitude.  The step 2^(e-30)
+    // is at most 2^-29 S: with the weight maxima in S, about the rounding
+    // of the FP32 transforms that follow.  One round: S from the registers;
+    // more rounds: a pass over the candidates first.
     const bool one_round = ncand <= NT;
     {
         double v[1] = {0.0};
         if (one_round) {
             if (tid < ncand) {
                 load_cand(tid);
-                v[0] = asrc;
+                v[0] = abound;
             }
         } else {
             for (int cidx = tid; cidx < ncand; cidx += NT) {
-                const int sg = seg_of(cidx);
-                v[0] += fabs(src[seg_lo[sg] + (cidx - seg_off[sg])]);
+                load_cand(cidx);
+                v[0] += abound;
             }
         }
         block_sum<1>(v);
         if (tid == 0) {
             int e = 0;
             (void)frexp(v[0] > 0.0 ? v[0] : 1.0, &e);   // v < 2^e
-            sh_scale = ldexpf(1.0f, max(-126, min(126, 50 - e)));
+            sh_scale = ldexpf(1.0f, max(-126, min(126, 30 - e)));
         }
         __syncthreads();
     }
     const float scale = sh_scale;
-    // A term t (|t| < 2^51) becomes an integer by one FP64 fused multiply-add
+    // A term t (|t| < 2^31) becomes an integer by one FP64 fused multiply-add
     // with 1.5 * 2^52: the sum lies in [2^52, 2^53), where the spacing of
     // doubles is 1, so it is t rounded to the nearest integer plus 2^52 + 2^51,
-    // and its bit pattern minus that of 1.5 * 2^52 (low word zero) is the
+    // and the low word of its bit pattern (that of 1.5 * 2^52 is zero) is the
     // two's-complement integer.
     constexpr double RND = 6755399441055744.0;   // 1.5 * 2^52
-    unsigned long long* acc_u = reinterpret_cast<unsigned long long*>(acc);
     for (int base = 0; base < ncand; base += NT) {
         const int cidx = base + tid;
         if (cidx < ncand) {
@@ -214,10 +219,8 @@ __global__ __launch_bounds__(NT) void k_spread_r2c(KParams k, FftAxis ax3, const
 #pragma unroll
                 for (int k3 = 0; k3 < PM; ++k3) {
                     if (!PC && k3 >= p) break;
-                    const long long b = __double_as_longlong(fma(a1, w3d[k3], RND));
-                    const unsigned hi = (unsigned)(b >> 32) - 0x43380000u;
-                    const unsigned long long t = ((unsigned long long)hi << 32) | (unsigned)b;
-                    atomicAdd(acc_u + col[k3] + r, t);
+                    const int t = (int)(unsigned)__double_as_longlong(fma(a1, w3d[k3], RND));
+                    atomicAdd(acc + col[k3] + r, t);
                 }
             }
         }
@@ -241,8 +244,8 @@ __global__ __launch_bounds__(NT) void k_spread_r2c(KParams k, FftAxis ax3, const
                 const int c = item % NCS, j = item / NCS;
 #pragma unroll
                 for (int r = 0; r < R0; ++r) {
-                    const int g3 = j + r * PER0;
-                    v[it][r] = make_float2((float)acc[g3 * TWC + 2 * c] * inv, (float)acc[g3 * TWC + 2 * c + 1] * inv);
+                    const int2 a = *reinterpret_cast<const int2*>(acc + (j + r * PER0) * TWC + 2 * c);
+                    v[it][r] = make_float2((float)a.x * inv, (float)a.y * inv);
                 }
             }
         }
@@ -1131,7 +1134,7 @@ __global__ __launch_bounds__(NT) void k_cols_virial(KParams k, FftAxis ax1, cons
 }
 
 size_t smem_spread(const KParams& k) {
-    return sizeof(float2) * (size_t)k.K3 + sizeof(long long) * (size_t)k.K3 * k.TWS;
+    return sizeof(float2) * (size_t)k.K3 + sizeof(int) * (size_t)k.K3 * k.TWS;
 }
 size_t smem_rows(const KParams& k) { return sizeof(float2) * ((size_t)k.K2 + (size_t)k.K2 * (k.NR + 1)); }
 size_t smem_cols(const KParams& k) { return sizeof(float2) * ((size_t)k.K1 + (size_t)k.K1 * k.TW); }
@@ -1141,14 +1144,15 @@ size_t smem_c2r(const KParams& k) {
 
 // Specialised (length, tile) pairs; anything else runs the runtime-sized kernels.
 #define QEQ_FOR_EACH_SIZE(X) X(24, 8) X(48, 16) X(96, 16) X(192, 16) X(320, 16) X(320, 8)
-#define QEQ_FOR_EACH_SPREAD(X) X(24, 8) X(48, 16) X(96, 16) X(192, 12) X(192, 16) X(320, 8)
+#define QEQ_FOR_EACH_SPREAD(X) \
+    X(24, 8) X(48, 16) X(96, 16) X(192, 12) X(192, 16) X(192, 24) X(320, 8) X(320, 16)
 
 int spread_pass(qeq_plan* pl, const double* src, const int* done) {
     const KParams& k = pl->kp;
     dim3 g(k.K1 * k.ntile_s), b(NT);
     const size_t sh = smem_spread(k);
     ProfScope ps(pl, PK_SPREAD_R2C);
-    // the int64 accumulator of long axes can exceed the default 64 KB window
+    // the accumulator of long axes can exceed the default 64 KB window
 #define X(KK, TT)                                                                                  \
     if (k.K3 == KK && k.TWS == TT && k.p == 6) {                                                    \
         if (sh > 65536)                                                                            \
