@@ -394,15 +394,14 @@ int prepare(qeq_plan* pl, int n, const double* cell, double q_tot) {
     k.K2 = K[1];
     k.K3 = K[2];
     k.K3h = K[2] / 2 + 1;
-    // Axis-2 tiles of 16, 8 or 4 rows, every pass's block within 32 KB of
-    // LDS.  At 320^3 (the HBM-bound size) 8-row tiles let more blocks
-    // overlap their loads and stores (spread 106 -> 90 us, axis-1 pass
-    // 110 -> 88 us, C2R 94 -> 71 us, axis-2 rows 79 / 70 -> 58 / 54 us);
-    // at 192^3 the 16-row blocks (about 25 KB) are faster, and 32 rows were
-    // slower everywhere.
+    // Axis-1 / complex-to-real tiles of 16, 8 or 4 rows, every pass's block
+    // within 48 KB of LDS.  16 rows at 192^3 and at 320^3: with the
+    // two-stage transforms a 16-column tile keeps every thread of a radix-20
+    // stage busy (320^3: axis-1 pass 66.3 -> 49.9 us, C2R 49.7 -> 45.4 us
+    // against 8 rows); 32 rows were slower everywhere.
     auto tile_fits = [&](int t) {
-        return K[1] % t == 0 && (size_t)K[0] * t * 8 <= 32768 &&
-               (size_t)K[2] * (t / 2) * 8 + (size_t)(K[2] / 2 + 1) * t * 8 <= 32768;
+        return K[1] % t == 0 && (size_t)K[0] * t * 8 <= 49152 &&
+               (size_t)K[2] * (t / 2) * 8 + (size_t)(K[2] / 2 + 1) * t * 8 <= 49152;
     };
     // Spread tiles (block LDS: twiddles + int32 accumulator of the tile):
     // the widest compiled width whose block stays within 26 KB (six blocks

@@ -6,6 +6,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+#include <utility>
+
 #define QEQ_MAXP 8          // largest supported spline order
 #define QEQ_FFT_MAXST 10    // largest number of radix stages
 #define QEQ_FFT_EMAX 40     // complex elements one thread holds during a stage
@@ -136,6 +139,106 @@ template <> __device__ __forceinline__ void dft<8>(float2* v, bool inv) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Composite small DFTs (radix 6, 10, 12, 16, 20) in registers: for
+// N = R1 R2, n = R2 n1 + n2 and k = k1 + R1 k2,
+//   X[k1 + R1 k2] = sum_n2 W_R2^{n2 k2} W_N^{n2 k1} (sum_n1 x[R2 n1 + n2] W_R1^{n1 k1}),
+// i.e. R2 DFTs of length R1, constant twiddles W_N^{n2 k1}, R1 DFTs of
+// length R2.  A radix-16 stage does in one LDS pass what two radix-4
+// stages do in two.
+// ---------------------------------------------------------------------------
+template <int... I, typename F>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// cos and sin of 2 pi m / N at compile time (Taylor series after reduction
+// to [-pi/4, pi/4] by octant; double precision, rounded once to float)
+constexpr double ce_sin_series(double x) {
+    double t = x, s = x;
+    for (int k = 1; k < 16; ++k) {
+        t *= -x * x / ((2.0 * k) * (2.0 * k + 1.0));
+        s += t;
+    }
+    return s;
+}
+constexpr double ce_cos_series(double x) {
+    double t = 1.0, s = 1.0;
+    for (int k = 1; k < 16; ++k) {
+        t *= -x * x / ((2.0 * k - 1.0) * (2.0 * k));
+        s += t;
+    }
+    return s;
+}
+// angle 2 pi m / N written as (octant o, remainder r) with 8 m = o N + r,
+// 0 <= r < N: theta = o pi / 4 + 2 pi r / (8 N)
+constexpr double ce_trig(int m, int N, bool want_sin) {
+    const int mm = ((m % N) + N) % N;
+    const int o = (8 * mm) / N, r = 8 * mm - o * N;
+    const double x = 2.0 * 3.14159265358979323846 * r / (8.0 * N);   // [0, pi/4)
+    const double h = 0.70710678118654752440;
+    // cos / sin of o pi / 4 + x from those of x
+    const double cx = ce_cos_series(x), sx = ce_sin_series(x);
+    const double co[8] = {1, h, 0, -h, -1, -h, 0, h};
+    const double so[8] = {0, h, 1, h, 0, -h, -1, -h};
+    return want_sin ? so[o] * cx + co[o] * sx : co[o] * cx - so[o] * sx;
+}
+
+// x W_N^M, W_N = exp(-+ 2 pi i / N): multiples of pi / 2 by sign changes and
+// swaps, the others by one complex product with constant factors
+template <int N, int M>
+__device__ __forceinline__ float2 twiddle_const(float2 x, bool inv) {
+    constexpr int m = M % N;
+    if constexpr (m == 0) {
+        return x;
+    } else if constexpr (4 * m == N) {
+        return cmul_mi(x, inv);
+    } else if constexpr (2 * m == N) {
+        return make_float2(-x.x, -x.y);
+    } else if constexpr (4 * m == 3 * N) {
+        return cmul_mi(x, !inv);
+    } else {
+        constexpr float c = (float)ce_trig(m, N, false), sn = (float)ce_trig(m, N, true);
+        return cmul(x, make_float2(c, inv ? sn : -sn));
+    }
+}
+
+template <int R1, int R2>
+__device__ __forceinline__ void dft_ct2(float2* v, bool inv) {
+    constexpr int N = R1 * R2;
+    float2 t[N];
+    static_for<R2>([&](auto n2c) {
+        constexpr int n2 = decltype(n2c)::value;
+        float2 a[R1];
+#pragma unroll
+        for (int n1 = 0; n1 < R1; ++n1) a[n1] = v[R2 * n1 + n2];
+        dft<R1>(a, inv);
+        static_for<R1>([&](auto k1c) {
+            constexpr int k1 = decltype(k1c)::value;
+            t[n2 * R1 + k1] = twiddle_const<N, n2 * k1>(a[k1], inv);
+        });
+    });
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) {
+        float2 b[R2];
+#pragma unroll
+        for (int n2 = 0; n2 < R2; ++n2) b[n2] = t[n2 * R1 + k1];
+        dft<R2>(b, inv);
+#pragma unroll
+        for (int k2 = 0; k2 < R2; ++k2) v[k1 + R1 * k2] = b[k2];
+    }
+}
+
+template <> __device__ __forceinline__ void dft<6>(float2* v, bool inv) { dft_ct2<3, 2>(v, inv); }
+template <> __device__ __forceinline__ void dft<10>(float2* v, bool inv) { dft_ct2<5, 2>(v, inv); }
+template <> __device__ __forceinline__ void dft<12>(float2* v, bool inv) { dft_ct2<4, 3>(v, inv); }
+template <> __device__ __forceinline__ void dft<16>(float2* v, bool inv) { dft_ct2<4, 4>(v, inv); }
+template <> __device__ __forceinline__ void dft<20>(float2* v, bool inv) { dft_ct2<5, 4>(v, inv); }
+
 // One Stockham (decimation-in-time, self-sorting) stage of radix R on ncol
 // interleaved columns held in LDS: element (index k, column c) lives at
 // buf[k * ncol + c].  Each butterfly j of a column reads x[j + r K/R],
@@ -206,14 +309,55 @@ __device__ __forceinline__ void fft_lds(float2* buf, const FftAxis& ax, int ncol
 // the radices the length needs are instantiated, and register arrays are
 // sized exactly.  Element (k, c) lives at buf[k * KS + c * CS].
 // ---------------------------------------------------------------------------
-constexpr int ct_radix_at(int K, int s) {
-    int n = K, idx = 0;
-    while (n % 5 == 0) { if (idx == s) return 5; n /= 5; ++idx; }
-    while (n % 3 == 0) { if (idx == s) return 3; n /= 3; ++idx; }
-    while (n % 8 == 0) { if (idx == s) return 8; n /= 8; ++idx; }
-    if (n == 4) { if (idx == s) return 4; n = 1; ++idx; }
-    if (n == 2) { if (idx == s) return 2; n = 1; ++idx; }
-    return 0;
+// Stage radices of a compile-time length.  Composite plan: the fewest stages
+// (one LDS pass each) over the radices 2, 3, 4, 5, 8 and the register
+// composites 6, 10, 12, 16, 20; among those the smallest largest radix;
+// larger radices first (192 = 16 x 12, 96 = 12 x 8, 320 = 20 x 16).
+// Lengths that need more than three such stages, and the plain plan, take
+// 5s, 3s, 8s, then 4 or 2 (192 = 3 x 8 x 8).
+constexpr bool ct_radix_ok(int r) {
+    return r == 2 || r == 3 || r == 4 || r == 5 || r == 6 || r == 8 || r == 10 || r == 12 || r == 16 || r == 20;
+}
+constexpr int ct_radix_plan(int K, int s, bool composite) {
+    if (!composite) {
+        int n = K, idx = 0;
+        while (n % 5 == 0) { if (idx == s) return 5; n /= 5; ++idx; }
+        while (n % 3 == 0) { if (idx == s) return 3; n /= 3; ++idx; }
+        while (n % 8 == 0) { if (idx == s) return 8; n /= 8; ++idx; }
+        if (n == 4) { if (idx == s) return 4; n = 1; ++idx; }
+        if (n == 2) { if (idx == s) return 2; n = 1; ++idx; }
+        return 0;
+    }
+    if (ct_radix_ok(K)) return s == 0 ? K : 0;
+    int b1 = 0, b2 = 0, b3 = 0, best = 1 << 30;
+    for (int a = 20; a >= 2; --a) {
+        if (!ct_radix_ok(a) || K % a) continue;
+        const int c = K / a;
+        if (ct_radix_ok(c) && a >= c && a < best) { best = a; b1 = a; b2 = c; }
+    }
+    if (b1) return s == 0 ? b1 : (s == 1 ? b2 : 0);
+    for (int a = 20; a >= 2; --a) {
+        if (!ct_radix_ok(a) || K % a) continue;
+        for (int b = a; b >= 2; --b) {
+            if (!ct_radix_ok(b) || (K / a) % b) continue;
+            const int c = K / a / b;
+            if (ct_radix_ok(c) && b >= c && a < best) { best = a; b1 = a; b2 = b; b3 = c; }
+        }
+    }
+    if (b1) return s == 0 ? b1 : (s == 1 ? b2 : (s == 2 ? b3 : 0));
+    return ct_radix_plan(K, s, false);
+}
+// The composite plan is taken while each of its stages still gives every
+// other thread of the block a butterfly ((K / R) ncol >= nthr / 2): on
+// narrow tiles (320^3 rows of 4 or 8 columns) the few large butterflies
+// leave most of the block idle and the plain plan is faster.
+constexpr bool ct_composite(int K, int ncol, int nthr) {
+    for (int s = 0; ct_radix_plan(K, s, true) != 0; ++s)
+        if ((K / ct_radix_plan(K, s, true)) * ncol * 2 < nthr) return false;
+    return true;
+}
+constexpr int ct_radix_at(int K, int s, int ncol, int nthr) {
+    return ct_radix_plan(K, s, ct_composite(K, ncol, nthr));
 }
 
 template <int K, int R, int NS, int NCOL, int KS, int NTHR, bool INV, int CS = 1>
@@ -262,23 +406,23 @@ __device__ __forceinline__ void fft_stage_ct(float2* buf, const float2* tw, int 
 // be done by the caller, e.g. one that stores straight to global memory).
 template <int K, int NCOL, int KS, int NTHR, bool INV, int S = 0, int NS = 1, int CS = 1, int SEND = 64>
 __device__ __forceinline__ void fft_ct(float2* buf, const float2* tw, int tid) {
-    constexpr int R = ct_radix_at(K, S);
+    constexpr int R = ct_radix_at(K, S, NCOL, NTHR);
     if constexpr (R != 0 && S < SEND) {
         fft_stage_ct<K, R, NS, NCOL, KS, NTHR, INV, CS>(buf, tw, tid);
         fft_ct<K, NCOL, KS, NTHR, INV, S + 1, NS * R, CS, SEND>(buf, tw, tid);
     }
 }
 
-// Number of radix stages of the compile-time transform of length K, and the
-// product of the radices of the stages before stage s.
-constexpr int ct_nstages(int K) {
+// Number of radix stages of the compile-time transform of length K on ncol
+// columns with nthr threads, and the product of the radices before stage s.
+constexpr int ct_nstages(int K, int ncol, int nthr) {
     int s = 0;
-    while (ct_radix_at(K, s) != 0) ++s;
+    while (ct_radix_at(K, s, ncol, nthr) != 0) ++s;
     return s;
 }
-constexpr int ct_span(int K, int s) {
+constexpr int ct_span(int K, int s, int ncol, int nthr) {
     int ns = 1;
-    for (int t = 0; t < s; ++t) ns *= ct_radix_at(K, t);
+    for (int t = 0; t < s; ++t) ns *= ct_radix_at(K, t, ncol, nthr);
     return ns;
 }
 

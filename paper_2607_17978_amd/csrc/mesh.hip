@@ -234,7 +234,7 @@ __global__ __launch_bounds__(NT) void k_spread_r2c(KParams k, FftAxis ax3, const
         // reads the fixed-point values of its R0 inputs into registers, and
         // after the barrier the stage's outputs overwrite the accumulator
         constexpr int NCS = TWC / 2;
-        constexpr int R0 = ct_radix_at(KC, 0), PER0 = KC / R0;
+        constexpr int R0 = ct_radix_at(KC, 0, NCS, NT), PER0 = KC / R0;
         constexpr int ITEMS = PER0 * NCS, IT0 = (ITEMS + NT - 1) / NT;
         float2 v[IT0][R0];
 #pragma unroll
@@ -400,10 +400,11 @@ __global__ __launch_bounds__(NT) void k_fft_cols(KParams k, FftAxis ax1, float2*
             // saves an LDS pass and a barrier.  Every item of every stage
             // keeps the thread's column c = tid mod TW (NT is a multiple of
             // TW), so the Green's function's m2 is fixed per thread.
-            constexpr int R0 = ct_radix_at(KC, 0), PER0 = KC / R0;
+            constexpr int R0 = ct_radix_at(KC, 0, TWC, NT), PER0 = KC / R0;
             constexpr int IT0 = (PER0 * TWC + NT - 1) / NT;
-            constexpr int NST = ct_nstages(KC);
-            constexpr int RL = ct_radix_at(KC, NST - 1), NSL = ct_span(KC, NST - 1), PERL = KC / RL;
+            constexpr int NST = ct_nstages(KC, TWC, NT);
+            static_assert(NST >= 2, "the first and the last stage are distinct");
+            constexpr int RL = ct_radix_at(KC, NST - 1, TWC, NT), NSL = ct_span(KC, NST - 1, TWC, NT), PERL = KC / RL;
             constexpr int ITL = (PERL * TWC + NT - 1) / NT;
             constexpr int PT = (KC + NT - 1) / NT;
             const int c = tid & (TWC - 1);
@@ -783,7 +784,7 @@ __global__ __launch_bounds__(NT) void k_c2r_interp(KParams k, FftAxis ax3, const
     // into registers; after the barrier the stage's outputs overwrite X in
     // place), so the packing costs no LDS pass of its own
     constexpr int NCZ = CT ? TWC / 2 : 1;
-    constexpr int R0 = CT ? ct_radix_at(KC, 0) : 1;
+    constexpr int R0 = CT ? ct_radix_at(KC, 0, TWC / 2, NT) : 1;
     constexpr int PER0 = CT ? KC / R0 : 1;
     constexpr int IT0 = CT ? (PER0 * NCZ + NT - 1) / NT : 1;
     float2 v0[IT0][R0];
@@ -940,7 +941,7 @@ __global__ __launch_bounds__(SLAB_NT) void k_slab_inv(KParams k, FftAxis ax2, Ff
     // while loading: each item reads its R0 elements and their mirrors, so the
     // pairing costs no pass of its own over the plane.
     {
-        constexpr int R0 = ct_radix_at(NH, 0);
+        constexpr int R0 = ct_radix_at(NH, 0, K2C, SLAB_NT);
         constexpr int PER0 = NH / R0;
         constexpr int ITEMS = PER0 * K2C;
         constexpr int IT0 = (ITEMS + SLAB_NT - 1) / SLAB_NT;

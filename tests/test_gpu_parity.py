@@ -351,9 +351,11 @@ def test_fused_interp_matches_grid_path(dev, which):
     print(which, "tol 1e-9 iters", st0["iters"], st1["iters"], "max |dq|", dq)
     # tol 1e-9 lies below the FP32 floor of the true residual (~2e-7 at
     # 32,768 atoms): both paths end through true-residual restarts, whose
-    # count depends on rounding, so only the charges are compared there
+    # count depends on rounding, so only the charges are compared there; the
+    # two paths sum in different FP32 orders, which at that floor leaves
+    # 0.5e-7 to 1.2e-7 e between their charges (the oracle bar is 1e-5 e)
     assert st0["rc"] == 0 and st1["rc"] == 0
-    assert dq <= 1e-7
+    assert dq <= 2e-7
     plan.close()
     # at the benchmark tolerance the two paths stop within a few iterations
     # of each other (the last iterations before 1e-6 reduce the residual
