@@ -47,8 +47,8 @@ MEASURED_TRAFFIC = {
     # partials), whose blocks hold whole planes (no tile width)
     "c2r": {"kernel": "k_slab_inv", "file": "paper_2607_17978_amd/csrc/mesh.hip",
             "grid": (192, 192, 192), "spread_rows": None,
-            "source_sha256_16": "5da4cf40da0bef7e",
-            "fetch_kib": 16351.5625, "fetch_scale": 2.0, "write_kib": 1536.5, "write_scale": 1.0},
+            "source_sha256_16": "2663c72b68804186",
+            "fetch_kib": 16359.5625, "fetch_scale": 2.0, "write_kib": 1536.5, "write_scale": 1.0},
 }
 
 

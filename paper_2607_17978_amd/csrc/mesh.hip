@@ -917,7 +917,25 @@ __global__ __launch_bounds__(SLAB_NT) void k_slab_inv(KParams k, FftAxis ax2, Ff
     // on the same XCD and share its L2
     const int g1 = xcd_remap(blockIdx.x, gridDim.x);
     const int K1 = k.K1;
-    // the three twiddle tables (K2C + K3C + NH entries) and the plane
+    // interpolation: atom ranges of the p planes whose support reaches g1
+    // (read now, used at the end)
+    constexpr int P = 6;
+    int blo[P], bhi[P];
+    if constexpr (INTERP) {
+#pragma unroll
+        for (int k1 = 0; k1 < P; ++k1) {
+            int h1 = g1 + k1;
+            if (h1 >= K1) h1 -= K1;
+            blo[k1] = bin_start[h1 * K2C];
+            bhi[k1] = bin_start[(h1 + 1) * K2C];
+        }
+    }
+    // The three twiddle tables (K2C + K3C + NH entries) and the plane, in two
+    // groups of m3 columns: the axis-2 transforms of the first group run
+    // while the second group's loads are in flight (barriers wait on LDS
+    // only), and the columns are independent.
+    constexpr int CA = (K3H + 1) / 2, CB = K3H - CA;
+    auto ld_col = [&](int m3, int m2) { return C[((size_t)m3 * K1 + g1) * K2C + m2]; };
     {
         auto ld_tw = [&](int t) {
             return t < K2C ? ax2.tw[t] : (t < K2C + K3C ? ax3.tw[t - K2C] : ax3.tw[2 * (t - K2C - K3C)]);
@@ -925,16 +943,36 @@ __global__ __launch_bounds__(SLAB_NT) void k_slab_inv(KParams k, FftAxis ax2, Ff
         auto st_tw = [&](int t, float2 v) { tw2[t] = v; };   // tw2 | tw3 | twh are contiguous
         auto ld = [&](int t) {
             const int m3 = t / K2C, m2 = t - m3 * K2C;
-            return C[((size_t)m3 * K1 + g1) * K2C + m2];
+            return ld_col(m3, m2);
         };
         auto st = [&](int t, float2 v) {
             const int m3 = t / K2C, m2 = t - m3 * K2C;
             X[m2 * KS + m3] = v;
         };
-        stage2_ct<K2C + K3C + NH, K3H * K2C, SLAB_NT, float2>(tid, ld_tw, st_tw, ld, st);
+        stage2_ct<K2C + K3C + NH, CA * K2C, SLAB_NT, float2>(tid, ld_tw, st_tw, ld, st);
+    }
+    constexpr int PB = (CB * K2C + SLAB_NT - 1) / SLAB_NT;
+    float2 vb[PB];
+#pragma unroll
+    for (int u = 0; u < PB; ++u) {
+        const int t = tid + u * SLAB_NT;
+        if ((CB * K2C) % SLAB_NT == 0 || t < CB * K2C) {
+            const int m3 = t / K2C, m2 = t - m3 * K2C;
+            vb[u] = ld_col(CA + m3, m2);
+        }
     }
     __syncthreads();
-    fft_ct<K2C, K3H, KS, SLAB_NT, true>(X, tw2, tid);
+    fft_ct<K2C, CA, KS, SLAB_NT, true>(X, tw2, tid);
+#pragma unroll
+    for (int u = 0; u < PB; ++u) {
+        const int t = tid + u * SLAB_NT;
+        if ((CB * K2C) % SLAB_NT == 0 || t < CB * K2C) {
+            const int m3 = t / K2C, m2 = t - m3 * K2C;
+            X[m2 * KS + CA + m3] = vb[u];
+        }
+    }
+    __syncthreads();
+    fft_ct<K2C, CB, KS, SLAB_NT, true>(X + CA, tw2, tid);
     // Length-NH inverse transform along each row g2 of the packed sequence
     // z(n) = (X(n) + conj X(NH - n)) + i (X(n) - conj X(NH - n)) e^{2 pi i n / K3}
     // (two real outputs per complex one).  Its first radix stage builds z
@@ -987,15 +1025,25 @@ __global__ __launch_bounds__(SLAB_NT) void k_slab_inv(KParams k, FftAxis ax2, Ff
             R2[t] = X[g2 * KS + n];
         }
     } else {
-        // phi(g1, g2, g3) = xf[2 KS g2 + g3]
+        // phi(g1, g2, g3) = xf[2 KS g2 + g3].  The atoms of the p planes form
+        // one index range (plane k1's atoms from off[k1]), so the block's
+        // threads take them all at once: one round of atom loads, not p.
         const float* xf = reinterpret_cast<const float*>(X);
-        constexpr int P = 6;
         const int n = k.n;
-        for (int k1 = 0; k1 < P; ++k1) {
-            int h1 = g1 + k1;
-            if (h1 >= K1) h1 -= K1;
-            const int lo = bin_start[h1 * K2C], hi = bin_start[(h1 + 1) * K2C];
-            for (int a = lo + tid; a < hi; a += SLAB_NT) {
+        int off[P + 1];
+        off[0] = 0;
+#pragma unroll
+        for (int k1 = 0; k1 < P; ++k1) off[k1 + 1] = off[k1] + (bhi[k1] - blo[k1]);
+        for (int t = tid; t < off[P]; t += SLAB_NT) {
+            int k1 = 0, a = blo[0] + t;
+#pragma unroll
+            for (int u = 1; u < P; ++u) {
+                if (t >= off[u]) {
+                    k1 = u;
+                    a = blo[u] + (t - off[u]);
+                }
+            }
+            {
                 const float* w = wts + (size_t)a * 3 * QEQ_MAXP;
                 const int h2 = home[4 * a + 1];
                 const int h3 = home[4 * a + 2];
@@ -1005,14 +1053,14 @@ __global__ __launch_bounds__(SLAB_NT) void k_slab_inv(KParams k, FftAxis ax2, Ff
                     int g2 = h2 - k2;
                     if (g2 < 0) g2 += K2C;
                     const float* row = xf + 2 * KS * g2;
-                    float t = 0.f;
+                    float r3 = 0.f;
 #pragma unroll
                     for (int k3 = 0; k3 < P; ++k3) {
                         int g3 = h3 - k3;
                         if (g3 < 0) g3 += K3C;
-                        t += w[2 * QEQ_MAXP + k3] * row[g3];
+                        r3 += w[2 * QEQ_MAXP + k3] * row[g3];
                     }
-                    s += w[QEQ_MAXP + k2] * t;
+                    s += w[QEQ_MAXP + k2] * r3;
                 }
                 mpart[(size_t)(2 * k1) * n + a] = w[k1] * s;
                 mpart[(size_t)(2 * k1 + 1) * n + a] = 0.f;
@@ -1396,9 +1444,15 @@ int launch_mesh_from_spectrum(qeq_plan* pl, const int* done) {
     return inverse_tail(pl, done);
 }
 
+// One pass on its own (for timing): the spread, or the complex-to-real pass
+// that the CG products run (interpolating from LDS where they do).
 int launch_mesh_stage(qeq_plan* pl, int kind, const double* src) {
     if (kind == PK_SPREAD_R2C) return spread_pass(pl, src, nullptr);
-    if (kind == PK_C2R) return slab_available(pl) ? slab_inv_pass(pl, nullptr) : c2r_pass(pl, nullptr);
+    if (kind == PK_C2R) {
+        if (slab_interp_available(pl)) return slab_interp_pass(pl, nullptr);
+        if (c2r_interp_available(pl)) return c2r_interp_pass(pl, nullptr);
+        return slab_available(pl) ? slab_inv_pass(pl, nullptr) : c2r_pass(pl, nullptr);
+    }
     return QEQ_EINVAL;
 }
 
