@@ -40,8 +40,8 @@ KIND_NAMES = ["spread_r2c", "fft_rows_fwd", "fft_cols_green", "fft_rows_inv", "c
 MEASURED_TRAFFIC = {
     "spread_r2c": {"kernel": "k_spread_r2c", "file": "paper_2607_17978_amd/csrc/mesh.hip",
                    "grid": (192, 192, 192), "spread_rows": 24,
-                   "source_sha256_16": "6f02c4eb07aceb6f",
-                   "fetch_kib": 2564.0625, "fetch_scale": 2.0, "write_kib": 27936.0, "write_scale": 1.0},
+                   "source_sha256_16": "121128032eb2f944",
+                   "fetch_kib": 2579.5625, "fetch_scale": 2.0, "write_kib": 27936.1875, "write_scale": 1.0},
     # the complex-to-real pass of the CG products at 192^3: the plane kernel
     # (inverse axis-2 and axis-3 transforms, then the back-interpolation
     # partials), whose blocks hold whole planes (no tile width)

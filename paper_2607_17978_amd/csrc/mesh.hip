@@ -280,6 +280,34 @@ __global__ __launch_bounds__(NT) void k_spread_r2c(KParams k, FftAxis ax3, const
     }
     // unpack the two real rows of each complex column and write the half spectra
     const int K3h = K3 / 2 + 1;
+    if constexpr (KC > 0 && TWC > 0) {
+        // compile-time tiles: every LDS read of the thread first, then the
+        // unpacking (both rows' formulas, selected) and the stores
+        constexpr int NW = (KC / 2 + 1) * TWC, PW = (NW + NT - 1) / NT, NCS = TWC / 2;
+        float2 zv[PW], zc[PW];
+#pragma unroll
+        for (int u = 0; u < PW; ++u) {
+            const int t = tid + u * NT;
+            if (NW % NT == 0 || t < NW) {
+                const int m = t / TWC, pr = (t - m * TWC) >> 1;
+                zv[u] = buf[m * NCS + pr];
+                zc[u] = buf[(m == 0 ? 0 : KC - m) * NCS + pr];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < PW; ++u) {
+            const int t = tid + u * NT;
+            if (NW % NT == 0 || t < NW) {
+                const int m = t / TWC, r = t - m * TWC;
+                const float2 Z = zv[u], Zc = make_float2(zc[u].x, -zc[u].y);
+                const float2 ev = make_float2(0.5f * (Z.x + Zc.x), 0.5f * (Z.y + Zc.y));
+                const float2 d = csub(Z, Zc);
+                const float2 od = make_float2(0.5f * d.y, -0.5f * d.x);
+                C[((size_t)m * K1 + g1) * K2 + g20 + r] = (r & 1) ? od : ev;
+            }
+        }
+        return;
+    }
     const int twl = ilog2_dev(TW);
     for (int t = tid; t < K3h * TW; t += NT) {
         // compile-time tiles may have any even width (division by a constant)
@@ -336,11 +364,18 @@ __global__ __launch_bounds__(NT) void k_fft_rows(KParams k, FftAxis ax2, float2*
         fft_ct<KC, NRC, NRC + 1, NT, INV>(buf, tw, tid);
     else
         fft_lds(buf, ax2, k.NRlog2, tw, INV, tid, NT);
-    for (int t = tid; t < NR * K2; t += NT) {
-        const int row = t / K2;
-        const int kk = t - row * K2;
-        if (row0 + row < nrows) C[(size_t)(row0 + row) * K2 + kk] = buf[kk * KS + row];
-    }
+    auto ld_out = [&](int t) {
+        const int row = t / K2, kk = t - row * K2;
+        return buf[kk * KS + row];
+    };
+    auto st_out = [&](int t, float2 v) {
+        const int row = t / K2, kk = t - row * K2;
+        if (row0 + row < nrows) C[(size_t)(row0 + row) * K2 + kk] = v;
+    };
+    if constexpr (KC > 0 && NRC > 0)
+        stage_ct<NRC * KC, NT, float2>(tid, ld_out, st_out);   // LDS reads first, then the stores
+    else
+        stage_rt<4, float2>(NR * K2, tid, NT, ld_out, st_out);
 }
 
 // Reciprocal kernel of the split (SI "Ewald Summation" Gaussian filter with the
