@@ -361,8 +361,9 @@ int qeq_use_fused_inverse(qeq_plan* plan, int32_t enable);
 int qeq_use_fused_interp(qeq_plan* plan, int32_t enable);
 
 /* Tile widths of the mesh passes for later solves on this plan, replacing the
-   built-in rule (which keeps every block within 32 KB of LDS and picks narrower
-   tiles for grids beyond the Infinity Cache): spread_rows = axis-2 rows per
+   built-in rule (spread tiles whose block fits 26 KB of LDS with at least two
+   blocks per CU, axis-1 / complex-to-real tiles within 48 KB, fewer axis-2
+   rows per block for grids beyond the Infinity Cache): spread_rows = axis-2 rows per
    block of the spread + axis-3 real-to-complex pass, tile_rows = axis-2 rows
    of the axis-1 and complex-to-real passes, fft_rows = rows per block of the
    axis-2 pass; 0 keeps the rule for that one.  Powers of two, 4..32 rows (1..32
