@@ -228,6 +228,35 @@ def test_long_pair_rows_match_oracle(dev, rc):
     plan.close()
 
 
+def test_spread_candidate_rounds_agree(dev):
+    """A spread tile reached by more candidate atoms than its block has
+    threads (32,768 atoms on a 96^3 grid: about 450 per 16-row tile) takes
+    the multi-round path, whose fixed-point bound comes from a pass over the
+    candidates' weights before the accumulation; 4-row tiles (about 190
+    candidates, one round, bound from the registers) give the same
+    reciprocal product, charges and energy up to FP32 rounding."""
+    from paper_2607_17978_amd import qeq
+    s = gen.system_32k()
+    grid = (96, 96, 96)
+    v = np.random.default_rng(11).normal(size=s.n)
+    args = (T(s.pos, dev), s.cell, T(s.sigma, dev))
+    out = {}
+    for tiles in ((16, 0, 0), (4, 0, 0)):
+        plan = qeq.Plan(s.n, eta=ETA, r_cut=RC, grid=grid, tol=1e-6)
+        plan.set_tiles(*tiles)
+        y = plan.matvec(*args, T(v, dev), parts=qeq.PART_RECIP).cpu().numpy()
+        q, en, f, st = plan.solve(*args, T(s.J, dev), T(s.chi, dev), s.q_tot)
+        out[tiles] = (y, q.cpu().numpy(), en.cpu().numpy(), st)
+        plan.close()
+    (y1, q1, e1, s1), (y0, q0, e0, s0) = out[(16, 0, 0)], out[(4, 0, 0)]
+    err = np.abs(y1 - y0).max() / np.abs(y0).max()
+    dq = np.abs(q1 - q0).max()
+    de = abs(e1[0] - e0[0]) / abs(e0[0])
+    print("multi-round vs one-round spread: product", err, "dq", dq, "dE", de, "iters", s1["iters"], s0["iters"])
+    assert s1["rc"] == 0 and s0["rc"] == 0
+    assert err <= 1e-6 and dq <= 5e-6 and de <= 1e-6
+
+
 @pytest.mark.parametrize("which", ["n64", "n32768"])
 def test_literal_settings_errors(dev, which):
     """The configs' literal discretisation (real-space cutoff 9 bohr, order-6
