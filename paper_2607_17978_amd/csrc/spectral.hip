@@ -47,7 +47,7 @@ constexpr int SPC_ATOM_PAD = 256;    // table rows padded to this many atoms
 constexpr int SPC_FROWS = 16;        // table rows per block of t = Psi^T u (4 per wave)
 constexpr int SPC_FSPLIT_MAX = 16;   // atom splits of t = Psi^T u
 constexpr int SPC_KSPLIT = 4;        // k splits of the dense products
-constexpr int SPC_BATOMS = 128;      // atoms per block of v = Psi s
+constexpr int SPC_BATOMS = 256;      // atoms per block of v = Psi s (four per lane)
 constexpr double PI = 3.14159265358979323846;
 
 // F_i(k) (cos, sin)(k.r_i) with k.r = 2 pi m.s (fractional coordinates), the
@@ -333,6 +333,7 @@ __global__ __launch_bounds__(256) void k_spc_fwd(int npad, int ncp, int fsplit, 
     const int s0 = sp * per, s1 = min(steps, s0 + per);
     const unsigned short* p = psi + (size_t)a0 * npad + 4 * lane;
     float v[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
     for (int st = s0; st < s1; ++st) {
         const int i = st * 256;
         const float4 uu = *(const float4*)(u + i + 4 * lane);
@@ -393,7 +394,7 @@ __global__ __launch_bounds__(1024) void k_spc_mid(int nm, int ncp, const double*
 }
 
 // w = D'^-1/2 (u - Psi s), u = D'^-1/2 r: block of SPC_BATOMS atoms, lane l
-// takes atoms 2l, 2l+1 (one 4-byte load per row), wave q the rows
+// takes atoms 4l .. 4l+3 (one 8-byte load per row), wave q the rows
 // q ncp/4 .. (q+1) ncp/4 - 1, summed across the waves in LDS; partials
 // [sum w, sum r w, sum r^2] per block.
 __global__ __launch_bounds__(256) void k_spc_back(int n, int npad, int nm, int ncp,
@@ -408,20 +409,26 @@ __global__ __launch_bounds__(256) void k_spc_back(int n, int npad, int nm, int n
     for (int a = threadIdx.x; a < ncp; a += blockDim.x) ssh[a] = a < nc ? (float)s[a] : 0.f;
     __syncthreads();
     const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
-    const int i = blockIdx.x * SPC_BATOMS + 2 * lane;
+    const int i = blockIdx.x * SPC_BATOMS + 4 * lane;
     const int rows = ncp / 4, a0 = q * rows;
-    float v0 = 0.f, v1 = 0.f;
+    float v0 = 0.f, v1 = 0.f, v2 = 0.f, v3 = 0.f;
     if (i < npad) {
+        // 8-byte loads (four atoms) and four rows in flight per lane
         const unsigned short* p = psi + (size_t)a0 * npad + i;
+#pragma unroll 4
         for (int a = 0; a < rows; ++a) {
-            const unsigned h = *(const unsigned*)(p + (size_t)a * npad);
+            const uint2 h = *(const uint2*)(p + (size_t)a * npad);
             const float sa = ssh[a0 + a];
-            v0 += sa * spc_f32((unsigned short)(h & 0xFFFFu));
-            v1 += sa * spc_f32((unsigned short)(h >> 16));
+            v0 += sa * spc_f32((unsigned short)(h.x & 0xFFFFu));
+            v1 += sa * spc_f32((unsigned short)(h.x >> 16));
+            v2 += sa * spc_f32((unsigned short)(h.y & 0xFFFFu));
+            v3 += sa * spc_f32((unsigned short)(h.y >> 16));
         }
     }
-    red[q][2 * lane] = v0;
-    red[q][2 * lane + 1] = v1;
+    red[q][4 * lane] = v0;
+    red[q][4 * lane + 1] = v1;
+    red[q][4 * lane + 2] = v2;
+    red[q][4 * lane + 3] = v3;
     __syncthreads();
     double pv[3] = {0.0, 0.0, 0.0};
     if (threadIdx.x < SPC_BATOMS) {
