@@ -62,16 +62,26 @@ struct DescParams {
 
 // G_i,mu = sum_j w_j exp(-eta (r_ij - c_mu)^2) f_c(r_ij) over the pair list
 // (sorted order); w_j = weights[perm[j]] (caller order) or 1 without weights.
-__global__ void k_descriptors(int n, DescParams d, const int* __restrict__ rowptr, const int* __restrict__ col,
-                              const float4* __restrict__ pdr, const int* __restrict__ perm,
-                              const double* __restrict__ weights, float* __restrict__ G) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+// Sixteen lanes per atom take its pair row in interleaved strides (the pair
+// data of a row is contiguous, so the group's loads coalesce), each keeping
+// partial sums of the nf functions; the sums are then reduced across the
+// group and lane m writes feature m.
+constexpr int DESC_G = 16;
+__global__ __launch_bounds__(QEQ_BLOCK) void k_descriptors(int n, DescParams d, const int* __restrict__ rowptr,
+                                                           const int* __restrict__ col,
+                                                           const float4* __restrict__ pdr,
+                                                           const int* __restrict__ perm,
+                                                           const double* __restrict__ weights,
+                                                           float* __restrict__ G) {
+    const int lane = threadIdx.x & (DESC_G - 1);
+    const int i = (blockIdx.x * blockDim.x + threadIdx.x) / DESC_G;
+    if (i >= n) return;   // whole groups
     float acc[32];
 #pragma unroll
     for (int m = 0; m < 32; ++m) acc[m] = 0.f;
     const float pi_rc = 3.14159265358979323846f / d.rc;
-    for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+    const int e1 = rowptr[i + 1];
+    for (int e = rowptr[i] + lane; e < e1; e += DESC_G) {
         const float4 v = pdr[e];
         const float r = sqrtf(v.x * v.x + v.y * v.y + v.z * v.z);
         if (r >= d.rc) continue;
@@ -87,8 +97,14 @@ __global__ void k_descriptors(int n, DescParams d, const int* __restrict__ rowpt
     }
     float* out = G + (size_t)perm[i] * d.nf;
 #pragma unroll
-    for (int m = 0; m < 32; ++m)
-        if (m < d.nf) out[m] = acc[m];
+    for (int m = 0; m < 32; ++m) {
+        if (m < d.nf) {
+            float a = acc[m];
+#pragma unroll
+            for (int off = DESC_G / 2; off > 0; off >>= 1) a += __shfl_xor(a, off, DESC_G);
+            if (lane == (m & (DESC_G - 1))) out[m] = a;
+        }
+    }
 }
 
 // ------------------------------------------------------------------ feature statistics
@@ -456,7 +472,8 @@ int launch_descriptors(qeq_plan* pl, const double* weights, int nf, const double
     for (int m = 0; m < 32; ++m) d.centers[m] = m < nf ? (float)centers[m] : 0.f;
     d.eta = (float)(1.0 / (2.0 * width * width));
     d.rc = (float)rc;
-    hipLaunchKernelGGL(k_descriptors, dim3(nblocks(pl->kp.n)), dim3(QEQ_BLOCK), 0, pl->stream, pl->kp.n, d,
+    const int nb = (int)(((size_t)pl->kp.n * DESC_G + QEQ_BLOCK - 1) / QEQ_BLOCK);
+    hipLaunchKernelGGL(k_descriptors, dim3(nb), dim3(QEQ_BLOCK), 0, pl->stream, pl->kp.n, d,
                        pl->rowptr, pl->col, pl->pdr, pl->perm, weights, G);
     return qeq_check(hipGetLastError());
 }
