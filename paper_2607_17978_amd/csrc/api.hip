@@ -677,7 +677,7 @@ int cg_run(qeq_plan* pl, const double* q0, double* q_out, double* energies, doub
     pl->warm_rejected = false;
     // initial guess (projected onto the constraint plane)
     QEQ_TRY(launch_cg_init_q(pl, q0));
-    const int chunk = 8;
+    const int chunk = 16;
     int it = 0;
     bool conv = false;
     // The recursive residual of CG drifts from the true one by the FP32 error
