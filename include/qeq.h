@@ -333,7 +333,8 @@ int mlp_train_step_noalloc(const float* G, const int32_t* species, const double*
                            void* stream);
 
 /* The CG loop of qeq_solve / qeq_backward runs as a replayed HIP graph of
-   16 iterations (captured on a private stream, launched on the plan's stream,
+   16 iterations, 8 with the spectral preconditioner (captured on a private
+   stream, launched on the plan's stream,
    re-captured when the geometry or buffers change); enable = 0 launches every
    kernel separately instead.  Results are the same either way up to the
    rounding order of the mesh atomics.  Default on.  While per-stage timers

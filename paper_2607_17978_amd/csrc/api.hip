@@ -602,6 +602,9 @@ int cg_iteration(qeq_plan* pl, int parity) {
 int ensure_chunk_graph(qeq_plan* pl, int chunk) {
     std::vector<unsigned char> key;
     chunk_key(pl, key);
+    // the captured length is part of the key
+    const unsigned char* cb = reinterpret_cast<const unsigned char*>(&chunk);
+    key.insert(key.end(), cb, cb + sizeof(chunk));
     if (pl->graph_exec && key == pl->graph_key) return QEQ_OK;
     drop_graph(pl);
     if (!pl->cap_stream) QEQ_HIP(hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking));
@@ -677,7 +680,11 @@ int cg_run(qeq_plan* pl, const double* q0, double* q_out, double* energies, doub
     pl->warm_rejected = false;
     // initial guess (projected onto the constraint plane)
     QEQ_TRY(launch_cg_init_q(pl, q0));
-    const int chunk = 16;
+    // iterations per replayed graph: 16 for the Jacobi solves (57-125
+    // iterations here), 8 with the spectral preconditioner (17-29), whose
+    // early-returning launches after convergence would outweigh the saved
+    // graph launches
+    const int chunk = pl->spc_active ? 8 : 16;
     int it = 0;
     bool conv = false;
     // The recursive residual of CG drifts from the true one by the FP32 error
