@@ -333,7 +333,7 @@ int mlp_train_step_noalloc(const float* G, const int32_t* species, const double*
                            void* stream);
 
 /* The CG loop of qeq_solve / qeq_backward runs as a replayed HIP graph of
-   16 iterations, 8 with the spectral preconditioner (captured on a private
+   12 iterations, 4 with the spectral preconditioner (captured on a private
    stream, launched on the plan's stream,
    re-captured when the geometry or buffers change); enable = 0 launches every
    kernel separately instead.  Results are the same either way up to the

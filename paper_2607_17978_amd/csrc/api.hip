@@ -680,11 +680,11 @@ int cg_run(qeq_plan* pl, const double* q0, double* q_out, double* energies, doub
     pl->warm_rejected = false;
     // initial guess (projected onto the constraint plane)
     QEQ_TRY(launch_cg_init_q(pl, q0));
-    // iterations per replayed graph: 16 for the Jacobi solves (57-125
-    // iterations here), 8 with the spectral preconditioner (17-29), whose
+    // iterations per replayed graph: 12 for the Jacobi solves (57-125
+    // iterations here), 4 with the spectral preconditioner (17-29), whose
     // early-returning launches after convergence would outweigh the saved
-    // graph launches
-    const int chunk = pl->spc_active ? 8 : 16;
+    // graph launches of longer chunks
+    const int chunk = pl->spc_active ? 4 : 12;
     int it = 0;
     bool conv = false;
     // The recursive residual of CG drifts from the true one by the FP32 error
