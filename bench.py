@@ -390,24 +390,18 @@ def main():
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / args.steps
     # the dominant kernel's launch duration: HIP events on the plan's stream
-    # around 20 back-to-back launches of that pass on the last solve's charges
-    # (events recorded inside a replayed graph cannot be read back); kinds
-    # without a stand-alone timer use the per-launch timers of eager solves
+    # around each of its launches inside eager solves (events recorded inside
+    # a replayed graph cannot be read back), with only that kernel bracketed;
+    # launches that find the solve converged are left out of the mean
     te0 = time.perf_counter()
     n_eager = max(2, args.steps // 3)
-    ms_eager = None
-    if dom in (0, 4):
-        us_dom = plan.time_kernel(dom, reps=20)
-        ms_dom, cnt_dom = [0.0] * 9, [0] * 9
-        ms_dom[dom], cnt_dom[dom] = us_dom * 1e-3, 1
-    else:
-        plan.profile(1 << dom)
-        for _ in range(n_eager):
-            plan.solve(pos, s.cell, sig, J, chi, s.q_tot)
-        torch.cuda.synchronize()
-        ms_eager = (time.perf_counter() - te0) * 1e3 / n_eager
-        ms_dom, cnt_dom = prof_read()
-        plan.profile(0)
+    plan.profile(1 << dom)
+    for _ in range(n_eager):
+        plan.solve(pos, s.cell, sig, J, chi, s.q_tot)
+    torch.cuda.synchronize()
+    ms_eager = (time.perf_counter() - te0) * 1e3 / n_eager
+    ms_dom, cnt_dom = prof_read()
+    plan.profile(0)
     # virial of the last solve (not part of the timed step): first call for the
     # cell (builds the strain tables of the self-correction), then steady state
     torch.cuda.synchronize()
