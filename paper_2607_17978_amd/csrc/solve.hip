@@ -376,23 +376,63 @@ __global__ void k_start_energy(const double* __restrict__ part_mv, int n_mv, con
     if (threadIdx.x == 0) sc->e_start = 0.5 * a[0] + a[1];
 }
 
+// Loads of NV per-block partial sums (layout part[b * QEQ_NPART + t]) into
+// this thread's running sums, in the order reduce_strided adds them; the
+// block sum follows in block_total.
+template <int NV>
+__device__ __forceinline__ void load_strided(const double* part, int nparts, double* v) {
+#pragma unroll
+    for (int t = 0; t < NV; ++t) v[t] = 0.0;
+#pragma unroll 4
+    for (int b = threadIdx.x; b < nparts; b += blockDim.x) {
+#pragma unroll
+        for (int t = 0; t < NV; ++t) v[t] += part[b * QEQ_NPART + t];
+    }
+}
+
+template <int NV>
+__device__ __forceinline__ void block_total(double* v) {
+    __shared__ double tot[NV];
+    block_sum<NV>(v);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int t = 0; t < NV; ++t) tot[t] = v[t];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < NV; ++t) v[t] = tot[t];
+}
+
 // alpha = r.z / p.A p; q += alpha p; r -= alpha (A p - mean(A p)).
+// Every load is issued before the converged flag is tested (the flag is the
+// same for all blocks), so that the flag, the partial sums and the vector
+// elements arrive in one memory round trip rather than three.
 __global__ void k_cg_update(KParams k, const double* __restrict__ p, const double* __restrict__ y,
                             const double* __restrict__ dinv, double* __restrict__ q, double* __restrict__ r,
                             const double* __restrict__ part_in, int nparts, double* __restrict__ part_out,
                             CgScalars* sc, int parity) {
-    if (sc->done) return;
-    double tot[2];
-    reduce_strided<2>(part_in, nparts, tot);
-    const double alpha = sc->rz[parity] / tot[0];
-    const double ymean = tot[1] / (double)k.n;
+    const int done = sc->done;
+    const double rzp = sc->rz[parity];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double pi = 0.0, yi = 0.0, qi = 0.0, ri = 0.0, di = 0.0;
+    if (i < k.n) {
+        pi = p[i];
+        yi = y[i];
+        qi = q[i];
+        ri = r[i];
+        di = dinv[i];
+    }
+    double tot[2];
+    load_strided<2>(part_in, nparts, tot);
+    if (done) return;
+    block_total<2>(tot);
+    const double alpha = rzp / tot[0];
+    const double ymean = tot[1] / (double)k.n;
     double acc[3] = {0.0, 0.0, 0.0};
     if (i < k.n) {
-        q[i] += alpha * p[i];
-        const double ri = r[i] - alpha * (y[i] - ymean);
+        q[i] = qi + alpha * pi;
+        ri -= alpha * (yi - ymean);
         r[i] = ri;
-        const double di = dinv[i];
         acc[0] = di * ri;
         acc[1] = di * ri * ri;
         acc[2] = ri * ri;
@@ -409,20 +449,30 @@ __global__ void k_cg_update(KParams k, const double* __restrict__ p, const doubl
 
 // c = sum(D^-1 r) / sum(D^-1) projects the preconditioned residual onto sum = 0,
 // r.z = sum(r^2/D) - c sum(D^-1 r), beta = r.z / r.z_old, p = D^-1 (r - c) + beta p;
-// the relative residual ||r|| / ||P chi_eff|| decides convergence.
+// the relative residual ||r|| / ||P chi_eff|| decides convergence.  Loads
+// are issued before the converged flag is tested, as in k_cg_update.
 __global__ void k_cg_dir(KParams k, const double* __restrict__ r, const double* __restrict__ dinv,
                          double* __restrict__ p, const double* __restrict__ part_in, int nparts,
                          CgScalars* sc, int parity, int init) {
-    if (sc->done) return;
-    double tot[3];
-    reduce_strided<3>(part_in, nparts, tot);
-    const double c = tot[0] / sc->dinv_sum;
-    const double rz = tot[1] - c * tot[0];
-    const double beta = init ? 0.0 : rz / sc->rz[parity];
-    const double res = sc->chi_norm > 0.0 ? sqrt(tot[2]) / sc->chi_norm : sqrt(tot[2]);
+    const int done = sc->done;
+    const double rz_old = sc->rz[parity], dinv_sum = sc->dinv_sum, chi_norm = sc->chi_norm;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    // the first direction does not read p: its memory may hold anything (0 * NaN = NaN)
-    if (i < k.n) p[i] = dinv[i] * (r[i] - c) + (init ? 0.0 : beta * p[i]);
+    double ri = 0.0, di = 0.0, pi = 0.0;
+    if (i < k.n) {
+        ri = r[i];
+        di = dinv[i];
+        pi = p[i];
+    }
+    double tot[3];
+    load_strided<3>(part_in, nparts, tot);
+    if (done) return;
+    block_total<3>(tot);
+    const double c = tot[0] / dinv_sum;
+    const double rz = tot[1] - c * tot[0];
+    const double beta = init ? 0.0 : rz / rz_old;
+    const double res = chi_norm > 0.0 ? sqrt(tot[2]) / chi_norm : sqrt(tot[2]);
+    // the first direction does not use p: its memory may hold anything (0 * NaN = NaN)
+    if (i < k.n) p[i] = di * (ri - c) + (init ? 0.0 : beta * pi);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         sc->rz[parity ^ 1] = rz;
         sc->res = res;
