@@ -227,7 +227,7 @@ __global__ __launch_bounds__(QEQ_BLOCK) void k_pairs_fused(
     const int* __restrict__ col, const float* __restrict__ kval, const double* __restrict__ dself,
     const double* __restrict__ Jv, const float* __restrict__ mpart, double* __restrict__ part,
     CgScalars* __restrict__ sc) {
-    if (MODE == QEQ_MODE_CG && sc->done) return;
+    const int done = MODE == QEQ_MODE_CG ? sc->done : 0;
     constexpr int G = 16;
     const int lane = threadIdx.x & (G - 1);
     const int grp = (xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) / G;
@@ -235,14 +235,38 @@ __global__ __launch_bounds__(QEQ_BLOCK) void k_pairs_fused(
     const int n = k.n;
     const bool do_real = (k.parts & QEQ_PART_REAL) != 0;
     const bool do_recip = (k.parts & QEQ_PART_RECIP) != 0 && lane < 2 * k.p;
+    const bool do_self = (k.parts & QEQ_PART_SELF) != 0;
+    // The loads of a round that do not depend on its row (the row bounds, the
+    // mesh partial, the atom's own terms) are issued one round ahead; the
+    // first round's before the converged flag is tested, so that they share
+    // its memory round trip.
+    int e0n = 0, e1n = 0;
+    float mpn = 0.f;
+    double vin = 0.0, dsn = 0.0, jvn = 0.0;
+    auto fetch = [&](int i) {
+        if (i < n) {
+            e0n = rowptr[i];
+            e1n = rowptr[i + 1];
+            mpn = do_recip ? mpart[(size_t)lane * n + i] : 0.f;
+            if (lane == 0) {
+                vin = src[i];
+                if (do_self) dsn = dself[i];
+                if (MODE == QEQ_MODE_CG) jvn = Jv[i];
+            }
+        }
+    };
+    fetch(grp);
+    if (done) return;
     double acc[2] = {0.0, 0.0};
     const int rounds = (n + ngrp - 1) / ngrp;
     for (int rnd = 0; rnd < rounds; ++rnd) {
         const int i = rnd * ngrp + grp;
+        const int e0 = e0n, e1 = e1n;
+        const float mp = mpn;
+        const double vi = vin, ds = dsn, jv = jvn;
+        fetch(i + ngrp);
         double v = 0.0;
         if (i < n) {
-            const int e0 = rowptr[i], e1 = rowptr[i + 1];
-            const float mp = do_recip ? mpart[(size_t)lane * n + i] : 0.f;
             if (do_real) {
                 for (int base = e0 + lane; base < e1; base += 4 * G) {
                     int cj[4];
@@ -265,11 +289,10 @@ __global__ __launch_bounds__(QEQ_BLOCK) void k_pairs_fused(
 #pragma unroll
         for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, G);
         if (i < n && lane == 0) {
-            const double vi = src[i];
             double y = v;
-            if (k.parts & QEQ_PART_SELF) y += dself[i] * vi;
+            if (do_self) y += ds * vi;
             if (MODE == QEQ_MODE_CG) {
-                y += Jv[i] * vi;
+                y += jv * vi;
                 acc[0] += vi * y;
                 acc[1] += y;
             }
