@@ -38,10 +38,12 @@ KIND_NAMES = ["spread_r2c", "fft_rows_fwd", "fft_cols_green", "fft_rows_inv", "c
 # figures belong to the kernel source whose hash is stored; after any change to
 # that source the traffic is reported as null until it is measured again.
 MEASURED_TRAFFIC = {
-    "spread_r2c": {"kernel": "k_spread_r2c", "file": "paper_2607_17978_amd/csrc/mesh.hip",
-                   "grid": (192, 192, 192), "spread_rows": 24,
-                   "source_sha256_16": "121128032eb2f944",
-                   "fetch_kib": 2579.5625, "fetch_scale": 2.0, "write_kib": 27936.1875, "write_scale": 1.0},
+    # the spread kind of the CG products at 192^3: the forward plane kernel
+    # (spread, axis-3 and axis-2 transforms of one g1 plane per block)
+    "spread_r2c": {"kernel": "k_plane_fwd", "file": "paper_2607_17978_amd/csrc/mesh.hip",
+                   "grid": (192, 192, 192), "spread_rows": None,
+                   "source_sha256_16": "265cfb73d912eb58",
+                   "fetch_kib": 2589.5625, "fetch_scale": 2.0, "write_kib": 27936.0, "write_scale": 1.0},
     # the complex-to-real pass of the CG products at 192^3: the plane kernel
     # (inverse axis-2 and axis-3 transforms, then the back-interpolation
     # partials), whose blocks hold whole planes (no tile width)
@@ -90,7 +92,10 @@ def algorithmic_bytes(K, n, nnz, fused=True):
     fused: the CG products' default path, where the complex-to-real pass
     interpolates from LDS (kind "c2r": half spectrum read, per-atom spline
     data read and 2p = 12 FP32 partials written) and the pair kernel reads
-    those partials instead of the real grid (kind "interp_pairs")."""
+    those partials instead of the real grid (kind "interp_pairs").  Where the
+    forward plane pass runs (192^3), kind "spread_r2c" also carries the
+    forward axis-2 transform for the same bytes (per-atom data read, half
+    spectrum written once) and kind "fft_rows_fwd" is not launched."""
     K1, K2, K3 = K
     wc = 8.0 * K1 * K2 * (K3 // 2 + 1)      # half-complex grid, complex64
     wr = 4.0 * K1 * K2 * K3                 # real grid, float32

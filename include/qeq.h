@@ -349,6 +349,14 @@ int qeq_use_graphs(qeq_plan* plan, int32_t enable);
    up to FP32 rounding.  Default on. */
 int qeq_use_fused_inverse(qeq_plan* plan, int32_t enable);
 
+/* Where a g1 plane of the half spectrum fits in the LDS of one compute unit
+   (192^3 grids with K1 >= 64, spline order 6), the charge spreading of eq.
+   matvec, the axis-3 real-to-complex transform and the forward axis-2
+   transform run as one pass, with one fixed-point scale per grid row; enable
+   = 0 runs the spread pass (row tiles) and the axis-2 pass.  Both give the
+   same spectrum up to FP32 rounding.  Default on. */
+int qeq_use_fused_forward(qeq_plan* plan, int32_t enable);
+
 /* The CG products of qeq_solve / qeq_backward: enable != 0 (default) runs the
    axis-3 complex-to-real transform of each (g1, row-tile) block and the
    back-interpolation of eq. matvec (sum_g theta_i(g) phi(g)) over that tile in

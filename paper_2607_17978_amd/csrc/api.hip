@@ -1124,6 +1124,14 @@ int qeq_use_fused_inverse(qeq_plan* plan, int32_t enable) {
     return QEQ_OK;
 }
 
+int qeq_use_fused_forward(qeq_plan* plan, int32_t enable) {
+    if (!plan) return QEQ_EINVAL;
+    if (plan->stream) (void)hipStreamSynchronize(plan->stream);
+    plan->fused_forward = enable != 0;
+    drop_graph(plan);
+    return QEQ_OK;
+}
+
 int qeq_set_tiles(qeq_plan* plan, int32_t spread_rows, int32_t tile_rows, int32_t fft_rows) {
     if (!plan) return QEQ_EINVAL;
     const int v[3] = {spread_rows, tile_rows, fft_rows};

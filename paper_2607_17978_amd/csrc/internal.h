@@ -282,6 +282,7 @@ struct qeq_plan {
     double* pw_f = nullptr;       // forces of the final product, sorted order
     double* pw_smax = nullptr;    // per-block maxima of sigma (host read once per set-up)
     bool fused_inverse = true;    // fused inverse axis-2 + complex-to-real slab pass where it fits
+    bool fused_forward = true;    // fused spread + axis-3 + axis-2 forward plane pass where it fits
     bool fused_interp = true;     // CG products: complex-to-real pass fused with the interpolation
     int tile_set[3] = {0, 0, 0};  // qeq_set_tiles: spread rows, tile rows, axis-2 rows (0 = rule)
     float* mpart = nullptr;       // [2 MAXP][n_max] interpolation partials of the fused pass

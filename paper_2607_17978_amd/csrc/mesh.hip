@@ -37,6 +37,7 @@ constexpr int NT = QEQ_FFT_THREADS;
 
 __device__ __forceinline__ int ilog2_dev(int x) { return 31 - __clz(x); }
 
+
 // ------------------------------------------------------------------ pass 1
 template <int KC, int TWC, int PC>
 __global__ __launch_bounds__(NT) void k_spread_r2c(KParams k, FftAxis ax3, const double* __restrict__ src,
@@ -911,6 +912,270 @@ __global__ __launch_bounds__(NT) void k_c2r_interp(KParams k, FftAxis ax3, const
     }
 }
 
+// ------------------------------------------------------------------ passes 1 + 2 fused
+// Spread, axis-3 real-to-complex and axis-2 forward transforms of one g1
+// plane in LDS, for grids whose plane half spectrum K2 (K3/2 + 1) fits (one
+// block per CU): the mirror image of k_slab_inv, saving the grid round trip
+// between the spread and the axis-2 pass.
+//   Candidates: the atoms whose home plane h1 = g1 + k1 (k1 < p) reaches g1,
+//   one index range per k1 (atoms are sorted by home bin), taken by the
+//   block's threads together and held in registers (CPT per thread).
+//   Fixed point, one scale per row g2: every value of row g2 is a sum of one
+//   term per candidate whose axis-2 support covers the row, so |value| <=
+//   S(g2) = sum of |src| w1(k1) max(w2) max(w3) over those candidates.  The
+//   plane total S (< 2^eS) fixes a quantum U = 2^(eS - 20); each candidate
+//   adds floor(bound / U) + 1 to the integer bounds of its p rows (integer
+//   sums: order-independent), so S(g2) <= rb(g2) U, and the row is scaled by
+//   2^(30 - e) with rb(g2) U < 2^e.  Rows see about p K2 / (K1 K2) of the
+//   plane's atoms, so their bounds are tighter than those of the row tiles
+//   of k_spread_r2c.
+//   Then two real rows per complex line for the axis-3 transform (the
+//   conversion inside its first radix stage), their half spectra unpacked
+//   to X[g2][m3] (row stride K3/2 + 1), the axis-2 transform of every m3
+//   column, and C[m3][g1][m2] written.
+constexpr int PLANE_NT = 1024;
+
+template <int K2C, int K3C>
+__global__ __launch_bounds__(PLANE_NT) void k_plane_fwd(KParams k, FftAxis ax2, FftAxis ax3,
+                                                       const double* __restrict__ src,
+                                                       const int* __restrict__ bin_start,
+                                                       const int* __restrict__ home,
+                                                       const float* __restrict__ wts, float2* __restrict__ C,
+                                                       const int* __restrict__ done) {
+    constexpr int P = 6, CPT = 2;
+    constexpr int KS = K3C / 2 + 1;   // complex row stride of X
+    constexpr int AS = K3C + 1;       // int row stride of the accumulator
+    constexpr int NP = K2C / 2;       // row pairs
+    static_assert(K2C * AS * 4 <= K2C * KS * 8, "accumulator must fit the plane buffer");
+    static_assert(K3C * NP <= K2C * KS, "packed rows must fit the plane buffer");
+    extern __shared__ float2 sm[];
+    float2* tw2 = sm;              // K2C: e^{-2 pi i j / K2}
+    float2* tw3 = tw2 + K2C;       // K3C: e^{-2 pi i j / K3}
+    float2* X = tw3 + K3C;         // K2C x KS
+    int* acc = reinterpret_cast<int*>(X);
+    __shared__ int rb[K2C];
+    __shared__ float rinv[K2C], rsc[K2C];
+    __shared__ int sh_e;
+    const int tid = threadIdx.x;
+    // XCD-aware plane order: the p planes that read one atom run on one XCD
+    const int g1 = xcd_remap(blockIdx.x, gridDim.x);
+    const int K1 = k.K1;
+    // twiddles and the candidate ranges are requested before the converged
+    // flag is examined, so the loads share one round trip
+    constexpr int NTW = K2C + K3C;
+    float2 twv = make_float2(0.f, 0.f);
+    if (tid < NTW) twv = tid < K2C ? ax2.tw[tid] : ax3.tw[tid - K2C];
+    int blo[P], bhi[P];
+#pragma unroll
+    for (int k1 = 0; k1 < P; ++k1) {
+        int h1 = g1 + k1;
+        if (h1 >= K1) h1 -= K1;
+        blo[k1] = bin_start[h1 * K2C];
+        bhi[k1] = bin_start[(h1 + 1) * K2C];
+    }
+    if (done && *done) return;
+    if (tid < NTW) sm[tid] = twv;
+    {
+        int4* a4 = reinterpret_cast<int4*>(acc);
+        constexpr int N4 = K2C * AS / 4;
+        static_assert((K2C * AS) % 4 == 0, "accumulator clears as int4");
+        for (int t = tid; t < N4; t += PLANE_NT) a4[t] = make_int4(0, 0, 0, 0);
+    }
+    if (tid < K2C) rb[tid] = 0;
+    int off[P + 1];
+    off[0] = 0;
+#pragma unroll
+    for (int k1 = 0; k1 < P; ++k1) off[k1 + 1] = off[k1] + (bhi[k1] - blo[k1]);
+    const int ncand = off[P];
+    // candidate t: plane k1 (the last range starting at or before t), atom a
+    float a0[CPT], w2[CPT][P], w3[CPT][P];
+    double bnd[CPT];
+    int h2[CPT], h3[CPT];
+    auto load = [&](int s, int t) {
+        int k1 = 0, a = blo[0] + t;
+#pragma unroll
+        for (int u = 1; u < P; ++u) {
+            if (t >= off[u]) {
+                k1 = u;
+                a = blo[u] + (t - off[u]);
+            }
+        }
+        const float* w = wts + (size_t)a * 3 * QEQ_MAXP;
+        const double sv = src[a];
+        const float w1 = w[k1];
+        a0[s] = (float)sv * w1;
+        float m2 = 0.f, m3 = 0.f;
+#pragma unroll
+        for (int kk = 0; kk < P; ++kk) {
+            w2[s][kk] = w[QEQ_MAXP + kk];
+            w3[s][kk] = w[2 * QEQ_MAXP + kk];
+            m2 = fmaxf(m2, w2[s][kk]);
+            m3 = fmaxf(m3, w3[s][kk]);
+        }
+        bnd[s] = fabs((double)a0[s]) * (double)m2 * (double)m3;
+        h2[s] = home[4 * a + 1];
+        h3[s] = home[4 * a + 2];
+    };
+    const int nround = (ncand + CPT * PLANE_NT - 1) / (CPT * PLANE_NT);
+    // pass A: the plane bound S (candidates of later rounds are loaded again
+    // in the passes below; one round keeps them in registers)
+    {
+        double v[1] = {0.0};
+        for (int rd = 0; rd < nround; ++rd) {
+#pragma unroll
+            for (int s = 0; s < CPT; ++s) {
+                const int t = (rd * CPT + s) * PLANE_NT + tid;
+                if (t < ncand) {
+                    load(s, t);
+                    v[0] += bnd[s];
+                }
+            }
+        }
+        block_sum<1>(v);   // its barriers also order the clears above
+        if (tid == 0) {
+            int e = 0;
+            (void)frexp(v[0] > 0.0 ? v[0] : 1.0, &e);   // S < 2^e
+            sh_e = e;
+        }
+        __syncthreads();
+    }
+    const int eS = sh_e;
+    // pass B: integer row bounds in units of U = 2^(eS - 20); each term is
+    // below 2^20 and the terms of a row sum to below 2^20 + ncand
+    for (int rd = 0; rd < nround; ++rd) {
+#pragma unroll
+        for (int s = 0; s < CPT; ++s) {
+            const int t = (rd * CPT + s) * PLANE_NT + tid;
+            if (t < ncand) {
+                if (nround > 1) load(s, t);
+                const int q = (int)ldexp(bnd[s], 20 - eS) + 1;
+#pragma unroll
+                for (int k2 = 0; k2 < P; ++k2) {
+                    int r = h2[s] - k2;
+                    if (r < 0) r += K2C;
+                    atomicAdd(rb + r, q);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (tid < K2C) {
+        int e = 0;
+        const double sr = ldexp((double)rb[tid], eS - 20);
+        (void)frexp(sr > 0.0 ? sr : 1.0, &e);   // S(g2) <= sr < 2^e
+        const int x = max(-126, min(126, 30 - e));
+        rsc[tid] = ldexpf(1.0f, x);
+        rinv[tid] = ldexpf(1.0f, -x);
+    }
+    __syncthreads();
+    // pass C: terms rounded to integers by one FP64 fused multiply-add with
+    // 1.5 * 2^52 (the low word of the sum is the two's-complement integer)
+    constexpr double RND = 6755399441055744.0;
+    for (int rd = 0; rd < nround; ++rd) {
+#pragma unroll
+        for (int s = 0; s < CPT; ++s) {
+            const int t = (rd * CPT + s) * PLANE_NT + tid;
+            if (t < ncand) {
+                if (nround > 1) load(s, t);
+                double w3d[P];
+                int col[P];
+#pragma unroll
+                for (int k3 = 0; k3 < P; ++k3) {
+                    w3d[k3] = (double)w3[s][k3];
+                    int g3 = h3[s] - k3;
+                    if (g3 < 0) g3 += K3C;
+                    col[k3] = g3;
+                }
+#pragma unroll
+                for (int k2 = 0; k2 < P; ++k2) {
+                    int r = h2[s] - k2;
+                    if (r < 0) r += K2C;
+                    const double a1 = (double)(a0[s] * rsc[r]) * (double)w2[s][k2];   // exact
+                    int* row = acc + r * AS;
+#pragma unroll
+                    for (int k3 = 0; k3 < P; ++k3) {
+                        const int v = (int)(unsigned)__double_as_longlong(fma(a1, w3d[k3], RND));
+                        atomicAdd(row + col[k3], v);
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // rows 2c and 2c + 1 as one complex line along g3 (Z[g3][c], c < NP):
+    // the conversion to FP32 inside the first radix stage
+    float2* Z = X;
+    {
+        constexpr int R0 = ct_radix_at(K3C, 0, NP, PLANE_NT), PER0 = K3C / R0;
+        constexpr int ITEMS = PER0 * NP, IT0 = (ITEMS + PLANE_NT - 1) / PLANE_NT;
+        float2 v[IT0][R0];
+#pragma unroll
+        for (int it = 0; it < IT0; ++it) {
+            const int item = tid + it * PLANE_NT;
+            if (ITEMS % PLANE_NT == 0 || item < ITEMS) {
+                const int c = item % NP, j = item / NP;
+                const int* re = acc + (2 * c) * AS;
+                const int* im = re + AS;
+                const float se = rinv[2 * c], so = rinv[2 * c + 1];
+#pragma unroll
+                for (int r = 0; r < R0; ++r) {
+                    const int g3 = j + r * PER0;
+                    v[it][r] = make_float2((float)re[g3] * se, (float)im[g3] * so);
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < IT0; ++it) {
+            const int item = tid + it * PLANE_NT;
+            if (ITEMS % PLANE_NT == 0 || item < ITEMS) {
+                const int c = item % NP, j = item / NP;
+                dft<R0>(v[it], false);
+#pragma unroll
+                for (int r = 0; r < R0; ++r) Z[(j * R0 + r) * NP + c] = v[it][r];
+            }
+        }
+        __syncthreads();
+        fft_ct<K3C, NP, NP, PLANE_NT, false, 1, R0>(Z, tw3, tid);
+    }
+    // unpack the two rows' half spectra, m3 = 0 .. K3/2: every LDS read of the
+    // thread first (the rows overwrite the packed lines)
+    {
+        constexpr int NI = NP * KS, PI = (NI + PLANE_NT - 1) / PLANE_NT;
+        float2 za[PI], zb[PI];
+#pragma unroll
+        for (int u = 0; u < PI; ++u) {
+            const int t = tid + u * PLANE_NT;
+            if (NI % PLANE_NT == 0 || t < NI) {
+                const int m = t / NP, c = t - m * NP;
+                za[u] = Z[m * NP + c];
+                zb[u] = Z[(m == 0 ? 0 : K3C - m) * NP + c];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < PI; ++u) {
+            const int t = tid + u * PLANE_NT;
+            if (NI % PLANE_NT == 0 || t < NI) {
+                const int m = t / NP, c = t - m * NP;
+                const float2 Zv = za[u], Zc = make_float2(zb[u].x, -zb[u].y);
+                const float2 d = csub(Zv, Zc);
+                X[(2 * c) * KS + m] = make_float2(0.5f * (Zv.x + Zc.x), 0.5f * (Zv.y + Zc.y));
+                X[(2 * c + 1) * KS + m] = make_float2(0.5f * d.y, -0.5f * d.x);
+            }
+        }
+        __syncthreads();
+    }
+    // axis-2 transform of every m3 column, then C[m3][g1][m2]
+    fft_ct<K2C, KS, KS, PLANE_NT, false>(X, tw2, tid);
+    __syncthreads();
+#pragma unroll 4
+    for (int t = tid; t < KS * K2C; t += PLANE_NT) {
+        const int m3 = t / K2C, m2 = t - m3 * K2C;
+        C[((size_t)m3 * K1 + g1) * K2C + m2] = X[m2 * KS + m3];
+    }
+}
+
 // ------------------------------------------------------------------ passes 4 + 5 fused
 // Inverse axis-2 and axis-3 complex-to-real transforms of one g1 slab in LDS,
 // for grids whose slab half spectrum K2 (K3/2 + 1) fits (one block per CU):
@@ -1429,6 +1694,48 @@ int slab_inv_pass(qeq_plan* pl, const int* done) {
     return QEQ_EPLAN;
 }
 
+// Lengths with a fused forward plane kernel (spread + axis-3 + axis-2).
+#define QEQ_FOR_EACH_PLANE_FWD(X) X(192, 192)
+
+size_t smem_plane_fwd(int K2, int K3) {
+    return sizeof(float2) * ((size_t)K2 + K3 + (size_t)K2 * (K3 / 2 + 1));
+}
+
+bool plane_fwd_available(const qeq_plan* pl) {
+    const KParams& k = pl->kp;
+    if (!pl->fused_forward || k.K1 < 64 || k.p != 6) return false;
+#define X(A, B) if (k.K2 == A && k.K3 == B) return true;
+    QEQ_FOR_EACH_PLANE_FWD(X)
+#undef X
+    return false;
+}
+
+int plane_fwd_pass(qeq_plan* pl, const double* src, const int* done) {
+    const KParams& k = pl->kp;
+    ProfScope ps(pl, PK_SPREAD_R2C);
+#define X(A, B)                                                                                    \
+    if (k.K2 == A && k.K3 == B && k.p == 6) {                                                      \
+        const size_t sh = smem_plane_fwd(A, B);                                                    \
+        QEQ_HIP(hipFuncSetAttribute((const void*)k_plane_fwd<A, B>,                                \
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));         \
+        hipExtLaunchKernelGGL((k_plane_fwd<A, B>), dim3(k.K1), dim3(PLANE_NT), sh, pl->stream, ps.start(), \
+                              ps.stop(), 0, k, pl->axes.ax[1], pl->axes.ax[2], src, pl->bin_start, \
+                              pl->home, pl->wts, pl->grid_c, done);                                 \
+        return qeq_check(hipGetLastError());                                                       \
+    }
+    QEQ_FOR_EACH_PLANE_FWD(X)
+#undef X
+    return QEQ_EPLAN;
+}
+
+// Spread and forward axis-2 transform: the fused plane kernel where it
+// applies, else the spread pass and the axis-2 pass.
+int forward_head(qeq_plan* pl, const double* src, const int* done) {
+    if (plane_fwd_available(pl)) return plane_fwd_pass(pl, src, done);
+    QEQ_TRY(spread_pass(pl, src, done));
+    return rows_pass(pl, 0, done);
+}
+
 // Inverse transforms after the axis-1 pass: the fused slab kernel where it
 // applies, else the inverse axis-2 pass and the complex-to-real pass.
 int inverse_tail(qeq_plan* pl, const int* done) {
@@ -1454,8 +1761,7 @@ size_t qeq_mesh_max_smem(const KParams& k) {
 }
 
 int launch_mesh_potential(qeq_plan* pl, const double* src, const int* done) {
-    QEQ_TRY(spread_pass(pl, src, done));
-    QEQ_TRY(rows_pass(pl, 0, done));
+    QEQ_TRY(forward_head(pl, src, done));
     QEQ_TRY(cols_pass(pl, MESH_FWD | MESH_GREEN | MESH_INV, nullptr, done));
     return inverse_tail(pl, done);
 }
@@ -1464,8 +1770,7 @@ int launch_mesh_cg(qeq_plan* pl, const double* src, const int* done, bool* parti
     *partials = false;
     const bool slab = slab_interp_available(pl);
     if (!slab && !c2r_interp_available(pl)) return launch_mesh_potential(pl, src, done);
-    QEQ_TRY(spread_pass(pl, src, done));
-    QEQ_TRY(rows_pass(pl, 0, done));
+    QEQ_TRY(forward_head(pl, src, done));
     QEQ_TRY(cols_pass(pl, MESH_FWD | MESH_GREEN | MESH_INV, nullptr, done));
     *partials = true;
     if (slab) return slab_interp_pass(pl, done);
@@ -1482,7 +1787,8 @@ int launch_mesh_from_spectrum(qeq_plan* pl, const int* done) {
 // One pass on its own (for timing): the spread, or the complex-to-real pass
 // that the CG products run (interpolating from LDS where they do).
 int launch_mesh_stage(qeq_plan* pl, int kind, const double* src) {
-    if (kind == PK_SPREAD_R2C) return spread_pass(pl, src, nullptr);
+    if (kind == PK_SPREAD_R2C)
+        return plane_fwd_available(pl) ? plane_fwd_pass(pl, src, nullptr) : spread_pass(pl, src, nullptr);
     if (kind == PK_C2R) {
         if (slab_interp_available(pl)) return slab_interp_pass(pl, nullptr);
         if (c2r_interp_available(pl)) return c2r_interp_pass(pl, nullptr);

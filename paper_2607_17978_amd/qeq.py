@@ -110,6 +110,8 @@ def load_library():
     L.qeq_use_spectral_preconditioner.restype = ctypes.c_int
     L.qeq_use_fused_inverse.argtypes = [vp, i32]
     L.qeq_use_fused_inverse.restype = ctypes.c_int
+    L.qeq_use_fused_forward.argtypes = [vp, i32]
+    L.qeq_use_fused_forward.restype = ctypes.c_int
     L.qeq_use_fused_interp.argtypes = [vp, i32]
     L.qeq_use_fused_interp.restype = ctypes.c_int
     L.qeq_set_tiles.argtypes = [vp, i32, i32, i32]
@@ -443,6 +445,10 @@ class Plan:
     def use_fused_inverse(self, enable=True):
         """Fused inverse axis-2 + complex-to-real slab pass where it fits (default) or two passes."""
         load_library().qeq_use_fused_inverse(self._h, 1 if enable else 0)
+
+    def use_fused_forward(self, enable=True):
+        """Fused spread + axis-3 + axis-2 forward plane pass where it fits (default) or two passes."""
+        load_library().qeq_use_fused_forward(self._h, 1 if enable else 0)
 
     def set_tiles(self, spread_rows=0, tile_rows=0, fft_rows=0):
         """Tile widths of the mesh passes (0 = the built-in rule); see qeq_set_tiles."""

@@ -351,6 +351,33 @@ def test_fused_inverse_matches_two_passes(dev, which):
     plan.close()
 
 
+def test_fused_forward_matches_two_passes(dev):
+    """The fused forward plane pass (spread, axis-3 and axis-2 transforms in
+    one kernel with a fixed-point scale per row, 192^3 grids) gives the mesh
+    product of the spread and axis-2 passes to FP32 rounding, and the same
+    charges, on the 32,768-atom workload."""
+    from paper_2607_17978_amd import qeq
+    s = gen.system_32k()
+    plan = qeq.Plan(s.n, eta=ETA, r_cut=RC, grid=s.grid, tol=1e-6)
+    v = T(np.random.default_rng(9).normal(size=s.n), dev)
+    args = (T(s.pos, dev), s.cell, T(s.sigma, dev))
+    solve_args = args + (T(s.J, dev), T(s.chi, dev), s.q_tot)
+    y1 = plan.matvec(*args, v, parts=qeq.PART_RECIP).cpu().numpy()
+    q1, e1, _, st1 = plan.solve(*solve_args)
+    plan.use_fused_forward(False)
+    y0 = plan.matvec(*args, v, parts=qeq.PART_RECIP).cpu().numpy()
+    q0, e0, _, st0 = plan.solve(*solve_args)
+    err = np.abs(y1 - y0).max() / np.abs(y0).max()
+    dq = (q1 - q0).abs().max().item()
+    print("fused forward vs two passes: product rel max diff", err, "dq", dq, "iters", st1["iters"], st0["iters"])
+    # both products carry FP32 transforms (relative rounding ~1e-7 of the largest value)
+    assert err <= 1e-5
+    assert abs(st1["iters"] - st0["iters"]) <= max(2, st0["iters"] // 10)
+    assert dq <= 1e-6
+    assert abs(e1[0].item() - e0[0].item()) <= 1e-6 * abs(e0[0].item())
+    plan.close()
+
+
 @pytest.mark.parametrize("which", ["n64", "batch3", "n4096", "n32768", "grid320"])
 def test_fused_interp_matches_grid_path(dev, which):
     """The complex-to-real pass fused with the back-interpolation (the CG
