@@ -926,9 +926,10 @@ __global__ __launch_bounds__(NT) void k_c2r_interp(KParams k, FftAxis ax3, const
 //   plane total S (< 2^eS) fixes a quantum U = 2^(eS - 20); each candidate
 //   adds floor(bound / U) + 1 to the integer bounds of its p rows (integer
 //   sums: order-independent), so S(g2) <= rb(g2) U, and the row is scaled by
-//   2^(30 - e) with rb(g2) U < 2^e.  Rows see about p K2 / (K1 K2) of the
-//   plane's atoms, so their bounds are tighter than those of the row tiles
-//   of k_spread_r2c.
+//   2^(30 - e) with rb(g2) U < 2^e.  A row's bound sums over about p / K2 of
+//   the plane's candidates (about 32 of 1,024 at 192^3 and 32,768 atoms), a
+//   row tile's of k_spread_r2c over about (TW + p - 1) / K2 of them, so the
+//   row scales are finer.
 //   Then two real rows per complex line for the axis-3 transform (the
 //   conversion inside its first radix stage), their half spectra unpacked
 //   to X[g2][m3] (row stride K3/2 + 1), the axis-2 transform of every m3
