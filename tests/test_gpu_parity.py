@@ -378,6 +378,25 @@ def test_fused_forward_matches_two_passes(dev):
     plan.close()
 
 
+def test_fused_forward_many_candidates(dev):
+    """A 192^3 grid with 97,336 atoms: about 3,000 candidates per plane, more
+    than the 2 x 1,024 that the forward plane pass holds in registers, so its
+    candidates are loaded again in each pass.  The product still matches the
+    spread and axis-2 passes to FP32 rounding."""
+    from paper_2607_17978_amd import qeq
+    s = gen.lattice_system(46, 213.5, 2027, grid=(192, 192, 192), name="n97336_L213.5")
+    plan = qeq.Plan(s.n, eta=ETA, r_cut=RC, grid=s.grid, tol=1e-6)
+    v = T(np.random.default_rng(11).normal(size=s.n), dev)
+    args = (T(s.pos, dev), s.cell, T(s.sigma, dev))
+    y1 = plan.matvec(*args, v, parts=qeq.PART_RECIP).cpu().numpy()
+    plan.use_fused_forward(False)
+    y0 = plan.matvec(*args, v, parts=qeq.PART_RECIP).cpu().numpy()
+    err = np.abs(y1 - y0).max() / np.abs(y0).max()
+    print("fused forward, 97,336 atoms: product rel max diff", err)
+    assert err <= 1e-5
+    plan.close()
+
+
 @pytest.mark.parametrize("which", ["n64", "batch3", "n4096", "n32768", "grid320"])
 def test_fused_interp_matches_grid_path(dev, which):
     """The complex-to-real pass fused with the back-interpolation (the CG
