@@ -397,6 +397,26 @@ def test_fused_forward_many_candidates(dev):
     plan.close()
 
 
+def test_fused_forward_empty_planes(dev):
+    """Atoms only in the lower half of the cell along axis 1 (8,000 atoms,
+    192^3): the planes of the upper half have no candidates, and the forward
+    plane pass still gives the two-pass product."""
+    from paper_2607_17978_amd import qeq
+    s = gen.lattice_system(20, 148.6, 7, grid=(192, 192, 192), name="n8000_half")
+    pos = s.pos.copy()
+    pos[:, 0] *= 0.5
+    plan = qeq.Plan(s.n, eta=ETA, r_cut=RC, grid=s.grid, tol=1e-6)
+    v = T(np.random.default_rng(13).normal(size=s.n), dev)
+    args = (T(pos, dev), s.cell, T(s.sigma, dev))
+    y1 = plan.matvec(*args, v, parts=qeq.PART_RECIP).cpu().numpy()
+    plan.use_fused_forward(False)
+    y0 = plan.matvec(*args, v, parts=qeq.PART_RECIP).cpu().numpy()
+    err = np.abs(y1 - y0).max() / np.abs(y0).max()
+    print("fused forward, half-filled cell: product rel max diff", err)
+    assert err <= 1e-5
+    plan.close()
+
+
 @pytest.mark.parametrize("which", ["n64", "batch3", "n4096", "n32768", "grid320"])
 def test_fused_interp_matches_grid_path(dev, which):
     """The complex-to-real pass fused with the back-interpolation (the CG
