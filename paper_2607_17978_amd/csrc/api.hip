@@ -540,7 +540,7 @@ void chunk_key(const qeq_plan* pl, std::vector<unsigned char>& key) {
                           pl->tw[0], pl->tw[1], pl->tw[2], pl->bmod[0], pl->bmod[1], pl->bmod[2],
                           pl->spc_active ? (const void*)pl->spc_mats : nullptr, pl->spc_wvec, pl->spc_m1,
                           pl->spc_atom, pl->spc_dpinv, pl->spc_tpart, pl->spc_s, pl->spc_scal,
-                          pl->spc_sd, pl->spc_psi, (const void*)(size_t)pl->spc_nm,
+                          pl->spc_sd, pl->spc_u, pl->spc_psi, (const void*)(size_t)pl->spc_nm,
                           (const void*)(size_t)pl->spc_npad, (const void*)(size_t)pl->direct, pl->np_pos,
                           pl->np_ypart, (const void*)(size_t)pl->np_nsplit, (const void*)(size_t)pl->np_tps,
                           (const void*)(size_t)pl->ew_active, pl->ew_modes, pl->ew_w, pl->ew_sf, pl->ew_y,
@@ -566,9 +566,11 @@ void drop_graph(qeq_plan* pl) {
 // One CG iteration: matvec of the direction, update of q and r, new direction.
 // Search direction from the current residual: Jacobi, or the spectral
 // preconditioner when it was built for this geometry.
-int next_direction(qeq_plan* pl, int parity, int init) {
+// u_ready: the update kernel has already written the spectral
+// preconditioner's input from r.
+int next_direction(qeq_plan* pl, int parity, int init, bool u_ready = false) {
     if (!pl->spc_active) return launch_cg_dir(pl, parity, init);
-    QEQ_TRY(spc_apply(pl, pl->r, &pl->sc->done));
+    QEQ_TRY(spc_apply(pl, pl->r, &pl->sc->done, u_ready));
     return spc_direction(pl, parity, init);
 }
 
@@ -592,7 +594,7 @@ int cg_matvec(qeq_plan* pl, const double* src, int parity) {
 int cg_iteration(qeq_plan* pl, int parity) {
     QEQ_TRY(cg_matvec(pl, pl->pvec, parity));
     QEQ_TRY(launch_cg_update(pl, parity));
-    return next_direction(pl, parity, 0);
+    return next_direction(pl, parity, 0, true);
 }
 
 // Capture `chunk` iterations (starting at even parity) into a graph unless the

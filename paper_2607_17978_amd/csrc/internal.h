@@ -373,7 +373,8 @@ void reciprocal_self_strain(const double* H, const double* Hinv, double vol, dou
 int virial_impl(qeq_plan* pl, double* virial);
 // spectral preconditioner (spectral.hip)
 int spc_setup(qeq_plan* pl);                          // after the geometry set-up
-int spc_apply(qeq_plan* pl, const double* r, const int* done);   // spc_wvec = M^-1 r, partials
+// spc_wvec = M^-1 r, partials; u_ready: k_cg_update has written spc_u from r
+int spc_apply(qeq_plan* pl, const double* r, const int* done, bool u_ready = false);
 int spc_direction(qeq_plan* pl, int parity, int init);            // p from spc_wvec
 void spc_free(qeq_plan* pl);
 // non-periodic solve (direct.hip)

@@ -430,10 +430,13 @@ __device__ __forceinline__ void block_total(double* v) {
 // Every load is issued before the converged flag is tested (the flag is the
 // same for all blocks), so that the flag, the partial sums and the vector
 // elements arrive in one memory round trip rather than three.
+// With the spectral preconditioner (sd != nullptr) it also writes that
+// preconditioner's input u = D'^-1/2 r (as k_spc_u does; the padding past n
+// keeps the zeros of the solve's first application).
 __global__ void k_cg_update(KParams k, const double* __restrict__ p, const double* __restrict__ y,
                             const double* __restrict__ dinv, double* __restrict__ q, double* __restrict__ r,
                             const double* __restrict__ part_in, int nparts, double* __restrict__ part_out,
-                            CgScalars* sc, int parity) {
+                            CgScalars* sc, int parity, const float* __restrict__ sd, float* __restrict__ u) {
     const int done = sc->done;
     const double rzp = sc->rz[parity];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -456,6 +459,7 @@ __global__ void k_cg_update(KParams k, const double* __restrict__ p, const doubl
         q[i] = qi + alpha * pi;
         ri -= alpha * (yi - ymean);
         r[i] = ri;
+        if (u) u[i] = (float)((double)sd[i] * ri);
         acc[0] = di * ri;
         acc[1] = di * ri * ri;
         acc[2] = ri * ri;
@@ -669,7 +673,8 @@ int launch_cg_update(qeq_plan* pl, int parity) {
     hipExtLaunchKernelGGL(k_cg_update, dim3(nb), dim3(vb), 0, pl->stream, ps.start(), ps.stop(), 0, pl->kp,
                        pl->pvec, pl->y,
                        pl->dinv, pl->q, pl->r, part_buf(pl, 0), interp_blocks(pl->kp.n), part_buf(pl, 1),
-                       pl->sc, parity);
+                       pl->sc, parity, pl->spc_active ? pl->spc_sd : nullptr,
+                       pl->spc_active ? pl->spc_u : nullptr);
     return qeq_check(hipGetLastError());
 }
 

@@ -692,13 +692,14 @@ int spc_setup(qeq_plan* pl) {
     return qeq_check(hipGetLastError());
 }
 
-int spc_apply(qeq_plan* pl, const double* r, const int* done) {
+int spc_apply(qeq_plan* pl, const double* r, const int* done, bool u_ready) {
     const KParams& k = pl->kp;
     const int nm = pl->spc_nm, nc = 2 * nm, ncp = pl->spc_ncp, npad = pl->spc_npad;
     const double* S = pl->spc_mats + 5 * (size_t)ncp * ncp;
     const unsigned short* psi = pl->spc_psi;
-    hipLaunchKernelGGL(k_spc_u, dim3(npad / 256), dim3(256), 0, pl->stream, k.n, npad, pl->spc_sd, r, pl->spc_u,
-                       done);
+    if (!u_ready)
+        hipLaunchKernelGGL(k_spc_u, dim3(npad / 256), dim3(256), 0, pl->stream, k.n, npad, pl->spc_sd, r, pl->spc_u,
+                           done);
     hipLaunchKernelGGL(k_spc_fwd, dim3(ncp / SPC_FROWS * pl->spc_fsplit), dim3(256), 0, pl->stream, npad, ncp,
                        pl->spc_fsplit, psi, pl->spc_u, pl->spc_tpart, done);
     hipLaunchKernelGGL(k_spc_treduce, dim3((nc + 3) / 4), dim3(256), 0, pl->stream, nc, ncp, pl->spc_fsplit,
