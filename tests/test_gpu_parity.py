@@ -417,6 +417,23 @@ def test_fused_forward_empty_planes(dev):
     plan.close()
 
 
+def test_fused_forward_other_axis1_length(dev):
+    """A 128 x 192 x 192 grid (8,000 atoms): the forward plane pass runs one
+    block per g1 plane for any K1 >= 64 and gives the two-pass product."""
+    from paper_2607_17978_amd import qeq
+    s = gen.lattice_system(20, 148.6, 31, grid=(128, 192, 192), name="n8000_k128")
+    plan = qeq.Plan(s.n, eta=ETA, r_cut=RC, grid=s.grid, tol=1e-6)
+    v = T(np.random.default_rng(17).normal(size=s.n), dev)
+    args = (T(s.pos, dev), s.cell, T(s.sigma, dev))
+    y1 = plan.matvec(*args, v, parts=qeq.PART_RECIP).cpu().numpy()
+    plan.use_fused_forward(False)
+    y0 = plan.matvec(*args, v, parts=qeq.PART_RECIP).cpu().numpy()
+    err = np.abs(y1 - y0).max() / np.abs(y0).max()
+    print("fused forward, 128 x 192 x 192: product rel max diff", err)
+    assert err <= 1e-5
+    plan.close()
+
+
 @pytest.mark.parametrize("which", ["n64", "batch3", "n4096", "n32768", "grid320"])
 def test_fused_interp_matches_grid_path(dev, which):
     """The complex-to-real pass fused with the back-interpolation (the CG
