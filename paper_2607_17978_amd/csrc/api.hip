@@ -935,6 +935,7 @@ int qeq_plan_create(qeq_plan** out, const qeq_params* params, int32_t n_atoms_ma
     A(dalloc(&pl->rowptr, n + 1));
     A(dalloc(&pl->cell_atoms, n));
     A(dalloc(&pl->rowcnt, n + 1));
+    A(dalloc(&pl->lanecnt, (size_t)64 * n));
     int np = 2 * QEQ_MAXP - 1;
     A(dalloc(&pl->theta_tab, (size_t)np * np * np));
     pl->nblk_max = std::max(interp_blocks(n_atoms_max), nblocks(n_atoms_max)) + 1;   // most blocks of any reduction
@@ -970,7 +971,7 @@ int qeq_plan_destroy(qeq_plan* pl) {
     dfree(pl->perm); dfree(pl->key); dfree(pl->frac); dfree(pl->home); dfree(pl->wts); dfree(pl->dwts);
     dfree(pl->sig); dfree(pl->Jv); dfree(pl->chi); dfree(pl->chi_raw); dfree(pl->dself); dfree(pl->dinv);
     dfree(pl->selfgrad); dfree(pl->q); dfree(pl->r); dfree(pl->pvec); dfree(pl->y); dfree(pl->forces_s);
-    dfree(pl->gtmp); dfree(pl->q_adj); dfree(pl->y_adj); dfree(pl->chi_adj); dfree(pl->adj_scratch); dfree(pl->tq); dfree(pl->rowptr); dfree(pl->rowcnt); dfree(pl->theta_tab); dfree(pl->part);
+    dfree(pl->gtmp); dfree(pl->q_adj); dfree(pl->y_adj); dfree(pl->chi_adj); dfree(pl->adj_scratch); dfree(pl->tq); dfree(pl->rowptr); dfree(pl->rowcnt); dfree(pl->lanecnt); dfree(pl->theta_tab); dfree(pl->part);
     dfree(pl->strain_tab); dfree(pl->vir_part); dfree(pl->mpart);
     spc_free(pl);
     np_free(pl);

@@ -179,6 +179,7 @@ struct qeq_plan {
     int* cell_atoms = nullptr;
     int* rowptr = nullptr;        // n + 1
     int* rowcnt = nullptr;
+    int* lanecnt = nullptr;       // [n_max][64] pairs per lane of the count pass (the fill's slices)
     size_t nnz_cap = 0;
     int* col = nullptr;
     float* kval = nullptr;

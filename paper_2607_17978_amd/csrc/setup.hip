@@ -271,7 +271,7 @@ __global__ __launch_bounds__(QEQ_BLOCK) void k_pairs(KParams k, const double* __
                                                     const int* __restrict__ cell_atoms, int* __restrict__ rowcnt,
                                                     const int* __restrict__ rowptr, int* __restrict__ col,
                                                     float* __restrict__ kval, float4* __restrict__ pdr,
-                                                    long long cap) {
+                                                    long long cap, int* __restrict__ lanecnt) {
     // FILL stages a row of up to PBUF pairs in this wave's LDS slice and
     // evaluates the FP64 kernel values afterwards with one pair per lane
     // (inside the stencil loop the divergent lanes would run the erf pair
@@ -301,8 +301,21 @@ __global__ __launch_bounds__(QEQ_BLOCK) void k_pairs(KParams k, const double* __
     const int w2 = 2 * k.ns[1] + 1, w3 = 2 * k.ns[2] + 1;
     const int nst = (2 * k.ns[0] + 1) * w2 * w3;
     int off = 0;
-    for (int pass = FILL ? 0 : 1; pass < 2; ++pass) {
-        // pass 0 (FILL only): count to find this lane's slice; pass 1: count or write
+    if (FILL) {
+        // this lane's slice of the row, from the counts that the count pass
+        // took over the same stencil walk
+        const int c = lanecnt[(size_t)i * 64 + lane];
+        int incl = c;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int y = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += y;
+        }
+        off = rowptr[i] + incl - c;
+        loff = incl - c;
+    }
+    {
+        // count (with the lane's count kept for the fill) or write
         int cnt = 0;
         for (int t = lane; t < nst; t += 64) {
             const int d3 = t % w3 - k.ns[2], d2 = (t / w3) % w2 - k.ns[1], d1 = t / (w3 * w2) - k.ns[0];
@@ -323,7 +336,7 @@ __global__ __launch_bounds__(QEQ_BLOCK) void k_pairs(KParams k, const double* __
                 const double dz = ds0 * k.H[2] + ds1 * k.H[5] + ds2 * k.H[8];
                 const double r2v = dx * dx + dy * dy + dz * dz;
                 if (r2v >= k.rc2) continue;
-                if (FILL && pass == 1) {
+                if (FILL) {
                     if (staged) {
                         // r_i - r_j(image) for the force, the FP64 distance beside it
                         st_j[sbase + loff] = j;
@@ -343,17 +356,15 @@ __global__ __launch_bounds__(QEQ_BLOCK) void k_pairs(KParams k, const double* __
                 ++cnt;
             }
         }
-        int incl = cnt;
+        if (!FILL) {
+            lanecnt[(size_t)i * 64 + lane] = cnt;
+            int incl = cnt;
 #pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const int y = __shfl_up(incl, d, 64);
-            if (lane >= d) incl += y;
-        }
-        if (FILL) {
-            off = rowptr[i] + incl - cnt;
-            loff = incl - cnt;
-        } else if (lane == 63) {
-            rowcnt[i] = incl;
+            for (int d = 1; d < 64; d <<= 1) {
+                const int y = __shfl_up(incl, d, 64);
+                if (lane >= d) incl += y;
+            }
+            if (lane == 63) rowcnt[i] = incl;
         }
     }
     if (staged) {
@@ -546,7 +557,7 @@ int launch_cells_and_pairs(qeq_plan* pl) {
     const int pair_blocks = nblocks(k.n * 64);   // one wave per atom
     hipLaunchKernelGGL(k_pairs<false>, dim3(pair_blocks), dim3(QEQ_BLOCK), 0, pl->stream, k,
                        pl->frac, pl->home, pl->sig, pl->cell_start, pl->cell_atoms, pl->rowcnt,
-                       pl->rowptr, pl->col, pl->kval, pl->pdr, (long long)0);
+                       pl->rowptr, pl->col, pl->kval, pl->pdr, (long long)0, pl->lanecnt);
     QEQ_TRY(launch_scan(pl, pl->rowcnt, pl->rowptr, k.n));
     // the total goes to the host with the set-up's error flag (one read-back
     // for both, in setup_geometry); until then the arrays keep their size, or
@@ -564,7 +575,7 @@ int launch_pair_fill(qeq_plan* pl) {
     const KParams& k = pl->kp;
     hipLaunchKernelGGL(k_pairs<true>, dim3(nblocks(k.n * 64)), dim3(QEQ_BLOCK), 0, pl->stream, k,
                        pl->frac, pl->home, pl->sig, pl->cell_start, pl->cell_atoms, pl->rowcnt,
-                       pl->rowptr, pl->col, pl->kval, pl->pdr, (long long)pl->nnz_cap);
+                       pl->rowptr, pl->col, pl->kval, pl->pdr, (long long)pl->nnz_cap, pl->lanecnt);
     return qeq_check(hipGetLastError());
 }
 
