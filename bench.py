@@ -489,6 +489,13 @@ def main():
         "spectral_preconditioner": spectral,
     }
     plan.close()
+    if name == "spread_r2c" and cnt_all[1] == 0:
+        # the forward plane pass ran (no separate axis-2 pass): context only,
+        # the bytes that the spread and axis-2 passes it replaces would move
+        # for the same work, and the rate on them
+        two = by["spread_r2c"] + by["fft_rows_fwd"]
+        out["roofline"]["two_pass_bytes"] = two
+        out["roofline"]["frac_two_pass_bytes"] = round(two / dur_s / 1e9 / HBM_PEAK_GBPS, 4)
     if tiles is not None:
         out["autotune_tiles"] = tiles
     if args.workload == "cold32k":
