@@ -512,7 +512,7 @@ int prepare(qeq_plan* pl, int n, const double* cell, double q_tot) {
 // Geometry-dependent setup on the device; one host sync (pair count, input flag).
 int setup_geometry(qeq_plan* pl, const double* pos, const double* sigma, const double* J,
                    const double* chi) {
-    QEQ_HIP(hipMemsetAsync(pl->sc, 0, sizeof(CgScalars), pl->stream));
+    QEQ_TRY(launch_setup_clear(pl));   // CG scalars, bin and cell counters
     QEQ_TRY(launch_stage(pl, pos, sigma, J, chi));
     QEQ_TRY(launch_sort_bins(pl));
     QEQ_TRY(launch_gather(pl, pos, sigma, J, chi));

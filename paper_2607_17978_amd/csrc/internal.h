@@ -350,6 +350,7 @@ inline int interp_blocks(int n) {
 }
 
 // ------------------------------------------------------------------ setup kernels (setup.hip)
+int launch_setup_clear(qeq_plan* pl);   // zeroes the CG scalars and the bin / cell counters
 int launch_stage(qeq_plan* pl, const double* pos, const double* sigma, const double* J,
                  const double* chi);
 int launch_sort_bins(qeq_plan* pl);

@@ -493,12 +493,37 @@ int launch_scan(qeq_plan* pl, const int* in, int* out, int m) {
     return qeq_check(hipGetLastError());
 }
 
+// The set-up's bin and cell counters and the CG scalars, zeroed in one launch
+// (separate memsets would each cost the host a call while the GPU waits).
+__global__ void k_setup_clear(int* __restrict__ sc_words, int nsc, int* __restrict__ bc, int* __restrict__ bf,
+                              int nbins, int* __restrict__ cc, int* __restrict__ cf, int ncells) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < nsc) sc_words[t] = 0;
+    if (t < nbins) {
+        bc[t] = 0;
+        bf[t] = 0;
+    }
+    if (t < ncells) {
+        cc[t] = 0;
+        cf[t] = 0;
+    }
+}
+
+int launch_setup_clear(qeq_plan* pl) {
+    const KParams& k = pl->kp;
+    static_assert(sizeof(CgScalars) % sizeof(int) == 0, "CgScalars clears as ints");
+    const int nsc = (int)(sizeof(CgScalars) / sizeof(int));
+    const int nbins = k.K1 * k.K2 + 1, ncells = k.nc[0] * k.nc[1] * k.nc[2] + 1;
+    const int m = std::max(nsc, std::max(nbins, ncells));
+    hipLaunchKernelGGL(k_setup_clear, dim3((m + QEQ_BLOCK - 1) / QEQ_BLOCK), dim3(QEQ_BLOCK), 0, pl->stream,
+                       reinterpret_cast<int*>(pl->sc), nsc, pl->bin_count, pl->bin_fill, nbins, pl->cell_count,
+                       pl->cell_fill, ncells);
+    return qeq_check(hipGetLastError());
+}
+
 int launch_stage(qeq_plan* pl, const double* pos, const double* sigma, const double* J,
                  const double* chi) {
     const KParams& k = pl->kp;
-    int nb = k.K1 * k.K2;
-    QEQ_HIP(hipMemsetAsync(pl->bin_count, 0, sizeof(int) * (nb + 1), pl->stream));
-    QEQ_HIP(hipMemsetAsync(pl->bin_fill, 0, sizeof(int) * (nb + 1), pl->stream));
     hipLaunchKernelGGL(k_stage, dim3(nblocks(k.n)), dim3(QEQ_BLOCK), 0, pl->stream, k, pos, sigma,
                        J, chi, pl->key, pl->bin_count, pl->sc);
     return qeq_check(hipGetLastError());
@@ -518,9 +543,6 @@ int launch_sort_bins(qeq_plan* pl) {
 int launch_gather(qeq_plan* pl, const double* pos, const double* sigma, const double* J,
                   const double* chi) {
     const KParams& k = pl->kp;
-    int ncell = k.nc[0] * k.nc[1] * k.nc[2];
-    QEQ_HIP(hipMemsetAsync(pl->cell_count, 0, sizeof(int) * (ncell + 1), pl->stream));
-    QEQ_HIP(hipMemsetAsync(pl->cell_fill, 0, sizeof(int) * (ncell + 1), pl->stream));
     int nb = nblocks(k.n);
     double* part1 = pl->part;
     double* part2 = pl->part + (size_t)pl->nblk_max * QEQ_NPART;
